@@ -1,0 +1,161 @@
+/*
+ * fmm.h -- C ABI of the MI355X 3-D Laplace fast multipole library.
+ *
+ * The operation (Yokota, Ibeid, Keyes, "Fast Multipole Method as a Matrix-Free
+ * Hierarchical Low-Rank Approximation", Sec. 1): for N points x_i that are both
+ * sources and targets, with charges q_i,
+ *
+ *     phi_i  = sum_{j != i, x_j != x_i} q_j / |x_i - x_j|        (no 4*pi)
+ *     grad_i = d phi / d x_i  (the gradient of phi, not the field -grad phi)
+ *
+ * approximated by the FMM: a hierarchical octree decomposition with multipole
+ * and local expansions of order p for the far field, and a direct sum over
+ * neighbouring leaves for the near field.  The paper treats the FMM as a
+ * matrix-free H^2 mat-vec whose set-up and application are timed separately
+ * (Sec. 1; Sec. 4.1), and asks for a split between the hierarchical structure
+ * and the inner kernels (Sec. 5); hence a plan (octree + interaction lists,
+ * Sec. 2.2) built once per point set and applied to any number of charge
+ * vectors.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers on the current HIP device, owned by
+ *     the caller, FP32, contiguous, row-major.  points/gradients are [n][3].
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *     is asynchronous on that stream except fmm_plan, which synchronises the
+ *     stream a few times to read counts back to the host.
+ *   - Errors are returned as fmm_status; nothing crosses the ABI as an
+ *     exception.  fmm_last_error() gives a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - Results are deterministic: the same inputs give bit-identical outputs.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan_s *fmm_plan_t;
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_EINVAL = 1,       /* bad argument (n < 1, ncrit < 1, p outside [0,16], theta outside (0, 1/sqrt 3), NULL pointer) */
+    FMM_ENOMEM = 2,       /* the allocator returned NULL */
+    FMM_EDEVICE = 3,      /* a HIP runtime call failed */
+    FMM_ENONFINITE = 4,   /* a coordinate is NaN or infinite */
+    FMM_EUNSUPPORTED = 5  /* geometry outside the library's limits (e.g. an M2L offset too large to key) */
+} fmm_status;
+
+typedef enum {
+    FMM_PREC_FP32 = 0,    /* FP32 everywhere (M2L on FP32 MFMA) */
+    FMM_PREC_MIXED = 1    /* split-FP16 M2L on MFMA with FP32 accumulation, compensated FP32 P2P,
+                             FP64 coefficient accumulation at the root levels */
+} fmm_precision;
+
+/* Phase mask for fmm_eval_ex */
+#define FMM_NEAR 1        /* near field only: P2P over neighbouring leaves */
+#define FMM_FAR 2         /* far field only: P2M, M2M, M2L, L2L, L2P */
+#define FMM_ALL 3
+
+/*
+ * Device allocator used for every plan workspace.  alloc returns NULL on
+ * failure (the call then fails with FMM_ENOMEM).  Both are called with the
+ * stream of the plan call.  Passing NULL for both restores the default
+ * (hipMallocAsync / hipFreeAsync on that stream).  Plans keep the allocator
+ * that was current when they were built.
+ */
+typedef void *(*fmm_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*fmm_free_fn)(void *ptr, void *stream, void *ctx);
+fmm_status fmm_set_allocator(fmm_alloc_fn alloc, fmm_free_fn release, void *ctx);
+
+/*
+ * Build a plan for `n` points (device [n][3] FP32).
+ *   ncrit  >= 1   a cell is split while it holds more than ncrit points (and is above level 21)
+ *   p in [0, 16]  expansion order: spherical harmonics of degree 0..p, (p+1)^2 coefficients
+ *   theta         opening angle of the multipole acceptance criterion: the pair (A <- B) is
+ *                 far iff A != B and theta*|c_A - c_B| >= R_A + R_B (R = half box side);
+ *                 0 < theta < 1/sqrt(3) so that accepted pairs are always convergent
+ *   prec          FMM_PREC_FP32 or FMM_PREC_MIXED
+ * On success *out owns all plan memory (allocated through the current allocator on
+ * `stream`).  The plan copies what it needs from `points`; the buffer may be reused
+ * after the call returns.
+ */
+fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float theta,
+                    fmm_precision prec, void *stream, fmm_plan_t *out);
+
+/*
+ * Apply the plan to charges q (device [n]): potential (device [n]) and, when
+ * `gradient` is not NULL, grad phi (device [n][3]).  Outputs are in input order.
+ * Calls that share one plan must not overlap (the plan holds the work buffers).
+ */
+fmm_status fmm_eval(fmm_plan_t plan, const float *charges, float *potential, float *gradient, void *stream);
+
+/* As fmm_eval, restricted to the phases in `phases` (FMM_NEAR | FMM_FAR). */
+fmm_status fmm_eval_ex(fmm_plan_t plan, const float *charges, float *potential, float *gradient,
+                       int phases, void *stream);
+
+/*
+ * Adjoint of L = sum_i w_i phi_i with w = dL_dphi (device [n]), for the frozen plan:
+ *   dL_dq[i]  = sum_k w_k A_ki  = (A w)_i            (A is symmetric: the same FMM with charges w)
+ *   dL_dx[i]  = w_i grad phi(x_i) + q_i grad psi(x_i),  psi = A w
+ * gradient_fwd is grad phi from fmm_eval with `charges` ([n][3]); when NULL it is recomputed.
+ * dL_dq is [n], dL_dx is [n][3]; either may be NULL to skip it.
+ */
+fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradient_fwd,
+                       const float *dL_dphi, float *dL_dq, float *dL_dx, void *stream);
+
+/* Plan statistics (host struct, filled synchronously from host-side copies). */
+#define FMM_MAX_LEVELS 22
+struct fmm_stats {
+    int64_t n;
+    int32_t p, ncrit, precision, max_level;
+    float theta;
+    int32_t root_exponent;                  /* root side = 2^root_exponent */
+    double root_corner[3];
+    int64_t ncells, nleaves;
+    int64_t cells_per_level[FMM_MAX_LEVELS];
+    int64_t leaves_per_level[FMM_MAX_LEVELS];
+    int64_t m2l_pairs, m2l_pairs_same_level;
+    int64_t m2l_keys, m2l_keys_same_level;  /* distinct (level difference, offset) operators */
+    int64_t m2l_targets, m2l_tiles, m2l_entries, m2l_work_items;
+    int64_t p2p_pairs;                      /* (target leaf, source leaf) pairs */
+    int64_t p2p_interactions;               /* ordered (target, source) point pairs, self excluded */
+    int64_t ncoef, ncoef_padded;            /* (p+1)^2 and its padded length */
+    double m2l_flops;                       /* 2 (p+1)^4 per M2L pair */
+    double p2p_flops;                       /* 20 per interaction (stated convention) */
+    int64_t workspace_bytes;
+};
+fmm_status fmm_plan_stats(fmm_plan_t plan, struct fmm_stats *out);
+
+/*
+ * Copies of the plan's tree and lists into HOST arrays (sizes from fmm_plan_stats),
+ * for checking the plan against an independent construction.  Cells are numbered
+ * level by level, Morton order inside a level.  Any pointer may be NULL.
+ *   level[ncells], prefix[ncells] (Morton prefix: key >> 3*(21-level)), start[ncells],
+ *   count[ncells] (range in the sorted order), leaf[ncells] (0/1)
+ *   order[n]: sorted position -> input index
+ *   m2l[m2l_pairs][2], p2p[p2p_pairs][2]: (target cell, source cell)
+ */
+fmm_status fmm_plan_export(fmm_plan_t plan, int32_t *level, uint64_t *prefix, int64_t *start,
+                           int64_t *count, int32_t *leaf, int64_t *order, int64_t *m2l, int64_t *p2p);
+
+/*
+ * Per-phase device time of the most recent fmm_eval / fmm_adjoint on this plan, measured
+ * with HIP events on the stream each phase ran on, when timing is enabled (fmm_plan_set_timing).
+ * ms[] order: 0 permute, 1 P2M, 2 M2M, 3 M2L, 4 L2L, 5 L2P, 6 P2P, 7 combine, 8 total.
+ * Synchronises the plan's events.
+ */
+#define FMM_NUM_PHASES 9
+fmm_status fmm_plan_set_timing(fmm_plan_t plan, int enable);
+fmm_status fmm_plan_phase_times(fmm_plan_t plan, float *ms);
+
+void fmm_plan_destroy(fmm_plan_t plan);
+const char *fmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H */

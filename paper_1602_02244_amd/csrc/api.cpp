@@ -1,0 +1,278 @@
+// C ABI of the FMM library: argument validation, status codes, plan lifetime,
+// statistics and exports.  All computation happens in the device kernels of
+// plan.hip and eval.hip.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+void build_plan(fmm_plan_s *P, const float *points, hipStream_t s);
+void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phases, hipStream_t s);
+void run_adjoint_combine(fmm_plan_s *Pl, const float *w, const float *gphi, const float *q, const float *gpsi, float *dx,
+                         hipStream_t s);
+}  // namespace fmm
+
+using namespace fmm;
+
+namespace {
+thread_local std::string g_err;
+std::mutex g_alloc_mu;
+fmm_alloc_fn g_alloc = nullptr;
+fmm_free_fn g_free = nullptr;
+void *g_ctx = nullptr;
+
+fmm_status set_err(fmm_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+void destroy_plan(fmm_plan_s *P) {
+    if (!P) return;
+    if (P->last_stream_set) (void)hipStreamSynchronize(P->last_stream);
+    if (P->side) (void)hipStreamSynchronize(P->side);
+    (void)hipStreamSynchronize(P->mem.stream);
+    P->mem.release_all();
+    (void)hipStreamSynchronize(P->mem.stream);
+    if (P->side) (void)hipStreamDestroy(P->side);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    for (auto &e : P->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete P;
+}
+
+template <class F> fmm_status guarded(F &&f) {
+    try {
+        f();
+        return FMM_OK;
+    } catch (const Error &e) {
+        return set_err(e.status, e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(FMM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_err(FMM_EDEVICE, "unexpected internal error");
+    }
+}
+
+void fill_stats(fmm_plan_s *P) {
+    fmm_stats &st = P->stats;
+    std::memset(&st, 0, sizeof(st));
+    st.n = P->n;
+    st.p = P->p;
+    st.ncrit = P->ncrit;
+    st.precision = (int32_t)P->prec;
+    st.max_level = P->max_level;
+    st.theta = P->theta;
+    st.root_exponent = P->k;
+    for (int a = 0; a < 3; ++a) st.root_corner[a] = P->x0[a];
+    st.ncells = P->ncells;
+    st.nleaves = P->nleaves;
+    for (int l = 0; l <= P->max_level && l < FMM_MAX_LEVELS; ++l)
+        st.cells_per_level[l] = P->level_off[l + 1] - P->level_off[l];
+    // leaves per level from a host copy of the child counts
+    std::vector<int32_t> nch(P->ncells);
+    HIP_CHECK(hipMemcpyAsync(nch.data(), P->c_nchild, 4 * P->ncells, hipMemcpyDeviceToHost, P->mem.stream));
+    HIP_CHECK(hipStreamSynchronize(P->mem.stream));
+    for (int l = 0; l <= P->max_level && l < FMM_MAX_LEVELS; ++l)
+        for (int64_t c = P->level_off[l]; c < P->level_off[l + 1]; ++c) st.leaves_per_level[l] += nch[c] == 0;
+    st.m2l_pairs = P->nm2l;
+    st.m2l_pairs_same_level = P->nm2l_same;
+    st.m2l_keys = P->nkeys;
+    st.m2l_keys_same_level = P->nkeys_same;
+    st.m2l_targets = P->ntargets;
+    st.m2l_tiles = P->ntiles;
+    st.m2l_entries = P->nentries;
+    st.m2l_work_items = P->nwork;
+    st.p2p_pairs = P->np2p;
+    st.p2p_interactions = P->p2p_interactions;
+    st.ncoef = ncoef(P->p);
+    st.ncoef_padded = P->KP;
+    double nc = (double)ncoef(P->p);
+    st.m2l_flops = 2.0 * nc * nc * (double)P->nm2l;
+    st.p2p_flops = 20.0 * (double)P->p2p_interactions;
+    st.workspace_bytes = P->mem.bytes;
+}
+}  // namespace
+
+extern "C" {
+
+const char *fmm_last_error(void) { return g_err.c_str(); }
+
+fmm_status fmm_set_allocator(fmm_alloc_fn alloc, fmm_free_fn release, void *ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) return set_err(FMM_EINVAL, "allocator and release must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = alloc;
+    g_free = release;
+    g_ctx = ctx;
+    return FMM_OK;
+}
+
+fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec, void *stream,
+                    fmm_plan_t *out) {
+    if (!out) return set_err(FMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!points) return set_err(FMM_EINVAL, "points is NULL");
+    if (n < 1) return set_err(FMM_EINVAL, "n must be >= 1");
+    if (n >= (int64_t(1) << 31) - 1) return set_err(FMM_EUNSUPPORTED, "n must be below 2^31 - 1");
+    if (ncrit < 1) return set_err(FMM_EINVAL, "ncrit must be >= 1");
+    if (p < 0 || p > kMaxP) return set_err(FMM_EINVAL, "p must be in [0, 16]");
+    if (!std::isfinite(theta) || !(theta > 0.f) || !(3.0 * (double)theta * (double)theta < 1.0))
+        return set_err(FMM_EINVAL, "theta must be in (0, 1/sqrt(3))");
+    if (prec != FMM_PREC_FP32 && prec != FMM_PREC_MIXED) return set_err(FMM_EINVAL, "unknown precision");
+    if (prec == FMM_PREC_MIXED) return set_err(FMM_EUNSUPPORTED, "mixed precision is not available in this build");
+    fmm_plan_s *P = new (std::nothrow) fmm_plan_s();
+    if (!P) return set_err(FMM_ENOMEM, "host allocation failed");
+    P->n = n;
+    P->ncrit = ncrit;
+    P->p = p;
+    P->theta = theta;
+    P->prec = prec;
+    P->KP = ncoef_pad(p);
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        P->mem.alloc = g_alloc;
+        P->mem.release = g_free;
+        P->mem.ctx = g_ctx;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    P->mem.stream = s;
+    fmm_status st = guarded([&] {
+        HIP_CHECK(hipGetDevice(&P->device));
+        HIP_CHECK(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+        build_plan(P, points, s);
+        fill_stats(P);
+    });
+    if (st != FMM_OK) {
+        destroy_plan(P);
+        return st;
+    }
+    *out = P;
+    return FMM_OK;
+}
+
+fmm_status fmm_eval_ex(fmm_plan_t plan, const float *charges, float *potential, float *gradient, int phases,
+                       void *stream) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    if (!charges) return set_err(FMM_EINVAL, "charges is NULL");
+    if (!potential && !gradient) return set_err(FMM_EINVAL, "potential and gradient are both NULL");
+    if (phases < 1 || phases > 3) return set_err(FMM_EINVAL, "phases must be a non-empty subset of FMM_NEAR | FMM_FAR");
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        plan->last_stream = s;
+        plan->last_stream_set = true;
+        run_eval(plan, charges, potential, gradient, phases, s);
+    });
+}
+
+fmm_status fmm_eval(fmm_plan_t plan, const float *charges, float *potential, float *gradient, void *stream) {
+    return fmm_eval_ex(plan, charges, potential, gradient, FMM_ALL, stream);
+}
+
+fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradient_fwd, const float *dL_dphi,
+                       float *dL_dq, float *dL_dx, void *stream) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    if (!dL_dphi) return set_err(FMM_EINVAL, "dL_dphi is NULL");
+    if (dL_dx && !charges) return set_err(FMM_EINVAL, "charges is NULL");
+    if (!dL_dq && !dL_dx) return FMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        fmm_plan_s *P = plan;
+        P->last_stream = s;
+        P->last_stream_set = true;
+        if (!P->tmp_phi) {
+            hipStream_t keep = P->mem.stream;
+            P->mem.stream = s;
+            P->tmp_phi = P->mem.get_n<float>(P->n);
+            P->tmp_grad = P->mem.get_n<float>(3 * P->n);
+            P->tmp_gfwd = P->mem.get_n<float>(3 * P->n);
+            P->mem.stream = keep;
+        }
+        // psi = A w and grad psi: the same FMM with charges w (A is symmetric)
+        run_eval(P, dL_dphi, dL_dq ? dL_dq : P->tmp_phi, dL_dx ? P->tmp_grad : nullptr, FMM_ALL, s);
+        if (dL_dx) {
+            const float *gphi = gradient_fwd;
+            if (!gphi) {
+                float *scratch_phi = dL_dq ? P->tmp_phi : P->tmp_gfwd;   // potential is not needed
+                (void)scratch_phi;
+                run_eval(P, charges, nullptr, P->tmp_gfwd, FMM_ALL, s);
+                gphi = P->tmp_gfwd;
+            }
+            run_adjoint_combine(P, dL_dphi, gphi, charges, P->tmp_grad, dL_dx, s);
+        }
+    });
+}
+
+fmm_status fmm_plan_stats(fmm_plan_t plan, struct fmm_stats *out) {
+    if (!plan || !out) return set_err(FMM_EINVAL, "NULL argument");
+    *out = plan->stats;
+    out->workspace_bytes = plan->mem.bytes;
+    return FMM_OK;
+}
+
+fmm_status fmm_plan_export(fmm_plan_t plan, int32_t *level, uint64_t *prefix, int64_t *start, int64_t *count,
+                           int32_t *leaf, int64_t *order, int64_t *m2l, int64_t *p2p) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    fmm_plan_s *P = plan;
+    hipStream_t s = P->mem.stream;
+    return guarded([&] {
+        const int64_t nc = P->ncells;
+        std::vector<int32_t> tmp;
+        auto i32 = [&](const int32_t *dev, int64_t nn) {
+            tmp.resize(nn);
+            HIP_CHECK(hipMemcpyAsync(tmp.data(), dev, 4 * nn, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+        };
+        if (level) {
+            i32(P->c_level, nc);
+            std::memcpy(level, tmp.data(), 4 * nc);
+        }
+        if (prefix) {
+            HIP_CHECK(hipMemcpyAsync(prefix, P->c_prefix_dev, 8 * nc, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+        }
+        if (start) { i32(P->c_start, nc); for (int64_t c = 0; c < nc; ++c) start[c] = tmp[c]; }
+        if (count) { i32(P->c_count, nc); for (int64_t c = 0; c < nc; ++c) count[c] = tmp[c]; }
+        if (leaf) { i32(P->c_nchild, nc); for (int64_t c = 0; c < nc; ++c) leaf[c] = tmp[c] == 0; }
+        if (order) { i32(P->perm, P->n); for (int64_t i = 0; i < P->n; ++i) order[i] = tmp[i]; }
+        auto pairs = [&](const int2 *dev, int64_t np, int64_t *outp) {
+            std::vector<int2> h(np);
+            if (np > 0) {
+                HIP_CHECK(hipMemcpyAsync(h.data(), dev, sizeof(int2) * np, hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+            }
+            for (int64_t i = 0; i < np; ++i) { outp[2 * i] = h[i].x; outp[2 * i + 1] = h[i].y; }
+        };
+        if (m2l) pairs(P->m2l_pairs, P->nm2l, m2l);
+        if (p2p) pairs(P->p2p_pairs, P->np2p, p2p);
+    });
+}
+
+fmm_status fmm_plan_set_timing(fmm_plan_t plan, int enable) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    return guarded([&] {
+        if (enable && !plan->ev[0])
+            for (auto &e : plan->ev) HIP_CHECK(hipEventCreate(&e));
+        plan->timing = enable != 0;
+        plan->ev_valid = false;
+    });
+}
+
+fmm_status fmm_plan_phase_times(fmm_plan_t plan, float *ms) {
+    if (!plan || !ms) return set_err(FMM_EINVAL, "NULL argument");
+    if (!plan->ev_valid) return set_err(FMM_EINVAL, "no timed evaluation recorded (enable timing first)");
+    return guarded([&] {
+        for (int ph = 0; ph < FMM_NUM_PHASES; ++ph) {
+            HIP_CHECK(hipEventSynchronize(plan->ev[2 * ph + 1]));
+            HIP_CHECK(hipEventElapsedTime(&ms[ph], plan->ev[2 * ph], plan->ev[2 * ph + 1]));
+        }
+    });
+}
+
+void fmm_plan_destroy(fmm_plan_t plan) { destroy_plan(plan); }
+
+}  // extern "C"

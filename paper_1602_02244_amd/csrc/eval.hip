@@ -1,0 +1,569 @@
+// Evaluation kernels of the FMM (Sec. 1: upward pass P2M/M2M, M2L over the
+// interaction lists, downward pass L2L/L2P, near-field P2P) for CDNA4.
+//
+// Expansions are scaled complex solid harmonics stored as real vectors (see
+// operators.cpp); every cell's coefficients use its own side s as the length unit,
+// so one translation matrix serves all levels.
+//
+//   P2M   one wave per leaf; each lane evaluates R_lm at one body, wave reductions
+//   M2M   one wave per parent; lanes own output rows, child vectors broadcast from LDS
+//   M2L   grouped GEMM on FP32 MFMA (16x16x4): a tile of 64 target cells (same level,
+//         same octant, Morton order) accumulates T_key * [M of the 64 sources] over the
+//         tile's operator keys; T streams from L2, the gathered sources sit in LDS
+//   L2L   one wave per cell
+//   L2P   one wave per leaf; potential and gradient from the local expansion
+//   P2P   one 256-thread workgroup per target leaf; source bodies staged through LDS in
+//         batches of 1024, each lane owns (target, source subset), rsqrt inner loop
+#include <algorithm>
+#include <cmath>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+#define TRI(l, m) ((l) * ((l) + 1) / 2 + (m))
+
+template <int P> struct Dims {
+    static constexpr int NT = (P + 1) * (P + 2) / 2;    // (l, m >= 0) pairs
+    static constexpr int NC = (P + 1) * (P + 1);        // real coefficients
+    static constexpr int KP = (NC + 15) / 16 * 16;      // padded
+};
+
+// Regular solid harmonics R_lm(x, y, z), m >= 0, as (re, im) in TRI order.
+template <int P>
+__device__ __forceinline__ void regular_harmonics(float x, float y, float z, float *Rr, float *Ri) {
+    const float r2 = x * x + y * y + z * z;
+    Rr[0] = 1.f;
+    Ri[0] = 0.f;
+#pragma unroll
+    for (int m = 1; m <= P; ++m) {
+        const float c = -1.f / (2.f * m);
+        const float ar = Rr[TRI(m - 1, m - 1)], ai = Ri[TRI(m - 1, m - 1)];
+        Rr[TRI(m, m)] = c * (x * ar - y * ai);
+        Ri[TRI(m, m)] = c * (x * ai + y * ar);
+    }
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        Rr[TRI(m + 1, m)] = z * Rr[TRI(m, m)];
+        Ri[TRI(m + 1, m)] = z * Ri[TRI(m, m)];
+#pragma unroll
+        for (int l = m + 1; l < P; ++l) {
+            const float den = 1.f / (float)((l + m + 1) * (l - m + 1));
+            const float c1 = (2 * l + 1) * den;
+            Rr[TRI(l + 1, m)] = c1 * z * Rr[TRI(l, m)] - den * r2 * Rr[TRI(l - 1, m)];
+            Ri[TRI(l + 1, m)] = c1 * z * Ri[TRI(l, m)] - den * r2 * Ri[TRI(l - 1, m)];
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void cell_center(int lvl, int ix, int iy, int iz, double x0x, double x0y, double x0z, int k,
+                                            double &cx, double &cy, double &cz, double &inv_side) {
+    double side = ldexp(1.0, k - lvl);
+    inv_side = ldexp(1.0, lvl - k);
+    cx = x0x + ((double)ix + 0.5) * side;
+    cy = x0y + ((double)iy + 0.5) * side;
+    cz = x0z + ((double)iz + 0.5) * side;
+}
+
+struct Geo {
+    const int32_t *start, *count, *level, *ix, *iy, *iz, *parent, *child0, *nchild;
+    double x0x, x0y, x0z;
+    int k;
+};
+
+// ------------------------------------------------------------------ P2M
+template <int P>
+__global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, Geo g, const float4 *bodies, float *M) {
+    using D = Dims<P>;
+    constexpr int NR = (D::KP + 63) / 64;
+    const int c = leaves[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int s = g.start[c], n = g.count[c];
+    double cx, cy, cz, inv;
+    cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
+    float acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.f;
+    for (int base = 0; base < n; base += 64) {
+        const int j = base + lane;
+        float ux = 0.f, uy = 0.f, uz = 0.f, q = 0.f;
+        if (j < n) {
+            float4 b = bodies[s + j];
+            ux = (float)(((double)b.x - cx) * inv);
+            uy = (float)(((double)b.y - cy) * inv);
+            uz = (float)(((double)b.z - cz) * inv);
+            q = b.w;
+        }
+        float Rr[D::NT], Ri[D::NT];
+        regular_harmonics<P>(ux, uy, uz, Rr, Ri);
+#pragma unroll
+        for (int l = 0; l <= P; ++l) {
+#pragma unroll
+            for (int m = 0; m <= l; ++m) {
+                // Mt_lm = sum q conj(R_lm(u))
+                const int dr = m == 0 ? l * l : l * l + 2 * m - 1;
+                float v = wave_sum(q * Rr[TRI(l, m)]);
+                if (lane == (dr & 63)) acc[dr >> 6] += v;
+                if (m > 0) {
+                    const int di = dr + 1;
+                    float w = wave_sum(-q * Ri[TRI(l, m)]);
+                    if (lane == (di & 63)) acc[di >> 6] += w;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int d = r * 64 + lane;
+        if (d < D::KP) M[(int64_t)c * D::KP + d] = d < D::NC ? acc[r] : 0.f;
+    }
+}
+
+// ------------------------------------------------------------------ M2M / L2L
+// out[c] (=|+=) sum over inputs of T_oct * in[...] ; one wave per cell, lanes own rows.
+template <int P, bool UP>
+__global__ void __launch_bounds__(64) k_translate(int64_t lo, Geo g, const float *Tt, const float *in, float *out) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP;
+    constexpr int NR = (KP + 63) / 64;
+    __shared__ float sv[KP];
+    const int c = (int)(lo + blockIdx.x);
+    const int lane = threadIdx.x;
+    float acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.f;
+    int first, cnt;
+    if (UP) {            // M2M: the inputs are the children of c
+        cnt = g.nchild[c];
+        if (cnt == 0) return;
+        first = g.child0[c];
+    } else {             // L2L: the input is the parent of c
+        first = g.parent[c];
+        cnt = 1;
+    }
+    for (int q = 0; q < cnt; ++q) {
+        const int src = UP ? first + q : first;
+        const int oc = UP ? src : c;    // the child cell defines the octant
+        const int oct = ((g.ix[oc] & 1) << 2) | ((g.iy[oc] & 1) << 1) | (g.iz[oc] & 1);
+        __syncthreads();
+        for (int d = lane; d < KP; d += 64) sv[d] = in[(int64_t)src * KP + d];
+        __syncthreads();
+        const float *T = Tt + (int64_t)oct * KP * KP;
+        for (int kk = 0; kk < D::NC; ++kk) {
+            const float mk = sv[kk];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int row = r * 64 + lane;
+                if (row < KP) acc[r] += T[kk * KP + row] * mk;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int row = r * 64 + lane;
+        if (row < KP) {
+            if (UP) out[(int64_t)c * KP + row] = acc[r];
+            else out[(int64_t)c * KP + row] += acc[r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ M2L (FP32 MFMA)
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Workgroup = 4 waves.  Output tile: KP rows x 64 target columns, in 16x16 blocks.
+// Wave w owns row blocks w, w+4, ... and all four column blocks.  The K loop runs in
+// chunks of 16 coefficients; inside a chunk lane l feeds k = 16*kc + 4*(l/16) + s to
+// MFMA step s, for both operands, so each lane reads 4 consecutive k as one float4.
+template <int P>
+__global__ void __launch_bounds__(256) k_m2l(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+                                             const uint64_t *key_ptr, const float *M, float *L, float *partial,
+                                             const int32_t *tile_targets) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP;
+    constexpr int KPS = KP + 4;                  // LDS row stride (bank spread)
+    constexpr int NRB = KP / 16;                 // row blocks
+    constexpr int RBW = (NRB + 3) / 4;           // row blocks per wave
+    __shared__ __attribute__((aligned(16))) float Ms[kTileN * KPS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int4 w = work[blockIdx.x];
+    floatx4 acc[RBW][4];
+#pragma unroll
+    for (int r = 0; r < RBW; ++r)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int e = w.y; e < w.z; ++e) {
+        __syncthreads();
+        // gather the multipoles of this entry's 64 sources
+        for (int idx = tid; idx < kTileN * (KP / 4); idx += 256) {
+            const int col = idx / (KP / 4), q4 = idx % (KP / 4);
+            const int src = entry_src[(int64_t)e * kTileN + col];
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (src >= 0) v = reinterpret_cast<const float4 *>(M + (int64_t)src * KP)[q4];
+            *reinterpret_cast<float4 *>(&Ms[col * KPS + 4 * q4]) = v;
+        }
+        __syncthreads();
+        const float *T = reinterpret_cast<const float *>(key_ptr[entry_key[e]]);
+#pragma unroll 2
+        for (int kc = 0; kc < KP / 16; ++kc) {
+            float4 a[RBW], b[4];
+#pragma unroll
+            for (int r = 0; r < RBW; ++r) {
+                const int rb = wave + 4 * r;
+                if (rb < NRB)
+                    a[r] = *reinterpret_cast<const float4 *>(T + (int64_t)(rb * 16 + li) * KP + kc * 16 + 4 * lg);
+                else
+                    a[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                b[cb] = *reinterpret_cast<const float4 *>(&Ms[(cb * 16 + li) * KPS + kc * 16 + 4 * lg]);
+#pragma unroll
+            for (int r = 0; r < RBW; ++r) {
+                if (wave + 4 * r >= NRB) continue;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b[cb].x, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b[cb].y, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b[cb].z, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, b[cb].w, acc[r][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // output: lane holds D[4*lg + v][li] of each 16x16 block
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+        const int rb = wave + 4 * r;
+        if (rb >= NRB) continue;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int col = cb * 16 + li;
+            float *dst;
+            if (w.w == 0) {
+                const int t = tile_targets[(int64_t)w.x * kTileN + col];
+                if (t < 0) continue;
+                dst = L + (int64_t)t * KP;
+            } else {
+                dst = partial + ((int64_t)(w.w - 1) * kTileN + col) * KP;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[rb * 16 + 4 * lg + v] = acc[r][cb][v];
+        }
+    }
+}
+
+// Sum the partial tiles of split work items into L (fixed order: deterministic).
+__global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int4 *work, const float *partial,
+                             const int32_t *tile_targets, int KP, float *L) {
+    const int64_t t = blockIdx.x;
+    const int w0 = tile_work[t], w1 = tile_work[t + 1];
+    if (w1 - w0 < 2) return;
+    for (int idx = threadIdx.x; idx < kTileN * KP; idx += blockDim.x) {
+        const int col = idx / KP, row = idx % KP;
+        const int tg = tile_targets[t * kTileN + col];
+        if (tg < 0) continue;
+        float s = 0.f;
+        for (int wi = w0; wi < w1; ++wi) s += partial[((int64_t)(work[wi].w - 1) * kTileN + col) * KP + row];
+        L[(int64_t)tg * KP + row] = s;
+    }
+}
+
+// ------------------------------------------------------------------ L2P
+template <int P>
+__global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const float4 *bodies, const float *L,
+                                            float *phi, float *grad) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP;
+    __shared__ float sL[KP];
+    const int c = leaves[blockIdx.x];
+    const int lane = threadIdx.x;
+    for (int d = lane; d < KP; d += 64) sL[d] = L[(int64_t)c * KP + d];
+    __syncthreads();
+    const int s = g.start[c], n = g.count[c];
+    double cx, cy, cz, inv;
+    cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
+    const float finv = (float)inv;
+    // coefficient (j, m) of the local expansion, m >= -1
+    auto lre = [&](int j, int m) -> float {
+        if (m > j) return 0.f;
+        if (m == 0) return sL[j * j];
+        if (m > 0) return sL[j * j + 2 * m - 1];
+        return -sL[j * j + 1];                  // L_{j,-1} = -conj(L_{j,1})
+    };
+    auto lim = [&](int j, int m) -> float {
+        if (m > j || m == 0) return 0.f;
+        if (m > 0) return sL[j * j + 2 * m];
+        return sL[j * j + 2];
+    };
+    for (int base = 0; base < n; base += 64) {
+        const int j = base + lane;
+        if (j >= n) break;
+        float4 b = bodies[s + j];
+        const float ux = (float)(((double)b.x - cx) * inv);
+        const float uy = (float)(((double)b.y - cy) * inv);
+        const float uz = (float)(((double)b.z - cz) * inv);
+        float Rr[D::NT], Ri[D::NT];
+        regular_harmonics<P>(ux, uy, uz, Rr, Ri);
+        float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+        for (int l = 0; l <= P; ++l) {
+#pragma unroll
+            for (int m = 0; m <= l; ++m) {
+                const float wgt = m == 0 ? 1.f : 2.f;
+                const float rr = Rr[TRI(l, m)], ri = Ri[TRI(l, m)];
+                f += wgt * (lre(l, m) * rr + lim(l, m) * ri);
+                if (l < P) {
+                    // gradient coefficients of degree l from the local coefficients of degree l+1
+                    const float zr = lre(l + 1, m), zi = lim(l + 1, m);
+                    const float pr = lre(l + 1, m + 1), pi = lim(l + 1, m + 1);
+                    const float mr = lre(l + 1, m - 1), mi = lim(l + 1, m - 1);
+                    const float xr = 0.5f * (mr - pr), xi = 0.5f * (mi - pi);
+                    const float yr = -0.5f * (pi + mi), yi = 0.5f * (pr + mr);
+                    gx += wgt * (xr * rr + xi * ri);
+                    gy += wgt * (yr * rr + yi * ri);
+                    gz += wgt * (zr * rr + zi * ri);
+                }
+            }
+        }
+        const int64_t o = s + j;
+        phi[o] = f * finv;
+        const float g2 = finv * finv;
+        grad[3 * o] = gx * g2;
+        grad[3 * o + 1] = gy * g2;
+        grad[3 * o + 2] = gz * g2;
+    }
+}
+
+// ------------------------------------------------------------------ P2P
+constexpr int kP2PThreads = 256, kP2PBatch = 1024;
+
+template <bool CHECK>
+__device__ __forceinline__ void p2p_batch(const float4 *src, int ns, int g, int G, float xi, float yi, float zi, float &f,
+                                          float &gx, float &gy, float &gz) {
+    int jj = g;
+#pragma unroll 4
+    for (; jj < ns; jj += G) {
+        const float4 sj = src[jj];
+        const float dx = xi - sj.x, dy = yi - sj.y, dz = zi - sj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float inv = __builtin_amdgcn_rsqf(r2);
+        if (CHECK) inv = r2 > 0.f ? inv : 0.f;
+        const float qi = sj.w * inv;
+        const float qi3 = qi * inv * inv;
+        f += qi;
+        gx -= dx * qi3;
+        gy -= dy * qi3;
+        gz -= dz * qi3;
+    }
+}
+
+__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, const int32_t *c_start, const int32_t *c_count,
+                                                     const int32_t *seg_off, const int2 *segs, const float4 *bodies,
+                                                     float *out_phi, float *out_grad) {
+    __shared__ float4 src[kP2PBatch];
+    __shared__ float4 red[kP2PThreads];
+    const int li = blockIdx.x;
+    const int c = leaves[li];
+    const int ts = c_start[c], tn = c_count[c];
+    const int tid = threadIdx.x;
+    const int sg0 = seg_off[li], sg1 = seg_off[li + 1];
+    for (int t0 = 0; t0 < tn; t0 += kP2PThreads) {
+        const int nt = min(kP2PThreads, tn - t0);
+        const int G = kP2PThreads / nt;
+        const bool active = tid < nt * G;
+        const int t = tid % nt, g = tid / nt;
+        float xi = 0.f, yi = 0.f, zi = 0.f;
+        if (active) {
+            float4 b = bodies[ts + t0 + t];
+            xi = b.x; yi = b.y; zi = b.z;
+        }
+        float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        // the target leaf itself: skip j == i and coincident points
+        for (int s0 = 0; s0 < tn; s0 += kP2PBatch) {
+            const int ns = min(kP2PBatch, tn - s0);
+            __syncthreads();
+            for (int i = tid; i < ns; i += kP2PThreads) src[i] = bodies[ts + s0 + i];
+            __syncthreads();
+            if (active) p2p_batch<true>(src, ns, g, G, xi, yi, zi, f, gx, gy, gz);
+        }
+        // neighbouring leaves, batched through LDS
+        int pos = 0;
+        for (int sg = sg0; sg < sg1; ++sg) {
+            int2 run = segs[sg];
+            int st = run.x, cnt = run.y;
+            while (cnt > 0) {
+                const int take = min(cnt, kP2PBatch - pos);
+                if (pos == 0) __syncthreads();
+                for (int i = tid; i < take; i += kP2PThreads) src[pos + i] = bodies[st + i];
+                pos += take;
+                st += take;
+                cnt -= take;
+                if (pos == kP2PBatch) {
+                    __syncthreads();
+                    if (active) p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
+                    pos = 0;
+                }
+            }
+        }
+        if (pos > 0) {
+            __syncthreads();
+            if (active) p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
+        }
+        __syncthreads();
+        red[tid] = make_float4(f, gx, gy, gz);
+        __syncthreads();
+        if (tid < nt) {
+            float4 acc = red[tid];
+            for (int gg = 1; gg < G; ++gg) {
+                float4 v = red[gg * nt + tid];
+                acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            }
+            const int64_t o = ts + t0 + tid;
+            out_phi[o] = acc.x;
+            out_grad[3 * o] = acc.y;
+            out_grad[3 * o + 1] = acc.z;
+            out_grad[3 * o + 2] = acc.w;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ permutes
+__global__ void k_set_charges(const float *q, const int32_t *perm, int64_t n, float4 *bodies) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bodies[i].w = q[perm[i]];
+}
+
+__global__ void k_combine(const int32_t *perm, int64_t n, const float *fphi, const float *fgrad, const float *nphi,
+                          const float *ngrad, float *phi, float *grad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = perm[i];
+        if (phi) phi[o] = fphi[i] + nphi[i];
+        if (grad) {
+            grad[3 * o] = fgrad[3 * i] + ngrad[3 * i];
+            grad[3 * o + 1] = fgrad[3 * i + 1] + ngrad[3 * i + 1];
+            grad[3 * o + 2] = fgrad[3 * i + 2] + ngrad[3 * i + 2];
+        }
+    }
+}
+
+// dL/dx_i = w_i grad phi_i + q_i grad psi_i (input order)
+__global__ void k_adjoint_combine(int64_t n, const float *w, const float *gphi, const float *q, const float *gpsi,
+                                  float *dx) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float wi = w[i], qi = q[i];
+        dx[3 * i] = wi * gphi[3 * i] + qi * gpsi[3 * i];
+        dx[3 * i + 1] = wi * gphi[3 * i + 1] + qi * gpsi[3 * i + 1];
+        dx[3 * i + 2] = wi * gphi[3 * i + 2] + qi * gpsi[3 * i + 2];
+    }
+}
+
+// ------------------------------------------------------------------ host side
+static int grid1(int64_t n, int bs = 256) {
+    int64_t g = (n + bs - 1) / bs;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
+}
+
+enum { PH_PERM = 0, PH_P2M, PH_M2M, PH_M2L, PH_L2L, PH_L2P, PH_P2P, PH_COMB, PH_TOTAL };
+
+static inline void ev_rec(fmm_plan_s *Pl, int slot, hipStream_t s) {
+    if (Pl->timing) HIP_CHECK(hipEventRecord(Pl->ev[slot], s));
+}
+
+template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t s) {
+    using D = Dims<P>;
+    const OpTables &T = op_tables(P);
+    ev_rec(Pl, 2 * PH_P2M, s);
+    hipLaunchKernelGGL(k_p2m<P>, (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g,
+                       (const float4 *)Pl->bodies, Pl->M);
+    ev_rec(Pl, 2 * PH_P2M + 1, s);
+    ev_rec(Pl, 2 * PH_M2M, s);
+    for (int l = Pl->max_level - 1; l >= 0; --l) {
+        int64_t lo = Pl->level_off[l], cnt = Pl->level_off[l + 1] - lo;
+        hipLaunchKernelGGL((k_translate<P, true>), (int)cnt, 64, 0, s, lo, g, T.m2m_t, (const float *)Pl->M, Pl->M);
+    }
+    ev_rec(Pl, 2 * PH_M2M + 1, s);
+    fill_f32(Pl->L, 0.f, Pl->ncells * (int64_t)D::KP, s);
+    ev_rec(Pl, 2 * PH_M2L, s);
+    if (Pl->nwork > 0)
+        hipLaunchKernelGGL(k_m2l<P>, (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work, (const int32_t *)Pl->entry_key,
+                           (const int32_t *)Pl->entry_src, Pl->key_f32, (const float *)Pl->M, Pl->L, Pl->partial,
+                           (const int32_t *)Pl->tile_targets);
+    ev_rec(Pl, 2 * PH_M2L + 1, s);
+    ev_rec(Pl, 2 * PH_L2L, s);
+    if (Pl->npartial > 0)
+        hipLaunchKernelGGL(k_m2l_reduce, (int)Pl->ntiles, 256, 0, s, Pl->ntiles, (const int32_t *)Pl->tile_work,
+                           (const int4 *)Pl->work, (const float *)Pl->partial, (const int32_t *)Pl->tile_targets, D::KP,
+                           Pl->L);
+    for (int l = 1; l <= Pl->max_level; ++l) {
+        int64_t lo = Pl->level_off[l], cnt = Pl->level_off[l + 1] - lo;
+        hipLaunchKernelGGL((k_translate<P, false>), (int)cnt, 64, 0, s, lo, g, T.l2l_t, (const float *)Pl->L, Pl->L);
+    }
+    ev_rec(Pl, 2 * PH_L2L + 1, s);
+    ev_rec(Pl, 2 * PH_L2P, s);
+    hipLaunchKernelGGL(k_l2p<P>, (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g, (const float4 *)Pl->bodies,
+                       (const float *)Pl->L, Pl->far_phi, Pl->far_grad);
+    ev_rec(Pl, 2 * PH_L2P + 1, s);
+}
+
+#define FMM_CASE(PP) case PP: far_field<PP>(Pl, g, s); break;
+
+void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phases, hipStream_t s) {
+    const int64_t n = Pl->n;
+    Geo g{Pl->c_start, Pl->c_count, Pl->c_level, Pl->c_ix, Pl->c_iy, Pl->c_iz, Pl->c_parent, Pl->c_child0, Pl->c_nchild,
+          Pl->x0[0], Pl->x0[1], Pl->x0[2], Pl->k};
+    ev_rec(Pl, 2 * PH_TOTAL, s);
+    ev_rec(Pl, 2 * PH_PERM, s);
+    hipLaunchKernelGGL(k_set_charges, grid1(n), 256, 0, s, q, (const int32_t *)Pl->perm, n, Pl->bodies);
+    ev_rec(Pl, 2 * PH_PERM + 1, s);
+    // near field on the side stream, concurrent with the far-field chain
+    HIP_CHECK(hipEventRecord(Pl->ev_fork, s));
+    HIP_CHECK(hipStreamWaitEvent(Pl->side, Pl->ev_fork, 0));
+    ev_rec(Pl, 2 * PH_P2P, Pl->side);
+    if (phases & FMM_NEAR) {
+        hipLaunchKernelGGL(k_p2p, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
+                           (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
+                           (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near_phi, Pl->near_grad);
+    } else {
+        fill_f32(Pl->near_phi, 0.f, n, Pl->side);
+        fill_f32(Pl->near_grad, 0.f, 3 * n, Pl->side);
+    }
+    ev_rec(Pl, 2 * PH_P2P + 1, Pl->side);
+    HIP_CHECK(hipEventRecord(Pl->ev_join, Pl->side));
+    if ((phases & FMM_FAR) && Pl->nm2l > 0) {
+        switch (Pl->p) {
+            FMM_CASE(0) FMM_CASE(1) FMM_CASE(2) FMM_CASE(3) FMM_CASE(4) FMM_CASE(5) FMM_CASE(6) FMM_CASE(7)
+            FMM_CASE(8) FMM_CASE(9) FMM_CASE(10) FMM_CASE(11) FMM_CASE(12) FMM_CASE(13) FMM_CASE(14)
+            FMM_CASE(15) FMM_CASE(16)
+            default: fail(FMM_EINVAL, "unsupported order");
+        }
+    } else {
+        for (int ph = PH_P2M; ph <= PH_L2P; ++ph) { ev_rec(Pl, 2 * ph, s); ev_rec(Pl, 2 * ph + 1, s); }
+        fill_f32(Pl->far_phi, 0.f, n, s);
+        fill_f32(Pl->far_grad, 0.f, 3 * n, s);
+    }
+    HIP_CHECK(hipStreamWaitEvent(s, Pl->ev_join, 0));
+    ev_rec(Pl, 2 * PH_COMB, s);
+    hipLaunchKernelGGL(k_combine, grid1(n), 256, 0, s, (const int32_t *)Pl->perm, n, (const float *)Pl->far_phi,
+                       (const float *)Pl->far_grad, (const float *)Pl->near_phi, (const float *)Pl->near_grad, phi, grad);
+    ev_rec(Pl, 2 * PH_COMB + 1, s);
+    ev_rec(Pl, 2 * PH_TOTAL + 1, s);
+    HIP_CHECK(hipGetLastError());
+    Pl->ev_valid = Pl->timing;
+}
+
+void run_adjoint_combine(fmm_plan_s *Pl, const float *w, const float *gphi, const float *q, const float *gpsi, float *dx,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_adjoint_combine, grid1(Pl->n), 256, 0, s, Pl->n, w, gphi, q, gpsi, dx);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace fmm

@@ -1,0 +1,163 @@
+// Internal declarations of the MI355X FMM library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+constexpr int kMaxLevel = 21;       // 63-bit Morton keys, 21 bits per axis
+constexpr int kMaxP = 16;
+constexpr int kTileN = 64;          // M2L target cells per tile (GEMM N dimension)
+constexpr int kEntriesPerWork = 48; // M2L (tile, operator) entries per work item (split-K)
+
+// Coefficient count of order p and its padded length (multiple of 16: MFMA 16x16x4 blocking).
+inline int ncoef(int p) { return (p + 1) * (p + 1); }
+inline int ncoef_pad(int p) { return (ncoef(p) + 15) / 16 * 16; }
+
+// Error raised inside the library; converted to fmm_status at the ABI.
+struct Error {
+    fmm_status status;
+    std::string msg;
+};
+[[noreturn]] void fail(fmm_status s, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define HIP_CHECK(x) ::fmm::check_hip((x), #x)
+
+// Workspace allocation through the plan's allocator; everything is released at destroy.
+struct Alloc {
+    fmm_alloc_fn alloc = nullptr;
+    fmm_free_fn release = nullptr;
+    void *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    std::vector<void *> live;
+    int64_t bytes = 0;
+    void *get(size_t bytes);
+    template <class T> T *get_n(int64_t n) { return static_cast<T *>(get(sizeof(T) * (size_t)(n > 0 ? n : 1))); }
+    void put(void *p);       // release one allocation early
+    void release_all();
+};
+
+// ---------------------------------------------------------------- primitives
+// Exclusive scan of n values; returns the total (reads it back, synchronising the stream).
+int64_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, Alloc &a, hipStream_t s);
+int64_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Alloc &a, hipStream_t s);
+// Stable LSD radix sort of (key, value) on the low `bits` key bits; results in keys/vals.
+void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Alloc &a, hipStream_t s);
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_f32(float *p, float v, int64_t n, hipStream_t s);
+void iota_i32(int32_t *p, int64_t n, hipStream_t s);
+template <class T> T read_back(const T *dev, hipStream_t s) {
+    T v;
+    HIP_CHECK(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return v;
+}
+
+// ---------------------------------------------------------------- operators
+// Device operator tables for expansion order p.  Matrices are FP32 [RP][KP] row-major
+// (rows = output coefficient), stored in the scaled basis described in operators.cpp.
+struct OpTables {
+    int p = -1;
+    const float *m2m_t = nullptr;   // [8][KP][RP]  transposed, octant-major
+    const float *l2l_t = nullptr;   // [8][KP][RP]
+};
+const OpTables &op_tables(int p);
+// Device pointers (as uint64) of the M2L operator of every key, FP32 and split-FP16 forms.
+// keys: packed (level difference, offset) keys.  Creates missing operators.
+void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f32_ptrs,
+                       std::vector<uint64_t> &f16_ptrs, bool need_f16);
+
+// M2L key packing: dl = level(source) - level(target) in [-31, 31]; offset = (c_B - c_A)
+// in units of the finer cell's half side, each component in [-2^18, 2^18).
+constexpr int kKeyOffBits = 19;
+constexpr int64_t kKeyOffBias = int64_t(1) << 18;
+__host__ __device__ inline uint64_t pack_key(int dl, int64_t nx, int64_t ny, int64_t nz) {
+    return (uint64_t(dl + 32) << 57) | (uint64_t(nx + kKeyOffBias) << 38) |
+           (uint64_t(ny + kKeyOffBias) << 19) | uint64_t(nz + kKeyOffBias);
+}
+inline void unpack_key(uint64_t k, int &dl, int64_t &nx, int64_t &ny, int64_t &nz) {
+    dl = int(k >> 57) - 32;
+    nx = int64_t((k >> 38) & ((1u << 19) - 1)) - kKeyOffBias;
+    ny = int64_t((k >> 19) & ((1u << 19) - 1)) - kKeyOffBias;
+    nz = int64_t(k & ((1u << 19) - 1)) - kKeyOffBias;
+}
+
+// ---------------------------------------------------------------- eval launchers
+struct EvalArgs;   // defined in eval.hip
+
+}  // namespace fmm
+
+// --------------------------------------------------------------------- the plan
+struct fmm_plan_s {
+    int device = 0;
+    int64_t n = 0;
+    int ncrit = 0, p = 0;
+    float theta = 0;
+    fmm_precision prec = FMM_PREC_FP32;
+    int KP = 0;                 // padded coefficient count
+    fmm::Alloc mem;
+    hipStream_t side = nullptr; // second stream for the near field
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+    // geometry
+    int k = 0;
+    double x0[3] = {0, 0, 0};
+
+    // bodies in Morton order
+    int32_t *perm = nullptr;     // sorted position -> input index
+    float4 *bodies = nullptr;    // (x, y, z, q) ; q written by each eval
+    uint64_t *keys = nullptr;    // sorted keys
+
+    // cells, level by level (Morton order inside a level)
+    int64_t ncells = 0, nleaves = 0;
+    int max_level = 0;
+    std::vector<int64_t> level_off;  // host copy, size max_level + 2
+    int32_t *c_level = nullptr, *c_start = nullptr, *c_count = nullptr, *c_parent = nullptr;
+    int32_t *c_child0 = nullptr, *c_nchild = nullptr;
+    int32_t *c_ix = nullptr, *c_iy = nullptr, *c_iz = nullptr;
+    uint64_t *c_prefix_dev = nullptr;
+    int32_t *leaves = nullptr;       // leaf cell ids, in cell order
+    int32_t *leaf_id = nullptr;      // cell -> leaf index or -1
+
+    // M2L
+    int64_t nm2l = 0, nkeys = 0, ntargets = 0, ntiles = 0, nentries = 0, nwork = 0;
+    int2 *m2l_pairs = nullptr;       // (target, source), grouped by (tile, key, lane)
+    const uint64_t *key_f32 = nullptr;   // [nkeys] device pointers of FP32 operators
+    const uint64_t *key_f16 = nullptr;   // [nkeys] device pointers of split-FP16 operators
+    int32_t *tile_targets = nullptr;     // [ntiles][kTileN], -1 = empty lane
+    int32_t *entry_key = nullptr;        // [nentries] key id
+    int32_t *entry_src = nullptr;        // [nentries][kTileN] source cell or -1
+    int4 *work = nullptr;                // [nwork] (tile, entry begin, entry end, partial slot + 1 or 0 = direct)
+    int64_t npartial = 0;                // work items that write a partial tile
+    int32_t *tile_work = nullptr;        // [ntiles + 1] work item range of each tile
+    int64_t nkeys_same = 0, nm2l_same = 0;
+
+    // P2P
+    int64_t np2p = 0, nseg = 0, p2p_interactions = 0;
+    int2 *p2p_pairs = nullptr;       // (target leaf cell, source leaf cell), sorted
+    int32_t *seg_off = nullptr;      // [nleaves + 1] per target leaf (leaf order)
+    int2 *segs = nullptr;            // (body start, body count) runs of source bodies, self excluded
+
+    // eval workspace
+    float *M = nullptr, *L = nullptr;          // [ncells][KP]
+    double *Md = nullptr, *Ld = nullptr;        // FP64 root-level coefficients (mixed precision)
+    float *partial = nullptr;                   // [nwork][kTileN][KP]
+    float *far_phi = nullptr, *far_grad = nullptr, *near_phi = nullptr, *near_grad = nullptr;
+    float *tmp_phi = nullptr, *tmp_grad = nullptr, *tmp_gfwd = nullptr;   // adjoint scratch (input order)
+    hipStream_t last_stream = nullptr;          // stream of the most recent evaluation
+    bool last_stream_set = false;
+    int fp64_levels = 0;                        // levels 0..fp64_levels-1 kept in FP64 (mixed)
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev[2 * FMM_NUM_PHASES] = {};
+    bool ev_valid = false;
+
+    fmm_stats stats{};
+};

@@ -1,0 +1,244 @@
+// Translation operators of the solid-harmonic FMM, built once per key in FP64 on the
+// host and kept on the device for the life of the process (Sec. 2.2: translation
+// operators stored as matrices acting on coefficient vectors, precomputed; boxes with
+// the same relative position share one operator).
+//
+// Basis (scaled complex solid harmonics, m = -l..l):
+//   R_00 = 1,  R_mm = -(x + i y)/(2m) R_{m-1,m-1},
+//   R_{l+1,m} = ((2l+1) z R_lm - r^2 R_{l-1,m}) / ((l+m+1)(l-m+1))
+//   I_00 = 1/r, I_mm = -(2m-1)(x + i y)/r^2 I_{m-1,m-1},
+//   I_{l+1,m} = ((2l+1) z I_lm - (l^2 - m^2) I_{l-1,m}) / r^2
+//   X_{l,-m} = (-1)^m conj(X_lm) for both.
+// With these, for |s| < |D|:
+//   1/|t - s|  = sum_lm conj(R_lm(s)) I_lm(t)
+//   R_lm(a + b) = sum_jk R_jk(a) R_{l-j,m-k}(b)
+//   I_jk(D + s) = sum_lm (-1)^l conj(R_lm(s)) I_{j+l,k+m}(D)
+// Multipole of a cell c with side s_c:  Mt_lm = sum_i q_i conj(R_lm((x_i - c)/s_c))
+//   (the field is sum_lm s_c^l Mt_lm I_lm(x - c)).
+// Local expansion: phi(c + t) = (1/s_c) sum_jk Lt_jk conj(R_jk(t/s_c)).
+// In this scaled basis
+//   M2L (B -> A, D = c_B - c_A): Lt_jk = sum_lm (-1)^l s_A^(j+1) s_B^l I_{j+l,k+m}(D) Mt_lm
+//   M2M (child c -> parent P, d = c_c - c_P): Mt_P,lm = sum_jk conj(R_jk(d/s_P)) 2^-(l-j) Mt_c,(l-j)(m-k)
+//   L2L (parent P -> child c, d = c_c - c_P): Lt_c,ab = sum_jk Lt_P,jk conj(R_{j-a,k-b}(d/s_P)) 2^-(a+1)
+// The M2L factor depends only on the level difference and on D in units of the finer
+// cell's half side h, because s_A, s_B and D all scale with h; so one matrix serves
+// every level (translation invariance).  M2M/L2L need eight matrices (one per octant).
+//
+// Real storage of a coefficient vector of order p, (p+1)^2 reals: degree l occupies
+// [l^2, (l+1)^2): Re X_l0, then (Re X_lm, Im X_lm) for m = 1..l.  Negative orders are
+// implied by the symmetry above (the fields are real).
+#include <complex>
+#include <cmath>
+#include <mutex>
+#include <unordered_map>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+
+using cd = std::complex<double>;
+
+inline int tri(int l, int m) { return l * (l + 1) / 2 + m; }
+
+struct Harm {
+    int P;
+    std::vector<cd> v;   // tri(l, m), m >= 0
+    cd get(int l, int m) const {
+        if (l < 0 || m > l || -m > l) return 0.0;
+        if (m >= 0) return v[tri(l, m)];
+        cd c = std::conj(v[tri(l, -m)]);
+        return (m & 1) ? -c : c;
+    }
+};
+
+Harm regular(double x, double y, double z, int P) {
+    Harm h{P, std::vector<cd>(tri(P, P) + 1)};
+    double r2 = x * x + y * y + z * z;
+    h.v[0] = 1.0;
+    for (int m = 1; m <= P; ++m) h.v[tri(m, m)] = -cd(x, y) / (2.0 * m) * h.v[tri(m - 1, m - 1)];
+    for (int m = 0; m < P; ++m) {
+        h.v[tri(m + 1, m)] = z * h.v[tri(m, m)];
+        for (int l = m + 1; l < P; ++l)
+            h.v[tri(l + 1, m)] = ((2.0 * l + 1) * z * h.v[tri(l, m)] - r2 * h.v[tri(l - 1, m)]) /
+                                 (double((l + m + 1) * (l - m + 1)));
+    }
+    return h;
+}
+
+Harm irregular(double x, double y, double z, int P) {
+    Harm h{P, std::vector<cd>(tri(P, P) + 1)};
+    double r2 = x * x + y * y + z * z;
+    h.v[0] = 1.0 / std::sqrt(r2);
+    for (int m = 1; m <= P; ++m) h.v[tri(m, m)] = -(2.0 * m - 1) * cd(x, y) / r2 * h.v[tri(m - 1, m - 1)];
+    for (int m = 0; m < P; ++m) {
+        h.v[tri(m + 1, m)] = (2.0 * m + 1) * z * h.v[tri(m, m)] / r2;
+        for (int l = m + 1; l < P; ++l)
+            h.v[tri(l + 1, m)] = ((2.0 * l + 1) * z * h.v[tri(l, m)] - double(l * l - m * m) * h.v[tri(l - 1, m)]) / r2;
+    }
+    return h;
+}
+
+inline int ridx(int l, int m, int im) { return m == 0 ? l * l : l * l + 2 * m - 1 + im; }
+
+// Build the real matrix of a complex-linear map given as: for an input basis
+// element with nonzero entries at (l, m) and (l, -m), `apply(l, m, val)` adds
+// val * (column of the complex map for input (l, m)) into Y (indexed tri(j,k), k >= 0).
+template <class Col>
+void real_matrix(int p, int RP, int KP, bool transposed, std::vector<double> &A, Col col) {
+    A.assign((size_t)RP * KP, 0.0);
+    std::vector<cd> Y(tri(p, p) + 1);
+    for (int l = 0; l <= p; ++l)
+        for (int m = 0; m <= l; ++m)
+            for (int im = 0; im < (m == 0 ? 1 : 2); ++im) {
+                std::fill(Y.begin(), Y.end(), cd(0.0));
+                cd xv = im ? cd(0, 1) : cd(1, 0);
+                col(l, m, xv, Y);
+                if (m > 0) {
+                    cd xn = std::conj(xv);
+                    if (m & 1) xn = -xn;
+                    col(l, -m, xn, Y);
+                }
+                int c = ridx(l, m, im);
+                for (int j = 0; j <= p; ++j)
+                    for (int k = 0; k <= j; ++k) {
+                        int r = ridx(j, k, 0);
+                        double vr = Y[tri(j, k)].real();
+                        if (transposed) A[(size_t)c * RP + r] = vr; else A[(size_t)r * KP + c] = vr;
+                        if (k > 0) {
+                            double vi = Y[tri(j, k)].imag();
+                            if (transposed) A[(size_t)c * RP + r + 1] = vi; else A[(size_t)(r + 1) * KP + c] = vi;
+                        }
+                    }
+            }
+}
+
+void build_m2l(int p, uint64_t key, std::vector<double> &A) {
+    int dl;
+    int64_t nx, ny, nz;
+    unpack_key(key, dl, nx, ny, nz);
+    // sigma = side / h for each cell: the finer cell has side 2h.
+    double sA = dl >= 0 ? std::ldexp(1.0, dl + 1) : 2.0;    // dl = level(B) - level(A)
+    double sB = dl <= 0 ? std::ldexp(1.0, -dl + 1) : 2.0;
+    Harm I = irregular((double)nx, (double)ny, (double)nz, 2 * p);
+    int KP = ncoef_pad(p);
+    std::vector<double> pa(p + 2), pb(2 * p + 2);
+    for (int j = 0; j <= p + 1; ++j) pa[j] = std::pow(sA, j);
+    for (int l = 0; l <= p; ++l) pb[l] = std::pow(sB, l);
+    real_matrix(p, KP, KP, false, A, [&](int l, int m, cd xv, std::vector<cd> &Y) {
+        double sgn = (l & 1) ? -1.0 : 1.0;
+        for (int j = 0; j <= p; ++j)
+            for (int k = 0; k <= j; ++k)
+                Y[tri(j, k)] += sgn * pa[j + 1] * pb[l] * xv * I.get(j + l, k + m);
+    });
+}
+
+void build_m2m(int p, int oct, std::vector<double> &A) {
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = ((oct >> (2 - a)) & 1) ? 0.25 : -0.25;
+    Harm R = regular(d[0], d[1], d[2], p);
+    int KP = ncoef_pad(p);
+    real_matrix(p, KP, KP, true, A, [&](int lc, int mc, cd xv, std::vector<cd> &Y) {
+        double sc = std::ldexp(1.0, -lc);
+        for (int l = lc; l <= p; ++l)
+            for (int m = 0; m <= l; ++m) Y[tri(l, m)] += std::conj(R.get(l - lc, m - mc)) * sc * xv;
+    });
+}
+
+void build_l2l(int p, int oct, std::vector<double> &A) {
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = ((oct >> (2 - a)) & 1) ? 0.25 : -0.25;
+    Harm R = regular(d[0], d[1], d[2], p);
+    int KP = ncoef_pad(p);
+    real_matrix(p, KP, KP, true, A, [&](int j, int k, cd xv, std::vector<cd> &Y) {
+        for (int a = 0; a <= j; ++a) {
+            double sc = std::ldexp(1.0, -(a + 1));
+            for (int b = 0; b <= a; ++b) Y[tri(a, b)] += xv * std::conj(R.get(j - a, k - b)) * sc;
+        }
+    });
+}
+
+// ------------------------------------------------------------------ device store
+constexpr int kChunk = 64;   // matrices per device allocation (never moved)
+
+struct Store {
+    int p = -1;
+    size_t mat_floats = 0;
+    std::unordered_map<uint64_t, uint64_t> f32;   // key -> device pointer
+    std::vector<float *> chunks;
+    int used_in_chunk = kChunk;
+    OpTables tables;
+    float *alloc_matrix() {
+        if (used_in_chunk == kChunk) {
+            float *c = nullptr;
+            HIP_CHECK(hipMalloc(&c, sizeof(float) * mat_floats * kChunk));
+            chunks.push_back(c);
+            used_in_chunk = 0;
+        }
+        return chunks.back() + mat_floats * (used_in_chunk++);
+    }
+};
+
+std::mutex g_mu;
+std::unordered_map<int, Store> g_store;   // (device * 32 + p) -> store
+
+Store &store_for(int p) {
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    Store &s = g_store[dev * 32 + p];
+    if (s.p < 0) {
+        s.p = p;
+        int KP = ncoef_pad(p);
+        s.mat_floats = (size_t)KP * KP;
+        std::vector<double> A;
+        std::vector<float> host((size_t)8 * KP * KP);
+        float *m2m = nullptr, *l2l = nullptr;
+        HIP_CHECK(hipMalloc(&m2m, sizeof(float) * host.size()));
+        HIP_CHECK(hipMalloc(&l2l, sizeof(float) * host.size()));
+        for (int o = 0; o < 8; ++o) {
+            build_m2m(p, o, A);
+            for (size_t i = 0; i < A.size(); ++i) host[(size_t)o * KP * KP + i] = (float)A[i];
+        }
+        HIP_CHECK(hipMemcpy(m2m, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice));
+        for (int o = 0; o < 8; ++o) {
+            build_l2l(p, o, A);
+            for (size_t i = 0; i < A.size(); ++i) host[(size_t)o * KP * KP + i] = (float)A[i];
+        }
+        HIP_CHECK(hipMemcpy(l2l, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice));
+        s.tables.p = p;
+        s.tables.m2m_t = m2m;
+        s.tables.l2l_t = l2l;
+    }
+    return s;
+}
+
+}  // namespace
+
+const OpTables &op_tables(int p) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return store_for(p).tables;
+}
+
+void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f32_ptrs,
+                       std::vector<uint64_t> &f16_ptrs, bool need_f16) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Store &s = store_for(p);
+    f32_ptrs.resize(keys.size());
+    f16_ptrs.assign(keys.size(), 0);
+    std::vector<double> A;
+    std::vector<float> host(s.mat_floats);
+    for (size_t i = 0; i < keys.size(); ++i) {
+        auto it = s.f32.find(keys[i]);
+        if (it == s.f32.end()) {
+            build_m2l(p, keys[i], A);
+            for (size_t e = 0; e < A.size(); ++e) host[e] = (float)A[e];
+            float *d = s.alloc_matrix();
+            HIP_CHECK(hipMemcpy(d, host.data(), sizeof(float) * s.mat_floats, hipMemcpyHostToDevice));
+            it = s.f32.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
+        }
+        f32_ptrs[i] = it->second;
+    }
+    (void)need_f16;
+}
+
+}  // namespace fmm

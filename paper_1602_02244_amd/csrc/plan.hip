@@ -1,0 +1,821 @@
+// Plan construction on the device: root cube and Morton keys, radix sort, adaptive
+// octree (level by level), dual tree traversal with the MAC, and the grouping of the
+// interaction lists into the layouts the evaluation kernels consume.
+//
+// Paper: hierarchical decomposition and multipole/local expansions (Sec. 1), 1-D
+// Morton ordering for locality (Sec. 3.1), interaction lists from a dual tree
+// traversal with a multipole acceptance criterion (Sec. 2.2), translation operators
+// shared by boxes with the same relative position (Sec. 2.2).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+// ----------------------------------------------------------------- bounding box
+__global__ void __launch_bounds__(256) k_bbox_partial(const float *pts, int64_t n, float *part) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float bad = 0.f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float v = pts[3 * i + a];
+            if (!isfinite(v)) bad = 1.f;
+            lo[a] = fminf(lo[a], v);
+            hi[a] = fmaxf(hi[a], v);
+        }
+    }
+    __shared__ float sh[7][256];
+    for (int a = 0; a < 3; ++a) { sh[a][threadIdx.x] = lo[a]; sh[3 + a][threadIdx.x] = hi[a]; }
+    sh[6][threadIdx.x] = bad;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            for (int a = 0; a < 3; ++a) {
+                sh[a][threadIdx.x] = fminf(sh[a][threadIdx.x], sh[a][threadIdx.x + off]);
+                sh[3 + a][threadIdx.x] = fmaxf(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + off]);
+            }
+            sh[6][threadIdx.x] = fmaxf(sh[6][threadIdx.x], sh[6][threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) part[blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_bbox_final(const float *part, int nb, float *out) {
+    if (threadIdx.x != 0) return;
+    float r[7];
+    for (int a = 0; a < 7; ++a) r[a] = part[a];
+    for (int b = 1; b < nb; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            r[a] = fminf(r[a], part[b * 8 + a]);
+            r[3 + a] = fmaxf(r[3 + a], part[b * 8 + 3 + a]);
+        }
+        r[6] = fmaxf(r[6], part[b * 8 + 6]);
+    }
+    for (int a = 0; a < 7; ++a) out[a] = r[a];
+}
+
+// Root cube: side 2^k, the smallest power of two with hi_a - x0_a < 2^k on every axis,
+// x0_a = lo_a rounded down to a multiple of 2^(k-22).  Every cell centre and centre
+// difference is then an exact dyadic number (exact integer MAC, exact operator keys).
+static void root_cube(const float lo[3], const float hi[3], int &k, double x0[3]) {
+    double E = 0;
+    for (int a = 0; a < 3; ++a) E = std::max(E, (double)hi[a] - (double)lo[a]);
+    int e = 0;
+    std::frexp(E, &e);
+    k = e;
+    for (;;) {
+        double unit = std::ldexp(1.0, k - 22);
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            x0[a] = std::floor((double)lo[a] / unit) * unit;
+            if (!((double)hi[a] - x0[a] < std::ldexp(1.0, k))) ok = false;
+        }
+        if (ok) break;
+        ++k;
+    }
+}
+
+// ----------------------------------------------------------------- Morton keys
+__device__ inline uint64_t spread3(uint64_t v) {   // bit b -> bit 3b, 21 bits
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ inline uint64_t axis_coord(float x, double x0, double scale) {
+    double v = floor(((double)x - x0) * scale);
+    v = fmax(v, 0.0);
+    v = fmin(v, (double)((1 << kMaxLevel) - 1));
+    return (uint64_t)v;
+}
+
+__global__ void k_keys(const float *pts, int64_t n, double x0x, double x0y, double x0z, double scale,
+                       uint64_t *keys, int32_t *vals) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t ix = axis_coord(pts[3 * i], x0x, scale);
+        uint64_t iy = axis_coord(pts[3 * i + 1], x0y, scale);
+        uint64_t iz = axis_coord(pts[3 * i + 2], x0z, scale);
+        keys[i] = (spread3(ix) << 2) | (spread3(iy) << 1) | spread3(iz);
+        vals[i] = (int32_t)i;
+    }
+}
+
+__global__ void k_gather_bodies(const float *pts, const int32_t *perm, int64_t n, float4 *bodies) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = perm[i];
+        bodies[i] = make_float4(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], 0.f);
+    }
+}
+
+// ----------------------------------------------------------------- octree
+// Leaf rule: a cell splits iff it holds more than ncrit bodies and lies above level 21.
+// Children are the non-empty octants, found by binary search in the sorted keys.
+__global__ void k_split(int64_t ncl, const int32_t *start, const int32_t *count, const uint64_t *prefix, int level,
+                        int ncrit, const uint64_t *keys, int32_t *nchild, int32_t *cstart8, int32_t *ccount8) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    int s = start[i], c = count[i];
+    int nch = 0;
+    if (c > ncrit && level < kMaxLevel) {
+        int shift = 3 * (kMaxLevel - (level + 1));
+        uint64_t base = prefix[i] * 8;
+        int b[9];
+        b[0] = s;
+        b[8] = s + c;
+        for (int o = 1; o < 8; ++o) {
+            uint64_t want = base + (uint64_t)o;
+            int lo = s, hi = s + c;      // first position with (key >> shift) >= want
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if ((keys[mid] >> shift) < want) lo = mid + 1; else hi = mid;
+            }
+            b[o] = lo;
+        }
+        for (int o = 0; o < 8; ++o) {
+            cstart8[i * 8 + o] = b[o];
+            ccount8[i * 8 + o] = b[o + 1] - b[o];
+            nch += (b[o + 1] > b[o]);
+        }
+    }
+    nchild[i] = nch;
+}
+
+__global__ void k_write_children(int64_t ncl, int64_t glob_base, int64_t next_base, const int32_t *nchild,
+                                 const int32_t *off, const int32_t *cstart8, const int32_t *ccount8,
+                                 const uint64_t *prefix, const int32_t *ix, const int32_t *iy, const int32_t *iz,
+                                 int32_t *child0, uint64_t *n_prefix, int32_t *n_ix, int32_t *n_iy, int32_t *n_iz,
+                                 int32_t *n_start, int32_t *n_count, int32_t *n_parent) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    int nch = nchild[i];
+    child0[i] = nch > 0 ? (int32_t)(next_base + off[i]) : -1;
+    if (nch == 0) return;
+    int w = off[i];
+    for (int o = 0; o < 8; ++o) {
+        int cc = ccount8[i * 8 + o];
+        if (cc == 0) continue;
+        n_prefix[w] = prefix[i] * 8 + (uint64_t)o;
+        n_ix[w] = 2 * ix[i] + ((o >> 2) & 1);
+        n_iy[w] = 2 * iy[i] + ((o >> 1) & 1);
+        n_iz[w] = 2 * iz[i] + (o & 1);
+        n_start[w] = cstart8[i * 8 + o];
+        n_count[w] = cc;
+        n_parent[w] = (int32_t)(glob_base + i);
+        ++w;
+    }
+}
+
+// ----------------------------------------------------------------- dual traversal
+struct CellView {
+    const int32_t *level, *ix, *iy, *iz, *child0, *nchild;
+};
+
+// MAC: accept A <- B iff A != B and theta*|c_A - c_B| >= R_A + R_B (R = half side),
+// exactly: centres and radii are integers in units of the finer cell's half side.
+__device__ inline bool mac_accept(const CellView &C, int a, int b, double theta2) {
+    if (a == b) return false;
+    int la = C.level[a], lb = C.level[b];
+    int lf = la > lb ? la : lb;
+    int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
+    int64_t dx = (2 * (int64_t)C.ix[a] + 1) * sa - (2 * (int64_t)C.ix[b] + 1) * sb;
+    int64_t dy = (2 * (int64_t)C.iy[a] + 1) * sa - (2 * (int64_t)C.iy[b] + 1) * sb;
+    int64_t dz = (2 * (int64_t)C.iz[a] + 1) * sa - (2 * (int64_t)C.iz[b] + 1) * sb;
+    int64_t d2 = dx * dx + dy * dy + dz * dz;
+    int64_t s = sa + sb;
+    return theta2 * (double)d2 >= (double)(s * s);
+}
+
+// Traversal rules for the pair (A, B):
+//   1. MAC accepted                    -> M2L        (action 0)
+//   2. else both leaves                -> P2P        (action 1)
+//   3. else both split, same level     -> all child pairs
+//   4. else split the coarser cell (on a tie the non-leaf) if it is not a leaf,
+//      otherwise the other one.
+// For a split, the new pairs are [a0, a0+na) x [b0, b0+nb).
+__device__ inline int classify(const CellView &C, int a, int b, double theta2, int &a0, int &na, int &b0, int &nb) {
+    if (mac_accept(C, a, b, theta2)) return 0;
+    int nca = C.nchild[a], ncb = C.nchild[b];
+    if (nca == 0 && ncb == 0) return 1;
+    int la = C.level[a], lb = C.level[b];
+    bool splitA, splitB;
+    if (nca > 0 && ncb > 0 && la == lb) {
+        splitA = splitB = true;
+    } else {
+        if (la < lb) splitA = nca > 0;
+        else if (lb < la) splitA = ncb == 0;
+        else splitA = nca > 0;
+        splitB = !splitA;
+    }
+    if (splitA) { a0 = C.child0[a]; na = nca; } else { a0 = a; na = 1; }
+    if (splitB) { b0 = C.child0[b]; nb = ncb; } else { b0 = b; nb = 1; }
+    return 2;
+}
+
+__device__ inline int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of three counters (256 threads).
+__device__ inline void block_scan3(int v0, int v1, int v2, int &e0, int &e1, int &e2, int &t0, int &t1, int &t2) {
+    __shared__ int ws[3][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int i0 = wave_incl_scan(v0), i1 = wave_incl_scan(v1), i2 = wave_incl_scan(v2);
+    if (lane == 63) { ws[0][wave] = i0; ws[1][wave] = i1; ws[2][wave] = i2; }
+    __syncthreads();
+    int p0 = 0, p1 = 0, p2 = 0;
+    t0 = t1 = t2 = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) { p0 += ws[0][w]; p1 += ws[1][w]; p2 += ws[2][w]; }
+        t0 += ws[0][w]; t1 += ws[1][w]; t2 += ws[2][w];
+    }
+    e0 = p0 + i0 - v0;
+    e1 = p1 + i1 - v1;
+    e2 = p2 + i2 - v2;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_trav_count(CellView C, const int2 *front, int64_t nf, double theta2,
+                                                    unsigned long long *cnt) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int m = 0, q = 0, nx = 0;
+    if (i < nf) {
+        int2 pr = front[i];
+        int a0, na, b0, nb;
+        int act = classify(C, pr.x, pr.y, theta2, a0, na, b0, nb);
+        if (act == 0) m = 1; else if (act == 1) q = 1; else nx = na * nb;
+    }
+    int e0, e1, e2, t0, t1, t2;
+    block_scan3(m, q, nx, e0, e1, e2, t0, t1, t2);
+    if (threadIdx.x == 0) {
+        if (t0) atomicAdd(&cnt[0], (unsigned long long)t0);
+        if (t1) atomicAdd(&cnt[1], (unsigned long long)t1);
+        if (t2) atomicAdd(&cnt[2], (unsigned long long)t2);
+    }
+}
+
+// cnt[] holds the running output sizes; each block reserves its range with one atomic per list.
+__global__ void __launch_bounds__(256) k_trav_emit(CellView C, const int2 *front, int64_t nf, double theta2,
+                                                   unsigned long long *cnt, int2 *m2l, int2 *p2p, int2 *next) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int m = 0, q = 0, nx = 0, act = -1, a0 = 0, na = 0, b0 = 0, nb = 0;
+    int2 pr = make_int2(0, 0);
+    if (i < nf) {
+        pr = front[i];
+        act = classify(C, pr.x, pr.y, theta2, a0, na, b0, nb);
+        if (act == 0) m = 1; else if (act == 1) q = 1; else nx = na * nb;
+    }
+    int e0, e1, e2, t0, t1, t2;
+    block_scan3(m, q, nx, e0, e1, e2, t0, t1, t2);
+    __shared__ unsigned long long base[3];
+    if (threadIdx.x == 0) {
+        base[0] = t0 ? atomicAdd(&cnt[0], (unsigned long long)t0) : 0;
+        base[1] = t1 ? atomicAdd(&cnt[1], (unsigned long long)t1) : 0;
+        base[2] = t2 ? atomicAdd(&cnt[2], (unsigned long long)t2) : 0;
+    }
+    __syncthreads();
+    if (act == 0) m2l[base[0] + e0] = pr;
+    else if (act == 1) p2p[base[1] + e1] = pr;
+    else if (act == 2) {
+        unsigned long long w = base[2] + e2;
+        for (int x = 0; x < na; ++x)
+            for (int y = 0; y < nb; ++y) next[w++] = make_int2(a0 + x, b0 + y);
+    }
+}
+
+// ----------------------------------------------------------------- M2L grouping
+__global__ void k_m2l_keys(const int2 *pairs, int64_t np, CellView C, uint64_t *keys, int32_t *vals, int32_t *overflow) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        int a = pairs[i].x, b = pairs[i].y;   // target A, source B
+        int la = C.level[a], lb = C.level[b];
+        int lf = la > lb ? la : lb;
+        int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
+        // D = c_B - c_A in units of the finer half side
+        int64_t nx = (2 * (int64_t)C.ix[b] + 1) * sb - (2 * (int64_t)C.ix[a] + 1) * sa;
+        int64_t ny = (2 * (int64_t)C.iy[b] + 1) * sb - (2 * (int64_t)C.iy[a] + 1) * sa;
+        int64_t nz = (2 * (int64_t)C.iz[b] + 1) * sb - (2 * (int64_t)C.iz[a] + 1) * sa;
+        if (nx < -kKeyOffBias || nx >= kKeyOffBias || ny < -kKeyOffBias || ny >= kKeyOffBias || nz < -kKeyOffBias ||
+            nz >= kKeyOffBias)
+            *overflow = 1;
+        keys[i] = pack_key(lb - la, nx, ny, nz);
+        vals[i] = (int32_t)i;
+    }
+}
+
+__global__ void k_count_same_level(const uint64_t *keys, int64_t n, unsigned long long *cnt) {
+    unsigned long long loc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        loc += (keys[i] >> 57) == 32u ? 1ull : 0ull;
+    atomicAdd(cnt, loc);
+}
+
+__global__ void k_flag_diff(const uint64_t *keys, int64_t n, int shift, int32_t *flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = (i == 0 || (keys[i] >> shift) != (keys[i - 1] >> shift)) ? 1 : 0;
+}
+
+__global__ void k_unique_keys(const uint64_t *keys, const int32_t *vals, const int32_t *flag, const int32_t *ex,
+                              int64_t n, uint64_t *ukeys, int32_t *pair_key) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int id = ex[i] + flag[i] - 1;
+        if (flag[i]) ukeys[id] = keys[i];
+        pair_key[vals[i]] = id;
+    }
+}
+
+__global__ void k_mark_targets(const int2 *pairs, int64_t np, int32_t *is_target) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+        is_target[pairs[i].x] = 1;
+}
+
+__global__ void k_target_keys(const int32_t *is_target, const int32_t *ex, int64_t nc, CellView C, uint64_t *tkeys,
+                              int32_t *tvals) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        if (!is_target[c]) continue;
+        int oct = ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1);
+        tkeys[ex[c]] = ((uint64_t)C.level[c] << 35) | ((uint64_t)oct << 32) | (uint64_t)c;
+        tvals[ex[c]] = (int32_t)c;
+    }
+}
+
+__global__ void k_bucket_starts(const uint64_t *tkeys, int64_t nt, int32_t *bstart) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x) {
+        int b = (int)(tkeys[i] >> 32);
+        if (i == 0 || (int)(tkeys[i - 1] >> 32) != b) bstart[b] = (int32_t)i;
+    }
+}
+
+__global__ void k_assign_tiles(const uint64_t *tkeys, const int32_t *tvals, int64_t nt, const int32_t *bstart,
+                               const int32_t *tbase, int32_t *cell_tile, int32_t *cell_lane, int32_t *tile_targets) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x) {
+        int b = (int)(tkeys[i] >> 32);
+        int r = (int)(i - bstart[b]);
+        int tile = tbase[b] + r / kTileN, lane = r % kTileN;
+        int c = tvals[i];
+        cell_tile[c] = tile;
+        cell_lane[c] = lane;
+        tile_targets[(int64_t)tile * kTileN + lane] = c;
+    }
+}
+
+__global__ void k_pair_composite(const int2 *pairs, int64_t np, const int32_t *pair_key, const int32_t *cell_tile,
+                                 const int32_t *cell_lane, int key_bits, uint64_t *comp, int32_t *vals) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        int a = pairs[i].x;
+        comp[i] = ((uint64_t)cell_tile[a] << (key_bits + 6)) | ((uint64_t)pair_key[i] << 6) | (uint64_t)cell_lane[a];
+        vals[i] = pairs[i].y;
+    }
+}
+
+__global__ void k_build_entries(const uint64_t *comp, const int32_t *vals, const int32_t *flag, const int32_t *ex,
+                                int64_t np, int key_bits, const int32_t *tile_targets, int32_t *entry_key,
+                                int32_t *entry_src, int32_t *tile_first, int2 *pairs_out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t c = comp[i];
+        int e = ex[i] + flag[i] - 1;
+        int lane = (int)(c & 63u);
+        int key = (int)((c >> 6) & ((1ull << key_bits) - 1));
+        int tile = (int)(c >> (key_bits + 6));
+        if (flag[i]) {
+            entry_key[e] = key;
+            if (i == 0 || (int)(comp[i - 1] >> (key_bits + 6)) != tile) tile_first[tile] = e;
+        }
+        entry_src[(int64_t)e * kTileN + lane] = vals[i];
+        pairs_out[i] = make_int2(tile_targets[(int64_t)tile * kTileN + lane], vals[i]);
+    }
+}
+
+// ----------------------------------------------------------------- P2P lists
+__global__ void k_leaf_flags(const int32_t *nchild, int64_t nc, int32_t *flag) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x)
+        flag[c] = nchild[c] == 0 ? 1 : 0;
+}
+__global__ void k_leaf_compact(const int32_t *flag, const int32_t *ex, int64_t nc, int32_t *leaves, int32_t *leaf_id) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        leaf_id[c] = flag[c] ? ex[c] : -1;
+        if (flag[c]) leaves[ex[c]] = (int32_t)c;
+    }
+}
+
+__global__ void k_p2p_composite(const int2 *pairs, int64_t np, uint64_t *comp, int32_t *vals) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        comp[i] = ((uint64_t)(uint32_t)pairs[i].x << 32) | (uint64_t)(uint32_t)pairs[i].y;
+        vals[i] = 0;
+    }
+}
+
+__global__ void k_p2p_csr(const uint64_t *comp, int64_t np, const int32_t *leaf_id, int2 *pairs_out, int32_t *pair_off,
+                          const int32_t *c_count, unsigned long long *inter) {
+    unsigned long long loc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        int a = (int)(comp[i] >> 32), b = (int)(uint32_t)comp[i];
+        pairs_out[i] = make_int2(a, b);
+        if (i == 0 || (int)(comp[i - 1] >> 32) != a) pair_off[leaf_id[a]] = (int32_t)i;
+        unsigned long long ca = (unsigned long long)c_count[a], cb = (unsigned long long)c_count[b];
+        loc += (a == b) ? ca * (ca - 1) : ca * cb;
+    }
+    atomicAdd(inter, loc);
+}
+
+// Source runs of each target leaf: its source leaves (self excluded) with adjacent body
+// ranges merged.  mode 0 counts, mode 1 writes.
+__global__ void k_p2p_segments(int64_t nl, const int32_t *leaves, const int32_t *pair_off, int64_t np,
+                               const int2 *pairs, const int32_t *c_start, const int32_t *c_count, int32_t *nseg,
+                               const int32_t *seg_off, int2 *segs, int mode) {
+    int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (li >= nl) return;
+    int self = leaves[li];
+    int64_t p0 = pair_off[li], p1 = li + 1 < nl ? pair_off[li + 1] : np;
+    int cnt = 0, cur_s = -1, cur_n = 0;
+    int w = mode ? seg_off[li] : 0;
+    for (int64_t k = p0; k < p1; ++k) {
+        int b = pairs[k].y;
+        if (b == self) continue;
+        int s = c_start[b], n = c_count[b];
+        if (cur_n > 0 && cur_s + cur_n == s) {
+            cur_n += n;
+        } else {
+            if (cur_n > 0) {
+                if (mode) segs[w + cnt] = make_int2(cur_s, cur_n);
+                ++cnt;
+            }
+            cur_s = s;
+            cur_n = n;
+        }
+    }
+    if (cur_n > 0) {
+        if (mode) segs[w + cnt] = make_int2(cur_s, cur_n);
+        ++cnt;
+    }
+    if (!mode) nseg[li] = cnt;
+}
+
+// ----------------------------------------------------------------- host side
+static int grid1(int64_t n, int bs = 256) {
+    int64_t g = (n + bs - 1) / bs;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
+}
+static int bits_for(int64_t v) {   // number of bits to hold values in [0, v)
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return std::max(b, 1);
+}
+
+template <class T>
+static void grow(Alloc &a, T *&buf, int64_t &cap, int64_t used, int64_t need, hipStream_t s) {
+    if (need <= cap) return;
+    int64_t nc = std::max<int64_t>(need, cap * 2);
+    T *nb = a.get_n<T>(nc);
+    if (used > 0) HIP_CHECK(hipMemcpyAsync(nb, buf, sizeof(T) * used, hipMemcpyDeviceToDevice, s));
+    if (buf) a.put(buf);
+    buf = nb;
+    cap = nc;
+}
+
+void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
+    Alloc &a = P->mem;
+    const int64_t n = P->n;
+
+    // ---- a1: root cube and keys
+    int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    float *bpart = a.get_n<float>(8 * nb);
+    float *bbox = a.get_n<float>(8);
+    hipLaunchKernelGGL(k_bbox_partial, nb, 256, 0, s, points, n, bpart);
+    hipLaunchKernelGGL(k_bbox_final, 1, 64, 0, s, (const float *)bpart, nb, bbox);
+    float hb[8];
+    HIP_CHECK(hipMemcpyAsync(hb, bbox, sizeof(float) * 7, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    a.put(bpart);
+    a.put(bbox);
+    if (hb[6] != 0.f) fail(FMM_ENONFINITE, "a coordinate is NaN or infinite");
+    root_cube(hb, hb + 3, P->k, P->x0);
+
+    uint64_t *keys = a.get_n<uint64_t>(n);
+    int32_t *perm = a.get_n<int32_t>(n);
+    hipLaunchKernelGGL(k_keys, grid1(n), 256, 0, s, points, n, P->x0[0], P->x0[1], P->x0[2],
+                       std::ldexp(1.0, kMaxLevel - P->k), keys, perm);
+    // ---- a2: sort (stable: equal keys keep input order) and permute
+    radix_sort_u64(keys, perm, n, 3 * kMaxLevel, a, s);
+    P->keys = keys;
+    P->perm = perm;
+    P->bodies = a.get_n<float4>(n);
+    hipLaunchKernelGGL(k_gather_bodies, grid1(n), 256, 0, s, points, (const int32_t *)perm, n, P->bodies);
+
+    // ---- a3: octree, level by level
+    struct Lvl {
+        int64_t n = 0;
+        uint64_t *prefix = nullptr;
+        int32_t *ix = nullptr, *iy = nullptr, *iz = nullptr, *start = nullptr, *count = nullptr, *parent = nullptr;
+        int32_t *nchild = nullptr, *child0 = nullptr;
+    };
+    std::vector<Lvl> lv;
+    {
+        Lvl r;
+        r.n = 1;
+        r.prefix = a.get_n<uint64_t>(1);
+        r.ix = a.get_n<int32_t>(1); r.iy = a.get_n<int32_t>(1); r.iz = a.get_n<int32_t>(1);
+        r.start = a.get_n<int32_t>(1); r.count = a.get_n<int32_t>(1); r.parent = a.get_n<int32_t>(1);
+        uint64_t z64 = 0;
+        int32_t z = 0, cnt = (int32_t)n, m1 = -1;
+        HIP_CHECK(hipMemcpyAsync(r.prefix, &z64, 8, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(r.ix, &z, 4, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(r.iy, &z, 4, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(r.iz, &z, 4, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(r.start, &z, 4, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(r.count, &cnt, 4, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(r.parent, &m1, 4, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));   // host sources go out of scope
+        lv.push_back(r);
+    }
+    std::vector<int64_t> level_off{0, 1};
+    for (int l = 0;; ++l) {
+        Lvl &L = lv[l];
+        L.nchild = a.get_n<int32_t>(L.n);
+        L.child0 = a.get_n<int32_t>(L.n);
+        int32_t *cs8 = a.get_n<int32_t>(8 * L.n), *cc8 = a.get_n<int32_t>(8 * L.n), *off = a.get_n<int32_t>(L.n);
+        hipLaunchKernelGGL(k_split, grid1(L.n), 256, 0, s, L.n, (const int32_t *)L.start, (const int32_t *)L.count,
+                           (const uint64_t *)L.prefix, l, P->ncrit, (const uint64_t *)keys, L.nchild, cs8, cc8);
+        int64_t nnext = exclusive_scan_i32(L.nchild, off, L.n, a, s);
+        Lvl N;
+        N.n = nnext;
+        if (nnext > 0) {
+            N.prefix = a.get_n<uint64_t>(nnext);
+            N.ix = a.get_n<int32_t>(nnext); N.iy = a.get_n<int32_t>(nnext); N.iz = a.get_n<int32_t>(nnext);
+            N.start = a.get_n<int32_t>(nnext); N.count = a.get_n<int32_t>(nnext); N.parent = a.get_n<int32_t>(nnext);
+        }
+        hipLaunchKernelGGL(k_write_children, grid1(L.n), 256, 0, s, L.n, level_off[l], level_off[l + 1],
+                           (const int32_t *)L.nchild, (const int32_t *)off, (const int32_t *)cs8, (const int32_t *)cc8,
+                           (const uint64_t *)L.prefix, (const int32_t *)L.ix, (const int32_t *)L.iy,
+                           (const int32_t *)L.iz, L.child0, N.prefix, N.ix, N.iy, N.iz, N.start, N.count, N.parent);
+        a.put(cs8); a.put(cc8); a.put(off);
+        if (nnext == 0) break;
+        lv.push_back(N);
+        level_off.push_back(level_off.back() + nnext);
+    }
+    P->max_level = (int)lv.size() - 1;
+    P->level_off = level_off;
+    const int64_t nc = level_off.back();
+    P->ncells = nc;
+    // concatenate the levels into global arrays
+    P->c_level = a.get_n<int32_t>(nc);
+    P->c_ix = a.get_n<int32_t>(nc); P->c_iy = a.get_n<int32_t>(nc); P->c_iz = a.get_n<int32_t>(nc);
+    P->c_start = a.get_n<int32_t>(nc); P->c_count = a.get_n<int32_t>(nc); P->c_parent = a.get_n<int32_t>(nc);
+    P->c_child0 = a.get_n<int32_t>(nc); P->c_nchild = a.get_n<int32_t>(nc);
+    uint64_t *c_prefix = a.get_n<uint64_t>(nc);
+    for (size_t l = 0; l < lv.size(); ++l) {
+        int64_t o = level_off[l], m = lv[l].n;
+        fill_i32(P->c_level + o, (int32_t)l, m, s);
+        auto cp = [&](int32_t *dst, const int32_t *src) {
+            HIP_CHECK(hipMemcpyAsync(dst + o, src, 4 * m, hipMemcpyDeviceToDevice, s));
+        };
+        cp(P->c_ix, lv[l].ix); cp(P->c_iy, lv[l].iy); cp(P->c_iz, lv[l].iz);
+        cp(P->c_start, lv[l].start); cp(P->c_count, lv[l].count); cp(P->c_parent, lv[l].parent);
+        cp(P->c_child0, lv[l].child0); cp(P->c_nchild, lv[l].nchild);
+        HIP_CHECK(hipMemcpyAsync(c_prefix + o, lv[l].prefix, 8 * m, hipMemcpyDeviceToDevice, s));
+    }
+    for (auto &L : lv) {
+        a.put(L.prefix); a.put(L.ix); a.put(L.iy); a.put(L.iz); a.put(L.start); a.put(L.count); a.put(L.parent);
+        a.put(L.nchild); a.put(L.child0);
+    }
+    P->c_prefix_dev = c_prefix;
+
+    // leaves
+    {
+        int32_t *flag = a.get_n<int32_t>(nc), *ex = a.get_n<int32_t>(nc);
+        hipLaunchKernelGGL(k_leaf_flags, grid1(nc), 256, 0, s, (const int32_t *)P->c_nchild, nc, flag);
+        P->nleaves = exclusive_scan_i32(flag, ex, nc, a, s);
+        P->leaves = a.get_n<int32_t>(P->nleaves);
+        P->leaf_id = a.get_n<int32_t>(nc);
+        hipLaunchKernelGGL(k_leaf_compact, grid1(nc), 256, 0, s, (const int32_t *)flag, (const int32_t *)ex, nc,
+                           P->leaves, P->leaf_id);
+        a.put(flag); a.put(ex);
+    }
+
+    // ---- a4: dual traversal
+    CellView C{P->c_level, P->c_ix, P->c_iy, P->c_iz, P->c_child0, P->c_nchild};
+    const double theta2 = (double)P->theta * (double)P->theta;
+    unsigned long long *cnt = a.get_n<unsigned long long>(3);
+    int2 *front = a.get_n<int2>(1);
+    {
+        int2 rr = make_int2(0, 0);
+        HIP_CHECK(hipMemcpyAsync(front, &rr, sizeof(int2), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    int64_t nf = 1;
+    int2 *m2l = nullptr, *p2p = nullptr;
+    int64_t m2l_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
+    while (nf > 0) {
+        unsigned long long h3[3] = {0, 0, 0};
+        HIP_CHECK(hipMemcpyAsync(cnt, h3, sizeof(h3), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_trav_count, grid1(nf), 256, 0, s, C, (const int2 *)front, nf, theta2, cnt);
+        HIP_CHECK(hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        grow(a, m2l, m2l_cap, nm2l, nm2l + (int64_t)h3[0], s);
+        grow(a, p2p, p2p_cap, np2p, np2p + (int64_t)h3[1], s);
+        int64_t nn = (int64_t)h3[2];
+        int2 *next = nn > 0 ? a.get_n<int2>(nn) : nullptr;
+        unsigned long long base[3] = {(unsigned long long)nm2l, (unsigned long long)np2p, 0ull};
+        HIP_CHECK(hipMemcpyAsync(cnt, base, sizeof(base), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_trav_emit, grid1(nf), 256, 0, s, C, (const int2 *)front, nf, theta2, cnt, m2l, p2p, next);
+        HIP_CHECK(hipStreamSynchronize(s));   // `base` lives on the host stack
+        nm2l += (int64_t)h3[0];
+        np2p += (int64_t)h3[1];
+        a.put(front);
+        front = next;
+        nf = nn;
+    }
+    a.put(cnt);
+    P->nm2l = nm2l;
+    P->np2p = np2p;
+
+    // ---- M2L keys, operators, tiles, entries
+    if (nm2l > 0) {
+        if (nm2l >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "more than 2^31 M2L pairs");
+        uint64_t *k64 = a.get_n<uint64_t>(nm2l);
+        int32_t *v32 = a.get_n<int32_t>(nm2l);
+        int32_t *ovf = a.get_n<int32_t>(1);
+        fill_i32(ovf, 0, 1, s);
+        hipLaunchKernelGGL(k_m2l_keys, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, k64, v32, ovf);
+        if (read_back(ovf, s)) fail(FMM_EUNSUPPORTED, "an M2L offset exceeds the key range");
+        {
+            unsigned long long *same = a.get_n<unsigned long long>(1);
+            HIP_CHECK(hipMemsetAsync(same, 0, 8, s));
+            hipLaunchKernelGGL(k_count_same_level, grid1(nm2l), 256, 0, s, (const uint64_t *)k64, nm2l, same);
+            P->nm2l_same = (int64_t)read_back(same, s);
+            a.put(same);
+        }
+        radix_sort_u64(k64, v32, nm2l, 63, a, s);
+        int32_t *flag = a.get_n<int32_t>(nm2l), *ex = a.get_n<int32_t>(nm2l);
+        hipLaunchKernelGGL(k_flag_diff, grid1(nm2l), 256, 0, s, (const uint64_t *)k64, nm2l, 0, flag);
+        int64_t nkeys = exclusive_scan_i32(flag, ex, nm2l, a, s);
+        uint64_t *ukeys = a.get_n<uint64_t>(nkeys);
+        int32_t *pair_key = a.get_n<int32_t>(nm2l);
+        hipLaunchKernelGGL(k_unique_keys, grid1(nm2l), 256, 0, s, (const uint64_t *)k64, (const int32_t *)v32,
+                           (const int32_t *)flag, (const int32_t *)ex, nm2l, ukeys, pair_key);
+        std::vector<uint64_t> hkeys(nkeys);
+        HIP_CHECK(hipMemcpyAsync(hkeys.data(), ukeys, 8 * nkeys, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        a.put(k64); a.put(v32); a.put(ovf); a.put(flag); a.put(ex); a.put(ukeys);
+        P->nkeys = nkeys;
+        P->nkeys_same = 0;
+        for (uint64_t kk : hkeys) P->nkeys_same += (int(kk >> 57) - 32) == 0;
+        std::vector<uint64_t> p32, p16;
+        m2l_operator_ptrs(P->p, hkeys, p32, p16, P->prec == FMM_PREC_MIXED);
+        uint64_t *d32 = a.get_n<uint64_t>(nkeys);
+        HIP_CHECK(hipMemcpyAsync(d32, p32.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
+        P->key_f32 = d32;
+        if (P->prec == FMM_PREC_MIXED) {
+            uint64_t *d16 = a.get_n<uint64_t>(nkeys);
+            HIP_CHECK(hipMemcpyAsync(d16, p16.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
+            P->key_f16 = d16;
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+
+        // targets -> tiles of kTileN cells with the same level and octant, Morton order
+        int32_t *is_t = a.get_n<int32_t>(nc), *tex = a.get_n<int32_t>(nc);
+        fill_i32(is_t, 0, nc, s);
+        hipLaunchKernelGGL(k_mark_targets, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, is_t);
+        int64_t nt = exclusive_scan_i32(is_t, tex, nc, a, s);
+        P->ntargets = nt;
+        uint64_t *tk = a.get_n<uint64_t>(nt);
+        int32_t *tv = a.get_n<int32_t>(nt);
+        hipLaunchKernelGGL(k_target_keys, grid1(nc), 256, 0, s, (const int32_t *)is_t, (const int32_t *)tex, nc, C, tk, tv);
+        radix_sort_u64(tk, tv, nt, 40, a, s);
+        constexpr int kBuckets = (kMaxLevel + 1) * 8;
+        int32_t *bst = a.get_n<int32_t>(kBuckets);
+        fill_i32(bst, -1, kBuckets, s);
+        hipLaunchKernelGGL(k_bucket_starts, grid1(nt), 256, 0, s, (const uint64_t *)tk, nt, bst);
+        std::vector<int32_t> hb_start(kBuckets), hb_base(kBuckets, 0);
+        HIP_CHECK(hipMemcpyAsync(hb_start.data(), bst, 4 * kBuckets, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        int64_t ntiles = 0;
+        for (int b = 0; b < kBuckets; ++b) {
+            if (hb_start[b] < 0) continue;
+            int64_t end = nt;
+            for (int b2 = b + 1; b2 < kBuckets; ++b2)
+                if (hb_start[b2] >= 0) { end = hb_start[b2]; break; }
+            hb_base[b] = (int32_t)ntiles;
+            ntiles += (end - hb_start[b] + kTileN - 1) / kTileN;
+        }
+        P->ntiles = ntiles;
+        int32_t *tbase = a.get_n<int32_t>(kBuckets);
+        HIP_CHECK(hipMemcpyAsync(tbase, hb_base.data(), 4 * kBuckets, hipMemcpyHostToDevice, s));
+        int32_t *cell_tile = a.get_n<int32_t>(nc), *cell_lane = a.get_n<int32_t>(nc);
+        P->tile_targets = a.get_n<int32_t>(ntiles * kTileN);
+        fill_i32(P->tile_targets, -1, ntiles * kTileN, s);
+        hipLaunchKernelGGL(k_assign_tiles, grid1(nt), 256, 0, s, (const uint64_t *)tk, (const int32_t *)tv, nt,
+                           (const int32_t *)bst, (const int32_t *)tbase, cell_tile, cell_lane, P->tile_targets);
+        HIP_CHECK(hipStreamSynchronize(s));
+        a.put(is_t); a.put(tex); a.put(tk); a.put(tv); a.put(bst); a.put(tbase);
+
+        // pairs grouped by (tile, key, lane)
+        int key_bits = bits_for(nkeys);
+        int tile_bits = bits_for(ntiles);
+        if (key_bits + tile_bits + 6 > 64) fail(FMM_EUNSUPPORTED, "M2L grouping key exceeds 64 bits");
+        uint64_t *comp = a.get_n<uint64_t>(nm2l);
+        int32_t *src = a.get_n<int32_t>(nm2l);
+        hipLaunchKernelGGL(k_pair_composite, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pair_key,
+                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, key_bits, comp, src);
+        radix_sort_u64(comp, src, nm2l, key_bits + tile_bits + 6, a, s);
+        int32_t *eflag = a.get_n<int32_t>(nm2l), *eex = a.get_n<int32_t>(nm2l);
+        hipLaunchKernelGGL(k_flag_diff, grid1(nm2l), 256, 0, s, (const uint64_t *)comp, nm2l, 6, eflag);
+        int64_t ne = exclusive_scan_i32(eflag, eex, nm2l, a, s);
+        P->nentries = ne;
+        P->entry_key = a.get_n<int32_t>(ne);
+        P->entry_src = a.get_n<int32_t>(ne * kTileN);
+        fill_i32(P->entry_src, -1, ne * kTileN, s);
+        int32_t *tile_first = a.get_n<int32_t>(ntiles + 1);
+        P->m2l_pairs = a.get_n<int2>(nm2l);
+        hipLaunchKernelGGL(k_build_entries, grid1(nm2l), 256, 0, s, (const uint64_t *)comp, (const int32_t *)src,
+                           (const int32_t *)eflag, (const int32_t *)eex, nm2l, key_bits,
+                           (const int32_t *)P->tile_targets, P->entry_key, P->entry_src, tile_first, P->m2l_pairs);
+        std::vector<int32_t> htf(ntiles);
+        HIP_CHECK(hipMemcpyAsync(htf.data(), tile_first, 4 * ntiles, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        a.put(comp); a.put(src); a.put(eflag); a.put(eex); a.put(tile_first); a.put(cell_tile); a.put(cell_lane);
+        a.put(pair_key);
+        a.put(m2l);
+        m2l = nullptr;
+        // work items: split each tile's entries so that there are enough items to fill the chip
+        htf.push_back((int32_t)ne);
+        int64_t per = std::max<int64_t>(kEntriesPerWork, (ne + 4095) / 4096);
+        std::vector<int4> hw;
+        std::vector<int32_t> htw(ntiles + 1);
+        int64_t nsplit = 0;
+        for (int64_t t = 0; t < ntiles; ++t) {
+            htw[t] = (int32_t)hw.size();
+            int64_t e0 = htf[t], e1 = htf[t + 1];
+            int64_t cntE = e1 - e0;
+            int64_t chunks = std::max<int64_t>(1, (cntE + per - 1) / per);
+            int64_t sz = (cntE + chunks - 1) / chunks;
+            for (int64_t c0 = e0; c0 < e1; c0 += sz) {
+                int slot = 0;
+                if (chunks > 1) slot = (int)(++nsplit);
+                hw.push_back(make_int4((int)t, (int)c0, (int)std::min(e1, c0 + sz), slot));
+            }
+        }
+        htw[ntiles] = (int32_t)hw.size();
+        P->nwork = (int64_t)hw.size();
+        P->work = a.get_n<int4>(P->nwork);
+        P->tile_work = a.get_n<int32_t>(ntiles + 1);
+        HIP_CHECK(hipMemcpyAsync(P->work, hw.data(), sizeof(int4) * hw.size(), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(P->tile_work, htw.data(), 4 * (ntiles + 1), hipMemcpyHostToDevice, s));
+        P->npartial = nsplit;
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+
+    // ---- P2P lists
+    {
+        uint64_t *comp = a.get_n<uint64_t>(np2p);
+        int32_t *dummy = a.get_n<int32_t>(np2p);
+        hipLaunchKernelGGL(k_p2p_composite, grid1(np2p), 256, 0, s, (const int2 *)p2p, np2p, comp, dummy);
+        radix_sort_u64(comp, dummy, np2p, 32 + bits_for(nc), a, s);
+        P->p2p_pairs = a.get_n<int2>(np2p);
+        int32_t *pair_off = a.get_n<int32_t>(P->nleaves);
+        unsigned long long *inter = a.get_n<unsigned long long>(1);
+        HIP_CHECK(hipMemsetAsync(inter, 0, 8, s));
+        hipLaunchKernelGGL(k_p2p_csr, grid1(np2p), 256, 0, s, (const uint64_t *)comp, np2p, (const int32_t *)P->leaf_id,
+                           P->p2p_pairs, pair_off, (const int32_t *)P->c_count, inter);
+        P->p2p_interactions = (int64_t)read_back(inter, s);
+        int32_t *nseg = a.get_n<int32_t>(P->nleaves);
+        P->seg_off = a.get_n<int32_t>(P->nleaves + 1);
+        hipLaunchKernelGGL(k_p2p_segments, grid1(P->nleaves), 256, 0, s, P->nleaves, (const int32_t *)P->leaves,
+                           (const int32_t *)pair_off, np2p, (const int2 *)P->p2p_pairs, (const int32_t *)P->c_start,
+                           (const int32_t *)P->c_count, nseg, (const int32_t *)nullptr, (int2 *)nullptr, 0);
+        P->nseg = exclusive_scan_i32(nseg, P->seg_off, P->nleaves, a, s);
+        int32_t tot = (int32_t)P->nseg;
+        HIP_CHECK(hipMemcpyAsync(P->seg_off + P->nleaves, &tot, 4, hipMemcpyHostToDevice, s));
+        P->segs = a.get_n<int2>(P->nseg);
+        hipLaunchKernelGGL(k_p2p_segments, grid1(P->nleaves), 256, 0, s, P->nleaves, (const int32_t *)P->leaves,
+                           (const int32_t *)pair_off, np2p, (const int2 *)P->p2p_pairs, (const int32_t *)P->c_start,
+                           (const int32_t *)P->c_count, (int32_t *)nullptr, (const int32_t *)P->seg_off, P->segs, 1);
+        HIP_CHECK(hipStreamSynchronize(s));
+        a.put(comp); a.put(dummy); a.put(pair_off); a.put(inter); a.put(nseg); a.put(p2p);
+    }
+
+    // ---- evaluation workspace
+    const int KP = P->KP;
+    P->M = a.get_n<float>(nc * KP);
+    P->L = a.get_n<float>(nc * KP);
+    if (P->npartial > 0) P->partial = a.get_n<float>(P->npartial * kTileN * KP);
+    P->far_phi = a.get_n<float>(n);
+    P->far_grad = a.get_n<float>(3 * n);
+    P->near_phi = a.get_n<float>(n);
+    P->near_grad = a.get_n<float>(3 * n);
+    HIP_CHECK(hipStreamSynchronize(s));
+}
+
+}  // namespace fmm
