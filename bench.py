@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X FMM hot path on one GPU.
+
+One step = the whole path on one synthetic point set: plan (root cube, keys, sort,
+octree, dual traversal, operator grouping), forward evaluation (P2M, M2M, M2L, L2L,
+L2P, P2P, un-permute), a rebuilt plan and the adjoint (the same FMM with charges
+w = dL/dphi, plus dL/dx = w grad phi + q grad psi).  `value` is whole-step
+particles/s (forward + adjoint); the forward-only and evaluation-only rates are
+reported beside it.  Inputs are resident in device memory before timing starts.
+
+Prints one JSON line.  Accuracy is checked after the timed region against the exact
+FP64 direct sum on 1000 sampled targets (the result counts only at <= 1e-4).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+MFMA_FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 MFMA
+VALU_FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (packed); 78.6 without packed math
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform-1M")
+    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--p", type=int, default=None)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-accuracy", action="store_true")
+    return ap.parse_args()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1602_02244_amd import FMM, inputs
+
+    n0, dist, p, ncrit, theta = inputs.WORKLOADS[args.workload]
+    p = args.p if args.p is not None else p
+    theta = args.theta if args.theta is not None else theta
+    x, q = inputs.workload(args.workload)
+    n = x.shape[0]
+    w = inputs.adjoint_weights(n)
+    dev = torch.device("cuda:0")
+    xt, qt, wt = (torch.from_numpy(a).to(dev) for a in (x, q, w))
+    torch.cuda.synchronize()
+
+    def step(record):
+        t0 = time.perf_counter()
+        plan = FMM(xt, ncrit, p, theta, args.precision)
+        if record is not None:
+            plan.set_timing(True)
+        phi, grad = plan.eval(qt)
+        if record is not None:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            record["fwd"].append(t1 - t0)
+            record["eval_phases"].append(plan.phase_times())
+            record["stats"] = plan.stats()
+        plan.close()
+        plan2 = FMM(xt, ncrit, p, theta, args.precision)
+        if record is not None:
+            plan2.set_timing(True)
+        dq, dx = plan2.adjoint(qt, wt, gradient_fwd=grad)
+        if record is not None:
+            record["adj_phases"].append(plan2.phase_times())
+        plan2.close()
+        return phi, grad, dq, dx
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    rec = {"fwd": [], "eval_phases": [], "adj_phases": []}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step(rec)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    phi, grad, dq, dx = out
+
+    ms_step = 1e3 * total / args.steps
+    st = rec["stats"]
+    ph = {k: float(np.mean([d[k] for d in rec["eval_phases"] + rec["adj_phases"]])) for k in rec["eval_phases"][0]}
+    eval_ms = float(np.mean([d["total"] for d in rec["eval_phases"]]))
+    m2l_ms = ph["m2l"]
+    p2p_ms = ph["p2p"]
+    m2l_tflops = st["m2l_flops"] / (m2l_ms * 1e-3) / 1e12
+    p2p_tflops = st["p2p_flops"] / (p2p_ms * 1e-3) / 1e12
+    result = {
+        "metric": "Laplace FMM particles/s at 1e-4 rel err (fwd, fwd+adjoint); P2P TFLOP/s",
+        "value": n / (ms_step * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "mixed(f16x3 MFMA, f32, f64)",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "distribution": dist, "p": p, "ncrit": ncrit, "theta": theta,
+                   "precision": args.precision, "step": "plan + eval + plan + adjoint"},
+        "fwd_particles_per_s": n / float(np.mean(rec["fwd"])),
+        "eval_particles_per_s": n / (eval_ms * 1e-3),
+        "phase_ms": ph,
+        "p2p_tflops": p2p_tflops,
+        "m2l_tflops": m2l_tflops,
+        "p2p_interactions": st["p2p_interactions"],
+        "m2l_pairs": st["m2l_pairs"],
+        "m2l_keys": st["m2l_keys"],
+        "ncells": st["ncells"],
+        "roofline": {
+            "kernel": "k_m2l (FP32 MFMA grouped GEMM)",
+            "bound": "mfma",
+            "achieved": m2l_tflops,
+            "peak": MFMA_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": m2l_tflops / MFMA_FP32_PEAK_TFLOPS,
+            "traffic": None,
+        },
+        "p2p_roofline": {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_tflops, "peak": VALU_FP32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s (20 flop/interaction)", "frac": p2p_tflops / VALU_FP32_PEAK_TFLOPS},
+    }
+
+    if not args.skip_accuracy:
+        import oracle
+        oracle.set_threads(0)
+        samp = inputs.sample_targets(n, 1000)
+        dphi, dgrad = oracle.direct(x.astype(np.float64), q.astype(np.float64), samp)
+        dpsi, _ = oracle.direct(x.astype(np.float64), w.astype(np.float64), samp)
+        ph_np, g_np, dq_np = phi.cpu().numpy()[samp], grad.cpu().numpy()[samp], dq.cpu().numpy()[samp]
+        err = {"phi": rel_l2(ph_np, dphi), "grad": rel_l2(g_np, dgrad), "dL_dq": rel_l2(dq_np, dpsi)}
+        result["rel_err_vs_direct_1000"] = err
+        result["accuracy_ok"] = bool(max(err.values()) <= 1e-4)
+
+    if not args.skip_cpu_baseline:
+        import oracle
+        threads = oracle.set_threads(0)
+        t0 = time.perf_counter()
+        ora = oracle.Plan(x.astype(np.float64), ncrit, theta)
+        t_plan = time.perf_counter() - t0
+        cells = ora.cells()
+        order, _ = ora.order()
+        leaves = np.nonzero(cells["leaf"])[0]
+        nl_s = min(512, leaves.shape[0])
+        pick = np.sort(np.random.default_rng(4001).choice(leaves, nl_s, replace=False))
+        samp = np.concatenate([order[cells["start"][c]:cells["start"][c] + cells["count"][c]] for c in pick])
+        t0 = time.perf_counter()
+        _, _, tm = ora.eval(q.astype(np.float64), p, sample=samp)
+        t_eval = time.perf_counter() - t0
+        # upward pass is full; M2L, L2L, L2P and P2P ran for every target of nl_s random leaves
+        scale = leaves.shape[0] / nl_s
+        t_full = t_plan + tm[0] + (t_eval - tm[0]) * scale
+        result["cpu_baseline"] = {
+            "value": n / t_full,
+            "unit": "particles/s (forward only)",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": (f"FP64 oracle on the same {n}-point workload: full plan ({t_plan:.1f} s) and upward pass "
+                       f"({tm[0]:.1f} s); M2L/L2L/L2P/P2P for all {samp.shape[0]} targets of {nl_s} random leaves "
+                       f"({t_eval - tm[0]:.1f} s) scaled by {leaves.shape[0]}/{nl_s} leaves"),
+        }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
