@@ -63,9 +63,10 @@ typedef enum {
 /*
  * Device allocator used for every plan workspace.  alloc returns NULL on
  * failure (the call then fails with FMM_ENOMEM).  Both are called with the
- * stream of the plan call.  Passing NULL for both restores the default
- * (hipMallocAsync / hipFreeAsync on that stream).  Plans keep the allocator
- * that was current when they were built.
+ * stream of the plan call.  Passing NULL for both restores the default: a
+ * process-wide caching allocator over hipMalloc (blocks are kept for reuse and
+ * not returned to the driver).  Plans keep the allocator that was current when
+ * they were built.
  */
 typedef void *(*fmm_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*fmm_free_fn)(void *ptr, void *stream, void *ctx);

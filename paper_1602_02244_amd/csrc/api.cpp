@@ -1,7 +1,10 @@
 // C ABI of the FMM library: argument validation, status codes, plan lifetime,
 // statistics and exports.  All computation happens in the device kernels of
 // plan.hip and eval.hip.
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -29,19 +32,63 @@ fmm_status set_err(fmm_status s, const std::string &m) {
     return s;
 }
 
+void note_stream(fmm_plan_s *P, hipStream_t s) {
+    for (hipStream_t t : P->streams_used)
+        if (t == s) return;
+    P->streams_used.push_back(s);
+}
+
 void destroy_plan(fmm_plan_s *P) {
     if (!P) return;
-    if (P->last_stream_set) (void)hipStreamSynchronize(P->last_stream);
+    const bool log = getenv("FMM_LOG") != nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    auto stamp = [&](const char *w) {
+        if (log)
+            fprintf(stderr, "[fmm destroy] %-12s %8.3f ms\n", w,
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    };
+    for (hipStream_t st : P->streams_used) (void)hipStreamSynchronize(st);
     if (P->side) (void)hipStreamSynchronize(P->side);
     (void)hipStreamSynchronize(P->mem.stream);
+    stamp("synced");
     P->mem.release_all();
-    (void)hipStreamSynchronize(P->mem.stream);
-    if (P->side) (void)hipStreamDestroy(P->side);
+    stamp("freed");
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     for (auto &e : P->ev)
         if (e) (void)hipEventDestroy(e);
+    stamp("events");
     delete P;
+}
+
+// Keep freed stream-ordered allocations in the device's default pool instead of
+// returning them to the driver at every synchronisation (plans allocate and free
+// many work buffers).
+void keep_pool_memory(int dev) {
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int d : done)
+        if (d == dev) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done.push_back(dev);
+}
+
+// One near-field stream per device, shared by all plans (default priority).
+hipStream_t side_stream(int dev) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, hipStream_t>> streams;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &e : streams)
+        if (e.first == dev) return e.second;
+    hipStream_t st = nullptr;
+    HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams.emplace_back(dev, st);
+    return st;
 }
 
 template <class F> fmm_status guarded(F &&f) {
@@ -139,9 +186,11 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
     }
     hipStream_t s = (hipStream_t)stream;
     P->mem.stream = s;
+    note_stream(P, s);
     fmm_status st = guarded([&] {
         HIP_CHECK(hipGetDevice(&P->device));
-        HIP_CHECK(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+        keep_pool_memory(P->device);
+        P->side = side_stream(P->device);
         HIP_CHECK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
         build_plan(P, points, s);
@@ -163,8 +212,7 @@ fmm_status fmm_eval_ex(fmm_plan_t plan, const float *charges, float *potential, 
     if (phases < 1 || phases > 3) return set_err(FMM_EINVAL, "phases must be a non-empty subset of FMM_NEAR | FMM_FAR");
     hipStream_t s = (hipStream_t)stream;
     return guarded([&] {
-        plan->last_stream = s;
-        plan->last_stream_set = true;
+        note_stream(plan, s);
         run_eval(plan, charges, potential, gradient, phases, s);
     });
 }
@@ -182,8 +230,7 @@ fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradi
     hipStream_t s = (hipStream_t)stream;
     return guarded([&] {
         fmm_plan_s *P = plan;
-        P->last_stream = s;
-        P->last_stream_set = true;
+        note_stream(P, s);
         if (!P->tmp_phi) {
             hipStream_t keep = P->mem.stream;
             P->mem.stream = s;

@@ -78,10 +78,13 @@ struct Geo {
 };
 
 // ------------------------------------------------------------------ P2M
+// One wave per leaf: each lane evaluates the harmonics of one body and writes
+// q conj(R) into an LDS column; lanes then own coefficients and sum their row.
 template <int P>
 __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, Geo g, const float4 *bodies, float *M) {
     using D = Dims<P>;
     constexpr int NR = (D::KP + 63) / 64;
+    __shared__ float sc[D::NC][65];
     const int c = leaves[blockIdx.x];
     const int lane = threadIdx.x;
     const int s = g.start[c], n = g.count[c];
@@ -102,19 +105,29 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, Geo g, const 
         }
         float Rr[D::NT], Ri[D::NT];
         regular_harmonics<P>(ux, uy, uz, Rr, Ri);
+        __syncthreads();
 #pragma unroll
         for (int l = 0; l <= P; ++l) {
 #pragma unroll
             for (int m = 0; m <= l; ++m) {
                 // Mt_lm = sum q conj(R_lm(u))
-                const int dr = m == 0 ? l * l : l * l + 2 * m - 1;
-                float v = wave_sum(q * Rr[TRI(l, m)]);
-                if (lane == (dr & 63)) acc[dr >> 6] += v;
-                if (m > 0) {
-                    const int di = dr + 1;
-                    float w = wave_sum(-q * Ri[TRI(l, m)]);
-                    if (lane == (di & 63)) acc[di >> 6] += w;
+                if (m == 0) {
+                    sc[l * l][lane] = q * Rr[TRI(l, 0)];
+                } else {
+                    sc[l * l + 2 * m - 1][lane] = q * Rr[TRI(l, m)];
+                    sc[l * l + 2 * m][lane] = -q * Ri[TRI(l, m)];
                 }
+            }
+        }
+        __syncthreads();
+        const int cnt = min(64, n - base);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int d = r * 64 + lane;
+            if (d < D::NC) {
+                float t = 0.f;
+                for (int i = 0; i < cnt; ++i) t += sc[d][i];
+                acc[r] += t;
             }
         }
     }
@@ -125,55 +138,6 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, Geo g, const 
     }
 }
 
-// ------------------------------------------------------------------ M2M / L2L
-// out[c] (=|+=) sum over inputs of T_oct * in[...] ; one wave per cell, lanes own rows.
-template <int P, bool UP>
-__global__ void __launch_bounds__(64) k_translate(int64_t lo, Geo g, const float *Tt, const float *in, float *out) {
-    using D = Dims<P>;
-    constexpr int KP = D::KP;
-    constexpr int NR = (KP + 63) / 64;
-    __shared__ float sv[KP];
-    const int c = (int)(lo + blockIdx.x);
-    const int lane = threadIdx.x;
-    float acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = 0.f;
-    int first, cnt;
-    if (UP) {            // M2M: the inputs are the children of c
-        cnt = g.nchild[c];
-        if (cnt == 0) return;
-        first = g.child0[c];
-    } else {             // L2L: the input is the parent of c
-        first = g.parent[c];
-        cnt = 1;
-    }
-    for (int q = 0; q < cnt; ++q) {
-        const int src = UP ? first + q : first;
-        const int oc = UP ? src : c;    // the child cell defines the octant
-        const int oct = ((g.ix[oc] & 1) << 2) | ((g.iy[oc] & 1) << 1) | (g.iz[oc] & 1);
-        __syncthreads();
-        for (int d = lane; d < KP; d += 64) sv[d] = in[(int64_t)src * KP + d];
-        __syncthreads();
-        const float *T = Tt + (int64_t)oct * KP * KP;
-        for (int kk = 0; kk < D::NC; ++kk) {
-            const float mk = sv[kk];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const int row = r * 64 + lane;
-                if (row < KP) acc[r] += T[kk * KP + row] * mk;
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int row = r * 64 + lane;
-        if (row < KP) {
-            if (UP) out[(int64_t)c * KP + row] = acc[r];
-            else out[(int64_t)c * KP + row] += acc[r];
-        }
-    }
-}
-
 // ------------------------------------------------------------------ M2L (FP32 MFMA)
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -181,15 +145,26 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // Wave w owns row blocks w, w+4, ... and all four column blocks.  The K loop runs in
 // chunks of 16 coefficients; inside a chunk lane l feeds k = 16*kc + 4*(l/16) + s to
 // MFMA step s, for both operands, so each lane reads 4 consecutive k as one float4.
-template <int P>
-__global__ void __launch_bounds__(256) k_m2l(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
-                                             const uint64_t *key_ptr, const float *M, float *L, float *partial,
-                                             const int32_t *tile_targets) {
+// Software pipeline: the next entry's gathered sources are loaded into registers while
+// the current entry computes, and T's next k chunk is loaded ahead of its MFMAs.
+// Column blocks with no source in an entry (entry_mask bit clear) are skipped.
+//
+// The same kernel runs M2L (all levels at once, split into work items), M2M (per
+// level: targets are parents, one entry per child octant) and L2L (per level:
+// targets share an octant, the source is the parent; ADD accumulates onto the
+// M2L result).
+template <int P, bool ADD>
+__global__ void __launch_bounds__(256) k_gemm(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+                                              const uint8_t *entry_mask, const uint64_t *key_ptr, const float *M,
+                                              float *L, float *partial, const int32_t *tile_targets) {
     using D = Dims<P>;
     constexpr int KP = D::KP;
     constexpr int KPS = KP + 4;                  // LDS row stride (bank spread)
     constexpr int NRB = KP / 16;                 // row blocks
     constexpr int RBW = (NRB + 3) / 4;           // row blocks per wave
+    constexpr int NKC = KP / 16;                 // k chunks
+    constexpr int NQ = KP / 4;                   // float4 per coefficient vector
+    constexpr int NPF = (kTileN * NQ + 255) / 256;
     __shared__ __attribute__((aligned(16))) float Ms[kTileN * KPS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -200,42 +175,68 @@ __global__ void __launch_bounds__(256) k_m2l(const int4 *work, const int32_t *en
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    float4 pre[NPF];
+    auto gather = [&](int e) {
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int idx = tid + 256 * i;
+            pre[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (idx < kTileN * NQ) {
+                const int col = idx / NQ, q4 = idx % NQ;
+                const int src = entry_src[(int64_t)e * kTileN + col];
+                if (src >= 0) pre[i] = reinterpret_cast<const float4 *>(M + (int64_t)src * KP)[q4];
+            }
+        }
+    };
+    if (w.y < w.z) gather(w.y);
     for (int e = w.y; e < w.z; ++e) {
         __syncthreads();
-        // gather the multipoles of this entry's 64 sources
-        for (int idx = tid; idx < kTileN * (KP / 4); idx += 256) {
-            const int col = idx / (KP / 4), q4 = idx % (KP / 4);
-            const int src = entry_src[(int64_t)e * kTileN + col];
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (src >= 0) v = reinterpret_cast<const float4 *>(M + (int64_t)src * KP)[q4];
-            *reinterpret_cast<float4 *>(&Ms[col * KPS + 4 * q4]) = v;
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int idx = tid + 256 * i;
+            if (idx < kTileN * NQ) {
+                const int col = idx / NQ, q4 = idx % NQ;
+                *reinterpret_cast<float4 *>(&Ms[col * KPS + 4 * q4]) = pre[i];
+            }
         }
         __syncthreads();
         const float *T = reinterpret_cast<const float *>(key_ptr[entry_key[e]]);
-#pragma unroll 2
-        for (int kc = 0; kc < KP / 16; ++kc) {
-            float4 a[RBW], b[4];
+        const int mask = entry_mask ? (int)entry_mask[e] : 15;
+        if (e + 1 < w.z) gather(e + 1);
+        float4 a[RBW], an[RBW];
 #pragma unroll
-            for (int r = 0; r < RBW; ++r) {
-                const int rb = wave + 4 * r;
-                if (rb < NRB)
-                    a[r] = *reinterpret_cast<const float4 *>(T + (int64_t)(rb * 16 + li) * KP + kc * 16 + 4 * lg);
-                else
-                    a[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int r = 0; r < RBW; ++r) {
+            const int rb = wave + 4 * r;
+            a[r] = rb < NRB ? *reinterpret_cast<const float4 *>(T + (int64_t)(rb * 16 + li) * KP + 4 * lg)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+            if (kc + 1 < NKC) {
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) {
+                    const int rb = wave + 4 * r;
+                    an[r] = rb < NRB ? *reinterpret_cast<const float4 *>(T + (int64_t)(rb * 16 + li) * KP +
+                                                                         (kc + 1) * 16 + 4 * lg)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
             }
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                b[cb] = *reinterpret_cast<const float4 *>(&Ms[(cb * 16 + li) * KPS + kc * 16 + 4 * lg]);
+            for (int cb = 0; cb < 4; ++cb) {
+                if (!((mask >> cb) & 1)) continue;
+                const float4 b = *reinterpret_cast<const float4 *>(&Ms[(cb * 16 + li) * KPS + kc * 16 + 4 * lg]);
 #pragma unroll
-            for (int r = 0; r < RBW; ++r) {
-                if (wave + 4 * r >= NRB) continue;
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b[cb].x, acc[r][cb], 0, 0, 0);
-                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b[cb].y, acc[r][cb], 0, 0, 0);
-                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b[cb].z, acc[r][cb], 0, 0, 0);
-                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, b[cb].w, acc[r][cb], 0, 0, 0);
+                for (int r = 0; r < RBW; ++r) {
+                    if (wave + 4 * r >= NRB) continue;
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b.z, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, b.w, acc[r][cb], 0, 0, 0);
                 }
+            }
+            if (kc + 1 < NKC) {
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) a[r] = an[r];
             }
         }
     }
@@ -256,7 +257,10 @@ __global__ void __launch_bounds__(256) k_m2l(const int4 *work, const int32_t *en
                 dst = partial + ((int64_t)(w.w - 1) * kTileN + col) * KP;
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) dst[rb * 16 + 4 * lg + v] = acc[r][cb][v];
+            for (int v = 0; v < 4; ++v) {
+                if (ADD && w.w == 0) dst[rb * 16 + 4 * lg + v] += acc[r][cb][v];
+                else dst[rb * 16 + 4 * lg + v] = acc[r][cb][v];
+            }
         }
     }
 }
@@ -487,16 +491,21 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     ev_rec(Pl, 2 * PH_P2M + 1, s);
     ev_rec(Pl, 2 * PH_M2M, s);
     for (int l = Pl->max_level - 1; l >= 0; --l) {
-        int64_t lo = Pl->level_off[l], cnt = Pl->level_off[l + 1] - lo;
-        hipLaunchKernelGGL((k_translate<P, true>), (int)cnt, 64, 0, s, lo, g, T.m2m_t, (const float *)Pl->M, Pl->M);
+        const int t0 = Pl->m2m.bucket_tile[l * 8], t1 = Pl->m2m.bucket_tile[l * 8 + 8];
+        if (t1 > t0)
+            hipLaunchKernelGGL((k_gemm<P, false>), t1 - t0, 256, 0, s, (const int4 *)Pl->m2m.work + t0,
+                               (const int32_t *)Pl->m2m.entry_key, (const int32_t *)Pl->m2m.entry_src,
+                               (const uint8_t *)nullptr, T.m2m_ptrs,
+                               (const float *)Pl->M, Pl->M, (float *)nullptr, (const int32_t *)Pl->m2m.tile_targets);
     }
     ev_rec(Pl, 2 * PH_M2M + 1, s);
     fill_f32(Pl->L, 0.f, Pl->ncells * (int64_t)D::KP, s);
     ev_rec(Pl, 2 * PH_M2L, s);
     if (Pl->nwork > 0)
-        hipLaunchKernelGGL(k_m2l<P>, (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work, (const int32_t *)Pl->entry_key,
-                           (const int32_t *)Pl->entry_src, Pl->key_f32, (const float *)Pl->M, Pl->L, Pl->partial,
-                           (const int32_t *)Pl->tile_targets);
+        hipLaunchKernelGGL((k_gemm<P, false>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
+                           (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
+                           (const uint8_t *)Pl->entry_mask, Pl->key_f32,
+                           (const float *)Pl->M, Pl->L, Pl->partial, (const int32_t *)Pl->tile_targets);
     ev_rec(Pl, 2 * PH_M2L + 1, s);
     ev_rec(Pl, 2 * PH_L2L, s);
     if (Pl->npartial > 0)
@@ -504,8 +513,12 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
                            (const int4 *)Pl->work, (const float *)Pl->partial, (const int32_t *)Pl->tile_targets, D::KP,
                            Pl->L);
     for (int l = 1; l <= Pl->max_level; ++l) {
-        int64_t lo = Pl->level_off[l], cnt = Pl->level_off[l + 1] - lo;
-        hipLaunchKernelGGL((k_translate<P, false>), (int)cnt, 64, 0, s, lo, g, T.l2l_t, (const float *)Pl->L, Pl->L);
+        const int t0 = Pl->l2l.bucket_tile[l * 8], t1 = Pl->l2l.bucket_tile[l * 8 + 8];
+        if (t1 > t0)
+            hipLaunchKernelGGL((k_gemm<P, true>), t1 - t0, 256, 0, s, (const int4 *)Pl->l2l.work + t0,
+                               (const int32_t *)Pl->l2l.entry_key, (const int32_t *)Pl->l2l.entry_src,
+                               (const uint8_t *)nullptr, T.l2l_ptrs,
+                               (const float *)Pl->L, Pl->L, (float *)nullptr, (const int32_t *)Pl->l2l.tile_targets);
     }
     ev_rec(Pl, 2 * PH_L2L + 1, s);
     ev_rec(Pl, 2 * PH_L2P, s);

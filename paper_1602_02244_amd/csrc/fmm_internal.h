@@ -64,8 +64,8 @@ template <class T> T read_back(const T *dev, hipStream_t s) {
 // (rows = output coefficient), stored in the scaled basis described in operators.cpp.
 struct OpTables {
     int p = -1;
-    const float *m2m_t = nullptr;   // [8][KP][RP]  transposed, octant-major
-    const float *l2l_t = nullptr;   // [8][KP][RP]
+    const uint64_t *m2m_ptrs = nullptr;   // [8] device pointers of the octant M2M matrices [KP][KP]
+    const uint64_t *l2l_ptrs = nullptr;   // [8] device pointers of the octant L2L matrices [KP][KP]
 };
 const OpTables &op_tables(int p);
 // Device pointers (as uint64) of the M2L operator of every key, FP32 and split-FP16 forms.
@@ -92,6 +92,16 @@ inline void unpack_key(uint64_t k, int &dl, int64_t &nx, int64_t &ny, int64_t &n
 struct EvalArgs;   // defined in eval.hip
 
 }  // namespace fmm
+
+// Grouped-GEMM tables of a translation that runs level by level (M2M, L2L).
+struct LevelGemm {
+    int64_t ntiles = 0;
+    int32_t *tile_targets = nullptr;   // [ntiles][kTileN]
+    int32_t *entry_key = nullptr;      // operator (octant) of each entry
+    int32_t *entry_src = nullptr;      // [entries][kTileN]
+    int4 *work = nullptr;              // [ntiles] one work item per tile
+    std::vector<int32_t> bucket_tile;  // first tile of each (level, octant) bucket, size kBuckets + 1
+};
 
 // --------------------------------------------------------------------- the plan
 struct fmm_plan_s {
@@ -133,10 +143,12 @@ struct fmm_plan_s {
     int32_t *tile_targets = nullptr;     // [ntiles][kTileN], -1 = empty lane
     int32_t *entry_key = nullptr;        // [nentries] key id
     int32_t *entry_src = nullptr;        // [nentries][kTileN] source cell or -1
+    uint8_t *entry_mask = nullptr;       // [nentries] bit b: column block b (lanes 16b..16b+15) has a source
     int4 *work = nullptr;                // [nwork] (tile, entry begin, entry end, partial slot + 1 or 0 = direct)
     int64_t npartial = 0;                // work items that write a partial tile
     int32_t *tile_work = nullptr;        // [ntiles + 1] work item range of each tile
     int64_t nkeys_same = 0, nm2l_same = 0;
+    LevelGemm m2m, l2l;
 
     // P2P
     int64_t np2p = 0, nseg = 0, p2p_interactions = 0;
@@ -150,8 +162,7 @@ struct fmm_plan_s {
     float *partial = nullptr;                   // [nwork][kTileN][KP]
     float *far_phi = nullptr, *far_grad = nullptr, *near_phi = nullptr, *near_grad = nullptr;
     float *tmp_phi = nullptr, *tmp_grad = nullptr, *tmp_gfwd = nullptr;   // adjoint scratch (input order)
-    hipStream_t last_stream = nullptr;          // stream of the most recent evaluation
-    bool last_stream_set = false;
+    std::vector<hipStream_t> streams_used;       // every stream the plan's memory was used on
     int fp64_levels = 0;                        // levels 0..fp64_levels-1 kept in FP64 (mixed)
 
     // timing

@@ -138,7 +138,7 @@ void build_m2m(int p, int oct, std::vector<double> &A) {
     for (int a = 0; a < 3; ++a) d[a] = ((oct >> (2 - a)) & 1) ? 0.25 : -0.25;
     Harm R = regular(d[0], d[1], d[2], p);
     int KP = ncoef_pad(p);
-    real_matrix(p, KP, KP, true, A, [&](int lc, int mc, cd xv, std::vector<cd> &Y) {
+    real_matrix(p, KP, KP, false, A, [&](int lc, int mc, cd xv, std::vector<cd> &Y) {
         double sc = std::ldexp(1.0, -lc);
         for (int l = lc; l <= p; ++l)
             for (int m = 0; m <= l; ++m) Y[tri(l, m)] += std::conj(R.get(l - lc, m - mc)) * sc * xv;
@@ -150,7 +150,7 @@ void build_l2l(int p, int oct, std::vector<double> &A) {
     for (int a = 0; a < 3; ++a) d[a] = ((oct >> (2 - a)) & 1) ? 0.25 : -0.25;
     Harm R = regular(d[0], d[1], d[2], p);
     int KP = ncoef_pad(p);
-    real_matrix(p, KP, KP, true, A, [&](int j, int k, cd xv, std::vector<cd> &Y) {
+    real_matrix(p, KP, KP, false, A, [&](int j, int k, cd xv, std::vector<cd> &Y) {
         for (int a = 0; a <= j; ++a) {
             double sc = std::ldexp(1.0, -(a + 1));
             for (int b = 0; b <= a; ++b) Y[tri(a, b)] += xv * std::conj(R.get(j - a, k - b)) * sc;
@@ -193,8 +193,10 @@ Store &store_for(int p) {
         std::vector<double> A;
         std::vector<float> host((size_t)8 * KP * KP);
         float *m2m = nullptr, *l2l = nullptr;
+        uint64_t *ptrs = nullptr;
         HIP_CHECK(hipMalloc(&m2m, sizeof(float) * host.size()));
         HIP_CHECK(hipMalloc(&l2l, sizeof(float) * host.size()));
+        HIP_CHECK(hipMalloc(&ptrs, sizeof(uint64_t) * 16));
         for (int o = 0; o < 8; ++o) {
             build_m2m(p, o, A);
             for (size_t i = 0; i < A.size(); ++i) host[(size_t)o * KP * KP + i] = (float)A[i];
@@ -205,9 +207,15 @@ Store &store_for(int p) {
             for (size_t i = 0; i < A.size(); ++i) host[(size_t)o * KP * KP + i] = (float)A[i];
         }
         HIP_CHECK(hipMemcpy(l2l, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice));
+        uint64_t hp[16];
+        for (int o = 0; o < 8; ++o) {
+            hp[o] = (uint64_t)(uintptr_t)(m2m + (size_t)o * KP * KP);
+            hp[8 + o] = (uint64_t)(uintptr_t)(l2l + (size_t)o * KP * KP);
+        }
+        HIP_CHECK(hipMemcpy(ptrs, hp, sizeof(hp), hipMemcpyHostToDevice));
         s.tables.p = p;
-        s.tables.m2m_t = m2m;
-        s.tables.l2l_t = l2l;
+        s.tables.m2m_ptrs = ptrs;
+        s.tables.l2l_ptrs = ptrs + 8;
     }
     return s;
 }

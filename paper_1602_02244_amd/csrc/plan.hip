@@ -8,6 +8,9 @@
 // shared by boxes with the same relative position (Sec. 2.2).
 #include <algorithm>
 #include <cmath>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "fmm_internal.h"
@@ -44,18 +47,29 @@ __global__ void __launch_bounds__(256) k_bbox_partial(const float *pts, int64_t 
     if (threadIdx.x < 7) part[blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const float *part, int nb, float *out) {
-    if (threadIdx.x != 0) return;
-    float r[7];
-    for (int a = 0; a < 7; ++a) r[a] = part[a];
-    for (int b = 1; b < nb; ++b) {
+__global__ void __launch_bounds__(256) k_bbox_final(const float *part, int nb, float *out) {
+    __shared__ float sh[7][256];
+    float r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.f};
+    for (int b = threadIdx.x; b < nb; b += 256) {
         for (int a = 0; a < 3; ++a) {
             r[a] = fminf(r[a], part[b * 8 + a]);
             r[3 + a] = fmaxf(r[3 + a], part[b * 8 + 3 + a]);
         }
         r[6] = fmaxf(r[6], part[b * 8 + 6]);
     }
-    for (int a = 0; a < 7; ++a) out[a] = r[a];
+    for (int a = 0; a < 7; ++a) sh[a][threadIdx.x] = r[a];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            for (int a = 0; a < 3; ++a) {
+                sh[a][threadIdx.x] = fminf(sh[a][threadIdx.x], sh[a][threadIdx.x + off]);
+                sh[3 + a][threadIdx.x] = fmaxf(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + off]);
+            }
+            sh[6][threadIdx.x] = fmaxf(sh[6][threadIdx.x], sh[6][threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Root cube: side 2^k, the smallest power of two with hi_a - x0_a < 2^k on every axis,
@@ -248,36 +262,51 @@ __device__ inline void block_scan3(int v0, int v1, int v2, int &e0, int &e1, int
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_trav_count(CellView C, const int2 *front, int64_t nf, double theta2,
-                                                    unsigned long long *cnt) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int m = 0, q = 0, nx = 0;
-    if (i < nf) {
-        int2 pr = front[i];
-        int a0, na, b0, nb;
-        int act = classify(C, pr.x, pr.y, theta2, a0, na, b0, nb);
-        if (act == 0) m = 1; else if (act == 1) q = 1; else nx = na * nb;
+// One traversal step.  Every pair of `front` needs a split; its child pairs (rules 3-4)
+// are classified here: M2L and P2P pairs go to their lists, pairs that need a further
+// split to `next`.  Each thread counts its outputs, one block scan and one atomic per
+// list reserve the ranges, then the thread writes.  Writes past a list's capacity are
+// dropped; the counters still advance, so the host sees the exact sizes and repeats
+// the step with larger lists.
+__device__ inline void split_ranges(const CellView &C, int a, int b, int &a0, int &na, int &b0, int &nb) {
+    int nca = C.nchild[a], ncb = C.nchild[b];
+    int la = C.level[a], lb = C.level[b];
+    bool splitA, splitB;
+    if (nca > 0 && ncb > 0 && la == lb) {
+        splitA = splitB = true;
+    } else {
+        if (la < lb) splitA = nca > 0;
+        else if (lb < la) splitA = ncb == 0;
+        else splitA = nca > 0;
+        splitB = !splitA;
     }
-    int e0, e1, e2, t0, t1, t2;
-    block_scan3(m, q, nx, e0, e1, e2, t0, t1, t2);
-    if (threadIdx.x == 0) {
-        if (t0) atomicAdd(&cnt[0], (unsigned long long)t0);
-        if (t1) atomicAdd(&cnt[1], (unsigned long long)t1);
-        if (t2) atomicAdd(&cnt[2], (unsigned long long)t2);
-    }
+    if (splitA) { a0 = C.child0[a]; na = nca; } else { a0 = a; na = 1; }
+    if (splitB) { b0 = C.child0[b]; nb = ncb; } else { b0 = b; nb = 1; }
 }
 
-// cnt[] holds the running output sizes; each block reserves its range with one atomic per list.
-__global__ void __launch_bounds__(256) k_trav_emit(CellView C, const int2 *front, int64_t nf, double theta2,
-                                                   unsigned long long *cnt, int2 *m2l, int2 *p2p, int2 *next) {
+__device__ inline int action(const CellView &C, int a, int b, double theta2) {
+    if (mac_accept(C, a, b, theta2)) return 0;
+    if (C.nchild[a] == 0 && C.nchild[b] == 0) return 1;
+    return 2;
+}
+
+__global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front, int64_t nf, double theta2,
+                                                   unsigned long long *cnt, int2 *m2l, int64_t cap_m, int2 *p2p,
+                                                   int64_t cap_p, int2 *next, int64_t cap_n) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int m = 0, q = 0, nx = 0, act = -1, a0 = 0, na = 0, b0 = 0, nb = 0;
-    int2 pr = make_int2(0, 0);
+    int a0 = 0, na = 0, b0 = 0, nb = 0;
     if (i < nf) {
-        pr = front[i];
-        act = classify(C, pr.x, pr.y, theta2, a0, na, b0, nb);
-        if (act == 0) m = 1; else if (act == 1) q = 1; else nx = na * nb;
+        int2 pr = front[i];
+        split_ranges(C, pr.x, pr.y, a0, na, b0, nb);
     }
+    int m = 0, q = 0, nx = 0;
+    for (int x = 0; x < na; ++x)
+        for (int y = 0; y < nb; ++y) {
+            int act = action(C, a0 + x, b0 + y, theta2);
+            m += act == 0;
+            q += act == 1;
+            nx += act == 2;
+        }
     int e0, e1, e2, t0, t1, t2;
     block_scan3(m, q, nx, e0, e1, e2, t0, t1, t2);
     __shared__ unsigned long long base[3];
@@ -287,39 +316,125 @@ __global__ void __launch_bounds__(256) k_trav_emit(CellView C, const int2 *front
         base[2] = t2 ? atomicAdd(&cnt[2], (unsigned long long)t2) : 0;
     }
     __syncthreads();
-    if (act == 0) m2l[base[0] + e0] = pr;
-    else if (act == 1) p2p[base[1] + e1] = pr;
-    else if (act == 2) {
-        unsigned long long w = base[2] + e2;
-        for (int x = 0; x < na; ++x)
-            for (int y = 0; y < nb; ++y) next[w++] = make_int2(a0 + x, b0 + y);
-    }
+    int64_t wm = (int64_t)(base[0] + e0), wq = (int64_t)(base[1] + e1), wn = (int64_t)(base[2] + e2);
+    for (int x = 0; x < na; ++x)
+        for (int y = 0; y < nb; ++y) {
+            int a = a0 + x, b = b0 + y;
+            int act = action(C, a, b, theta2);
+            if (act == 0) { if (wm < cap_m) m2l[wm] = make_int2(a, b); ++wm; }
+            else if (act == 1) { if (wq < cap_p) p2p[wq] = make_int2(a, b); ++wq; }
+            else { if (wn < cap_n) next[wn] = make_int2(a, b); ++wn; }
+        }
 }
 
 // ----------------------------------------------------------------- M2L grouping
-__global__ void k_m2l_keys(const int2 *pairs, int64_t np, CellView C, uint64_t *keys, int32_t *vals, int32_t *overflow) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        int a = pairs[i].x, b = pairs[i].y;   // target A, source B
-        int la = C.level[a], lb = C.level[b];
-        int lf = la > lb ? la : lb;
-        int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
-        // D = c_B - c_A in units of the finer half side
-        int64_t nx = (2 * (int64_t)C.ix[b] + 1) * sb - (2 * (int64_t)C.ix[a] + 1) * sa;
-        int64_t ny = (2 * (int64_t)C.iy[b] + 1) * sb - (2 * (int64_t)C.iy[a] + 1) * sa;
-        int64_t nz = (2 * (int64_t)C.iz[b] + 1) * sb - (2 * (int64_t)C.iz[a] + 1) * sa;
-        if (nx < -kKeyOffBias || nx >= kKeyOffBias || ny < -kKeyOffBias || ny >= kKeyOffBias || nz < -kKeyOffBias ||
-            nz >= kKeyOffBias)
-            *overflow = 1;
-        keys[i] = pack_key(lb - la, nx, ny, nz);
-        vals[i] = (int32_t)i;
+
+// Sum of one 64-bit value per thread over a 256-thread block, added once per block.
+__device__ inline void block_add_u64(unsigned long long v, unsigned long long *dst) {
+    __shared__ unsigned long long ws[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = ws[0] + ws[1] + ws[2] + ws[3];
+        if (t) atomicAdd(dst, t);
     }
 }
 
-__global__ void k_count_same_level(const uint64_t *keys, int64_t n, unsigned long long *cnt) {
+__global__ void __launch_bounds__(256) k_count_same_level(const int32_t *pair_key_id, int64_t n,
+                                                          const int32_t *key_same, unsigned long long *cnt) {
     unsigned long long loc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        loc += (keys[i] >> 57) == 32u ? 1ull : 0ull;
-    atomicAdd(cnt, loc);
+        loc += key_same[pair_key_id[i]] ? 1ull : 0ull;
+    block_add_u64(loc, cnt);
+}
+
+__device__ inline uint64_t key_hash(uint64_t k) {   // splitmix64 finaliser
+    k ^= k >> 30; k *= 0xbf58476d1ce4e5b9ull;
+    k ^= k >> 27; k *= 0x94d049bb133111ebull;
+    k ^= k >> 31;
+    return k;
+}
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ inline uint64_t pair_key(const CellView &C, int a, int b, int32_t *overflow) {
+    int la = C.level[a], lb = C.level[b];
+    int lf = la > lb ? la : lb;
+    int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
+    // D = c_B - c_A in units of the finer half side
+    int64_t nx = (2 * (int64_t)C.ix[b] + 1) * sb - (2 * (int64_t)C.ix[a] + 1) * sa;
+    int64_t ny = (2 * (int64_t)C.iy[b] + 1) * sb - (2 * (int64_t)C.iy[a] + 1) * sa;
+    int64_t nz = (2 * (int64_t)C.iz[b] + 1) * sb - (2 * (int64_t)C.iz[a] + 1) * sa;
+    if (nx < -kKeyOffBias || nx >= kKeyOffBias || ny < -kKeyOffBias || ny >= kKeyOffBias || nz < -kKeyOffBias ||
+        nz >= kKeyOffBias) {
+        *overflow = 1;
+        return 0;
+    }
+    return pack_key(lb - la, nx, ny, nz);
+}
+
+// Insert the key of every M2L pair into an open-addressing table (linear probing,
+// at most `mask + 1` probes; a full table raises flags[1]).
+__global__ void k_key_insert(const int2 *pairs, int64_t np, CellView C, uint64_t *table, uint64_t mask,
+                             int32_t *flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t key = pair_key(C, pairs[i].x, pairs[i].y, flags);
+        uint64_t h = key_hash(key) & mask;
+        bool done = false;
+        for (uint64_t probe = 0; probe <= mask; ++probe) {
+            uint64_t cur = table[h];
+            if (cur == key) { done = true; break; }
+            if (cur == kEmpty) {
+                uint64_t prev = atomicCAS((unsigned long long *)&table[h], (unsigned long long)kEmpty,
+                                          (unsigned long long)key);
+                if (prev == kEmpty || prev == key) { done = true; break; }
+            }
+            h = (h + 1) & mask;
+        }
+        if (!done) flags[1] = 1;
+    }
+}
+
+// Key id of every pair (the key is in the table), and the (tile, key) presence table.
+__global__ void k_key_ids(const int2 *pairs, int64_t np, CellView C, const uint64_t *table, uint64_t mask,
+                          const int32_t *slot_id, const int32_t *cell_tile, int64_t nkeys, int32_t *pair_key_id,
+                          int32_t *present, int32_t *flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t key = pair_key(C, pairs[i].x, pairs[i].y, flags);
+        uint64_t h = key_hash(key) & mask;
+        for (uint64_t probe = 0; probe <= mask; ++probe) {
+            if (table[h] == key) break;
+            h = (h + 1) & mask;
+        }
+        int id = slot_id[h];
+        pair_key_id[i] = id;
+        present[(int64_t)cell_tile[pairs[i].x] * nkeys + id] = 1;
+    }
+}
+
+// Entries are the present (tile, key) cells in tile-major, key-ascending order.
+__global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pair_key_id, const int32_t *cell_tile,
+                               const int32_t *cell_lane, const int32_t *entry_of, int64_t nkeys, int32_t *entry_key,
+                               int32_t *entry_src, int32_t *entry_mask32) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        int a = pairs[i].x, k = pair_key_id[i];
+        int e = entry_of[(int64_t)cell_tile[a] * nkeys + k];
+        int lane = cell_lane[a];
+        entry_key[e] = k;
+        entry_src[(int64_t)e * kTileN + lane] = pairs[i].y;
+        atomicOr(&entry_mask32[e], 1 << (lane >> 4));
+    }
+}
+
+__global__ void k_mask_narrow(const int32_t *m32, int64_t n, uint8_t *m8) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m8[i] = (uint8_t)m32[i];
+}
+
+__global__ void k_tile_first(const int32_t *entry_of, int64_t ntiles, int64_t nkeys, int32_t *tile_first) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x)
+        tile_first[t] = entry_of[t * nkeys];
 }
 
 __global__ void k_flag_diff(const uint64_t *keys, int64_t n, int shift, int32_t *flag) {
@@ -327,25 +442,17 @@ __global__ void k_flag_diff(const uint64_t *keys, int64_t n, int shift, int32_t 
         flag[i] = (i == 0 || (keys[i] >> shift) != (keys[i - 1] >> shift)) ? 1 : 0;
 }
 
-__global__ void k_unique_keys(const uint64_t *keys, const int32_t *vals, const int32_t *flag, const int32_t *ex,
-                              int64_t n, uint64_t *ukeys, int32_t *pair_key) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int id = ex[i] + flag[i] - 1;
-        if (flag[i]) ukeys[id] = keys[i];
-        pair_key[vals[i]] = id;
-    }
-}
 
 __global__ void k_mark_targets(const int2 *pairs, int64_t np, int32_t *is_target) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
         is_target[pairs[i].x] = 1;
 }
 
-__global__ void k_target_keys(const int32_t *is_target, const int32_t *ex, int64_t nc, CellView C, uint64_t *tkeys,
-                              int32_t *tvals) {
+__global__ void k_target_keys(const int32_t *is_target, const int32_t *ex, int64_t nc, CellView C, int by_octant,
+                              uint64_t *tkeys, int32_t *tvals) {
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
         if (!is_target[c]) continue;
-        int oct = ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1);
+        int oct = by_octant ? ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1) : 0;
         tkeys[ex[c]] = ((uint64_t)C.level[c] << 35) | ((uint64_t)oct << 32) | (uint64_t)c;
         tvals[ex[c]] = (int32_t)c;
     }
@@ -371,30 +478,46 @@ __global__ void k_assign_tiles(const uint64_t *tkeys, const int32_t *tvals, int6
     }
 }
 
-__global__ void k_pair_composite(const int2 *pairs, int64_t np, const int32_t *pair_key, const int32_t *cell_tile,
-                                 const int32_t *cell_lane, int key_bits, uint64_t *comp, int32_t *vals) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        int a = pairs[i].x;
-        comp[i] = ((uint64_t)cell_tile[a] << (key_bits + 6)) | ((uint64_t)pair_key[i] << 6) | (uint64_t)cell_lane[a];
-        vals[i] = pairs[i].y;
+
+
+// ----------------------------------------------------------------- M2M / L2L tiles
+__global__ void k_flag_internal(const int32_t *nchild, int64_t nc, int32_t *flag) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x)
+        flag[c] = nchild[c] > 0 ? 1 : 0;
+}
+__global__ void k_flag_nonroot(const int32_t *level, int64_t nc, int32_t *flag) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x)
+        flag[c] = level[c] > 0 ? 1 : 0;
+}
+// M2M: target = parent cell, one entry per child octant, source = the child in that octant.
+__global__ void k_m2m_entries(int64_t nc, CellView C, const int32_t *cell_tile, const int32_t *cell_lane,
+                              int32_t *entry_src) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        int nch = C.nchild[c];
+        if (nch == 0) continue;
+        int t = cell_tile[c], lane = cell_lane[c];
+        for (int q = 0; q < nch; ++q) {
+            int ch = C.child0[c] + q;
+            int oct = ((C.ix[ch] & 1) << 2) | ((C.iy[ch] & 1) << 1) | (C.iz[ch] & 1);
+            entry_src[((int64_t)t * 8 + oct) * kTileN + lane] = ch;
+        }
     }
 }
-
-__global__ void k_build_entries(const uint64_t *comp, const int32_t *vals, const int32_t *flag, const int32_t *ex,
-                                int64_t np, int key_bits, const int32_t *tile_targets, int32_t *entry_key,
-                                int32_t *entry_src, int32_t *tile_first, int2 *pairs_out) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t c = comp[i];
-        int e = ex[i] + flag[i] - 1;
-        int lane = (int)(c & 63u);
-        int key = (int)((c >> 6) & ((1ull << key_bits) - 1));
-        int tile = (int)(c >> (key_bits + 6));
-        if (flag[i]) {
-            entry_key[e] = key;
-            if (i == 0 || (int)(comp[i - 1] >> (key_bits + 6)) != tile) tile_first[tile] = e;
-        }
-        entry_src[(int64_t)e * kTileN + lane] = vals[i];
-        pairs_out[i] = make_int2(tile_targets[(int64_t)tile * kTileN + lane], vals[i]);
+// L2L: target = cell, one entry per tile (all targets of a tile share the octant), source = parent.
+__global__ void k_l2l_entries(int64_t nc, CellView C, const int32_t *parent, const int32_t *cell_tile,
+                              const int32_t *cell_lane, int32_t *entry_key, int32_t *entry_src) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        if (C.level[c] == 0) continue;
+        int t = cell_tile[c], lane = cell_lane[c];
+        entry_src[(int64_t)t * kTileN + lane] = parent[c];
+        if (lane == 0) entry_key[t] = ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1);
+    }
+}
+__global__ void k_work_uniform(int64_t ntiles, int per, int32_t *entry_key_mod8, int4 *work) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+        work[t] = make_int4((int)t, (int)(t * per), (int)(t * per + per), 0);
+        if (entry_key_mod8)
+            for (int q = 0; q < per; ++q) entry_key_mod8[t * per + q] = q;
     }
 }
 
@@ -410,24 +533,28 @@ __global__ void k_leaf_compact(const int32_t *flag, const int32_t *ex, int64_t n
     }
 }
 
-__global__ void k_p2p_composite(const int2 *pairs, int64_t np, uint64_t *comp, int32_t *vals) {
+// (target leaf id, source leaf id) packed into `lbits`-bit halves; the value is the source cell.
+__global__ void k_p2p_composite(const int2 *pairs, int64_t np, const int32_t *leaf_id, int lbits, uint64_t *comp,
+                                int32_t *vals) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        comp[i] = ((uint64_t)(uint32_t)pairs[i].x << 32) | (uint64_t)(uint32_t)pairs[i].y;
-        vals[i] = 0;
+        comp[i] = ((uint64_t)leaf_id[pairs[i].x] << lbits) | (uint64_t)leaf_id[pairs[i].y];
+        vals[i] = pairs[i].y;
     }
 }
 
-__global__ void k_p2p_csr(const uint64_t *comp, int64_t np, const int32_t *leaf_id, int2 *pairs_out, int32_t *pair_off,
-                          const int32_t *c_count, unsigned long long *inter) {
+__global__ void __launch_bounds__(256) k_p2p_csr(const uint64_t *comp, const int32_t *src, int64_t np, int lbits,
+                                                 const int32_t *leaves, int2 *pairs_out, int32_t *pair_off,
+                                                 const int32_t *c_count, unsigned long long *inter) {
     unsigned long long loc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        int a = (int)(comp[i] >> 32), b = (int)(uint32_t)comp[i];
+        int la = (int)(comp[i] >> lbits);
+        int a = leaves[la], b = src[i];
         pairs_out[i] = make_int2(a, b);
-        if (i == 0 || (int)(comp[i - 1] >> 32) != a) pair_off[leaf_id[a]] = (int32_t)i;
+        if (i == 0 || (int)(comp[i - 1] >> lbits) != la) pair_off[la] = (int32_t)i;
         unsigned long long ca = (unsigned long long)c_count[a], cb = (unsigned long long)c_count[b];
         loc += (a == b) ? ca * (ca - 1) : ca * cb;
     }
-    atomicAdd(inter, loc);
+    block_add_u64(loc, inter);
 }
 
 // Source runs of each target leaf: its source leaves (self excluded) with adjacent body
@@ -485,7 +612,72 @@ static void grow(Alloc &a, T *&buf, int64_t &cap, int64_t used, int64_t need, hi
     cap = nc;
 }
 
+// Tiles of kTileN cells: the flagged cells grouped by level (and octant when
+// by_octant), Morton order inside a group.  Returns the number of tiles; fills
+// tile_targets ([ntiles][kTileN], -1 = empty lane), cell -> (tile, lane) maps and the
+// first tile of every (level, octant) bucket (host, size kBuckets + 1).
+constexpr int kBuckets = (kMaxLevel + 1) * 8;
+static int64_t tile_cells(const CellView &C, int64_t nc, int32_t *flag, bool by_octant, Alloc &a, hipStream_t s,
+                          int32_t *&tile_targets, int32_t *cell_tile, int32_t *cell_lane, std::vector<int32_t> &bucket_tile,
+                          int64_t &ntargets) {
+    int32_t *tex = a.get_n<int32_t>(nc);
+    int64_t nt = exclusive_scan_i32(flag, tex, nc, a, s);
+    ntargets = nt;
+    bucket_tile.assign(kBuckets + 1, 0);
+    if (nt == 0) {
+        a.put(tex);
+        tile_targets = a.get_n<int32_t>(1);
+        return 0;
+    }
+    uint64_t *tk = a.get_n<uint64_t>(nt);
+    int32_t *tv = a.get_n<int32_t>(nt);
+    hipLaunchKernelGGL(k_target_keys, grid1(nc), 256, 0, s, (const int32_t *)flag, (const int32_t *)tex, nc, C,
+                       by_octant ? 1 : 0, tk, tv);
+    radix_sort_u64(tk, tv, nt, 40, a, s);
+    int32_t *bst = a.get_n<int32_t>(kBuckets);
+    fill_i32(bst, -1, kBuckets, s);
+    hipLaunchKernelGGL(k_bucket_starts, grid1(nt), 256, 0, s, (const uint64_t *)tk, nt, bst);
+    std::vector<int32_t> hb_start(kBuckets), hb_base(kBuckets, 0);
+    HIP_CHECK(hipMemcpyAsync(hb_start.data(), bst, 4 * kBuckets, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    int64_t ntiles = 0;
+    for (int b = 0; b < kBuckets; ++b) {
+        hb_base[b] = (int32_t)ntiles;
+        bucket_tile[b] = (int32_t)ntiles;
+        if (hb_start[b] < 0) continue;
+        int64_t end = nt;
+        for (int b2 = b + 1; b2 < kBuckets; ++b2)
+            if (hb_start[b2] >= 0) { end = hb_start[b2]; break; }
+        ntiles += (end - hb_start[b] + kTileN - 1) / kTileN;
+    }
+    bucket_tile[kBuckets] = (int32_t)ntiles;
+    int32_t *tbase = a.get_n<int32_t>(kBuckets);
+    HIP_CHECK(hipMemcpyAsync(tbase, hb_base.data(), 4 * kBuckets, hipMemcpyHostToDevice, s));
+    tile_targets = a.get_n<int32_t>(ntiles * kTileN);
+    fill_i32(tile_targets, -1, ntiles * kTileN, s);
+    hipLaunchKernelGGL(k_assign_tiles, grid1(nt), 256, 0, s, (const uint64_t *)tk, (const int32_t *)tv, nt,
+                       (const int32_t *)bst, (const int32_t *)tbase, cell_tile, cell_lane, tile_targets);
+    HIP_CHECK(hipStreamSynchronize(s));   // hb_base is read by the copy above
+    a.put(tex); a.put(tk); a.put(tv); a.put(bst); a.put(tbase);
+    return ntiles;
+}
+
+// Host-side stage timer, printed to stderr when FMM_LOG is set.
+struct StageLog {
+    bool on = getenv("FMM_LOG") != nullptr;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now(), last = t0;
+    void operator()(const char *what) {
+        if (!on) return;
+        auto now = std::chrono::steady_clock::now();
+        fprintf(stderr, "[fmm plan] %-28s +%8.3f ms  (t=%8.3f ms)\n", what,
+                std::chrono::duration<double, std::milli>(now - last).count(),
+                std::chrono::duration<double, std::milli>(now - t0).count());
+        last = now;
+    }
+};
+
 void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
+    StageLog lg;
     Alloc &a = P->mem;
     const int64_t n = P->n;
 
@@ -494,7 +686,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     float *bpart = a.get_n<float>(8 * nb);
     float *bbox = a.get_n<float>(8);
     hipLaunchKernelGGL(k_bbox_partial, nb, 256, 0, s, points, n, bpart);
-    hipLaunchKernelGGL(k_bbox_final, 1, 64, 0, s, (const float *)bpart, nb, bbox);
+    hipLaunchKernelGGL(k_bbox_final, 1, 256, 0, s, (const float *)bpart, nb, bbox);
     float hb[8];
     HIP_CHECK(hipMemcpyAsync(hb, bbox, sizeof(float) * 7, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -507,6 +699,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     int32_t *perm = a.get_n<int32_t>(n);
     hipLaunchKernelGGL(k_keys, grid1(n), 256, 0, s, points, n, P->x0[0], P->x0[1], P->x0[2],
                        std::ldexp(1.0, kMaxLevel - P->k), keys, perm);
+    lg("bbox+keys");
     // ---- a2: sort (stable: equal keys keep input order) and permute
     radix_sort_u64(keys, perm, n, 3 * kMaxLevel, a, s);
     P->keys = keys;
@@ -514,6 +707,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     P->bodies = a.get_n<float4>(n);
     hipLaunchKernelGGL(k_gather_bodies, grid1(n), 256, 0, s, points, (const int32_t *)perm, n, P->bodies);
 
+    lg("sort+permute");
     // ---- a3: octree, level by level
     struct Lvl {
         int64_t n = 0;
@@ -592,6 +786,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     }
     P->c_prefix_dev = c_prefix;
 
+    lg("octree");
     // leaves
     {
         int32_t *flag = a.get_n<int32_t>(nc), *ex = a.get_n<int32_t>(nc);
@@ -604,71 +799,144 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         a.put(flag); a.put(ex);
     }
 
-    // ---- a4: dual traversal
+    lg("leaves");
     CellView C{P->c_level, P->c_ix, P->c_iy, P->c_iz, P->c_child0, P->c_nchild};
+
+    // ---- M2M and L2L as grouped GEMMs: per-level tiles of parents (M2M) and of
+    // same-octant children (L2L)
+    {
+        int32_t *flag = a.get_n<int32_t>(nc);
+        int32_t *ct = a.get_n<int32_t>(nc), *cl = a.get_n<int32_t>(nc);
+        int64_t ntg = 0;
+        hipLaunchKernelGGL(k_flag_internal, grid1(nc), 256, 0, s, (const int32_t *)P->c_nchild, nc, flag);
+        P->m2m.ntiles = tile_cells(C, nc, flag, false, a, s, P->m2m.tile_targets, ct, cl, P->m2m.bucket_tile, ntg);
+        if (P->m2m.ntiles > 0) {
+            P->m2m.entry_src = a.get_n<int32_t>(P->m2m.ntiles * 8 * kTileN);
+            fill_i32(P->m2m.entry_src, -1, P->m2m.ntiles * 8 * kTileN, s);
+            P->m2m.entry_key = a.get_n<int32_t>(P->m2m.ntiles * 8);
+            P->m2m.work = a.get_n<int4>(P->m2m.ntiles);
+            hipLaunchKernelGGL(k_m2m_entries, grid1(nc), 256, 0, s, nc, C, (const int32_t *)ct, (const int32_t *)cl,
+                               P->m2m.entry_src);
+            hipLaunchKernelGGL(k_work_uniform, grid1(P->m2m.ntiles), 256, 0, s, P->m2m.ntiles, 8, P->m2m.entry_key,
+                               P->m2m.work);
+        }
+        hipLaunchKernelGGL(k_flag_nonroot, grid1(nc), 256, 0, s, (const int32_t *)P->c_level, nc, flag);
+        P->l2l.ntiles = tile_cells(C, nc, flag, true, a, s, P->l2l.tile_targets, ct, cl, P->l2l.bucket_tile, ntg);
+        if (P->l2l.ntiles > 0) {
+            P->l2l.entry_src = a.get_n<int32_t>(P->l2l.ntiles * kTileN);
+            fill_i32(P->l2l.entry_src, -1, P->l2l.ntiles * kTileN, s);
+            P->l2l.entry_key = a.get_n<int32_t>(P->l2l.ntiles);
+            P->l2l.work = a.get_n<int4>(P->l2l.ntiles);
+            hipLaunchKernelGGL(k_l2l_entries, grid1(nc), 256, 0, s, nc, C, (const int32_t *)P->c_parent,
+                               (const int32_t *)ct, (const int32_t *)cl, P->l2l.entry_key, P->l2l.entry_src);
+            hipLaunchKernelGGL(k_work_uniform, grid1(P->l2l.ntiles), 256, 0, s, P->l2l.ntiles, 1, (int32_t *)nullptr,
+                               P->l2l.work);
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        a.put(flag); a.put(ct); a.put(cl);
+    }
+
+    lg("m2m/l2l tiles");
+    // ---- a4: dual traversal, one fused step per level of the pair tree
     const double theta2 = (double)P->theta * (double)P->theta;
     unsigned long long *cnt = a.get_n<unsigned long long>(3);
-    int2 *front = a.get_n<int2>(1);
-    {
+    int2 *m2l = nullptr, *p2p = nullptr;
+    int64_t m2l_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
+    if (nc == 1) {               // the root is a leaf: one P2P pair
+        grow(a, p2p, p2p_cap, 0, 1, s);
+        int2 rr = make_int2(0, 0);
+        HIP_CHECK(hipMemcpyAsync(p2p, &rr, sizeof(int2), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        np2p = 1;
+    } else {
+        int2 *front = a.get_n<int2>(1);
         int2 rr = make_int2(0, 0);
         HIP_CHECK(hipMemcpyAsync(front, &rr, sizeof(int2), hipMemcpyHostToDevice, s));
         HIP_CHECK(hipStreamSynchronize(s));
-    }
-    int64_t nf = 1;
-    int2 *m2l = nullptr, *p2p = nullptr;
-    int64_t m2l_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
-    while (nf > 0) {
-        unsigned long long h3[3] = {0, 0, 0};
-        HIP_CHECK(hipMemcpyAsync(cnt, h3, sizeof(h3), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_trav_count, grid1(nf), 256, 0, s, C, (const int2 *)front, nf, theta2, cnt);
-        HIP_CHECK(hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        grow(a, m2l, m2l_cap, nm2l, nm2l + (int64_t)h3[0], s);
-        grow(a, p2p, p2p_cap, np2p, np2p + (int64_t)h3[1], s);
-        int64_t nn = (int64_t)h3[2];
-        int2 *next = nn > 0 ? a.get_n<int2>(nn) : nullptr;
-        unsigned long long base[3] = {(unsigned long long)nm2l, (unsigned long long)np2p, 0ull};
-        HIP_CHECK(hipMemcpyAsync(cnt, base, sizeof(base), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_trav_emit, grid1(nf), 256, 0, s, C, (const int2 *)front, nf, theta2, cnt, m2l, p2p, next);
-        HIP_CHECK(hipStreamSynchronize(s));   // `base` lives on the host stack
-        nm2l += (int64_t)h3[0];
-        np2p += (int64_t)h3[1];
+        int64_t nf = 1;
+        while (nf > 0) {
+            // steady state of a uniform tree: ~8 split pairs, ~56 M2L and ~8 P2P pairs per split pair
+            int64_t cap_n = std::max<int64_t>(1024, std::min<int64_t>(64 * nf, 10 * nf));
+            grow(a, m2l, m2l_cap, nm2l, nm2l + std::min<int64_t>(64 * nf, 70 * nf), s);
+            grow(a, p2p, p2p_cap, np2p, np2p + std::min<int64_t>(64 * nf, 12 * nf), s);
+            int2 *next = a.get_n<int2>(cap_n);
+            unsigned long long h3[3];
+            for (int attempt = 0;; ++attempt) {
+                unsigned long long base[3] = {(unsigned long long)nm2l, (unsigned long long)np2p, 0ull};
+                HIP_CHECK(hipMemcpyAsync(cnt, base, sizeof(base), hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_trav_step, grid1(nf), 256, 0, s, C, (const int2 *)front, nf, theta2, cnt, m2l,
+                                   m2l_cap, p2p, p2p_cap, next, cap_n);
+                HIP_CHECK(hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+                bool ok = (int64_t)h3[0] <= m2l_cap && (int64_t)h3[1] <= p2p_cap && (int64_t)h3[2] <= cap_n;
+                if (ok) break;
+                if (attempt > 0) fail(FMM_EDEVICE, "traversal step overflowed twice");
+                grow(a, m2l, m2l_cap, nm2l, (int64_t)h3[0], s);
+                grow(a, p2p, p2p_cap, np2p, (int64_t)h3[1], s);
+                if ((int64_t)h3[2] > cap_n) {
+                    a.put(next);
+                    cap_n = (int64_t)h3[2];
+                    next = a.get_n<int2>(cap_n);
+                }
+            }
+            nm2l = (int64_t)h3[0];
+            np2p = (int64_t)h3[1];
+            a.put(front);
+            front = next;
+            nf = (int64_t)h3[2];
+        }
         a.put(front);
-        front = next;
-        nf = nn;
     }
     a.put(cnt);
     P->nm2l = nm2l;
     P->np2p = np2p;
+    P->m2l_pairs = m2l;
 
+    lg("traversal");
     // ---- M2L keys, operators, tiles, entries
     if (nm2l > 0) {
         if (nm2l >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "more than 2^31 M2L pairs");
-        uint64_t *k64 = a.get_n<uint64_t>(nm2l);
-        int32_t *v32 = a.get_n<int32_t>(nm2l);
-        int32_t *ovf = a.get_n<int32_t>(1);
-        fill_i32(ovf, 0, 1, s);
-        hipLaunchKernelGGL(k_m2l_keys, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, k64, v32, ovf);
-        if (read_back(ovf, s)) fail(FMM_EUNSUPPORTED, "an M2L offset exceeds the key range");
-        {
-            unsigned long long *same = a.get_n<unsigned long long>(1);
-            HIP_CHECK(hipMemsetAsync(same, 0, 8, s));
-            hipLaunchKernelGGL(k_count_same_level, grid1(nm2l), 256, 0, s, (const uint64_t *)k64, nm2l, same);
-            P->nm2l_same = (int64_t)read_back(same, s);
-            a.put(same);
+        // target tiles
+        int32_t *is_t = a.get_n<int32_t>(nc);
+        fill_i32(is_t, 0, nc, s);
+        hipLaunchKernelGGL(k_mark_targets, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, is_t);
+        int32_t *cell_tile = a.get_n<int32_t>(nc), *cell_lane = a.get_n<int32_t>(nc);
+        std::vector<int32_t> btile;
+        int64_t ntiles = tile_cells(C, nc, is_t, true, a, s, P->tile_targets, cell_tile, cell_lane, btile, P->ntargets);
+        P->ntiles = ntiles;
+        a.put(is_t);
+        lg("m2l target tiles");
+
+        // distinct operator keys through a device hash table
+        uint64_t H = 1 << 15;
+        int32_t *flags = a.get_n<int32_t>(2);
+        uint64_t *table = nullptr;
+        std::vector<uint64_t> htab;
+        for (;;) {
+            table = a.get_n<uint64_t>((int64_t)H);
+            HIP_CHECK(hipMemsetAsync(table, 0xff, 8 * H, s));
+            fill_i32(flags, 0, 2, s);
+            hipLaunchKernelGGL(k_key_insert, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, table, H - 1, flags);
+            int32_t hf[2];
+            HIP_CHECK(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
+            htab.resize(H);
+            HIP_CHECK(hipMemcpyAsync(htab.data(), table, 8 * H, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            if (hf[0]) fail(FMM_EUNSUPPORTED, "an M2L offset exceeds the key range");
+            int64_t used = 0;
+            for (uint64_t v : htab) used += v != ~0ull;
+            if (!hf[1] && 2 * used <= (int64_t)H) break;
+            a.put(table);
+            H *= 4;
         }
-        radix_sort_u64(k64, v32, nm2l, 63, a, s);
-        int32_t *flag = a.get_n<int32_t>(nm2l), *ex = a.get_n<int32_t>(nm2l);
-        hipLaunchKernelGGL(k_flag_diff, grid1(nm2l), 256, 0, s, (const uint64_t *)k64, nm2l, 0, flag);
-        int64_t nkeys = exclusive_scan_i32(flag, ex, nm2l, a, s);
-        uint64_t *ukeys = a.get_n<uint64_t>(nkeys);
-        int32_t *pair_key = a.get_n<int32_t>(nm2l);
-        hipLaunchKernelGGL(k_unique_keys, grid1(nm2l), 256, 0, s, (const uint64_t *)k64, (const int32_t *)v32,
-                           (const int32_t *)flag, (const int32_t *)ex, nm2l, ukeys, pair_key);
-        std::vector<uint64_t> hkeys(nkeys);
-        HIP_CHECK(hipMemcpyAsync(hkeys.data(), ukeys, 8 * nkeys, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        a.put(k64); a.put(v32); a.put(ovf); a.put(flag); a.put(ex); a.put(ukeys);
+        std::vector<uint64_t> hkeys;
+        for (uint64_t v : htab)
+            if (v != ~0ull) hkeys.push_back(v);
+        std::sort(hkeys.begin(), hkeys.end());
+        const int64_t nkeys = (int64_t)hkeys.size();
+        std::vector<int32_t> hslot(H, -1);
+        for (uint64_t h = 0; h < H; ++h)
+            if (htab[h] != ~0ull) hslot[h] = (int32_t)(std::lower_bound(hkeys.begin(), hkeys.end(), htab[h]) - hkeys.begin());
         P->nkeys = nkeys;
         P->nkeys_same = 0;
         for (uint64_t kk : hkeys) P->nkeys_same += (int(kk >> 57) - 32) == 0;
@@ -682,73 +950,52 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             HIP_CHECK(hipMemcpyAsync(d16, p16.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
             P->key_f16 = d16;
         }
-        HIP_CHECK(hipStreamSynchronize(s));
+        int32_t *slot_id = a.get_n<int32_t>((int64_t)H);
+        HIP_CHECK(hipMemcpyAsync(slot_id, hslot.data(), 4 * H, hipMemcpyHostToDevice, s));
+        lg("m2l keys+operators");
 
-        // targets -> tiles of kTileN cells with the same level and octant, Morton order
-        int32_t *is_t = a.get_n<int32_t>(nc), *tex = a.get_n<int32_t>(nc);
-        fill_i32(is_t, 0, nc, s);
-        hipLaunchKernelGGL(k_mark_targets, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, is_t);
-        int64_t nt = exclusive_scan_i32(is_t, tex, nc, a, s);
-        P->ntargets = nt;
-        uint64_t *tk = a.get_n<uint64_t>(nt);
-        int32_t *tv = a.get_n<int32_t>(nt);
-        hipLaunchKernelGGL(k_target_keys, grid1(nc), 256, 0, s, (const int32_t *)is_t, (const int32_t *)tex, nc, C, tk, tv);
-        radix_sort_u64(tk, tv, nt, 40, a, s);
-        constexpr int kBuckets = (kMaxLevel + 1) * 8;
-        int32_t *bst = a.get_n<int32_t>(kBuckets);
-        fill_i32(bst, -1, kBuckets, s);
-        hipLaunchKernelGGL(k_bucket_starts, grid1(nt), 256, 0, s, (const uint64_t *)tk, nt, bst);
-        std::vector<int32_t> hb_start(kBuckets), hb_base(kBuckets, 0);
-        HIP_CHECK(hipMemcpyAsync(hb_start.data(), bst, 4 * kBuckets, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        int64_t ntiles = 0;
-        for (int b = 0; b < kBuckets; ++b) {
-            if (hb_start[b] < 0) continue;
-            int64_t end = nt;
-            for (int b2 = b + 1; b2 < kBuckets; ++b2)
-                if (hb_start[b2] >= 0) { end = hb_start[b2]; break; }
-            hb_base[b] = (int32_t)ntiles;
-            ntiles += (end - hb_start[b] + kTileN - 1) / kTileN;
-        }
-        P->ntiles = ntiles;
-        int32_t *tbase = a.get_n<int32_t>(kBuckets);
-        HIP_CHECK(hipMemcpyAsync(tbase, hb_base.data(), 4 * kBuckets, hipMemcpyHostToDevice, s));
-        int32_t *cell_tile = a.get_n<int32_t>(nc), *cell_lane = a.get_n<int32_t>(nc);
-        P->tile_targets = a.get_n<int32_t>(ntiles * kTileN);
-        fill_i32(P->tile_targets, -1, ntiles * kTileN, s);
-        hipLaunchKernelGGL(k_assign_tiles, grid1(nt), 256, 0, s, (const uint64_t *)tk, (const int32_t *)tv, nt,
-                           (const int32_t *)bst, (const int32_t *)tbase, cell_tile, cell_lane, P->tile_targets);
-        HIP_CHECK(hipStreamSynchronize(s));
-        a.put(is_t); a.put(tex); a.put(tk); a.put(tv); a.put(bst); a.put(tbase);
-
-        // pairs grouped by (tile, key, lane)
-        int key_bits = bits_for(nkeys);
-        int tile_bits = bits_for(ntiles);
-        if (key_bits + tile_bits + 6 > 64) fail(FMM_EUNSUPPORTED, "M2L grouping key exceeds 64 bits");
-        uint64_t *comp = a.get_n<uint64_t>(nm2l);
-        int32_t *src = a.get_n<int32_t>(nm2l);
-        hipLaunchKernelGGL(k_pair_composite, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pair_key,
-                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, key_bits, comp, src);
-        radix_sort_u64(comp, src, nm2l, key_bits + tile_bits + 6, a, s);
-        int32_t *eflag = a.get_n<int32_t>(nm2l), *eex = a.get_n<int32_t>(nm2l);
-        hipLaunchKernelGGL(k_flag_diff, grid1(nm2l), 256, 0, s, (const uint64_t *)comp, nm2l, 6, eflag);
-        int64_t ne = exclusive_scan_i32(eflag, eex, nm2l, a, s);
+        // (tile, key) entries: dense presence table, scanned tile-major
+        const int64_t ntk = ntiles * nkeys;
+        if (ntk >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "M2L tile x key table exceeds 2^31 entries");
+        int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk);
+        int32_t *pkid = a.get_n<int32_t>(nm2l);
+        fill_i32(present, 0, ntk, s);
+        hipLaunchKernelGGL(k_key_ids, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, (const uint64_t *)table, H - 1,
+                           (const int32_t *)slot_id, (const int32_t *)cell_tile, nkeys, pkid, present, flags);
+        const int64_t ne = exclusive_scan_i32(present, entry_of, ntk, a, s);
         P->nentries = ne;
         P->entry_key = a.get_n<int32_t>(ne);
         P->entry_src = a.get_n<int32_t>(ne * kTileN);
         fill_i32(P->entry_src, -1, ne * kTileN, s);
-        int32_t *tile_first = a.get_n<int32_t>(ntiles + 1);
-        P->m2l_pairs = a.get_n<int2>(nm2l);
-        hipLaunchKernelGGL(k_build_entries, grid1(nm2l), 256, 0, s, (const uint64_t *)comp, (const int32_t *)src,
-                           (const int32_t *)eflag, (const int32_t *)eex, nm2l, key_bits,
-                           (const int32_t *)P->tile_targets, P->entry_key, P->entry_src, tile_first, P->m2l_pairs);
+        int32_t *mask32 = a.get_n<int32_t>(ne);
+        fill_i32(mask32, 0, ne, s);
+        hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
+                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of, nkeys,
+                           P->entry_key, P->entry_src, mask32);
+        P->entry_mask = a.get_n<uint8_t>(ne);
+        hipLaunchKernelGGL(k_mask_narrow, grid1(ne), 256, 0, s, (const int32_t *)mask32, ne, P->entry_mask);
+        int32_t *tile_first = a.get_n<int32_t>(ntiles);
+        hipLaunchKernelGGL(k_tile_first, grid1(ntiles), 256, 0, s, (const int32_t *)entry_of, ntiles, nkeys, tile_first);
         std::vector<int32_t> htf(ntiles);
         HIP_CHECK(hipMemcpyAsync(htf.data(), tile_first, 4 * ntiles, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        a.put(comp); a.put(src); a.put(eflag); a.put(eex); a.put(tile_first); a.put(cell_tile); a.put(cell_lane);
-        a.put(pair_key);
-        a.put(m2l);
-        m2l = nullptr;
+        // M2L pairs between cells of the same level
+        {
+            std::vector<int32_t> hsame(nkeys);
+            for (int64_t k2 = 0; k2 < nkeys; ++k2) hsame[k2] = (int(hkeys[k2] >> 57) - 32) == 0;
+            int32_t *dsame = a.get_n<int32_t>(nkeys);
+            HIP_CHECK(hipMemcpyAsync(dsame, hsame.data(), 4 * nkeys, hipMemcpyHostToDevice, s));
+            unsigned long long *same = a.get_n<unsigned long long>(1);
+            HIP_CHECK(hipMemsetAsync(same, 0, 8, s));
+            hipLaunchKernelGGL(k_count_same_level, std::min(grid1(nm2l), 1024), 256, 0, s, (const int32_t *)pkid, nm2l,
+                               (const int32_t *)dsame, same);
+            P->nm2l_same = (int64_t)read_back(same, s);   // synchronises: host vectors above may go
+            a.put(same);
+            a.put(dsame);
+        }
+        a.put(flags); a.put(table); a.put(slot_id); a.put(present); a.put(entry_of); a.put(pkid);
+        a.put(tile_first); a.put(cell_tile); a.put(cell_lane); a.put(mask32);
+        lg("m2l entries");
+
         // work items: split each tile's entries so that there are enough items to fill the chip
         htf.push_back((int32_t)ne);
         int64_t per = std::max<int64_t>(kEntriesPerWork, (ne + 4095) / 4096);
@@ -777,18 +1024,22 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         HIP_CHECK(hipStreamSynchronize(s));
     }
 
+    lg("m2l work items");
     // ---- P2P lists
     {
         uint64_t *comp = a.get_n<uint64_t>(np2p);
         int32_t *dummy = a.get_n<int32_t>(np2p);
-        hipLaunchKernelGGL(k_p2p_composite, grid1(np2p), 256, 0, s, (const int2 *)p2p, np2p, comp, dummy);
-        radix_sort_u64(comp, dummy, np2p, 32 + bits_for(nc), a, s);
+        const int lbits = bits_for(P->nleaves);
+        hipLaunchKernelGGL(k_p2p_composite, grid1(np2p), 256, 0, s, (const int2 *)p2p, np2p, (const int32_t *)P->leaf_id,
+                           lbits, comp, dummy);
+        radix_sort_u64(comp, dummy, np2p, 2 * lbits, a, s);
         P->p2p_pairs = a.get_n<int2>(np2p);
         int32_t *pair_off = a.get_n<int32_t>(P->nleaves);
         unsigned long long *inter = a.get_n<unsigned long long>(1);
         HIP_CHECK(hipMemsetAsync(inter, 0, 8, s));
-        hipLaunchKernelGGL(k_p2p_csr, grid1(np2p), 256, 0, s, (const uint64_t *)comp, np2p, (const int32_t *)P->leaf_id,
-                           P->p2p_pairs, pair_off, (const int32_t *)P->c_count, inter);
+        hipLaunchKernelGGL(k_p2p_csr, std::min(grid1(np2p), 1024), 256, 0, s, (const uint64_t *)comp,
+                           (const int32_t *)dummy, np2p, lbits, (const int32_t *)P->leaves, P->p2p_pairs, pair_off,
+                           (const int32_t *)P->c_count, inter);
         P->p2p_interactions = (int64_t)read_back(inter, s);
         int32_t *nseg = a.get_n<int32_t>(P->nleaves);
         P->seg_off = a.get_n<int32_t>(P->nleaves + 1);
@@ -806,6 +1057,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         a.put(comp); a.put(dummy); a.put(pair_off); a.put(inter); a.put(nseg); a.put(p2p);
     }
 
+    lg("p2p lists");
     // ---- evaluation workspace
     const int KP = P->KP;
     P->M = a.get_n<float>(nc * KP);
@@ -816,6 +1068,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     P->near_phi = a.get_n<float>(n);
     P->near_grad = a.get_n<float>(3 * n);
     HIP_CHECK(hipStreamSynchronize(s));
+    lg("workspace");
 }
 
 }  // namespace fmm

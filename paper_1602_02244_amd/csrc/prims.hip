@@ -4,6 +4,9 @@
 
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 
 namespace fmm {
 
@@ -13,13 +16,73 @@ void check_hip(hipError_t e, const char *what) {
     if (e != hipSuccess) fail(FMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-void *Alloc::get(size_t nbytes) {
-    void *p = nullptr;
-    if (alloc) {
-        p = alloc(nbytes, (void *)stream, ctx);
-    } else {
-        if (hipMallocAsync(&p, nbytes, stream) != hipSuccess) p = nullptr;
+// Default device memory: a process-wide caching allocator.  Blocks come from
+// hipMalloc once and are kept; a block released while work may still be queued is
+// reused only by allocations on the same stream (stream order makes that safe);
+// blocks released after a synchronisation (plan destroy) serve any stream.
+namespace {
+struct Block {
+    void *p;
+    size_t size;
+    hipStream_t stream;
+    bool any_stream;
+    int dev;
+};
+std::mutex g_cache_mu;
+std::multimap<size_t, Block> g_free;                 // size -> free block
+std::unordered_map<void *, Block> g_used;            // pointer -> block
+
+size_t round_size(size_t n) {
+    if (n <= (1u << 20)) return (n + 511) & ~size_t(511);
+    return (n + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+}
+
+void *cache_get(size_t nbytes, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    size_t want = round_size(nbytes);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (auto it = g_free.lower_bound(want); it != g_free.end() && it->first <= want + want / 4; ++it) {
+            Block b = it->second;
+            if (b.dev != dev || !(b.any_stream || b.stream == s)) continue;
+            g_free.erase(it);
+            b.stream = s;
+            g_used[b.p] = b;
+            return b.p;
+        }
     }
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        // give cached blocks of this device back to the driver and retry once
+        (void)hipDeviceSynchronize();
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            for (auto it = g_free.begin(); it != g_free.end();) {
+                if (it->second.dev == dev) { (void)hipFree(it->second.p); it = g_free.erase(it); }
+                else ++it;
+            }
+        }
+        if (hipMalloc(&p, want) != hipSuccess) return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_used[p] = Block{p, want, s, false, dev};
+    return p;
+}
+
+void cache_put(void *p, bool synchronized) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_used.find(p);
+    if (it == g_used.end()) return;
+    Block b = it->second;
+    g_used.erase(it);
+    b.any_stream = synchronized;
+    g_free.emplace(b.size, b);
+}
+}  // namespace
+
+void *Alloc::get(size_t nbytes) {
+    void *p = alloc ? alloc(nbytes, (void *)stream, ctx) : cache_get(nbytes, stream);
     if (!p) fail(FMM_ENOMEM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
     live.push_back(p);
     bytes += (int64_t)nbytes;
@@ -30,8 +93,9 @@ void Alloc::put(void *p) {
     for (size_t i = 0; i < live.size(); ++i)
         if (live[i] == p) {
             if (release) release(p, (void *)stream, ctx);
-            else (void)hipFreeAsync(p, stream);
-            live.erase(live.begin() + (long)i);
+            else cache_put(p, false);
+            live[i] = live.back();
+            live.pop_back();
             return;
         }
 }
@@ -39,7 +103,7 @@ void Alloc::put(void *p) {
 void Alloc::release_all() {
     for (void *p : live) {
         if (release) release(p, (void *)stream, ctx);
-        else (void)hipFreeAsync(p, stream);
+        else cache_put(p, true);
     }
     live.clear();
 }
