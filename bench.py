@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-accuracy", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -61,6 +63,11 @@ def main():
     w = inputs.adjoint_weights(n)
     dev = torch.device("cuda:0")
     xt, qt, wt = (torch.from_numpy(a).to(dev) for a in (x, q, w))
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del src, dst
     torch.cuda.synchronize()
 
     def step(record):

@@ -1,0 +1,77 @@
+"""Full-size workloads, in the configuration the benchmark times.
+
+Each checks the GPU plan against the oracle's (exact counts or full identity), the
+GPU result against the FP64 oracle FMM on sampled targets (parity, 1e-5), and
+against the exact direct sum on sampled targets (FMM tolerance, 1e-4).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02244_amd import inputs
+from fmm_testlib import compare_plans, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def _check(name, theta=None, counts=None, full_plan_check=True, nsample=300):
+    from paper_1602_02244_amd import FMM
+    n0, dist, p, ncrit, th = inputs.WORKLOADS[name]
+    theta = th if theta is None else theta
+    x, q = inputs.workload(name)
+    n = x.shape[0]
+    plan = FMM(_dev(x), ncrit, p, theta)
+    phi, grad = plan.eval(_dev(q))
+    phi, grad = phi.cpu().numpy(), grad.cpu().numpy()
+    st = plan.stats()
+    ora = oracle.Plan(x.astype(np.float64), ncrit, theta)
+    assert (st["ncells"], st["m2l_pairs"], st["p2p_pairs"]) == (ora.ncells, ora.nm2l, ora.np2p)
+    if counts is not None:
+        assert (st["ncells"], st["m2l_pairs"], st["p2p_pairs"], st["m2l_keys_same_level"]) == counts
+    if full_plan_check:
+        compare_plans(plan.export(), ora)
+    samp = inputs.sample_targets(n, nsample)
+    ophi, ograd, _ = ora.eval(q.astype(np.float64), p, sample=samp)
+    e = (rel_l2(phi[samp], ophi), rel_l2(grad[samp], ograd))
+    dphi, dgrad = oracle.direct(x.astype(np.float64), q.astype(np.float64), samp)
+    d = (rel_l2(phi[samp], dphi), rel_l2(grad[samp], dgrad))
+    print(f"{name} theta={theta}: vs oracle {e[0]:.2e} {e[1]:.2e}; vs direct {d[0]:.2e} {d[1]:.2e}")
+    assert max(e) <= 1e-5
+    assert max(d) <= 1e-4
+    return st
+
+
+@pytest.mark.timeout(600)
+def test_uniform_1M_theta04():
+    # all leaves at level 5: 37,449 cells; 16,820,208 M2L pairs over 850 offsets; 2,421,064 near pairs
+    _check("uniform-1M", counts=(37449, 16820208, 2421064, 850))
+
+
+@pytest.mark.timeout(600)
+def test_uniform_1M_theta05_classical_lists():
+    # theta = 1/2 reproduces the classical interaction list: 316 distinct offsets
+    _check("uniform-1M", theta=0.5, counts=(37449, 6039504, 830584, 316))
+
+
+@pytest.mark.timeout(900)
+def test_sphere_4M_adaptive():
+    st = _check("sphere-4M", full_plan_check=True)
+    assert st["m2l_pairs_same_level"] < st["m2l_pairs"]       # uneven lists: mixed-level pairs occur
+    assert len([c for c in st["leaves_per_level"] if c > 0]) >= 3
+
+
+@pytest.mark.timeout(600)
+def test_plummer_1M_deep_tree():
+    st = _check("plummer-1M", full_plan_check=True)
+    assert st["max_level"] >= 7 and st["m2l_keys"] > st["m2l_keys_same_level"]
+
+
+@pytest.mark.timeout(1200)
+def test_uniform_16M_p12_fp32():
+    # 1.28M cells, ~4.5e8 M2L pairs: counts against the oracle, sampled parity
+    _check("uniform-16M", full_plan_check=False, nsample=100)
