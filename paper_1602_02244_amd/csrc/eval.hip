@@ -56,6 +56,40 @@ __device__ __forceinline__ void regular_harmonics(float x, float y, float z, flo
     }
 }
 
+// The same harmonics streamed to f(l, m, re, im) one column (fixed m, increasing l) at a
+// time, so that only the last two values of a column are live.
+template <int P, class F>
+__device__ __forceinline__ void stream_regular(float x, float y, float z, F &&f) {
+    const float r2 = x * x + y * y + z * z;
+    float mr = 1.f, mi = 0.f;                   // R_mm
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            const float c = -1.f / (2.f * m);
+            const float nr = c * (x * mr - y * mi), ni = c * (x * mi + y * mr);
+            mr = nr;
+            mi = ni;
+        }
+        f(m, m, mr, mi);
+        if (m < P) {
+            float pr = mr, pi = mi;             // R_{l-1,m}
+            float cr = z * mr, ci = z * mi;     // R_{m+1,m}
+            f(m + 1, m, cr, ci);
+#pragma unroll
+            for (int l = m + 1; l < P; ++l) {
+                const float den = 1.f / (float)((l + m + 1) * (l - m + 1));
+                const float c1 = (2 * l + 1) * den;
+                const float nr = c1 * z * cr - den * r2 * pr, ni = c1 * z * ci - den * r2 * pi;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+                f(l + 1, m, cr, ci);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -78,23 +112,28 @@ struct Geo {
 };
 
 // ------------------------------------------------------------------ P2M
-// One wave per leaf: each lane evaluates the harmonics of one body and writes
-// q conj(R) into an LDS column; lanes then own coefficients and sum their row.
+// Two leaves per wave, one per half-wave.  Each lane evaluates the harmonics of one
+// body (streamed) and writes q conj(R) into an LDS column; lanes then own
+// coefficients and sum their row over the bodies.
 template <int P>
-__global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, Geo g, const float4 *bodies, float *M) {
+__global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, int64_t nleaves, Geo g, const float4 *bodies,
+                                            float *M) {
     using D = Dims<P>;
-    constexpr int NR = (D::KP + 63) / 64;
-    __shared__ float sc[D::NC][65];
-    const int c = leaves[blockIdx.x];
-    const int lane = threadIdx.x;
-    const int s = g.start[c], n = g.count[c];
+    constexpr int NR = (D::KP + 31) / 32;
+    __shared__ float sc[2][D::NC][33];
+    const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+    const int64_t li = 2 * (int64_t)blockIdx.x + half;
+    const bool has = li < nleaves;
+    const int c = leaves[has ? li : 0];
+    const int s = g.start[c], n = has ? g.count[c] : 0;
     double cx, cy, cz, inv;
     cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
+    const int nmax = max(n, __shfl_xor(n, 32, 64));
     float acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = 0.f;
-    for (int base = 0; base < n; base += 64) {
-        const int j = base + lane;
+    for (int base = 0; base < nmax; base += 32) {
+        const int j = base + hl;
         float ux = 0.f, uy = 0.f, uz = 0.f, q = 0.f;
         if (j < n) {
             float4 b = bodies[s + j];
@@ -103,37 +142,32 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, Geo g, const 
             uz = (float)(((double)b.z - cz) * inv);
             q = b.w;
         }
-        float Rr[D::NT], Ri[D::NT];
-        regular_harmonics<P>(ux, uy, uz, Rr, Ri);
         __syncthreads();
-#pragma unroll
-        for (int l = 0; l <= P; ++l) {
-#pragma unroll
-            for (int m = 0; m <= l; ++m) {
-                // Mt_lm = sum q conj(R_lm(u))
-                if (m == 0) {
-                    sc[l * l][lane] = q * Rr[TRI(l, 0)];
-                } else {
-                    sc[l * l + 2 * m - 1][lane] = q * Rr[TRI(l, m)];
-                    sc[l * l + 2 * m][lane] = -q * Ri[TRI(l, m)];
-                }
+        // Mt_lm = sum q conj(R_lm(u))
+        stream_regular<P>(ux, uy, uz, [&](int l, int m, float re, float im) {
+            if (m == 0) {
+                sc[half][l * l][hl] = q * re;
+            } else {
+                sc[half][l * l + 2 * m - 1][hl] = q * re;
+                sc[half][l * l + 2 * m][hl] = -q * im;
             }
-        }
+        });
         __syncthreads();
-        const int cnt = min(64, n - base);
+        const int cnt = min(32, n - base);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int d = r * 64 + lane;
+            const int d = r * 32 + hl;
             if (d < D::NC) {
                 float t = 0.f;
-                for (int i = 0; i < cnt; ++i) t += sc[d][i];
+                for (int i = 0; i < cnt; ++i) t += sc[half][d][i];
                 acc[r] += t;
             }
         }
     }
+    if (!has) return;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int d = r * 64 + lane;
+        const int d = r * 32 + hl;
         if (d < D::KP) M[(int64_t)c * D::KP + d] = d < D::NC ? acc[r] : 0.f;
     }
 }
@@ -266,8 +300,8 @@ __global__ void __launch_bounds__(256) k_gemm(const int4 *work, const int32_t *e
 }
 
 // Sum the partial tiles of split work items into L (fixed order: deterministic).
-__global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int4 *work, const float *partial,
-                             const int32_t *tile_targets, int KP, float *L) {
+__global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int32_t *tile_work_idx, const int4 *work,
+                             const float *partial, const int32_t *tile_targets, int KP, float *L) {
     const int64_t t = blockIdx.x;
     const int w0 = tile_work[t], w1 = tile_work[t + 1];
     if (w1 - w0 < 2) return;
@@ -276,7 +310,8 @@ __global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int
         const int tg = tile_targets[t * kTileN + col];
         if (tg < 0) continue;
         float s = 0.f;
-        for (int wi = w0; wi < w1; ++wi) s += partial[((int64_t)(work[wi].w - 1) * kTileN + col) * KP + row];
+        for (int wi = w0; wi < w1; ++wi)
+            s += partial[((int64_t)(work[tile_work_idx[wi]].w - 1) * kTileN + col) * KP + row];
         L[(int64_t)tg * KP + row] = s;
     }
 }
@@ -297,16 +332,17 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
     cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
     const float finv = (float)inv;
     // coefficient (j, m) of the local expansion, m >= -1
+    const float *vL = sL;
     auto lre = [&](int j, int m) -> float {
         if (m > j) return 0.f;
-        if (m == 0) return sL[j * j];
-        if (m > 0) return sL[j * j + 2 * m - 1];
-        return -sL[j * j + 1];                  // L_{j,-1} = -conj(L_{j,1})
+        if (m == 0) return vL[j * j];
+        if (m > 0) return vL[j * j + 2 * m - 1];
+        return -vL[j * j + 1];                  // L_{j,-1} = -conj(L_{j,1})
     };
     auto lim = [&](int j, int m) -> float {
         if (m > j || m == 0) return 0.f;
-        if (m > 0) return sL[j * j + 2 * m];
-        return sL[j * j + 2];
+        if (m > 0) return vL[j * j + 2 * m];
+        return vL[j * j + 2];
     };
     for (int base = 0; base < n; base += 64) {
         const int j = base + lane;
@@ -315,29 +351,22 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
         const float ux = (float)(((double)b.x - cx) * inv);
         const float uy = (float)(((double)b.y - cy) * inv);
         const float uz = (float)(((double)b.z - cz) * inv);
-        float Rr[D::NT], Ri[D::NT];
-        regular_harmonics<P>(ux, uy, uz, Rr, Ri);
         float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-#pragma unroll
-        for (int l = 0; l <= P; ++l) {
-#pragma unroll
-            for (int m = 0; m <= l; ++m) {
-                const float wgt = m == 0 ? 1.f : 2.f;
-                const float rr = Rr[TRI(l, m)], ri = Ri[TRI(l, m)];
-                f += wgt * (lre(l, m) * rr + lim(l, m) * ri);
-                if (l < P) {
-                    // gradient coefficients of degree l from the local coefficients of degree l+1
-                    const float zr = lre(l + 1, m), zi = lim(l + 1, m);
-                    const float pr = lre(l + 1, m + 1), pi = lim(l + 1, m + 1);
-                    const float mr = lre(l + 1, m - 1), mi = lim(l + 1, m - 1);
-                    const float xr = 0.5f * (mr - pr), xi = 0.5f * (mi - pi);
-                    const float yr = -0.5f * (pi + mi), yi = 0.5f * (pr + mr);
-                    gx += wgt * (xr * rr + xi * ri);
-                    gy += wgt * (yr * rr + yi * ri);
-                    gz += wgt * (zr * rr + zi * ri);
-                }
+        stream_regular<P>(ux, uy, uz, [&](int l, int m, float rr, float ri) {
+            const float wgt = m == 0 ? 1.f : 2.f;
+            f += wgt * (lre(l, m) * rr + lim(l, m) * ri);
+            if (l < P) {
+                // gradient coefficients of degree l from the local coefficients of degree l+1
+                const float zr = lre(l + 1, m), zi = lim(l + 1, m);
+                const float pr = lre(l + 1, m + 1), pi = lim(l + 1, m + 1);
+                const float mr = lre(l + 1, m - 1), mi = lim(l + 1, m - 1);
+                const float xr = 0.5f * (mr - pr), xi = 0.5f * (mi - pi);
+                const float yr = -0.5f * (pi + mi), yi = 0.5f * (pr + mr);
+                gx += wgt * (xr * rr + xi * ri);
+                gy += wgt * (yr * rr + yi * ri);
+                gz += wgt * (zr * rr + zi * ri);
             }
-        }
+        });
         const int64_t o = s + j;
         phi[o] = f * finv;
         const float g2 = finv * finv;
@@ -486,8 +515,8 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     using D = Dims<P>;
     const OpTables &T = op_tables(P);
     ev_rec(Pl, 2 * PH_P2M, s);
-    hipLaunchKernelGGL(k_p2m<P>, (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g,
-                       (const float4 *)Pl->bodies, Pl->M);
+    hipLaunchKernelGGL(k_p2m<P>, (int)((Pl->nleaves + 1) / 2), 64, 0, s, (const int32_t *)Pl->leaves, Pl->nleaves,
+                       g, (const float4 *)Pl->bodies, Pl->M);
     ev_rec(Pl, 2 * PH_P2M + 1, s);
     ev_rec(Pl, 2 * PH_M2M, s);
     for (int l = Pl->max_level - 1; l >= 0; --l) {
@@ -510,8 +539,8 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     ev_rec(Pl, 2 * PH_L2L, s);
     if (Pl->npartial > 0)
         hipLaunchKernelGGL(k_m2l_reduce, (int)Pl->ntiles, 256, 0, s, Pl->ntiles, (const int32_t *)Pl->tile_work,
-                           (const int4 *)Pl->work, (const float *)Pl->partial, (const int32_t *)Pl->tile_targets, D::KP,
-                           Pl->L);
+                           (const int32_t *)Pl->tile_work_idx, (const int4 *)Pl->work, (const float *)Pl->partial,
+                           (const int32_t *)Pl->tile_targets, D::KP, Pl->L);
     for (int l = 1; l <= Pl->max_level; ++l) {
         const int t0 = Pl->l2l.bucket_tile[l * 8], t1 = Pl->l2l.bucket_tile[l * 8 + 8];
         if (t1 > t0)

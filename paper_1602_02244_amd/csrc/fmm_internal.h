@@ -146,7 +146,8 @@ struct fmm_plan_s {
     uint8_t *entry_mask = nullptr;       // [nentries] bit b: column block b (lanes 16b..16b+15) has a source
     int4 *work = nullptr;                // [nwork] (tile, entry begin, entry end, partial slot + 1 or 0 = direct)
     int64_t npartial = 0;                // work items that write a partial tile
-    int32_t *tile_work = nullptr;        // [ntiles + 1] work item range of each tile
+    int32_t *tile_work = nullptr;        // [ntiles + 1] range of each tile in tile_work_idx
+    int32_t *tile_work_idx = nullptr;    // [nwork] work items of each tile
     int64_t nkeys_same = 0, nm2l_same = 0;
     LevelGemm m2m, l2l;
 

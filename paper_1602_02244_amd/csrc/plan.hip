@@ -996,30 +996,51 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         a.put(tile_first); a.put(cell_tile); a.put(cell_lane); a.put(mask32);
         lg("m2l entries");
 
-        // work items: split each tile's entries so that there are enough items to fill the chip
+        // work items: split each tile's entries into pieces so that there are enough items
+        // to fill the chip.  Items are ordered piece-major: the workgroups in flight work
+        // on the same part of the key range (entries are key-sorted inside a tile), so the
+        // operators they stream stay in L2.
         htf.push_back((int32_t)ne);
-        int64_t per = std::max<int64_t>(kEntriesPerWork, (ne + 4095) / 4096);
-        std::vector<int4> hw;
-        std::vector<int32_t> htw(ntiles + 1);
-        int64_t nsplit = 0;
+        int64_t piece = kEntriesPerWork, items = 4096;   // tuning knobs, overridable from the environment
+        if (const char *ev = getenv("FMM_M2L_PIECE")) piece = std::max<int64_t>(1, atoll(ev));
+        if (const char *ev = getenv("FMM_M2L_ITEMS")) items = std::max<int64_t>(1, atoll(ev));
+        int64_t per = std::max<int64_t>(piece, (ne + items - 1) / items);
+        std::vector<std::vector<int4>> pieces;      // pieces[k]: the k-th piece of every tile
+        std::vector<int32_t> npieces(ntiles);
         for (int64_t t = 0; t < ntiles; ++t) {
-            htw[t] = (int32_t)hw.size();
             int64_t e0 = htf[t], e1 = htf[t + 1];
             int64_t cntE = e1 - e0;
             int64_t chunks = std::max<int64_t>(1, (cntE + per - 1) / per);
             int64_t sz = (cntE + chunks - 1) / chunks;
-            for (int64_t c0 = e0; c0 < e1; c0 += sz) {
-                int slot = 0;
-                if (chunks > 1) slot = (int)(++nsplit);
-                hw.push_back(make_int4((int)t, (int)c0, (int)std::min(e1, c0 + sz), slot));
+            int k2 = 0;
+            for (int64_t c0 = e0; c0 < e1; c0 += sz, ++k2) {
+                if ((int)pieces.size() <= k2) pieces.emplace_back();
+                pieces[k2].push_back(make_int4((int)t, (int)c0, (int)std::min(e1, c0 + sz), chunks > 1 ? 1 : 0));
             }
+            npieces[t] = k2;
         }
-        htw[ntiles] = (int32_t)hw.size();
+        std::vector<int4> hw;
+        std::vector<std::vector<int32_t>> per_tile(ntiles);
+        int64_t nsplit = 0;
+        for (auto &pc : pieces)
+            for (int4 w4 : pc) {
+                if (w4.w) w4.w = (int)(++nsplit);
+                per_tile[w4.x].push_back((int32_t)hw.size());
+                hw.push_back(w4);
+            }
+        std::vector<int32_t> htw(ntiles + 1), htwi;
+        for (int64_t t = 0; t < ntiles; ++t) {
+            htw[t] = (int32_t)htwi.size();
+            htwi.insert(htwi.end(), per_tile[t].begin(), per_tile[t].end());
+        }
+        htw[ntiles] = (int32_t)htwi.size();
         P->nwork = (int64_t)hw.size();
         P->work = a.get_n<int4>(P->nwork);
         P->tile_work = a.get_n<int32_t>(ntiles + 1);
+        P->tile_work_idx = a.get_n<int32_t>(P->nwork);
         HIP_CHECK(hipMemcpyAsync(P->work, hw.data(), sizeof(int4) * hw.size(), hipMemcpyHostToDevice, s));
         HIP_CHECK(hipMemcpyAsync(P->tile_work, htw.data(), 4 * (ntiles + 1), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(P->tile_work_idx, htwi.data(), 4 * P->nwork, hipMemcpyHostToDevice, s));
         P->npartial = nsplit;
         HIP_CHECK(hipStreamSynchronize(s));
     }
