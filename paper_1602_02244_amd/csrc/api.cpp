@@ -169,7 +169,6 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
     if (!std::isfinite(theta) || !(theta > 0.f) || !(3.0 * (double)theta * (double)theta < 1.0))
         return set_err(FMM_EINVAL, "theta must be in (0, 1/sqrt(3))");
     if (prec != FMM_PREC_FP32 && prec != FMM_PREC_MIXED) return set_err(FMM_EINVAL, "unknown precision");
-    if (prec == FMM_PREC_MIXED) return set_err(FMM_EUNSUPPORTED, "mixed precision is not available in this build");
     fmm_plan_s *P = new (std::nothrow) fmm_plan_s();
     if (!P) return set_err(FMM_ENOMEM, "host allocation failed");
     P->n = n;

@@ -299,6 +299,214 @@ __global__ void __launch_bounds__(256) k_gemm(const int4 *work, const int32_t *e
     }
 }
 
+// ------------------------------------------------------------------ M2L, split FP16 on MFMA
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+
+// Once per evaluation: every cell's multipole vector, normalised by nu (|nu_lm R_lm| <= 1)
+// and by a power of two per cell (largest value in [1, 2)), split into FP16 hi + lo.
+template <int P>
+__global__ void __launch_bounds__(64) k_split_m(const float *M, const float *nu, _Float16 *Mh, _Float16 *Ml,
+                                                float *sinv) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP;
+    constexpr int NR = (KP + 63) / 64;
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    float v[NR];
+    float m = 0.f;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int d = r * 64 + lane;
+        v[r] = d < KP ? M[c * KP + d] * nu[d] : 0.f;
+        m = fmaxf(m, fabsf(v[r]));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    const float sc = m > 0.f ? exp2f(-floorf(log2f(m))) : 1.f;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int d = r * 64 + lane;
+        if (d < KP) {
+            const float x = v[r] * sc;
+            const _Float16 h = (_Float16)x;
+            Mh[c * KP + d] = h;
+            Ml[c * KP + d] = (_Float16)(x - (float)h);
+        }
+    }
+    if (lane == 0) sinv[c] = 1.f / sc;
+}
+
+// Mixed-precision M2L.  Each operator is stored as diag(rs) (H + Lo) acting on the
+// normalised multipoles (H, Lo in FP16, rs powers of two).  Per entry the split
+// multipoles of the 64 sources are copied to LDS, the product is taken as
+// H hi + H lo + Lo hi on v_mfma_f32_16x16x32_f16 with FP32 accumulation, and the entry's
+// result is scaled back (rows by rs, columns by the source's inverse scale) and added in
+// FP32.  Tiling, work items and outputs are those of k_gemm.
+template <int P>
+__global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+                                                 const uint8_t *entry_mask, const uint64_t *key_ptr,
+                                                 const _Float16 *Mh, const _Float16 *Ml, const float *sinv, float *L,
+                                                 float *partial, const int32_t *tile_targets) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP;
+    constexpr int KPH = KP + 8;                  // LDS row stride in halves
+    constexpr int NRB = KP / 16;
+    constexpr int RBW = (NRB + 3) / 4;
+    constexpr int NK32 = KP / 32;                // k steps of 32
+    constexpr bool TAIL16 = (KP % 32) != 0;      // one k step of 16 at the end
+    constexpr int NQ = KP / 8;                   // 16-byte pieces (8 halves) per vector
+    constexpr int NPF = (kTileN * NQ + 255) / 256;
+    __shared__ __attribute__((aligned(16))) _Float16 Bh[kTileN * KPH];
+    __shared__ __attribute__((aligned(16))) _Float16 Bl[kTileN * KPH];
+    __shared__ float colinv[kTileN];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int4 w = work[blockIdx.x];
+    floatx4 acc[RBW][4];
+#pragma unroll
+    for (int r = 0; r < RBW; ++r)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    float4 ph[NPF], pl[NPF];
+    float pinv = 0.f;
+    auto gather = [&](int e) {
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int idx = tid + 256 * i;
+            ph[i] = pl[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (idx < kTileN * NQ) {
+                const int col = idx / NQ, q = idx % NQ;
+                const int src = entry_src[(int64_t)e * kTileN + col];
+                if (src >= 0) {
+                    ph[i] = reinterpret_cast<const float4 *>(Mh + (int64_t)src * KP)[q];
+                    pl[i] = reinterpret_cast<const float4 *>(Ml + (int64_t)src * KP)[q];
+                }
+            }
+        }
+        if (tid < kTileN) {
+            const int src = entry_src[(int64_t)e * kTileN + tid];
+            pinv = src >= 0 ? sinv[src] : 0.f;
+        }
+    };
+    if (w.y < w.z) gather(w.y);
+    for (int e = w.y; e < w.z; ++e) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int idx = tid + 256 * i;
+            if (idx < kTileN * NQ) {
+                const int col = idx / NQ, q = idx % NQ;
+                *reinterpret_cast<float4 *>(&Bh[col * KPH + 8 * q]) = ph[i];
+                *reinterpret_cast<float4 *>(&Bl[col * KPH + 8 * q]) = pl[i];
+            }
+        }
+        if (tid < kTileN) colinv[tid] = pinv;
+        __syncthreads();
+        const char *base = reinterpret_cast<const char *>(key_ptr[entry_key[e]]);
+        const _Float16 *H = reinterpret_cast<const _Float16 *>(base);
+        const _Float16 *Lo = H + KP * KP;
+        const float *rs = reinterpret_cast<const float *>(Lo + KP * KP);
+        const int mask = entry_mask ? (int)entry_mask[e] : 15;
+        if (e + 1 < w.z) gather(e + 1);
+        floatx4 tmp[RBW][4];
+#pragma unroll
+        for (int r = 0; r < RBW; ++r)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) tmp[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < NK32; ++kc) {
+            half8 ah[RBW], al[RBW];
+#pragma unroll
+            for (int r = 0; r < RBW; ++r) {
+                const int rb = wave + 4 * r;
+                if (rb < NRB) {
+                    const int64_t off = (int64_t)(rb * 16 + li) * KP + kc * 32 + 8 * lg;
+                    ah[r] = *reinterpret_cast<const half8 *>(H + off);
+                    al[r] = *reinterpret_cast<const half8 *>(Lo + off);
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                if (!((mask >> cb) & 1)) continue;
+                const int boff = (cb * 16 + li) * KPH + kc * 32 + 8 * lg;
+                const half8 bh = *reinterpret_cast<const half8 *>(&Bh[boff]);
+                const half8 bl = *reinterpret_cast<const half8 *>(&Bl[boff]);
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) {
+                    if (wave + 4 * r >= NRB) continue;
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bh, tmp[r][cb], 0, 0, 0);
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bl, tmp[r][cb], 0, 0, 0);
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], bh, tmp[r][cb], 0, 0, 0);
+                }
+            }
+        }
+        if (TAIL16) {
+            constexpr int k0 = NK32 * 32;
+            half4 ah[RBW], al[RBW];
+#pragma unroll
+            for (int r = 0; r < RBW; ++r) {
+                const int rb = wave + 4 * r;
+                if (rb < NRB) {
+                    const int64_t off = (int64_t)(rb * 16 + li) * KP + k0 + 4 * lg;
+                    ah[r] = *reinterpret_cast<const half4 *>(H + off);
+                    al[r] = *reinterpret_cast<const half4 *>(Lo + off);
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                if (!((mask >> cb) & 1)) continue;
+                const int boff = (cb * 16 + li) * KPH + k0 + 4 * lg;
+                const half4 bh = *reinterpret_cast<const half4 *>(&Bh[boff]);
+                const half4 bl = *reinterpret_cast<const half4 *>(&Bl[boff]);
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) {
+                    if (wave + 4 * r >= NRB) continue;
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[r], bh, tmp[r][cb], 0, 0, 0);
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[r], bl, tmp[r][cb], 0, 0, 0);
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(al[r], bh, tmp[r][cb], 0, 0, 0);
+                }
+            }
+        }
+        // back to the FP32 basis: rows by rs, columns by the source's inverse scale
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+            const int rb = wave + 4 * r;
+            if (rb >= NRB) continue;
+            const float4 r4 = *reinterpret_cast<const float4 *>(rs + rb * 16 + 4 * lg);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                if (!((mask >> cb) & 1)) continue;
+                const float ci = colinv[cb * 16 + li];
+                acc[r][cb][0] += r4.x * ci * tmp[r][cb][0];
+                acc[r][cb][1] += r4.y * ci * tmp[r][cb][1];
+                acc[r][cb][2] += r4.z * ci * tmp[r][cb][2];
+                acc[r][cb][3] += r4.w * ci * tmp[r][cb][3];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+        const int rb = wave + 4 * r;
+        if (rb >= NRB) continue;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int col = cb * 16 + li;
+            float *dst;
+            if (w.w == 0) {
+                const int t = tile_targets[(int64_t)w.x * kTileN + col];
+                if (t < 0) continue;
+                dst = L + (int64_t)t * KP;
+            } else {
+                dst = partial + ((int64_t)(w.w - 1) * kTileN + col) * KP;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[rb * 16 + 4 * lg + v] = acc[r][cb][v];
+        }
+    }
+}
+
 // Sum the partial tiles of split work items into L (fixed order: deterministic).
 __global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int32_t *tile_work_idx, const int4 *work,
                              const float *partial, const int32_t *tile_targets, int KP, float *L) {
@@ -314,6 +522,115 @@ __global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int
             s += partial[((int64_t)(work[tile_work_idx[wi]].w - 1) * kTileN + col) * KP + row];
         L[(int64_t)tg * KP + row] = s;
     }
+}
+
+// ------------------------------------------------------------------ FP64 root levels (mixed precision)
+// Cells [0, nroot) are the cells of the root levels (cells are numbered level by level).
+// Their multipole and local coefficients are accumulated in FP64 (Md, Ld) by one tiled
+// FP64 GEMM kernel, with FP64 operators stored transposed ([KP in][KP out]); it serves
+// the root M2M (targets: parents, entries: child octants), the root M2L (targets: root
+// cells of the M2L tiles) and the root L2L (targets: same-octant cells, source: parent;
+// ADD accumulates onto the M2L result).  A source below the root levels is read from
+// the FP32 array and widened.
+// 256 threads: thread (rt = tid % 32, ct = tid / 32) owns rows rt*4 + v + 128 i and
+// columns ct*8 .. ct*8 + 7 of the KP x 64 output tile.
+template <int P, bool ADD>
+__global__ void __launch_bounds__(256) k_gemm64(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+                                                const uint64_t *key_ptr64, int64_t nroot, const float *in32,
+                                                const double *in64, double *out, double *partial,
+                                                const int32_t *tile_targets) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP;
+    constexpr int RI = (KP + 127) / 128;
+    __shared__ __attribute__((aligned(16))) double B[KP * kTileN];   // [k][col]
+    const int tid = threadIdx.x, rt = tid & 31, ct = tid >> 5;
+    const int4 w = work[blockIdx.x];
+    double acc[RI][4][8];
+#pragma unroll
+    for (int i = 0; i < RI; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[i][v][c] = 0.0;
+    for (int e = w.y; e < w.z; ++e) {
+        __syncthreads();
+        for (int idx = tid; idx < kTileN * KP; idx += 256) {
+            const int col = idx / KP, k = idx % KP;
+            const int src = entry_src[(int64_t)e * kTileN + col];
+            double v = 0.0;
+            if (src >= 0) v = src < nroot ? in64[(int64_t)src * KP + k] : (double)in32[(int64_t)src * KP + k];
+            B[k * kTileN + col] = v;
+        }
+        __syncthreads();
+        const double *T = reinterpret_cast<const double *>(key_ptr64[entry_key[e]]);
+        for (int k = 0; k < D::NC; ++k) {
+            double b[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) b[c] = B[k * kTileN + ct * 8 + c];
+#pragma unroll
+            for (int i = 0; i < RI; ++i) {
+                const int r0 = rt * 4 + 128 * i;
+                if (r0 >= KP) continue;
+                const double4 a = *reinterpret_cast<const double4 *>(T + (int64_t)k * KP + r0);
+                const double av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc[i][v][c] += av[v] * b[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int col = ct * 8 + c;
+        double *dst;
+        if (w.w == 0) {
+            const int t = tile_targets[(int64_t)w.x * kTileN + col];
+            if (t < 0) continue;
+            dst = out + (int64_t)t * KP;
+        } else {
+            dst = partial + ((int64_t)(w.w - 1) * kTileN + col) * KP;
+        }
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const int r0 = rt * 4 + 128 * i;
+            if (r0 >= KP) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (ADD && w.w == 0) dst[r0 + v] += acc[i][v][c];
+                else dst[r0 + v] = acc[i][v][c];
+            }
+        }
+    }
+}
+
+// Partial tiles of the root M2L summed into Ld; blockIdx.y splits the outputs.
+__global__ void k_m2l64_reduce(int64_t ntiles, const int32_t *tile_work, const int32_t *tile_work_idx, const int4 *work,
+                               const double *partial, const int32_t *tile_targets, int KP, double *Ld) {
+    const int64_t t = blockIdx.x;
+    const int w0 = tile_work[t], w1 = tile_work[t + 1];
+    if (w1 - w0 < 2) return;
+    for (int idx = blockIdx.y * blockDim.x + threadIdx.x; idx < kTileN * KP; idx += gridDim.y * blockDim.x) {
+        const int col = idx / KP, row = idx % KP;
+        const int tg = tile_targets[t * kTileN + col];
+        if (tg < 0) continue;
+        double s = 0.0;
+        for (int wi = w0; wi < w1; ++wi)
+            s += partial[((int64_t)(work[tile_work_idx[wi]].w - 1) * kTileN + col) * KP + row];
+        Ld[(int64_t)tg * KP + row] = s;
+    }
+}
+
+// Root leaves take their FP32 P2M result into Md (before the root M2M).
+__global__ void k_root_leaves_to64(int64_t nroot, int KP, const int32_t *nchild, const float *M, double *Md) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nroot * KP; i += (int64_t)gridDim.x * blockDim.x)
+        if (nchild[i / KP] == 0) Md[i] = (double)M[i];
+}
+
+// FP32 copies of the root cells' FP64 coefficients.
+__global__ void k_root_to32(int64_t nroot, int KP, const double *in, float *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nroot * KP; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
 }
 
 // ------------------------------------------------------------------ L2P
@@ -399,11 +716,40 @@ __device__ __forceinline__ void p2p_batch(const float4 *src, int ns, int g, int 
     }
 }
 
+// Compensated accumulation: sums over blocks of 16 sources are added to (hi, lo) pairs
+// with Knuth's TwoSum, so the rounding error of the running sum is carried in lo.
+struct Comp4 {
+    float h[4] = {0.f, 0.f, 0.f, 0.f}, l[4] = {0.f, 0.f, 0.f, 0.f};
+    __device__ __forceinline__ void add(int i, float b) {
+        const float s = h[i] + b;
+        const float bb = s - h[i];
+        const float err = (h[i] - (s - bb)) + (b - bb);
+        h[i] = s;
+        l[i] += err;
+    }
+};
+
+template <bool CHECK>
+__device__ __forceinline__ void p2p_batch_comp(const float4 *src, int ns, int g, int G, float xi, float yi, float zi,
+                                               Comp4 &c) {
+    for (int j0 = g; j0 < ns; j0 += 16 * G) {
+        float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        const int j1 = min(ns, j0 + 16 * G);
+        p2p_batch<CHECK>(src + j0 - g, j1 - (j0 - g), g, G, xi, yi, zi, f, gx, gy, gz);
+        c.add(0, f);
+        c.add(1, gx);
+        c.add(2, gy);
+        c.add(3, gz);
+    }
+}
+
+template <bool COMP>
 __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, const int32_t *c_start, const int32_t *c_count,
                                                      const int32_t *seg_off, const int2 *segs, const float4 *bodies,
                                                      float *out_phi, float *out_grad) {
     __shared__ float4 src[kP2PBatch];
     __shared__ float4 red[kP2PThreads];
+    __shared__ float4 redl[COMP ? kP2PThreads : 1];
     const int li = blockIdx.x;
     const int c = leaves[li];
     const int ts = c_start[c], tn = c_count[c];
@@ -420,13 +766,17 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, cons
             xi = b.x; yi = b.y; zi = b.z;
         }
         float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        Comp4 cmp;
         // the target leaf itself: skip j == i and coincident points
         for (int s0 = 0; s0 < tn; s0 += kP2PBatch) {
             const int ns = min(kP2PBatch, tn - s0);
             __syncthreads();
             for (int i = tid; i < ns; i += kP2PThreads) src[i] = bodies[ts + s0 + i];
             __syncthreads();
-            if (active) p2p_batch<true>(src, ns, g, G, xi, yi, zi, f, gx, gy, gz);
+            if (active) {
+                if (COMP) p2p_batch_comp<true>(src, ns, g, G, xi, yi, zi, cmp);
+                else p2p_batch<true>(src, ns, g, G, xi, yi, zi, f, gx, gy, gz);
+            }
         }
         // neighbouring leaves, batched through LDS
         int pos = 0;
@@ -442,23 +792,46 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, cons
                 cnt -= take;
                 if (pos == kP2PBatch) {
                     __syncthreads();
-                    if (active) p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
+                    if (active) {
+                        if (COMP) p2p_batch_comp<false>(src, pos, g, G, xi, yi, zi, cmp);
+                        else p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
+                    }
                     pos = 0;
                 }
             }
         }
         if (pos > 0) {
             __syncthreads();
-            if (active) p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
+            if (active) {
+                if (COMP) p2p_batch_comp<false>(src, pos, g, G, xi, yi, zi, cmp);
+                else p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
+            }
         }
         __syncthreads();
-        red[tid] = make_float4(f, gx, gy, gz);
+        if (COMP) {
+            red[tid] = make_float4(cmp.h[0], cmp.h[1], cmp.h[2], cmp.h[3]);
+            redl[tid] = make_float4(cmp.l[0], cmp.l[1], cmp.l[2], cmp.l[3]);
+        } else {
+            red[tid] = make_float4(f, gx, gy, gz);
+        }
         __syncthreads();
         if (tid < nt) {
             float4 acc = red[tid];
-            for (int gg = 1; gg < G; ++gg) {
-                float4 v = red[gg * nt + tid];
-                acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            if (COMP) {
+                Comp4 tot;
+                float lsum[4] = {0.f, 0.f, 0.f, 0.f};
+                for (int gg = 0; gg < G; ++gg) {
+                    const float4 v = red[gg * nt + tid], vl = redl[gg * nt + tid];
+                    tot.add(0, v.x); tot.add(1, v.y); tot.add(2, v.z); tot.add(3, v.w);
+                    lsum[0] += vl.x; lsum[1] += vl.y; lsum[2] += vl.z; lsum[3] += vl.w;
+                }
+                acc = make_float4(tot.h[0] + (tot.l[0] + lsum[0]), tot.h[1] + (tot.l[1] + lsum[1]),
+                                  tot.h[2] + (tot.l[2] + lsum[2]), tot.h[3] + (tot.l[3] + lsum[3]));
+            } else {
+                for (int gg = 1; gg < G; ++gg) {
+                    float4 v = red[gg * nt + tid];
+                    acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+                }
             }
             const int64_t o = ts + t0 + tid;
             out_phi[o] = acc.x;
@@ -514,40 +887,89 @@ static inline void ev_rec(fmm_plan_s *Pl, int slot, hipStream_t s) {
 template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t s) {
     using D = Dims<P>;
     const OpTables &T = op_tables(P);
+    const bool mixed = Pl->prec == FMM_PREC_MIXED;
+    const int RL = mixed ? kRootLevels : 0;       // levels below RL accumulate in FP64
     ev_rec(Pl, 2 * PH_P2M, s);
     hipLaunchKernelGGL(k_p2m<P>, (int)((Pl->nleaves + 1) / 2), 64, 0, s, (const int32_t *)Pl->leaves, Pl->nleaves,
                        g, (const float4 *)Pl->bodies, Pl->M);
     ev_rec(Pl, 2 * PH_P2M + 1, s);
     ev_rec(Pl, 2 * PH_M2M, s);
-    for (int l = Pl->max_level - 1; l >= 0; --l) {
+    for (int l = Pl->max_level - 1; l >= RL; --l) {
         const int t0 = Pl->m2m.bucket_tile[l * 8], t1 = Pl->m2m.bucket_tile[l * 8 + 8];
         if (t1 > t0)
             hipLaunchKernelGGL((k_gemm<P, false>), t1 - t0, 256, 0, s, (const int4 *)Pl->m2m.work + t0,
                                (const int32_t *)Pl->m2m.entry_key, (const int32_t *)Pl->m2m.entry_src,
-                               (const uint8_t *)nullptr, T.m2m_ptrs,
-                               (const float *)Pl->M, Pl->M, (float *)nullptr, (const int32_t *)Pl->m2m.tile_targets);
+                               (const uint8_t *)nullptr, T.m2m_ptrs, (const float *)Pl->M, Pl->M, (float *)nullptr,
+                               (const int32_t *)Pl->m2m.tile_targets);
+    }
+    if (mixed) {
+        hipLaunchKernelGGL(k_root_leaves_to64, grid1(Pl->nroot * D::KP), 256, 0, s, Pl->nroot, D::KP,
+                           (const int32_t *)Pl->c_nchild, (const float *)Pl->M, Pl->Md);
+        for (int l = std::min(RL - 1, Pl->max_level - 1); l >= 0; --l) {
+            const int t0 = Pl->m2m.bucket_tile[l * 8], t1 = Pl->m2m.bucket_tile[l * 8 + 8];
+            if (t1 > t0)
+                hipLaunchKernelGGL((k_gemm64<P, false>), t1 - t0, 256, 0, s, (const int4 *)Pl->m2m.work + t0,
+                                   (const int32_t *)Pl->m2m.entry_key, (const int32_t *)Pl->m2m.entry_src,
+                                   T.m2m64_ptrs, Pl->nroot, (const float *)Pl->M, (const double *)Pl->Md, Pl->Md,
+                                   (double *)nullptr, (const int32_t *)Pl->m2m.tile_targets);
+        }
+        hipLaunchKernelGGL(k_root_to32, grid1(Pl->nroot * D::KP), 256, 0, s, Pl->nroot, D::KP,
+                           (const double *)Pl->Md, Pl->M);
+        hipLaunchKernelGGL(k_split_m<P>, (int)Pl->ncells, 64, 0, s, (const float *)Pl->M, T.nu, Pl->Mh, Pl->Ml,
+                           Pl->Msinv);
     }
     ev_rec(Pl, 2 * PH_M2M + 1, s);
     fill_f32(Pl->L, 0.f, Pl->ncells * (int64_t)D::KP, s);
+    if (mixed) fill_f32(reinterpret_cast<float *>(Pl->Ld), 0.f, 2 * Pl->nroot * (int64_t)D::KP, s);
     ev_rec(Pl, 2 * PH_M2L, s);
-    if (Pl->nwork > 0)
-        hipLaunchKernelGGL((k_gemm<P, false>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
-                           (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
-                           (const uint8_t *)Pl->entry_mask, Pl->key_f32,
-                           (const float *)Pl->M, Pl->L, Pl->partial, (const int32_t *)Pl->tile_targets);
+    if (Pl->nwork > 0) {
+        if (mixed)
+            hipLaunchKernelGGL(k_m2l_f16<P>, (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
+                               (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
+                               (const uint8_t *)Pl->entry_mask, Pl->key_f16, (const _Float16 *)Pl->Mh,
+                               (const _Float16 *)Pl->Ml, (const float *)Pl->Msinv, Pl->L, Pl->partial,
+                               (const int32_t *)Pl->tile_targets);
+        else
+            hipLaunchKernelGGL((k_gemm<P, false>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
+                               (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
+                               (const uint8_t *)Pl->entry_mask, Pl->key_f32, (const float *)Pl->M, Pl->L, Pl->partial,
+                               (const int32_t *)Pl->tile_targets);
+    }
+    if (mixed && Pl->nwork64 > 0)
+        hipLaunchKernelGGL((k_gemm64<P, false>), (int)Pl->nwork64, 256, 0, s, (const int4 *)Pl->work64,
+                           (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src, Pl->key_f64, Pl->nroot,
+                           (const float *)Pl->M, (const double *)Pl->Md, Pl->Ld, Pl->partial64,
+                           (const int32_t *)Pl->tile_targets);
     ev_rec(Pl, 2 * PH_M2L + 1, s);
     ev_rec(Pl, 2 * PH_L2L, s);
     if (Pl->npartial > 0)
         hipLaunchKernelGGL(k_m2l_reduce, (int)Pl->ntiles, 256, 0, s, Pl->ntiles, (const int32_t *)Pl->tile_work,
                            (const int32_t *)Pl->tile_work_idx, (const int4 *)Pl->work, (const float *)Pl->partial,
                            (const int32_t *)Pl->tile_targets, D::KP, Pl->L);
-    for (int l = 1; l <= Pl->max_level; ++l) {
+    if (mixed && Pl->partial64)
+        hipLaunchKernelGGL(k_m2l64_reduce, dim3((unsigned)Pl->ntiles_root, 16), 256, 0, s, Pl->ntiles_root,
+                           (const int32_t *)Pl->tile_work64, (const int32_t *)Pl->tile_work_idx64,
+                           (const int4 *)Pl->work64, (const double *)Pl->partial64, (const int32_t *)Pl->tile_targets,
+                           D::KP, Pl->Ld);
+    if (mixed) {
+        for (int l = 1; l <= std::min(RL - 1, Pl->max_level); ++l) {
+            const int t0 = Pl->l2l.bucket_tile[l * 8], t1 = Pl->l2l.bucket_tile[l * 8 + 8];
+            if (t1 > t0)
+                hipLaunchKernelGGL((k_gemm64<P, true>), t1 - t0, 256, 0, s, (const int4 *)Pl->l2l.work + t0,
+                                   (const int32_t *)Pl->l2l.entry_key, (const int32_t *)Pl->l2l.entry_src,
+                                   T.l2l64_ptrs, Pl->nroot, (const float *)Pl->L, (const double *)Pl->Ld, Pl->Ld,
+                                   (double *)nullptr, (const int32_t *)Pl->l2l.tile_targets);
+        }
+        hipLaunchKernelGGL(k_root_to32, grid1(Pl->nroot * D::KP), 256, 0, s, Pl->nroot, D::KP,
+                           (const double *)Pl->Ld, Pl->L);
+    }
+    for (int l = mixed ? RL : 1; l <= Pl->max_level; ++l) {
         const int t0 = Pl->l2l.bucket_tile[l * 8], t1 = Pl->l2l.bucket_tile[l * 8 + 8];
         if (t1 > t0)
             hipLaunchKernelGGL((k_gemm<P, true>), t1 - t0, 256, 0, s, (const int4 *)Pl->l2l.work + t0,
                                (const int32_t *)Pl->l2l.entry_key, (const int32_t *)Pl->l2l.entry_src,
-                               (const uint8_t *)nullptr, T.l2l_ptrs,
-                               (const float *)Pl->L, Pl->L, (float *)nullptr, (const int32_t *)Pl->l2l.tile_targets);
+                               (const uint8_t *)nullptr, T.l2l_ptrs, (const float *)Pl->L, Pl->L, (float *)nullptr,
+                               (const int32_t *)Pl->l2l.tile_targets);
     }
     ev_rec(Pl, 2 * PH_L2L + 1, s);
     ev_rec(Pl, 2 * PH_L2P, s);
@@ -571,9 +993,14 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phase
     HIP_CHECK(hipStreamWaitEvent(Pl->side, Pl->ev_fork, 0));
     ev_rec(Pl, 2 * PH_P2P, Pl->side);
     if (phases & FMM_NEAR) {
-        hipLaunchKernelGGL(k_p2p, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
-                           (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                           (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near_phi, Pl->near_grad);
+        if (Pl->prec == FMM_PREC_MIXED)
+            hipLaunchKernelGGL(k_p2p<true>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
+                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
+                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near_phi, Pl->near_grad);
+        else
+            hipLaunchKernelGGL(k_p2p<false>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
+                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
+                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near_phi, Pl->near_grad);
     } else {
         fill_f32(Pl->near_phi, 0.f, n, Pl->side);
         fill_f32(Pl->near_grad, 0.f, 3 * n, Pl->side);

@@ -66,12 +66,20 @@ struct OpTables {
     int p = -1;
     const uint64_t *m2m_ptrs = nullptr;   // [8] device pointers of the octant M2M matrices [KP][KP]
     const uint64_t *l2l_ptrs = nullptr;   // [8] device pointers of the octant L2L matrices [KP][KP]
+    const double *m2m64_t = nullptr;      // [8][KP in][KP out] FP64, transposed (root levels)
+    const double *l2l64_t = nullptr;      // [8][KP in][KP out] FP64, transposed
+    const uint64_t *m2m64_ptrs = nullptr; // [8] pointers into m2m64_t
+    const uint64_t *l2l64_ptrs = nullptr; // [8] pointers into l2l64_t
+    const float *nu = nullptr;            // [KP] FP16 normalisation of multipole coefficients
 };
 const OpTables &op_tables(int p);
 // Device pointers (as uint64) of the M2L operator of every key, FP32 and split-FP16 forms.
 // keys: packed (level difference, offset) keys.  Creates missing operators.
 void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f32_ptrs,
                        std::vector<uint64_t> &f16_ptrs, bool need_f16);
+// FP64 M2L operators ([KP in][KP out], transposed) of the given keys.
+void m2l_operator_ptrs64(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f64_ptrs);
+constexpr int kRootLevels = 4;     // mixed precision: levels 0..3 keep FP64 coefficients
 
 // M2L key packing: dl = level(source) - level(target) in [-31, 31]; offset = (c_B - c_A)
 // in units of the finer cell's half side, each component in [-2^18, 2^18).
@@ -159,7 +167,15 @@ struct fmm_plan_s {
 
     // eval workspace
     float *M = nullptr, *L = nullptr;          // [ncells][KP]
-    double *Md = nullptr, *Ld = nullptr;        // FP64 root-level coefficients (mixed precision)
+    // mixed precision: FP64 coefficients of the root levels (cells [0, nroot))
+    int64_t nroot = 0, ntiles_root = 0, nwork64 = 0;
+    double *Md = nullptr, *Ld = nullptr;        // [nroot][KP]
+    const uint64_t *key_f64 = nullptr;          // [nkeys] FP64 operators (0 where unused)
+    int4 *work64 = nullptr;                     // work items over the root tiles
+    int32_t *tile_work64 = nullptr, *tile_work_idx64 = nullptr;
+    double *partial64 = nullptr;
+    _Float16 *Mh = nullptr, *Ml = nullptr;      // [ncells][KP] split FP16 multipoles (normalised)
+    float *Msinv = nullptr;                     // [ncells] inverse power-of-two scale of each cell
     float *partial = nullptr;                   // [nwork][kTileN][KP]
     float *far_phi = nullptr, *far_grad = nullptr, *near_phi = nullptr, *near_grad = nullptr;
     float *tmp_phi = nullptr, *tmp_grad = nullptr, *tmp_gfwd = nullptr;   // adjoint scratch (input order)

@@ -27,6 +27,7 @@
 // Real storage of a coefficient vector of order p, (p+1)^2 reals: degree l occupies
 // [l^2, (l+1)^2): Re X_l0, then (Re X_lm, Im X_lm) for m = 1..l.  Negative orders are
 // implied by the symmetry above (the fields are real).
+#include <algorithm>
 #include <complex>
 #include <cmath>
 #include <mutex>
@@ -158,25 +159,84 @@ void build_l2l(int p, int oct, std::vector<double> &A) {
     });
 }
 
+void transpose_into(const std::vector<double> &A, int KP, double *out) {
+    for (int r = 0; r < KP; ++r)
+        for (int c = 0; c < KP; ++c) out[(size_t)c * KP + r] = A[(size_t)r * KP + c];
+}
+
+// Normalisation of the multipole coefficients for FP16: nu_lm = sqrt((l+m)! (l-m)!)
+// brings every |nu_lm R_lm(u)| below |u|^l <= 1 (applied to Re and Im alike).
+double nu_coef(int l, int m) { return std::sqrt(std::tgamma(l + m + 1.0) * std::tgamma(l - m + 1.0)); }
+
+std::vector<double> nu_vector(int p, int KP) {
+    std::vector<double> nu(KP, 1.0);
+    for (int l = 0; l <= p; ++l)
+        for (int m = 0; m <= l; ++m) {
+            nu[ridx(l, m, 0)] = nu_coef(l, m);
+            if (m > 0) nu[ridx(l, m, 1)] = nu_coef(l, m);
+        }
+    return nu;
+}
+
+// Split-FP16 form of an M2L operator A ([KP][KP], row-major, acting on the FP32 basis):
+// with the multipoles normalised as Mh = nu * M, A M = diag(rs) (H + Lo) Mh where
+// A' = diag(1/rs) A diag(1/nu), rs = power of two bringing each row maximum into [1, 2),
+// H = fp16(A'), Lo = fp16(A' - H).  Layout: H [KP][KP] half, Lo [KP][KP] half, rs [KP] float.
+size_t split16_bytes(int KP) { return (size_t)KP * KP * 2 * sizeof(_Float16) + (size_t)KP * sizeof(float); }
+
+void split16(const std::vector<double> &A, int p, int KP, std::vector<char> &out) {
+    out.assign(split16_bytes(KP), 0);
+    std::vector<double> nu = nu_vector(p, KP), rs(KP, 1.0), B(A);
+    auto pow2floor = [](double v) { int e; std::frexp(v, &e); return std::ldexp(1.0, e - 1); };
+    for (int r = 0; r < KP; ++r) {
+        double m = 0;
+        for (int c = 0; c < KP; ++c) {
+            B[(size_t)r * KP + c] /= nu[c];
+            m = std::max(m, std::fabs(B[(size_t)r * KP + c]));
+        }
+        if (m > 0) rs[r] = pow2floor(m);
+        for (int c = 0; c < KP; ++c) B[(size_t)r * KP + c] /= rs[r];
+    }
+    _Float16 *H = reinterpret_cast<_Float16 *>(out.data());
+    _Float16 *Lo = H + (size_t)KP * KP;
+    float *rsf = reinterpret_cast<float *>(Lo + (size_t)KP * KP);
+    for (size_t i = 0; i < (size_t)KP * KP; ++i) {
+        _Float16 h = (_Float16)B[i];
+        H[i] = h;
+        Lo[i] = (_Float16)(B[i] - (double)h);
+    }
+    for (int i = 0; i < KP; ++i) rsf[i] = (float)rs[i];
+}
+
 // ------------------------------------------------------------------ device store
 constexpr int kChunk = 64;   // matrices per device allocation (never moved)
+
+// Device memory for operators, handed out in fixed-size blocks from chunks that are
+// never moved or freed (pointers stay valid for the process).
+struct BlockPool {
+    size_t block_bytes = 0;
+    std::vector<char *> chunks;
+    int used = kChunk;
+    void *take() {
+        if (used == kChunk) {
+            char *c = nullptr;
+            HIP_CHECK(hipMalloc(&c, block_bytes * kChunk));
+            chunks.push_back(c);
+            used = 0;
+        }
+        return chunks.back() + block_bytes * (used++);
+    }
+};
 
 struct Store {
     int p = -1;
     size_t mat_floats = 0;
     std::unordered_map<uint64_t, uint64_t> f32;   // key -> device pointer
-    std::vector<float *> chunks;
-    int used_in_chunk = kChunk;
+    std::unordered_map<uint64_t, uint64_t> f16;   // key -> device pointer (split FP16 form)
+    std::unordered_map<uint64_t, uint64_t> f64;   // key -> device pointer (FP64, transposed)
+    BlockPool pool32, pool16, pool64;
     OpTables tables;
-    float *alloc_matrix() {
-        if (used_in_chunk == kChunk) {
-            float *c = nullptr;
-            HIP_CHECK(hipMalloc(&c, sizeof(float) * mat_floats * kChunk));
-            chunks.push_back(c);
-            used_in_chunk = 0;
-        }
-        return chunks.back() + mat_floats * (used_in_chunk++);
-    }
+    float *alloc_matrix() { return static_cast<float *>(pool32.take()); }
 };
 
 std::mutex g_mu;
@@ -190,6 +250,9 @@ Store &store_for(int p) {
         s.p = p;
         int KP = ncoef_pad(p);
         s.mat_floats = (size_t)KP * KP;
+        s.pool32.block_bytes = sizeof(float) * s.mat_floats;
+        s.pool16.block_bytes = split16_bytes(KP);
+        s.pool64.block_bytes = sizeof(double) * s.mat_floats;
         std::vector<double> A;
         std::vector<float> host((size_t)8 * KP * KP);
         float *m2m = nullptr, *l2l = nullptr;
@@ -216,6 +279,40 @@ Store &store_for(int p) {
         s.tables.p = p;
         s.tables.m2m_ptrs = ptrs;
         s.tables.l2l_ptrs = ptrs + 8;
+        // FP64 octant operators, transposed ([KP in][KP out]), for the root levels
+        std::vector<double> h64((size_t)8 * KP * KP);
+        double *m2m64 = nullptr, *l2l64 = nullptr;
+        HIP_CHECK(hipMalloc(&m2m64, sizeof(double) * h64.size()));
+        HIP_CHECK(hipMalloc(&l2l64, sizeof(double) * h64.size()));
+        for (int o = 0; o < 8; ++o) {
+            build_m2m(p, o, A);
+            transpose_into(A, KP, h64.data() + (size_t)o * KP * KP);
+        }
+        HIP_CHECK(hipMemcpy(m2m64, h64.data(), sizeof(double) * h64.size(), hipMemcpyHostToDevice));
+        for (int o = 0; o < 8; ++o) {
+            build_l2l(p, o, A);
+            transpose_into(A, KP, h64.data() + (size_t)o * KP * KP);
+        }
+        HIP_CHECK(hipMemcpy(l2l64, h64.data(), sizeof(double) * h64.size(), hipMemcpyHostToDevice));
+        s.tables.m2m64_t = m2m64;
+        s.tables.l2l64_t = l2l64;
+        uint64_t hp64[16];
+        for (int o = 0; o < 8; ++o) {
+            hp64[o] = (uint64_t)(uintptr_t)(m2m64 + (size_t)o * KP * KP);
+            hp64[8 + o] = (uint64_t)(uintptr_t)(l2l64 + (size_t)o * KP * KP);
+        }
+        uint64_t *ptrs64 = nullptr;
+        HIP_CHECK(hipMalloc(&ptrs64, sizeof(hp64)));
+        HIP_CHECK(hipMemcpy(ptrs64, hp64, sizeof(hp64), hipMemcpyHostToDevice));
+        s.tables.m2m64_ptrs = ptrs64;
+        s.tables.l2l64_ptrs = ptrs64 + 8;
+        std::vector<double> nu = nu_vector(p, KP);
+        std::vector<float> nuf(KP);
+        for (int i = 0; i < KP; ++i) nuf[i] = i < ncoef(p) ? (float)nu[i] : 0.f;
+        float *dnu = nullptr;
+        HIP_CHECK(hipMalloc(&dnu, sizeof(float) * KP));
+        HIP_CHECK(hipMemcpy(dnu, nuf.data(), sizeof(float) * KP, hipMemcpyHostToDevice));
+        s.tables.nu = dnu;
     }
     return s;
 }
@@ -245,8 +342,38 @@ void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uin
             it = s.f32.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
         }
         f32_ptrs[i] = it->second;
+        if (need_f16) {
+            auto jt = s.f16.find(keys[i]);
+            if (jt == s.f16.end()) {
+                build_m2l(p, keys[i], A);
+                std::vector<char> blob;
+                split16(A, p, ncoef_pad(p), blob);
+                void *d = s.pool16.take();
+                HIP_CHECK(hipMemcpy(d, blob.data(), blob.size(), hipMemcpyHostToDevice));
+                jt = s.f16.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
+            }
+            f16_ptrs[i] = jt->second;
+        }
     }
-    (void)need_f16;
+}
+
+void m2l_operator_ptrs64(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f64_ptrs) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Store &s = store_for(p);
+    f64_ptrs.resize(keys.size());
+    std::vector<double> A, At(s.mat_floats);
+    int KP = ncoef_pad(p);
+    for (size_t i = 0; i < keys.size(); ++i) {
+        auto it = s.f64.find(keys[i]);
+        if (it == s.f64.end()) {
+            build_m2l(p, keys[i], A);
+            transpose_into(A, KP, At.data());
+            void *d = s.pool64.take();
+            HIP_CHECK(hipMemcpy(d, At.data(), sizeof(double) * s.mat_floats, hipMemcpyHostToDevice));
+            it = s.f64.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
+        }
+        f64_ptrs[i] = it->second;
+    }
 }
 
 }  // namespace fmm

@@ -1043,6 +1043,58 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         HIP_CHECK(hipMemcpyAsync(P->tile_work_idx, htwi.data(), 4 * P->nwork, hipMemcpyHostToDevice, s));
         P->npartial = nsplit;
         HIP_CHECK(hipStreamSynchronize(s));
+
+        // mixed precision: the root levels accumulate in FP64, with FP64 operators for the
+        // keys their tiles use and their own split into small work items
+        if (P->prec == FMM_PREC_MIXED) {
+            const int rl = std::min<int>(kRootLevels, P->max_level + 1);
+            P->nroot = P->level_off[rl];
+            P->Md = a.get_n<double>(P->nroot * P->KP);
+            P->Ld = a.get_n<double>(P->nroot * P->KP);
+            const int64_t tr = btile[(size_t)kRootLevels * 8];
+            P->ntiles_root = tr;
+            if (tr > 0) {
+                const int64_t ner = htf[tr];
+                std::vector<int32_t> hek(ner);
+                HIP_CHECK(hipMemcpyAsync(hek.data(), P->entry_key, 4 * ner, hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+                std::vector<char> used(nkeys, 0);
+                for (int32_t kk : hek) used[kk] = 1;
+                std::vector<uint64_t> rkeys;
+                std::vector<int64_t> rid;
+                for (int64_t kk = 0; kk < nkeys; ++kk)
+                    if (used[kk]) { rkeys.push_back(hkeys[kk]); rid.push_back(kk); }
+                std::vector<uint64_t> rp, all(nkeys, 0);
+                m2l_operator_ptrs64(P->p, rkeys, rp);
+                for (size_t q2 = 0; q2 < rid.size(); ++q2) all[rid[q2]] = rp[q2];
+                uint64_t *d64 = a.get_n<uint64_t>(nkeys);
+                HIP_CHECK(hipMemcpyAsync(d64, all.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
+                P->key_f64 = d64;
+                constexpr int64_t kPiece64 = 24;
+                std::vector<int4> w64;
+                std::vector<int32_t> tw(tr + 1), twi;
+                int64_t slot = 0;
+                for (int64_t t = 0; t < tr; ++t) {
+                    tw[t] = (int32_t)twi.size();
+                    const int64_t e0 = htf[t], e1 = htf[t + 1];
+                    const bool split = e1 - e0 > kPiece64;
+                    for (int64_t c0 = e0; c0 < e1; c0 += kPiece64) {
+                        twi.push_back((int32_t)w64.size());
+                        w64.push_back(make_int4((int)t, (int)c0, (int)std::min(e1, c0 + kPiece64), split ? (int)(++slot) : 0));
+                    }
+                }
+                tw[tr] = (int32_t)twi.size();
+                P->nwork64 = (int64_t)w64.size();
+                P->work64 = a.get_n<int4>(P->nwork64);
+                P->tile_work64 = a.get_n<int32_t>(tr + 1);
+                P->tile_work_idx64 = a.get_n<int32_t>(P->nwork64);
+                HIP_CHECK(hipMemcpyAsync(P->work64, w64.data(), sizeof(int4) * w64.size(), hipMemcpyHostToDevice, s));
+                HIP_CHECK(hipMemcpyAsync(P->tile_work64, tw.data(), 4 * (tr + 1), hipMemcpyHostToDevice, s));
+                HIP_CHECK(hipMemcpyAsync(P->tile_work_idx64, twi.data(), 4 * P->nwork64, hipMemcpyHostToDevice, s));
+                if (slot > 0) P->partial64 = a.get_n<double>(slot * kTileN * P->KP);
+                HIP_CHECK(hipStreamSynchronize(s));
+            }
+        }
     }
 
     lg("m2l work items");
@@ -1088,6 +1140,11 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     P->far_grad = a.get_n<float>(3 * n);
     P->near_phi = a.get_n<float>(n);
     P->near_grad = a.get_n<float>(3 * n);
+    if (P->prec == FMM_PREC_MIXED) {
+        P->Mh = a.get_n<_Float16>(nc * KP);
+        P->Ml = a.get_n<_Float16>(nc * KP);
+        P->Msinv = a.get_n<float>(nc);
+    }
     HIP_CHECK(hipStreamSynchronize(s));
     lg("workspace");
 }
