@@ -415,18 +415,22 @@ __global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t
         for (int r = 0; r < RBW; ++r)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) tmp[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kc = 0; kc < NK32; ++kc) {
-            half8 ah[RBW], al[RBW];
+        half8 ah[RBW], al[RBW], nh[RBW], nl[RBW];
+        auto load_t = [&](int kc, half8 *dh, half8 *dl) {
 #pragma unroll
             for (int r = 0; r < RBW; ++r) {
                 const int rb = wave + 4 * r;
                 if (rb < NRB) {
                     const int64_t off = (int64_t)(rb * 16 + li) * KP + kc * 32 + 8 * lg;
-                    ah[r] = *reinterpret_cast<const half8 *>(H + off);
-                    al[r] = *reinterpret_cast<const half8 *>(Lo + off);
+                    dh[r] = *reinterpret_cast<const half8 *>(H + off);
+                    dl[r] = *reinterpret_cast<const half8 *>(Lo + off);
                 }
             }
+        };
+        if (NK32 > 0) load_t(0, ah, al);
+#pragma unroll
+        for (int kc = 0; kc < NK32; ++kc) {
+            if (kc + 1 < NK32) load_t(kc + 1, nh, nl);
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 if (!((mask >> cb) & 1)) continue;
@@ -439,6 +443,13 @@ __global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bh, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bl, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], bh, tmp[r][cb], 0, 0, 0);
+                }
+            }
+            if (kc + 1 < NK32) {
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) {
+                    ah[r] = nh[r];
+                    al[r] = nl[r];
                 }
             }
         }
