@@ -419,9 +419,10 @@ typedef struct {
 /*
  * Root cube (reading of the silent paper): lo/hi are the per-axis extremes of
  * the inputs; the side is the smallest power of two 2^k with
- * hi_a - x0_a < 2^k on every axis, where x0_a is lo_a rounded down to a
- * multiple of 2^(k-22).  All box centres and centre differences are then
- * dyadic and exact.
+ * hi_a - x0_a <= 2^k on every axis (the closed box), where x0_a is lo_a rounded
+ * down to a multiple of 2^(k-22).  A point on the upper face is clamped into the
+ * last cell, whose closure contains it.  All box centres and centre differences
+ * are then dyadic and exact.
  */
 static void root_cube(int64_t n, const double *pts, int *k_out, double x0[3]) {
     double lo[3], hi[3];
@@ -436,13 +437,13 @@ static void root_cube(int64_t n, const double *pts, int *k_out, double x0[3]) {
     for (int a = 0; a < 3; ++a) if (hi[a] - lo[a] > E) E = hi[a] - lo[a];
     int e = 0;
     frexp(E, &e);           /* 2^(e-1) <= E < 2^e  (e = 0 for E = 0) */
-    int k = e;
+    int k = e - 1;          /* smallest k with 2^k >= E when E is a power of two; raised below if needed */
     for (;;) {
         double unit = ldexp(1.0, k - 22);
         int ok = 1;
         for (int a = 0; a < 3; ++a) {
             x0[a] = floor(lo[a] / unit) * unit;
-            if (!(hi[a] - x0[a] < ldexp(1.0, k))) ok = 0;
+            if (!(hi[a] - x0[a] <= ldexp(1.0, k))) ok = 0;
         }
         if (ok) break;
         ++k;

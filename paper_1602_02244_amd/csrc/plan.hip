@@ -72,21 +72,22 @@ __global__ void __launch_bounds__(256) k_bbox_final(const float *part, int nb, f
     if (threadIdx.x < 7) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// Root cube: side 2^k, the smallest power of two with hi_a - x0_a < 2^k on every axis,
-// x0_a = lo_a rounded down to a multiple of 2^(k-22).  Every cell centre and centre
-// difference is then an exact dyadic number (exact integer MAC, exact operator keys).
+// Root cube: side 2^k, the smallest power of two with hi_a - x0_a <= 2^k on every axis
+// (the closed box), x0_a = lo_a rounded down to a multiple of 2^(k-22); a point on the
+// upper face is clamped into the last cell.  Every cell centre and centre difference is
+// then an exact dyadic number (exact integer MAC, exact operator keys).
 static void root_cube(const float lo[3], const float hi[3], int &k, double x0[3]) {
     double E = 0;
     for (int a = 0; a < 3; ++a) E = std::max(E, (double)hi[a] - (double)lo[a]);
     int e = 0;
     std::frexp(E, &e);
-    k = e;
+    k = e - 1;
     for (;;) {
         double unit = std::ldexp(1.0, k - 22);
         bool ok = true;
         for (int a = 0; a < 3; ++a) {
             x0[a] = std::floor((double)lo[a] / unit) * unit;
-            if (!((double)hi[a] - x0[a] < std::ldexp(1.0, k))) ok = false;
+            if (!((double)hi[a] - x0[a] <= std::ldexp(1.0, k))) ok = false;
         }
         if (ok) break;
         ++k;
@@ -557,37 +558,59 @@ __global__ void __launch_bounds__(256) k_p2p_csr(const uint64_t *comp, const int
     block_add_u64(loc, inter);
 }
 
-// Source runs of each target leaf: its source leaves (self excluded) with adjacent body
-// ranges merged.  mode 0 counts, mode 1 writes.
-__global__ void k_p2p_segments(int64_t nl, const int32_t *leaves, const int32_t *pair_off, int64_t np,
-                               const int2 *pairs, const int32_t *c_start, const int32_t *c_count, int32_t *nseg,
-                               const int32_t *seg_off, int2 *segs, int mode) {
-    int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (li >= nl) return;
-    int self = leaves[li];
-    int64_t p0 = pair_off[li], p1 = li + 1 < nl ? pair_off[li + 1] : np;
-    int cnt = 0, cur_s = -1, cur_n = 0;
-    int w = mode ? seg_off[li] : 0;
-    for (int64_t k = p0; k < p1; ++k) {
-        int b = pairs[k].y;
-        if (b == self) continue;
-        int s = c_start[b], n = c_count[b];
-        if (cur_n > 0 && cur_s + cur_n == s) {
-            cur_n += n;
-        } else {
-            if (cur_n > 0) {
-                if (mode) segs[w + cnt] = make_int2(cur_s, cur_n);
-                ++cnt;
-            }
-            cur_s = s;
-            cur_n = n;
+// Source runs of each target leaf: its source leaves (self excluded), in Morton order,
+// with adjacent body ranges merged into one run.  Built in parallel over pairs (pairs are
+// sorted by (target, source), so a target's sources are consecutive): a pair opens a run
+// unless the previous non-self pair of the same target ends where this one starts.
+__device__ inline int64_t p2p_prev(const int2 *pairs, int64_t k, int a) {   // previous non-self pair of target a
+    int64_t j = k - 1;
+    if (j >= 0 && pairs[j].x == a && pairs[j].y == a) --j;
+    return (j >= 0 && pairs[j].x == a) ? j : -1;
+}
+__device__ inline int64_t p2p_next(const int2 *pairs, int64_t k, int64_t np, int a) {
+    int64_t j = k + 1;
+    if (j < np && pairs[j].x == a && pairs[j].y == a) ++j;
+    return (j < np && pairs[j].x == a) ? j : -1;
+}
+
+__global__ void k_p2p_run_flags(const int2 *pairs, int64_t np, const int32_t *c_start, const int32_t *c_count,
+                                int32_t *open) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < np; k += (int64_t)gridDim.x * blockDim.x) {
+        const int a = pairs[k].x, b = pairs[k].y;
+        int f = 0;
+        if (a != b) {
+            const int64_t j = p2p_prev(pairs, k, a);
+            f = (j < 0 || c_start[pairs[j].y] + c_count[pairs[j].y] != c_start[b]) ? 1 : 0;
         }
+        open[k] = f;
     }
-    if (cur_n > 0) {
-        if (mode) segs[w + cnt] = make_int2(cur_s, cur_n);
-        ++cnt;
+}
+
+// A run's first pair writes its start, its last pair its end; run ids come from the
+// exclusive scan of the open flags.  seg_off[li] is the run id at the leaf's first pair.
+__global__ void k_p2p_run_write(const int2 *pairs, int64_t np, const int32_t *c_start, const int32_t *c_count,
+                                const int32_t *open, const int32_t *run_id, int2 *segs) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < np; k += (int64_t)gridDim.x * blockDim.x) {
+        const int a = pairs[k].x, b = pairs[k].y;
+        if (a == b) continue;
+        const int id = run_id[k] + open[k] - 1;
+        if (open[k]) segs[id].x = c_start[b];
+        const int64_t j = p2p_next(pairs, k, np, a);
+        if (j < 0 || open[j]) segs[id].y = c_start[b] + c_count[b];   // end for now; length below
     }
-    if (!mode) nseg[li] = cnt;
+}
+
+__global__ void k_p2p_run_len(int2 *segs, int64_t nseg) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nseg; i += (int64_t)gridDim.x * blockDim.x) {
+        int2 r = segs[i];
+        segs[i] = make_int2(r.x, r.y - r.x);
+    }
+}
+
+__global__ void k_p2p_seg_off(int64_t nl, const int32_t *pair_off, const int32_t *run_id, int32_t nseg,
+                              int32_t *seg_off) {
+    for (int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; li <= nl; li += (int64_t)gridDim.x * blockDim.x)
+        seg_off[li] = li < nl ? run_id[pair_off[li]] : nseg;
 }
 
 // ----------------------------------------------------------------- host side
@@ -665,9 +688,11 @@ static int64_t tile_cells(const CellView &C, int64_t nc, int32_t *flag, bool by_
 // Host-side stage timer, printed to stderr when FMM_LOG is set.
 struct StageLog {
     bool on = getenv("FMM_LOG") != nullptr;
+    hipStream_t s = nullptr;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now(), last = t0;
     void operator()(const char *what) {
         if (!on) return;
+        (void)hipStreamSynchronize(s);   // attribute device time to the stage that queued it
         auto now = std::chrono::steady_clock::now();
         fprintf(stderr, "[fmm plan] %-28s +%8.3f ms  (t=%8.3f ms)\n", what,
                 std::chrono::duration<double, std::milli>(now - last).count(),
@@ -678,6 +703,7 @@ struct StageLog {
 
 void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     StageLog lg;
+    lg.s = s;
     Alloc &a = P->mem;
     const int64_t n = P->n;
 
@@ -1106,6 +1132,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         hipLaunchKernelGGL(k_p2p_composite, grid1(np2p), 256, 0, s, (const int2 *)p2p, np2p, (const int32_t *)P->leaf_id,
                            lbits, comp, dummy);
         radix_sort_u64(comp, dummy, np2p, 2 * lbits, a, s);
+        lg("p2p sort");
         P->p2p_pairs = a.get_n<int2>(np2p);
         int32_t *pair_off = a.get_n<int32_t>(P->nleaves);
         unsigned long long *inter = a.get_n<unsigned long long>(1);
@@ -1114,20 +1141,24 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                            (const int32_t *)dummy, np2p, lbits, (const int32_t *)P->leaves, P->p2p_pairs, pair_off,
                            (const int32_t *)P->c_count, inter);
         P->p2p_interactions = (int64_t)read_back(inter, s);
-        int32_t *nseg = a.get_n<int32_t>(P->nleaves);
+        lg("p2p csr");
+        // runs: open flags in `dummy` (free after the CSR pass), run ids in `comp`'s storage
+        int32_t *open = dummy, *run_id = reinterpret_cast<int32_t *>(comp);
+        hipLaunchKernelGGL(k_p2p_run_flags, grid1(np2p), 256, 0, s, (const int2 *)P->p2p_pairs, np2p,
+                           (const int32_t *)P->c_start, (const int32_t *)P->c_count, open);
+        P->nseg = exclusive_scan_i32(open, run_id, np2p, a, s);
+        lg("p2p run flags");
+        if (P->nseg >= (int64_t)INT32_MAX) fail(FMM_EUNSUPPORTED, "near-field run count exceeds 2^31");
         P->seg_off = a.get_n<int32_t>(P->nleaves + 1);
-        hipLaunchKernelGGL(k_p2p_segments, grid1(P->nleaves), 256, 0, s, P->nleaves, (const int32_t *)P->leaves,
-                           (const int32_t *)pair_off, np2p, (const int2 *)P->p2p_pairs, (const int32_t *)P->c_start,
-                           (const int32_t *)P->c_count, nseg, (const int32_t *)nullptr, (int2 *)nullptr, 0);
-        P->nseg = exclusive_scan_i32(nseg, P->seg_off, P->nleaves, a, s);
-        int32_t tot = (int32_t)P->nseg;
-        HIP_CHECK(hipMemcpyAsync(P->seg_off + P->nleaves, &tot, 4, hipMemcpyHostToDevice, s));
-        P->segs = a.get_n<int2>(P->nseg);
-        hipLaunchKernelGGL(k_p2p_segments, grid1(P->nleaves), 256, 0, s, P->nleaves, (const int32_t *)P->leaves,
-                           (const int32_t *)pair_off, np2p, (const int2 *)P->p2p_pairs, (const int32_t *)P->c_start,
-                           (const int32_t *)P->c_count, (int32_t *)nullptr, (const int32_t *)P->seg_off, P->segs, 1);
+        P->segs = a.get_n<int2>(std::max<int64_t>(P->nseg, 1));
+        hipLaunchKernelGGL(k_p2p_run_write, grid1(np2p), 256, 0, s, (const int2 *)P->p2p_pairs, np2p,
+                           (const int32_t *)P->c_start, (const int32_t *)P->c_count, (const int32_t *)open,
+                           (const int32_t *)run_id, P->segs);
+        hipLaunchKernelGGL(k_p2p_run_len, grid1(P->nseg), 256, 0, s, P->segs, P->nseg);
+        hipLaunchKernelGGL(k_p2p_seg_off, grid1(P->nleaves + 1), 256, 0, s, (int64_t)P->nleaves,
+                           (const int32_t *)pair_off, (const int32_t *)run_id, (int32_t)P->nseg, P->seg_off);
         HIP_CHECK(hipStreamSynchronize(s));
-        a.put(comp); a.put(dummy); a.put(pair_off); a.put(inter); a.put(nseg); a.put(p2p);
+        a.put(comp); a.put(dummy); a.put(pair_off); a.put(inter); a.put(p2p);
     }
 
     lg("p2p lists");

@@ -282,3 +282,26 @@ def test_interior_list_counts_match_paper(theta):
     sel = (lev[m2l[:, 0]] == 4) & (lev[m2l[:, 1]] == 4)
     offs = {tuple(co[a] - co[b]) for a, b in m2l[sel]}
     assert len(offs) == keys_exp
+
+
+def test_root_cube_is_the_closed_box():
+    """Points on the upper face of [0,1]^3 keep the unit root cube (they sit in the closure of
+    the last cell); a cloud one ulp wider doubles it.  The lists still cover every pair once."""
+    g = np.arange(17) / 16.0                      # includes 0 and 1
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pl = oracle.Plan(x, 4, 0.5)
+    assert pl.k == 0 and np.all(pl.x0 == 0.0)
+    cov = _coverage(pl)
+    assert cov.min() == 1 and cov.max() == 1
+    c = pl.cells()
+    order, _ = pl.order()
+    side = 2.0 ** (pl.k - c["level"].astype(np.float64))
+    for li in np.nonzero(c["leaf"])[0]:
+        l, pref = int(c["level"][li]), int(c["prefix"][li])
+        ic = [sum(((pref >> (3 * bb + 2 - a)) & 1) << bb for bb in range(l)) for a in range(3)]
+        ctr = (np.array(ic) + 0.5) * side[li]
+        pts = x[order[c["start"][li]:c["start"][li] + c["count"][li]]]
+        assert np.all(np.abs(pts - ctr) <= side[li] / 2)
+    y = x.copy()
+    y[-1, 0] = np.nextafter(1.0, 2.0)
+    assert oracle.Plan(y, 4, 0.5).k == 1
