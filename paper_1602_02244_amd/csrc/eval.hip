@@ -174,20 +174,28 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, int64_t nleav
 
 // ------------------------------------------------------------------ M2L (FP32 MFMA)
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const floatx4 gfloatx4;   // global-memory float x4
 
 // Workgroup = 4 waves.  Output tile: KP rows x 64 target columns, in 16x16 blocks.
 // Wave w owns row blocks w, w+4, ... and all four column blocks.  The K loop runs in
 // chunks of 16 coefficients; inside a chunk lane l feeds k = 16*kc + 4*(l/16) + s to
 // MFMA step s, for both operands, so each lane reads 4 consecutive k as one float4.
-// Software pipeline: the next entry's gathered sources are loaded into registers while
-// the current entry computes, and T's next k chunk is loaded ahead of its MFMAs.
-// Column blocks with no source in an entry (entry_mask bit clear) are skipped.
+//
+// Software pipeline, with no branch on loaded data so that every wait is a counted one:
+//   entry e+2: source indices (lane = column), operator key and column mask are loaded;
+//   entry e+1: the operator pointer is resolved, and its 64 gathered source vectors are
+//              loaded one piece per k chunk of entry e (the source index reaches the
+//              loading lane by a cross-lane shuffle; empty columns load row 0 and are
+//              zeroed when stored to LDS);
+//   entry e:   T streams one k chunk ahead of its MFMAs, and the last chunk prefetches
+//              chunk 0 of entry e+1's operator.
+// Column blocks with no source in an entry (mask bit clear; MASKED only) are skipped.
 //
 // The same kernel runs M2L (all levels at once, split into work items), M2M (per
 // level: targets are parents, one entry per child octant) and L2L (per level:
 // targets share an octant, the source is the parent; ADD accumulates onto the
 // M2L result).
-template <int P, bool ADD>
+template <int P, bool ADD, bool MASKED>
 __global__ void __launch_bounds__(256) k_gemm(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                               const uint8_t *entry_mask, const uint64_t *key_ptr, const float *M,
                                               float *L, float *partial, const int32_t *tile_targets) {
@@ -198,81 +206,97 @@ __global__ void __launch_bounds__(256) k_gemm(const int4 *work, const int32_t *e
     constexpr int RBW = (NRB + 3) / 4;           // row blocks per wave
     constexpr int NKC = KP / 16;                 // k chunks
     constexpr int NQ = KP / 4;                   // float4 per coefficient vector
-    constexpr int NPF = (kTileN * NQ + 255) / 256;
+    constexpr int NPF = kTileN * NQ / 256;       // gathered float4 per thread per entry
+    static_assert(kTileN == 64 && (kTileN * NQ) % 256 == 0 && NPF == NKC, "one gather piece per k chunk");
     __shared__ __attribute__((aligned(16))) float Ms[kTileN * KPS];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar branches
     const int li = lane & 15, lg = lane >> 4;
     const int4 w = work[blockIdx.x];
+    const int e0 = w.y, e1 = w.z;
+    if (e0 >= e1) return;
     floatx4 acc[RBW][4];
 #pragma unroll
     for (int r = 0; r < RBW; ++r)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    float4 pre[NPF];
-    auto gather = [&](int e) {
-#pragma unroll
-        for (int i = 0; i < NPF; ++i) {
-            const int idx = tid + 256 * i;
-            pre[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (idx < kTileN * NQ) {
-                const int col = idx / NQ, q4 = idx % NQ;
-                const int src = entry_src[(int64_t)e * kTileN + col];
-                if (src >= 0) pre[i] = reinterpret_cast<const float4 *>(M + (int64_t)src * KP)[q4];
-            }
-        }
-    };
-    if (w.y < w.z) gather(w.y);
-    for (int e = w.y; e < w.z; ++e) {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NPF; ++i) {
-            const int idx = tid + 256 * i;
-            if (idx < kTileN * NQ) {
-                const int col = idx / NQ, q4 = idx % NQ;
-                *reinterpret_cast<float4 *>(&Ms[col * KPS + 4 * q4]) = pre[i];
-            }
-        }
-        __syncthreads();
-        const float *T = reinterpret_cast<const float *>(key_ptr[entry_key[e]]);
-        const int mask = entry_mask ? (int)entry_mask[e] : 15;
-        if (e + 1 < w.z) gather(e + 1);
-        float4 a[RBW], an[RBW];
+    auto clampe = [&](int e) { return min(e, e1 - 1); };
+    // operators are reached through a pointer table: global loads, not flat ones (a flat
+    // load also counts against the LDS wait counter)
+    auto t_chunk = [&](const float *T, int kc, floatx4 *dst) {
+        const gfloatx4 *Tg = (const gfloatx4 *)(T);
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
-            const int rb = wave + 4 * r;
-            a[r] = rb < NRB ? *reinterpret_cast<const float4 *>(T + (int64_t)(rb * 16 + li) * KP + 4 * lg)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int rb = min(wave + 4 * r, NRB - 1);
+            dst[r] = Tg[((rb * 16 + li) * KP + kc * 16 + 4 * lg) / 4];
         }
+    };
+    float4 pre[NPF];
+    int srcs[NPF];
+    auto gather_src = [&](int idxv) {            // the source behind each of this lane's pieces
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) srcs[i] = __shfl(idxv, (tid + 256 * i) / NQ, 64);
+    };
+    auto gather_piece = [&](int i) {
+        const int q4 = (tid + 256 * i) % NQ;
+        pre[i] = reinterpret_cast<const float4 *>(M + (int64_t)max(srcs[i], 0) * KP)[q4];
+    };
+    auto mask_of = [&](int e) { return MASKED ? (int)entry_mask[e] : 15; };
+
+    // prologue: entry e0's sources and operator chunk 0; entry e0+1's indices, key and mask
+    gather_src(entry_src[(int64_t)e0 * kTileN + lane]);
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) gather_piece(i);
+    const float *Tc = reinterpret_cast<const float *>(key_ptr[entry_key[e0]]);
+    int mask = mask_of(e0);
+    floatx4 a[RBW], an[RBW];
+    t_chunk(Tc, 0, a);
+    int idx = entry_src[(int64_t)clampe(e0 + 1) * kTileN + lane];
+    int key_n = entry_key[clampe(e0 + 1)];
+    int mask_n = mask_of(clampe(e0 + 1));
+
+    for (int e = e0; e < e1; ++e) {
+        // everything loaded during the previous entry is consumed here, before new loads
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int g = tid + 256 * i, col = g / NQ, q4 = g % NQ;
+            const float4 v = srcs[i] >= 0 ? pre[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            *reinterpret_cast<float4 *>(&Ms[col * KPS + 4 * q4]) = v;
+        }
+        gather_src(idx);                         // entry e+1
+        const int m = __builtin_amdgcn_readfirstlane(mask);
+        const int kn = __builtin_amdgcn_readfirstlane(key_n);
+        mask = mask_n;
+        __syncthreads();
+        // next entry's operator; the entry after that: indices, key, mask
+        const float *Tn = reinterpret_cast<const float *>(key_ptr[kn]);
+        idx = entry_src[(int64_t)clampe(e + 2) * kTileN + lane];
+        key_n = entry_key[clampe(e + 2)];
+        mask_n = mask_of(clampe(e + 2));
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
-            if (kc + 1 < NKC) {
-#pragma unroll
-                for (int r = 0; r < RBW; ++r) {
-                    const int rb = wave + 4 * r;
-                    an[r] = rb < NRB ? *reinterpret_cast<const float4 *>(T + (int64_t)(rb * 16 + li) * KP +
-                                                                         (kc + 1) * 16 + 4 * lg)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
+            if (kc + 1 < NKC) t_chunk(Tc, kc + 1, an);
+            else t_chunk(Tn, 0, an);
+            gather_piece(kc);                    // entry e+1 (a repeat of the last entry at the end)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
-                if (!((mask >> cb) & 1)) continue;
+                if (!((m >> cb) & 1)) continue;
                 const float4 b = *reinterpret_cast<const float4 *>(&Ms[(cb * 16 + li) * KPS + kc * 16 + 4 * lg]);
 #pragma unroll
                 for (int r = 0; r < RBW; ++r) {
-                    if (wave + 4 * r >= NRB) continue;
+                    if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, acc[r][cb], 0, 0, 0);
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, acc[r][cb], 0, 0, 0);
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b.z, acc[r][cb], 0, 0, 0);
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, b.w, acc[r][cb], 0, 0, 0);
                 }
             }
-            if (kc + 1 < NKC) {
 #pragma unroll
-                for (int r = 0; r < RBW; ++r) a[r] = an[r];
-            }
+            for (int r = 0; r < RBW; ++r) a[r] = an[r];
         }
+        Tc = Tn;
     }
     // output: lane holds D[4*lg + v][li] of each 16x16 block
 #pragma unroll
@@ -342,7 +366,9 @@ __global__ void __launch_bounds__(64) k_split_m(const float *M, const float *nu,
 // multipoles of the 64 sources are copied to LDS, the product is taken as
 // H hi + H lo + Lo hi on v_mfma_f32_16x16x32_f16 with FP32 accumulation, and the entry's
 // result is scaled back (rows by rs, columns by the source's inverse scale) and added in
-// FP32.  Tiling, work items and outputs are those of k_gemm.
+// FP32.  Tiling, work items, outputs and the software pipeline (indices two entries
+// ahead, gathered sources one entry ahead spread over the k steps, operator one k step
+// ahead, global loads only) are those of k_gemm.
 template <int P>
 __global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                                  const uint8_t *entry_mask, const uint64_t *key_ptr,
@@ -355,97 +381,146 @@ __global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t
     constexpr int RBW = (NRB + 3) / 4;
     constexpr int NK32 = KP / 32;                // k steps of 32
     constexpr bool TAIL16 = (KP % 32) != 0;      // one k step of 16 at the end
+    constexpr int NKS = NK32 + (TAIL16 ? 1 : 0); // k steps
     constexpr int NQ = KP / 8;                   // 16-byte pieces (8 halves) per vector
-    constexpr int NPF = (kTileN * NQ + 255) / 256;
+    constexpr int NG = kTileN * NQ;              // pieces per entry and half
+    constexpr int NPF = (NG + 255) / 256;
+    static_assert(kTileN == 64, "64-column tiles");
     __shared__ __attribute__((aligned(16))) _Float16 Bh[kTileN * KPH];
     __shared__ __attribute__((aligned(16))) _Float16 Bl[kTileN * KPH];
     __shared__ float colinv[kTileN];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lg = lane >> 4;
     const int4 w = work[blockIdx.x];
+    const int e0 = w.y, e1 = w.z;
+    if (e0 >= e1) return;
     floatx4 acc[RBW][4];
 #pragma unroll
     for (int r = 0; r < RBW; ++r)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    float4 ph[NPF], pl[NPF];
-    float pinv = 0.f;
-    auto gather = [&](int e) {
+    typedef __attribute__((address_space(1))) const half8 ghalf8;
+    typedef __attribute__((address_space(1))) const half4 ghalf4;
+    typedef __attribute__((address_space(1))) const float gfloat;
+    auto clampe = [&](int e) { return min(e, e1 - 1); };
+    auto mask_of = [&](int e) { return (int)entry_mask[e]; };
+    half8 ah[RBW], al[RBW], nh[RBW], nl[RBW];
+    auto t_step = [&](const _Float16 *H, int kc, half8 *dh, half8 *dl) {   // one 32-wide k step
+        const ghalf8 *Hg = (const ghalf8 *)H, *Lg = (const ghalf8 *)(H + KP * KP);
 #pragma unroll
-        for (int i = 0; i < NPF; ++i) {
-            const int idx = tid + 256 * i;
-            ph[i] = pl[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (idx < kTileN * NQ) {
-                const int col = idx / NQ, q = idx % NQ;
-                const int src = entry_src[(int64_t)e * kTileN + col];
-                if (src >= 0) {
-                    ph[i] = reinterpret_cast<const float4 *>(Mh + (int64_t)src * KP)[q];
-                    pl[i] = reinterpret_cast<const float4 *>(Ml + (int64_t)src * KP)[q];
-                }
-            }
-        }
-        if (tid < kTileN) {
-            const int src = entry_src[(int64_t)e * kTileN + tid];
-            pinv = src >= 0 ? sinv[src] : 0.f;
+        for (int r = 0; r < RBW; ++r) {
+            const int rb = min(wave + 4 * r, NRB - 1);
+            const int off = ((rb * 16 + li) * KP + kc * 32 + 8 * lg) / 8;
+            dh[r] = Hg[off];
+            dl[r] = Lg[off];
         }
     };
-    if (w.y < w.z) gather(w.y);
-    for (int e = w.y; e < w.z; ++e) {
+    float4 ph[NPF], pl[NPF];
+    int srcs[NPF];
+    float pinv = 0.f;
+    int csrc = -1;                               // this lane's column source (wave 0)
+    auto gather_src = [&](int idxv) {
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) srcs[i] = __shfl(idxv, min(tid + 256 * i, NG - 1) / NQ, 64);
+        csrc = idxv;
+    };
+    auto gather_piece = [&](int i) {
+        const int q = min(tid + 256 * i, NG - 1) % NQ;
+        const int64_t row = (int64_t)max(srcs[i], 0) * KP;
+        ph[i] = reinterpret_cast<const float4 *>(Mh + row)[q];
+        pl[i] = reinterpret_cast<const float4 *>(Ml + row)[q];
+    };
+    auto gather_step = [&](int ks) {             // the pieces issued during k step ks
+#pragma unroll
+        for (int i = ks * NPF / NKS; i < (ks + 1) * NPF / NKS; ++i) gather_piece(i);
+        if (ks == 0) pinv = sinv[max(csrc, 0)];
+    };
+
+    // prologue
+    gather_src(entry_src[(int64_t)e0 * kTileN + lane]);
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) gather_step(ks);
+    const char *Tc = reinterpret_cast<const char *>(key_ptr[entry_key[e0]]);
+    int mask = mask_of(e0);
+    if (NK32 > 0) t_step(reinterpret_cast<const _Float16 *>(Tc), 0, ah, al);
+    int idx = entry_src[(int64_t)clampe(e0 + 1) * kTileN + lane];
+    int key_n = entry_key[clampe(e0 + 1)];
+    int mask_n = mask_of(clampe(e0 + 1));
+
+    for (int e = e0; e < e1; ++e) {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NPF; ++i) {
-            const int idx = tid + 256 * i;
-            if (idx < kTileN * NQ) {
-                const int col = idx / NQ, q = idx % NQ;
-                *reinterpret_cast<float4 *>(&Bh[col * KPH + 8 * q]) = ph[i];
-                *reinterpret_cast<float4 *>(&Bl[col * KPH + 8 * q]) = pl[i];
+            const int g = tid + 256 * i;
+            if (g < NG) {
+                const int col = g / NQ, q = g % NQ;
+                const bool ok = srcs[i] >= 0;
+                *reinterpret_cast<float4 *>(&Bh[col * KPH + 8 * q]) = ok ? ph[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                *reinterpret_cast<float4 *>(&Bl[col * KPH + 8 * q]) = ok ? pl[i] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
-        if (tid < kTileN) colinv[tid] = pinv;
+        if (tid < kTileN) colinv[tid] = csrc >= 0 ? pinv : 0.f;
+        gather_src(idx);                         // entry e+1
+        const int m = __builtin_amdgcn_readfirstlane(mask);
+        const int kn = __builtin_amdgcn_readfirstlane(key_n);
+        mask = mask_n;
         __syncthreads();
-        const char *base = reinterpret_cast<const char *>(key_ptr[entry_key[e]]);
-        const _Float16 *H = reinterpret_cast<const _Float16 *>(base);
-        const _Float16 *Lo = H + KP * KP;
-        const float *rs = reinterpret_cast<const float *>(Lo + KP * KP);
-        const int mask = entry_mask ? (int)entry_mask[e] : 15;
-        if (e + 1 < w.z) gather(e + 1);
+        const _Float16 *H = reinterpret_cast<const _Float16 *>(Tc);
+        const char *Tn = reinterpret_cast<const char *>(key_ptr[kn]);
+        float4 r4[RBW];                          // this entry's row scales
+        {
+            const gfloat *rs = (const gfloat *)(H + 2 * KP * KP);
+#pragma unroll
+            for (int r = 0; r < RBW; ++r) {
+                const int rb = min(wave + 4 * r, NRB - 1);
+                r4[r] = make_float4(rs[rb * 16 + 4 * lg], rs[rb * 16 + 4 * lg + 1], rs[rb * 16 + 4 * lg + 2],
+                                    rs[rb * 16 + 4 * lg + 3]);
+            }
+        }
+        idx = entry_src[(int64_t)clampe(e + 2) * kTileN + lane];
+        key_n = entry_key[clampe(e + 2)];
+        mask_n = mask_of(clampe(e + 2));
         floatx4 tmp[RBW][4];
 #pragma unroll
         for (int r = 0; r < RBW; ++r)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) tmp[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        half8 ah[RBW], al[RBW], nh[RBW], nl[RBW];
-        auto load_t = [&](int kc, half8 *dh, half8 *dl) {
+        constexpr int k0 = NK32 * 32;
+        half4 th[RBW], tl[RBW];
+        auto t_tail = [&]() {
+            const ghalf4 *Hg = (const ghalf4 *)H, *Lg = (const ghalf4 *)(H + KP * KP);
 #pragma unroll
             for (int r = 0; r < RBW; ++r) {
-                const int rb = wave + 4 * r;
-                if (rb < NRB) {
-                    const int64_t off = (int64_t)(rb * 16 + li) * KP + kc * 32 + 8 * lg;
-                    dh[r] = *reinterpret_cast<const half8 *>(H + off);
-                    dl[r] = *reinterpret_cast<const half8 *>(Lo + off);
-                }
+                const int rb = min(wave + 4 * r, NRB - 1);
+                const int off = ((rb * 16 + li) * KP + k0 + 4 * lg) / 4;
+                th[r] = Hg[off];
+                tl[r] = Lg[off];
             }
         };
-        if (NK32 > 0) load_t(0, ah, al);
+        if (TAIL16 && NK32 == 0) t_tail();
 #pragma unroll
         for (int kc = 0; kc < NK32; ++kc) {
-            if (kc + 1 < NK32) load_t(kc + 1, nh, nl);
+            if (kc + 1 < NK32) t_step(H, kc + 1, nh, nl);
+            else if (TAIL16) t_tail();
+            else t_step(reinterpret_cast<const _Float16 *>(Tn), 0, nh, nl);
+            gather_step(kc);
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
-                if (!((mask >> cb) & 1)) continue;
+                if (!((m >> cb) & 1)) continue;
                 const int boff = (cb * 16 + li) * KPH + kc * 32 + 8 * lg;
                 const half8 bh = *reinterpret_cast<const half8 *>(&Bh[boff]);
                 const half8 bl = *reinterpret_cast<const half8 *>(&Bl[boff]);
 #pragma unroll
                 for (int r = 0; r < RBW; ++r) {
-                    if (wave + 4 * r >= NRB) continue;
+                    if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bh, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bl, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], bh, tmp[r][cb], 0, 0, 0);
                 }
             }
-            if (kc + 1 < NK32) {
+            if (kc + 1 < NK32 || !TAIL16) {
 #pragma unroll
                 for (int r = 0; r < RBW; ++r) {
                     ah[r] = nh[r];
@@ -454,48 +529,38 @@ __global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t
             }
         }
         if (TAIL16) {
-            constexpr int k0 = NK32 * 32;
-            half4 ah[RBW], al[RBW];
-#pragma unroll
-            for (int r = 0; r < RBW; ++r) {
-                const int rb = wave + 4 * r;
-                if (rb < NRB) {
-                    const int64_t off = (int64_t)(rb * 16 + li) * KP + k0 + 4 * lg;
-                    ah[r] = *reinterpret_cast<const half4 *>(H + off);
-                    al[r] = *reinterpret_cast<const half4 *>(Lo + off);
-                }
-            }
+            if (NK32 > 0) t_step(reinterpret_cast<const _Float16 *>(Tn), 0, ah, al);
+            gather_step(NKS - 1);
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
-                if (!((mask >> cb) & 1)) continue;
+                if (!((m >> cb) & 1)) continue;
                 const int boff = (cb * 16 + li) * KPH + k0 + 4 * lg;
                 const half4 bh = *reinterpret_cast<const half4 *>(&Bh[boff]);
                 const half4 bl = *reinterpret_cast<const half4 *>(&Bl[boff]);
 #pragma unroll
                 for (int r = 0; r < RBW; ++r) {
-                    if (wave + 4 * r >= NRB) continue;
-                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[r], bh, tmp[r][cb], 0, 0, 0);
-                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[r], bl, tmp[r][cb], 0, 0, 0);
-                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(al[r], bh, tmp[r][cb], 0, 0, 0);
+                    if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(th[r], bh, tmp[r][cb], 0, 0, 0);
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(th[r], bl, tmp[r][cb], 0, 0, 0);
+                    tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(tl[r], bh, tmp[r][cb], 0, 0, 0);
                 }
             }
         }
         // back to the FP32 basis: rows by rs, columns by the source's inverse scale
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
-            const int rb = wave + 4 * r;
-            if (rb >= NRB) continue;
-            const float4 r4 = *reinterpret_cast<const float4 *>(rs + rb * 16 + 4 * lg);
+            if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
-                if (!((mask >> cb) & 1)) continue;
+                if (!((m >> cb) & 1)) continue;
                 const float ci = colinv[cb * 16 + li];
-                acc[r][cb][0] += r4.x * ci * tmp[r][cb][0];
-                acc[r][cb][1] += r4.y * ci * tmp[r][cb][1];
-                acc[r][cb][2] += r4.z * ci * tmp[r][cb][2];
-                acc[r][cb][3] += r4.w * ci * tmp[r][cb][3];
+                acc[r][cb][0] += r4[r].x * ci * tmp[r][cb][0];
+                acc[r][cb][1] += r4[r].y * ci * tmp[r][cb][1];
+                acc[r][cb][2] += r4[r].z * ci * tmp[r][cb][2];
+                acc[r][cb][3] += r4[r].w * ci * tmp[r][cb][3];
             }
         }
+        Tc = Tn;
     }
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
@@ -518,7 +583,6 @@ __global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t
     }
 }
 
-// Sum the partial tiles of split work items into L (fixed order: deterministic).
 __global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int32_t *tile_work_idx, const int4 *work,
                              const float *partial, const int32_t *tile_targets, int KP, float *L) {
     const int64_t t = blockIdx.x;
@@ -908,7 +972,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     for (int l = Pl->max_level - 1; l >= RL; --l) {
         const int t0 = Pl->m2m.bucket_tile[l * 8], t1 = Pl->m2m.bucket_tile[l * 8 + 8];
         if (t1 > t0)
-            hipLaunchKernelGGL((k_gemm<P, false>), t1 - t0, 256, 0, s, (const int4 *)Pl->m2m.work + t0,
+            hipLaunchKernelGGL((k_gemm<P, false, false>), t1 - t0, 256, 0, s, (const int4 *)Pl->m2m.work + t0,
                                (const int32_t *)Pl->m2m.entry_key, (const int32_t *)Pl->m2m.entry_src,
                                (const uint8_t *)nullptr, T.m2m_ptrs, (const float *)Pl->M, Pl->M, (float *)nullptr,
                                (const int32_t *)Pl->m2m.tile_targets);
@@ -941,7 +1005,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
                                (const _Float16 *)Pl->Ml, (const float *)Pl->Msinv, Pl->L, Pl->partial,
                                (const int32_t *)Pl->tile_targets);
         else
-            hipLaunchKernelGGL((k_gemm<P, false>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
+            hipLaunchKernelGGL((k_gemm<P, false, true>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
                                (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
                                (const uint8_t *)Pl->entry_mask, Pl->key_f32, (const float *)Pl->M, Pl->L, Pl->partial,
                                (const int32_t *)Pl->tile_targets);
@@ -977,7 +1041,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     for (int l = mixed ? RL : 1; l <= Pl->max_level; ++l) {
         const int t0 = Pl->l2l.bucket_tile[l * 8], t1 = Pl->l2l.bucket_tile[l * 8 + 8];
         if (t1 > t0)
-            hipLaunchKernelGGL((k_gemm<P, true>), t1 - t0, 256, 0, s, (const int4 *)Pl->l2l.work + t0,
+            hipLaunchKernelGGL((k_gemm<P, true, false>), t1 - t0, 256, 0, s, (const int4 *)Pl->l2l.work + t0,
                                (const int32_t *)Pl->l2l.entry_key, (const int32_t *)Pl->l2l.entry_src,
                                (const uint8_t *)nullptr, T.l2l_ptrs, (const float *)Pl->L, Pl->L, (float *)nullptr,
                                (const int32_t *)Pl->l2l.tile_targets);

@@ -1031,29 +1031,30 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         if (const char *ev = getenv("FMM_M2L_PIECE")) piece = std::max<int64_t>(1, atoll(ev));
         if (const char *ev = getenv("FMM_M2L_ITEMS")) items = std::max<int64_t>(1, atoll(ev));
         int64_t per = std::max<int64_t>(piece, (ne + items - 1) / items);
-        std::vector<std::vector<int4>> pieces;      // pieces[k]: the k-th piece of every tile
-        std::vector<int32_t> npieces(ntiles);
+        std::vector<std::vector<int4>> tp(ntiles);   // pieces of each tile, in entry order
+        int64_t maxp = 0;
         for (int64_t t = 0; t < ntiles; ++t) {
             int64_t e0 = htf[t], e1 = htf[t + 1];
             int64_t cntE = e1 - e0;
             int64_t chunks = std::max<int64_t>(1, (cntE + per - 1) / per);
-            int64_t sz = (cntE + chunks - 1) / chunks;
-            int k2 = 0;
-            for (int64_t c0 = e0; c0 < e1; c0 += sz, ++k2) {
-                if ((int)pieces.size() <= k2) pieces.emplace_back();
-                pieces[k2].push_back(make_int4((int)t, (int)c0, (int)std::min(e1, c0 + sz), chunks > 1 ? 1 : 0));
-            }
-            npieces[t] = k2;
+            int64_t sz = std::max<int64_t>(1, (cntE + chunks - 1) / chunks);
+            for (int64_t c0 = e0; c0 < e1; c0 += sz)
+                tp[t].push_back(make_int4((int)t, (int)c0, (int)std::min(e1, c0 + sz), chunks > 1 ? 1 : 0));
+            maxp = std::max<int64_t>(maxp, (int64_t)tp[t].size());
         }
+        std::vector<int4> order;
+        order.reserve(ne);
+        for (int64_t k2 = 0; k2 < maxp; ++k2)
+            for (int64_t t = 0; t < ntiles; ++t)
+                if (k2 < (int64_t)tp[t].size()) order.push_back(tp[t][k2]);
         std::vector<int4> hw;
         std::vector<std::vector<int32_t>> per_tile(ntiles);
         int64_t nsplit = 0;
-        for (auto &pc : pieces)
-            for (int4 w4 : pc) {
-                if (w4.w) w4.w = (int)(++nsplit);
-                per_tile[w4.x].push_back((int32_t)hw.size());
-                hw.push_back(w4);
-            }
+        for (int4 w4 : order) {
+            if (w4.w) w4.w = (int)(++nsplit);
+            per_tile[w4.x].push_back((int32_t)hw.size());
+            hw.push_back(w4);
+        }
         std::vector<int32_t> htw(ntiles + 1), htwi;
         for (int64_t t = 0; t < ntiles; ++t) {
             htw[t] = (int32_t)htwi.size();
