@@ -167,7 +167,8 @@ __global__ void k_write_children(int64_t ncl, int64_t glob_base, int64_t next_ba
                                  const int32_t *off, const int32_t *cstart8, const int32_t *ccount8,
                                  const uint64_t *prefix, const int32_t *ix, const int32_t *iy, const int32_t *iz,
                                  int32_t *child0, uint64_t *n_prefix, int32_t *n_ix, int32_t *n_iy, int32_t *n_iz,
-                                 int32_t *n_start, int32_t *n_count, int32_t *n_parent) {
+                                 int32_t *n_start, int32_t *n_count, int32_t *n_parent, int32_t *n_level,
+                                 int32_t child_level) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= ncl) return;
     int nch = nchild[i];
@@ -184,7 +185,20 @@ __global__ void k_write_children(int64_t ncl, int64_t glob_base, int64_t next_ba
         n_start[w] = cstart8[i * 8 + o];
         n_count[w] = cc;
         n_parent[w] = (int32_t)(glob_base + i);
+        n_level[w] = child_level;
         ++w;
+    }
+}
+
+__global__ void k_init_root(int32_t n, uint64_t *prefix, int32_t *ix, int32_t *iy, int32_t *iz, int32_t *start,
+                            int32_t *count, int32_t *parent, int32_t *level) {
+    if (threadIdx.x == 0) {
+        prefix[0] = 0;
+        ix[0] = iy[0] = iz[0] = 0;
+        start[0] = 0;
+        count[0] = n;
+        parent[0] = -1;
+        level[0] = 0;
     }
 }
 
@@ -265,8 +279,8 @@ __device__ inline void block_scan3(int v0, int v1, int v2, int &e0, int &e1, int
 
 // One traversal step.  Every pair of `front` needs a split; its child pairs (rules 3-4)
 // are classified here: M2L and P2P pairs go to their lists, pairs that need a further
-// split to `next`.  Each thread counts its outputs, one block scan and one atomic per
-// list reserve the ranges, then the thread writes.  Writes past a list's capacity are
+// split to `next`.  Each lane classifies one child pair, one block scan and one atomic
+// per list reserve the ranges, then the lane writes.  Writes past a list's capacity are
 // dropped; the counters still advance, so the host sees the exact sizes and repeats
 // the step with larger lists.
 __device__ inline void split_ranges(const CellView &C, int a, int b, int &a0, int &na, int &b0, int &nb) {
@@ -291,23 +305,35 @@ __device__ inline int action(const CellView &C, int a, int b, double theta2) {
     return 2;
 }
 
+// Each wave takes kTravPerWave frontier pairs in turn, one lane per child pair (at most
+// 8 x 8); the lane keeps its outcomes, the block reserves its output ranges once.
+constexpr int kTravPerWave = 8;
 __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front, int64_t nf, double theta2,
                                                    unsigned long long *cnt, int2 *m2l, int64_t cap_m, int2 *p2p,
                                                    int64_t cap_p, int2 *next, int64_t cap_n) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int a0 = 0, na = 0, b0 = 0, nb = 0;
-    if (i < nf) {
-        int2 pr = front[i];
-        split_ranges(C, pr.x, pr.y, a0, na, b0, nb);
-    }
+    const int64_t f0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6)) * kTravPerWave;
+    const int lane = threadIdx.x & 63, x = lane >> 3, y = lane & 7;
+    int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave];
     int m = 0, q = 0, nx = 0;
-    for (int x = 0; x < na; ++x)
-        for (int y = 0; y < nb; ++y) {
-            int act = action(C, a0 + x, b0 + y, theta2);
-            m += act == 0;
-            q += act == 1;
-            nx += act == 2;
+#pragma unroll
+    for (int k = 0; k < kTravPerWave; ++k) {
+        const int64_t f = f0 + k;
+        pa[k] = pb[k] = 0;
+        act[k] = -1;
+        if (f < nf) {
+            int a0, na, b0, nb;
+            const int2 pr = front[f];
+            split_ranges(C, pr.x, pr.y, a0, na, b0, nb);
+            if (x < na && y < nb) {
+                pa[k] = a0 + x;
+                pb[k] = b0 + y;
+                act[k] = action(C, pa[k], pb[k], theta2);
+            }
         }
+        m += act[k] == 0;
+        q += act[k] == 1;
+        nx += act[k] == 2;
+    }
     int e0, e1, e2, t0, t1, t2;
     block_scan3(m, q, nx, e0, e1, e2, t0, t1, t2);
     __shared__ unsigned long long base[3];
@@ -318,14 +344,13 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
     }
     __syncthreads();
     int64_t wm = (int64_t)(base[0] + e0), wq = (int64_t)(base[1] + e1), wn = (int64_t)(base[2] + e2);
-    for (int x = 0; x < na; ++x)
-        for (int y = 0; y < nb; ++y) {
-            int a = a0 + x, b = b0 + y;
-            int act = action(C, a, b, theta2);
-            if (act == 0) { if (wm < cap_m) m2l[wm] = make_int2(a, b); ++wm; }
-            else if (act == 1) { if (wq < cap_p) p2p[wq] = make_int2(a, b); ++wq; }
-            else { if (wn < cap_n) next[wn] = make_int2(a, b); ++wn; }
-        }
+#pragma unroll
+    for (int k = 0; k < kTravPerWave; ++k) {
+        const int2 v = make_int2(pa[k], pb[k]);
+        if (act[k] == 0) { if (wm < cap_m) m2l[wm] = v; ++wm; }
+        else if (act[k] == 1) { if (wq < cap_p) p2p[wq] = v; ++wq; }
+        else if (act[k] == 2) { if (wn < cap_n) next[wn] = v; ++wn; }
+    }
 }
 
 // ----------------------------------------------------------------- M2L grouping
@@ -341,14 +366,6 @@ __device__ inline void block_add_u64(unsigned long long v, unsigned long long *d
         unsigned long long t = ws[0] + ws[1] + ws[2] + ws[3];
         if (t) atomicAdd(dst, t);
     }
-}
-
-__global__ void __launch_bounds__(256) k_count_same_level(const int32_t *pair_key_id, int64_t n,
-                                                          const int32_t *key_same, unsigned long long *cnt) {
-    unsigned long long loc = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        loc += key_same[pair_key_id[i]] ? 1ull : 0ull;
-    block_add_u64(loc, cnt);
 }
 
 __device__ inline uint64_t key_hash(uint64_t k) {   // splitmix64 finaliser
@@ -376,9 +393,9 @@ __device__ inline uint64_t pair_key(const CellView &C, int a, int b, int32_t *ov
 }
 
 // Insert the key of every M2L pair into an open-addressing table (linear probing,
-// at most `mask + 1` probes; a full table raises flags[1]).
+// at most `mask + 1` probes; a full table raises flags[1]) and record the pair's slot.
 __global__ void k_key_insert(const int2 *pairs, int64_t np, CellView C, uint64_t *table, uint64_t mask,
-                             int32_t *flags) {
+                             int32_t *pair_slot, int32_t *flags) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t key = pair_key(C, pairs[i].x, pairs[i].y, flags);
         uint64_t h = key_hash(key) & mask;
@@ -393,44 +410,55 @@ __global__ void k_key_insert(const int2 *pairs, int64_t np, CellView C, uint64_t
             }
             h = (h + 1) & mask;
         }
+        pair_slot[i] = (int32_t)h;
         if (!done) flags[1] = 1;
     }
 }
 
-// Key id of every pair (the key is in the table), and the (tile, key) presence table.
-__global__ void k_key_ids(const int2 *pairs, int64_t np, CellView C, const uint64_t *table, uint64_t mask,
-                          const int32_t *slot_id, const int32_t *cell_tile, int64_t nkeys, int32_t *pair_key_id,
-                          int32_t *present, int32_t *flags) {
+// Key id of every pair (from its slot), the (tile, key) presence table, and the number
+// of pairs whose key joins cells of the same level.
+__global__ void __launch_bounds__(256) k_key_ids(const int2 *pairs, int64_t np, const int32_t *slot_id,
+                                                 const int32_t *key_same, const int32_t *cell_tile, int64_t nkeys,
+                                                 int32_t *pair_key_id, int32_t *present,
+                                                 unsigned long long *nsame) {
+    unsigned long long loc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t key = pair_key(C, pairs[i].x, pairs[i].y, flags);
-        uint64_t h = key_hash(key) & mask;
-        for (uint64_t probe = 0; probe <= mask; ++probe) {
-            if (table[h] == key) break;
-            h = (h + 1) & mask;
-        }
-        int id = slot_id[h];
+        const int id = slot_id[pair_key_id[i]];
         pair_key_id[i] = id;
         present[(int64_t)cell_tile[pairs[i].x] * nkeys + id] = 1;
+        loc += key_same[id] ? 1ull : 0ull;
     }
+    block_add_u64(loc, nsame);
 }
 
 // Entries are the present (tile, key) cells in tile-major, key-ascending order.
 __global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pair_key_id, const int32_t *cell_tile,
-                               const int32_t *cell_lane, const int32_t *entry_of, int64_t nkeys, int32_t *entry_key,
-                               int32_t *entry_src, int32_t *entry_mask32) {
+                               const int32_t *cell_lane, const int32_t *entry_of, int64_t nkeys, int32_t *entry_src) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         int a = pairs[i].x, k = pair_key_id[i];
         int e = entry_of[(int64_t)cell_tile[a] * nkeys + k];
         int lane = cell_lane[a];
-        entry_key[e] = k;
         entry_src[(int64_t)e * kTileN + lane] = pairs[i].y;
-        atomicOr(&entry_mask32[e], 1 << (lane >> 4));
     }
 }
 
-__global__ void k_mask_narrow(const int32_t *m32, int64_t n, uint8_t *m8) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        m8[i] = (uint8_t)m32[i];
+__global__ void k_entry_keys(const int32_t *present, const int32_t *entry_of, int64_t ntk, int64_t nkeys,
+                             int32_t *entry_key) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntk; i += (int64_t)gridDim.x * blockDim.x)
+        if (present[i]) entry_key[entry_of[i]] = (int32_t)(i % nkeys);
+}
+
+// Column-block mask of every entry: bit cb set iff one of its columns 16cb..16cb+15 has a source.
+__global__ void k_entry_masks(const int32_t *entry_src, int64_t ne, uint8_t *m8) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+        const int4 *row = reinterpret_cast<const int4 *>(entry_src + e * kTileN);
+        int m = 0;
+        for (int q = 0; q < kTileN / 4; ++q) {
+            const int4 v = row[q];
+            if (v.x >= 0 || v.y >= 0 || v.z >= 0 || v.w >= 0) m |= 1 << (q / 4);
+        }
+        m8[e] = (uint8_t)m;
+    }
 }
 
 __global__ void k_tile_first(const int32_t *entry_of, int64_t ntiles, int64_t nkeys, int32_t *tile_first) {
@@ -734,82 +762,48 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_bodies, grid1(n), 256, 0, s, points, (const int32_t *)perm, n, P->bodies);
 
     lg("sort+permute");
-    // ---- a3: octree, level by level
-    struct Lvl {
-        int64_t n = 0;
-        uint64_t *prefix = nullptr;
-        int32_t *ix = nullptr, *iy = nullptr, *iz = nullptr, *start = nullptr, *count = nullptr, *parent = nullptr;
-        int32_t *nchild = nullptr, *child0 = nullptr;
+    // ---- a3: octree, level by level, written straight into the global cell arrays
+    // (level l occupies [level_off[l], level_off[l+1]); arrays grow by doubling)
+    int64_t cap = std::max<int64_t>(4096, 8 * n / std::max(1, P->ncrit) + 64);
+    uint64_t *c_prefix = a.get_n<uint64_t>(cap);
+    int32_t **c32[9] = {&P->c_ix, &P->c_iy, &P->c_iz, &P->c_start, &P->c_count, &P->c_parent, &P->c_nchild,
+                        &P->c_child0, &P->c_level};
+    for (int q = 0; q < 9; ++q) *c32[q] = a.get_n<int32_t>(cap);
+    auto ensure = [&](int64_t used, int64_t need) {
+        if (need <= cap) return;
+        int64_t c2 = cap;
+        grow(a, c_prefix, c2, used, need, s);
+        for (int q = 0; q < 9; ++q) {
+            c2 = cap;
+            grow(a, *c32[q], c2, used, need, s);
+        }
+        cap = c2;
     };
-    std::vector<Lvl> lv;
-    {
-        Lvl r;
-        r.n = 1;
-        r.prefix = a.get_n<uint64_t>(1);
-        r.ix = a.get_n<int32_t>(1); r.iy = a.get_n<int32_t>(1); r.iz = a.get_n<int32_t>(1);
-        r.start = a.get_n<int32_t>(1); r.count = a.get_n<int32_t>(1); r.parent = a.get_n<int32_t>(1);
-        uint64_t z64 = 0;
-        int32_t z = 0, cnt = (int32_t)n, m1 = -1;
-        HIP_CHECK(hipMemcpyAsync(r.prefix, &z64, 8, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(r.ix, &z, 4, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(r.iy, &z, 4, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(r.iz, &z, 4, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(r.start, &z, 4, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(r.count, &cnt, 4, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(r.parent, &m1, 4, hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));   // host sources go out of scope
-        lv.push_back(r);
-    }
+    hipLaunchKernelGGL(k_init_root, 1, 64, 0, s, (int32_t)n, c_prefix, P->c_ix, P->c_iy, P->c_iz, P->c_start,
+                       P->c_count, P->c_parent, P->c_level);
     std::vector<int64_t> level_off{0, 1};
     for (int l = 0;; ++l) {
-        Lvl &L = lv[l];
-        L.nchild = a.get_n<int32_t>(L.n);
-        L.child0 = a.get_n<int32_t>(L.n);
-        int32_t *cs8 = a.get_n<int32_t>(8 * L.n), *cc8 = a.get_n<int32_t>(8 * L.n), *off = a.get_n<int32_t>(L.n);
-        hipLaunchKernelGGL(k_split, grid1(L.n), 256, 0, s, L.n, (const int32_t *)L.start, (const int32_t *)L.count,
-                           (const uint64_t *)L.prefix, l, P->ncrit, (const uint64_t *)keys, L.nchild, cs8, cc8);
-        int64_t nnext = exclusive_scan_i32(L.nchild, off, L.n, a, s);
-        Lvl N;
-        N.n = nnext;
-        if (nnext > 0) {
-            N.prefix = a.get_n<uint64_t>(nnext);
-            N.ix = a.get_n<int32_t>(nnext); N.iy = a.get_n<int32_t>(nnext); N.iz = a.get_n<int32_t>(nnext);
-            N.start = a.get_n<int32_t>(nnext); N.count = a.get_n<int32_t>(nnext); N.parent = a.get_n<int32_t>(nnext);
-        }
-        hipLaunchKernelGGL(k_write_children, grid1(L.n), 256, 0, s, L.n, level_off[l], level_off[l + 1],
-                           (const int32_t *)L.nchild, (const int32_t *)off, (const int32_t *)cs8, (const int32_t *)cc8,
-                           (const uint64_t *)L.prefix, (const int32_t *)L.ix, (const int32_t *)L.iy,
-                           (const int32_t *)L.iz, L.child0, N.prefix, N.ix, N.iy, N.iz, N.start, N.count, N.parent);
+        const int64_t o0 = level_off[l], o1 = level_off[l + 1], m = o1 - o0;
+        int32_t *cs8 = a.get_n<int32_t>(8 * m), *cc8 = a.get_n<int32_t>(8 * m), *off = a.get_n<int32_t>(m);
+        hipLaunchKernelGGL(k_split, grid1(m), 256, 0, s, m, (const int32_t *)P->c_start + o0,
+                           (const int32_t *)P->c_count + o0, (const uint64_t *)c_prefix + o0, l, P->ncrit,
+                           (const uint64_t *)keys, P->c_nchild + o0, cs8, cc8);
+        const int64_t nnext = exclusive_scan_i32(P->c_nchild + o0, off, m, a, s);
+        ensure(o1, o1 + nnext);
+        hipLaunchKernelGGL(k_write_children, grid1(m), 256, 0, s, m, o0, o1, (const int32_t *)P->c_nchild + o0,
+                           (const int32_t *)off, (const int32_t *)cs8, (const int32_t *)cc8,
+                           (const uint64_t *)c_prefix + o0, (const int32_t *)P->c_ix + o0,
+                           (const int32_t *)P->c_iy + o0, (const int32_t *)P->c_iz + o0, P->c_child0 + o0,
+                           c_prefix + o1, P->c_ix + o1, P->c_iy + o1, P->c_iz + o1, P->c_start + o1, P->c_count + o1,
+                           P->c_parent + o1, P->c_level + o1, l + 1);
         a.put(cs8); a.put(cc8); a.put(off);
         if (nnext == 0) break;
-        lv.push_back(N);
-        level_off.push_back(level_off.back() + nnext);
+        level_off.push_back(o1 + nnext);
     }
-    P->max_level = (int)lv.size() - 1;
+    P->max_level = (int)level_off.size() - 2;
     P->level_off = level_off;
     const int64_t nc = level_off.back();
     P->ncells = nc;
-    // concatenate the levels into global arrays
-    P->c_level = a.get_n<int32_t>(nc);
-    P->c_ix = a.get_n<int32_t>(nc); P->c_iy = a.get_n<int32_t>(nc); P->c_iz = a.get_n<int32_t>(nc);
-    P->c_start = a.get_n<int32_t>(nc); P->c_count = a.get_n<int32_t>(nc); P->c_parent = a.get_n<int32_t>(nc);
-    P->c_child0 = a.get_n<int32_t>(nc); P->c_nchild = a.get_n<int32_t>(nc);
-    uint64_t *c_prefix = a.get_n<uint64_t>(nc);
-    for (size_t l = 0; l < lv.size(); ++l) {
-        int64_t o = level_off[l], m = lv[l].n;
-        fill_i32(P->c_level + o, (int32_t)l, m, s);
-        auto cp = [&](int32_t *dst, const int32_t *src) {
-            HIP_CHECK(hipMemcpyAsync(dst + o, src, 4 * m, hipMemcpyDeviceToDevice, s));
-        };
-        cp(P->c_ix, lv[l].ix); cp(P->c_iy, lv[l].iy); cp(P->c_iz, lv[l].iz);
-        cp(P->c_start, lv[l].start); cp(P->c_count, lv[l].count); cp(P->c_parent, lv[l].parent);
-        cp(P->c_child0, lv[l].child0); cp(P->c_nchild, lv[l].nchild);
-        HIP_CHECK(hipMemcpyAsync(c_prefix + o, lv[l].prefix, 8 * m, hipMemcpyDeviceToDevice, s));
-    }
-    for (auto &L : lv) {
-        a.put(L.prefix); a.put(L.ix); a.put(L.iy); a.put(L.iz); a.put(L.start); a.put(L.count); a.put(L.parent);
-        a.put(L.nchild); a.put(L.child0);
-    }
     P->c_prefix_dev = c_prefix;
 
     lg("octree");
@@ -890,7 +884,11 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             for (int attempt = 0;; ++attempt) {
                 unsigned long long base[3] = {(unsigned long long)nm2l, (unsigned long long)np2p, 0ull};
                 HIP_CHECK(hipMemcpyAsync(cnt, base, sizeof(base), hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_trav_step, grid1(nf), 256, 0, s, C, (const int2 *)front, nf, theta2, cnt, m2l,
+                const int64_t per_block = 4 * kTravPerWave;
+                const int64_t tb = (nf + per_block - 1) / per_block;
+                if (tb >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "traversal frontier too large");
+                hipLaunchKernelGGL(k_trav_step, (int)tb, 256, 0, s, C, (const int2 *)front, nf, theta2,
+                                   cnt, m2l,
                                    m2l_cap, p2p, p2p_cap, next, cap_n);
                 HIP_CHECK(hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, s));
                 HIP_CHECK(hipStreamSynchronize(s));
@@ -933,16 +931,18 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         a.put(is_t);
         lg("m2l target tiles");
 
-        // distinct operator keys through a device hash table
+        // distinct operator keys through a device hash table; every pair keeps its slot
         uint64_t H = 1 << 15;
         int32_t *flags = a.get_n<int32_t>(2);
+        int32_t *pkid = a.get_n<int32_t>(nm2l);
         uint64_t *table = nullptr;
         std::vector<uint64_t> htab;
         for (;;) {
             table = a.get_n<uint64_t>((int64_t)H);
             HIP_CHECK(hipMemsetAsync(table, 0xff, 8 * H, s));
             fill_i32(flags, 0, 2, s);
-            hipLaunchKernelGGL(k_key_insert, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, table, H - 1, flags);
+            hipLaunchKernelGGL(k_key_insert, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, table, H - 1, pkid,
+                               flags);
             int32_t hf[2];
             HIP_CHECK(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
             htab.resize(H);
@@ -964,8 +964,12 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         for (uint64_t h = 0; h < H; ++h)
             if (htab[h] != ~0ull) hslot[h] = (int32_t)(std::lower_bound(hkeys.begin(), hkeys.end(), htab[h]) - hkeys.begin());
         P->nkeys = nkeys;
+        std::vector<int32_t> hsame(nkeys);
         P->nkeys_same = 0;
-        for (uint64_t kk : hkeys) P->nkeys_same += (int(kk >> 57) - 32) == 0;
+        for (int64_t k2 = 0; k2 < nkeys; ++k2) {
+            hsame[k2] = (int(hkeys[k2] >> 57) - 32) == 0;
+            P->nkeys_same += hsame[k2];
+        }
         std::vector<uint64_t> p32, p16;
         m2l_operator_ptrs(P->p, hkeys, p32, p16, P->prec == FMM_PREC_MIXED);
         uint64_t *d32 = a.get_n<uint64_t>(nkeys);
@@ -978,48 +982,42 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         }
         int32_t *slot_id = a.get_n<int32_t>((int64_t)H);
         HIP_CHECK(hipMemcpyAsync(slot_id, hslot.data(), 4 * H, hipMemcpyHostToDevice, s));
+        int32_t *dsame = a.get_n<int32_t>(nkeys);
+        HIP_CHECK(hipMemcpyAsync(dsame, hsame.data(), 4 * nkeys, hipMemcpyHostToDevice, s));
         lg("m2l keys+operators");
 
         // (tile, key) entries: dense presence table, scanned tile-major
         const int64_t ntk = ntiles * nkeys;
         if (ntk >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "M2L tile x key table exceeds 2^31 entries");
         int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk);
-        int32_t *pkid = a.get_n<int32_t>(nm2l);
+        unsigned long long *same = a.get_n<unsigned long long>(1);
+        HIP_CHECK(hipMemsetAsync(same, 0, 8, s));
         fill_i32(present, 0, ntk, s);
-        hipLaunchKernelGGL(k_key_ids, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, (const uint64_t *)table, H - 1,
-                           (const int32_t *)slot_id, (const int32_t *)cell_tile, nkeys, pkid, present, flags);
+        hipLaunchKernelGGL(k_key_ids, std::min(grid1(nm2l), 4096), 256, 0, s, (const int2 *)m2l, nm2l,
+                           (const int32_t *)slot_id, (const int32_t *)dsame, (const int32_t *)cell_tile, nkeys, pkid,
+                           present, same);
         const int64_t ne = exclusive_scan_i32(present, entry_of, ntk, a, s);
+        P->nm2l_same = (int64_t)read_back(same, s);
         P->nentries = ne;
         P->entry_key = a.get_n<int32_t>(ne);
         P->entry_src = a.get_n<int32_t>(ne * kTileN);
         fill_i32(P->entry_src, -1, ne * kTileN, s);
-        int32_t *mask32 = a.get_n<int32_t>(ne);
-        fill_i32(mask32, 0, ne, s);
         hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
                            (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of, nkeys,
-                           P->entry_key, P->entry_src, mask32);
+                           P->entry_src);
+        hipLaunchKernelGGL(k_entry_keys, grid1(ntk), 256, 0, s, (const int32_t *)present, (const int32_t *)entry_of, ntk,
+                           nkeys, P->entry_key);
         P->entry_mask = a.get_n<uint8_t>(ne);
-        hipLaunchKernelGGL(k_mask_narrow, grid1(ne), 256, 0, s, (const int32_t *)mask32, ne, P->entry_mask);
+        hipLaunchKernelGGL(k_entry_masks, grid1(ne), 256, 0, s, (const int32_t *)P->entry_src, ne, P->entry_mask);
         int32_t *tile_first = a.get_n<int32_t>(ntiles);
         hipLaunchKernelGGL(k_tile_first, grid1(ntiles), 256, 0, s, (const int32_t *)entry_of, ntiles, nkeys, tile_first);
         std::vector<int32_t> htf(ntiles);
         HIP_CHECK(hipMemcpyAsync(htf.data(), tile_first, 4 * ntiles, hipMemcpyDeviceToHost, s));
-        // M2L pairs between cells of the same level
-        {
-            std::vector<int32_t> hsame(nkeys);
-            for (int64_t k2 = 0; k2 < nkeys; ++k2) hsame[k2] = (int(hkeys[k2] >> 57) - 32) == 0;
-            int32_t *dsame = a.get_n<int32_t>(nkeys);
-            HIP_CHECK(hipMemcpyAsync(dsame, hsame.data(), 4 * nkeys, hipMemcpyHostToDevice, s));
-            unsigned long long *same = a.get_n<unsigned long long>(1);
-            HIP_CHECK(hipMemsetAsync(same, 0, 8, s));
-            hipLaunchKernelGGL(k_count_same_level, std::min(grid1(nm2l), 1024), 256, 0, s, (const int32_t *)pkid, nm2l,
-                               (const int32_t *)dsame, same);
-            P->nm2l_same = (int64_t)read_back(same, s);   // synchronises: host vectors above may go
-            a.put(same);
-            a.put(dsame);
-        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        a.put(same);
+        a.put(dsame);
         a.put(flags); a.put(table); a.put(slot_id); a.put(present); a.put(entry_of); a.put(pkid);
-        a.put(tile_first); a.put(cell_tile); a.put(cell_lane); a.put(mask32);
+        a.put(tile_first); a.put(cell_tile); a.put(cell_lane);
         lg("m2l entries");
 
         // work items: split each tile's entries into pieces so that there are enough items
