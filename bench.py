@@ -29,7 +29,9 @@ MFMA_FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 MFMA
 # factors from a 1 GiB plain copy), measured with rocprofv3 on the kernel source whose
 # sha256 prefix is given; reported only while the source is unchanged.
 M2L_TRAFFIC = {"eval_sha256": "284b126a1c49deeb", "workload": "uniform-1M", "p": 10, "theta": 0.4, "bytes": 15.80e9}
-VALU_FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (packed); 78.6 without packed math
+VALU_FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X FP32 vector with packed (2-wide) FMA
+VALU_FP32_PEAK_TFLOPS = 78.6           # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 not used
+P2P_ISSUE_PEAK_TFLOPS = 46.3           # the same lanes at 17 issue slots per 20-flop interaction
 
 
 def parse():
@@ -93,6 +95,8 @@ def main():
         t0 = time.perf_counter()
         plan = FMM(xt, ncrit, p, theta, args.precision)
         if record is not None:
+            torch.cuda.synchronize()
+            record["plan"].append(time.perf_counter() - t0)
             plan.set_timing(True)
         phi, grad = plan.eval(qt)
         if record is not None:
@@ -111,10 +115,16 @@ def main():
         plan2.close()
         return phi, grad, dq, dx
 
+    # the first plan of a process also builds the (p, theta) operator tables, a cached constant
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    FMM(xt, ncrit, p, theta, args.precision).close()
+    torch.cuda.synchronize()
+    first_plan_ms = 1e3 * (time.perf_counter() - t0)
     for _ in range(args.warmup):
         step(None)
     torch.cuda.synchronize()
-    rec = {"fwd": [], "eval_phases": [], "adj_phases": []}
+    rec = {"fwd": [], "plan": [], "eval_phases": [], "adj_phases": []}
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = step(rec)
@@ -148,7 +158,10 @@ def main():
         "fwd_particles_per_s": n / float(np.mean(rec["fwd"])),
         "eval_particles_per_s": n / (eval_ms * 1e-3),
         "phase_ms": ph,
+        "plan_ms": 1e3 * float(np.mean(rec["plan"])),
+        "table_build_ms": first_plan_ms - 1e3 * float(np.mean(rec["plan"])),
         "p2p_tflops": p2p_tflops,
+        "p2p_interactions_per_s": st["p2p_interactions"] / (p2p_ms * 1e-3),
         "m2l_tflops": m2l_tflops,
         "p2p_interactions": st["p2p_interactions"],
         "m2l_pairs": st["m2l_pairs"],
@@ -164,7 +177,9 @@ def main():
             "traffic": m2l_traffic(args.workload, p, theta),
         },
         "p2p_roofline": {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_tflops, "peak": VALU_FP32_PEAK_TFLOPS,
-                         "unit": "TFLOP/s (20 flop/interaction)", "frac": p2p_tflops / VALU_FP32_PEAK_TFLOPS},
+                         "unit": "TFLOP/s (20 flop/interaction)", "frac": p2p_tflops / VALU_FP32_PEAK_TFLOPS,
+                         "frac_of_packed_peak": p2p_tflops / VALU_FP32_PACKED_PEAK_TFLOPS,
+                         "frac_of_issue_peak": p2p_tflops / P2P_ISSUE_PEAK_TFLOPS},
     }
 
     if not args.skip_accuracy:
@@ -179,6 +194,10 @@ def main():
         result["accuracy_ok"] = bool(max(err.values()) <= 1e-4)
 
     if not args.skip_cpu_baseline:
+        # the FP64 oracle runs the same step: plan + forward FMM + plan + adjoint FMM (the FMM
+        # with charges w, whose potential and gradient give dL/dq and dL/dx); the full plan
+        # and upward passes are timed, M2L/L2L/L2P/P2P are timed on the targets of 2048
+        # random leaves and scaled by the leaf count
         import oracle
         threads = oracle.set_threads(0)
         t0 = time.perf_counter()
@@ -187,23 +206,27 @@ def main():
         cells = ora.cells()
         order, _ = ora.order()
         leaves = np.nonzero(cells["leaf"])[0]
-        nl_s = min(512, leaves.shape[0])
+        nl_s = min(2048, leaves.shape[0])
         pick = np.sort(np.random.default_rng(4001).choice(leaves, nl_s, replace=False))
         samp = np.concatenate([order[cells["start"][c]:cells["start"][c] + cells["count"][c]] for c in pick])
-        t0 = time.perf_counter()
-        _, _, tm = ora.eval(q.astype(np.float64), p, sample=samp)
-        t_eval = time.perf_counter() - t0
-        # upward pass is full; M2L, L2L, L2P and P2P ran for every target of nl_s random leaves
         scale = leaves.shape[0] / nl_s
-        t_full = t_plan + tm[0] + (t_eval - tm[0]) * scale
+        t_up = t_rest = 0.0
+        for chg in (q, w):
+            t0 = time.perf_counter()
+            _, _, tm = ora.eval(chg.astype(np.float64), p, sample=samp)
+            t_eval = time.perf_counter() - t0
+            t_up += tm[0]
+            t_rest += t_eval - tm[0]
+        t_step = 2 * t_plan + t_up + t_rest * scale
         result["cpu_baseline"] = {
-            "value": n / t_full,
-            "unit": "particles/s (forward only)",
+            "value": n / t_step,
+            "unit": "particles/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": (f"FP64 oracle on the same {n}-point workload: full plan ({t_plan:.1f} s) and upward pass "
-                       f"({tm[0]:.1f} s); M2L/L2L/L2P/P2P for all {samp.shape[0]} targets of {nl_s} random leaves "
-                       f"({t_eval - tm[0]:.1f} s) scaled by {leaves.shape[0]}/{nl_s} leaves"),
+            "sample": (f"FP64 oracle, same {n}-point workload and step (plan + forward + plan + adjoint): plan "
+                       f"{t_plan:.1f} s (counted twice), upward passes {t_up:.1f} s, M2L/L2L/L2P/P2P for the "
+                       f"{samp.shape[0]} targets of {nl_s} random leaves {t_rest:.1f} s scaled by "
+                       f"{leaves.shape[0]}/{nl_s}; step {t_step:.0f} s"),
         }
     print(json.dumps(result), flush=True)
 

@@ -607,8 +607,11 @@ __global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int
 // cells of the M2L tiles) and the root L2L (targets: same-octant cells, source: parent;
 // ADD accumulates onto the M2L result).  A source below the root levels is read from
 // the FP32 array and widened.
-// 256 threads: thread (rt = tid % 32, ct = tid / 32) owns rows rt*4 + v + 128 i and
-// columns ct*8 .. ct*8 + 7 of the KP x 64 output tile.
+// Grid (work items, row slabs): a workgroup computes the 32-row slab blockIdx.y of the
+// KP x 64 output tile, so every tile is spread over KP/32 workgroups.  Thread
+// (rt = tid % 8, ct = tid / 8) owns rows 4 rt .. 4 rt + 3 of the slab and columns
+// 2 ct, 2 ct + 1.  The entry's 64 source vectors sit in LDS as [k][col].
+constexpr int kSlab64 = 32;
 template <int P, bool ADD>
 __global__ void __launch_bounds__(256) k_gemm64(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                                 const uint64_t *key_ptr64, int64_t nroot, const float *in32,
@@ -616,17 +619,14 @@ __global__ void __launch_bounds__(256) k_gemm64(const int4 *work, const int32_t 
                                                 const int32_t *tile_targets) {
     using D = Dims<P>;
     constexpr int KP = D::KP;
-    constexpr int RI = (KP + 127) / 128;
     __shared__ __attribute__((aligned(16))) double B[KP * kTileN];   // [k][col]
-    const int tid = threadIdx.x, rt = tid & 31, ct = tid >> 5;
+    const int tid = threadIdx.x, rt = tid & 7, ct = tid >> 3;
+    const int r0 = blockIdx.y * kSlab64 + rt * 4;
+    const bool rows_ok = r0 < KP;                // KP is a multiple of 16, so 4-row groups are whole
     const int4 w = work[blockIdx.x];
-    double acc[RI][4][8];
+    double acc[4][2];
 #pragma unroll
-    for (int i = 0; i < RI; ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc[i][v][c] = 0.0;
+    for (int v = 0; v < 4; ++v) acc[v][0] = acc[v][1] = 0.0;
     for (int e = w.y; e < w.z; ++e) {
         __syncthreads();
         for (int idx = tid; idx < kTileN * KP; idx += 256) {
@@ -637,27 +637,21 @@ __global__ void __launch_bounds__(256) k_gemm64(const int4 *work, const int32_t 
             B[k * kTileN + col] = v;
         }
         __syncthreads();
+        if (!rows_ok) continue;
         const double *T = reinterpret_cast<const double *>(key_ptr64[entry_key[e]]);
         for (int k = 0; k < D::NC; ++k) {
-            double b[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) b[c] = B[k * kTileN + ct * 8 + c];
-#pragma unroll
-            for (int i = 0; i < RI; ++i) {
-                const int r0 = rt * 4 + 128 * i;
-                if (r0 >= KP) continue;
-                const double4 a = *reinterpret_cast<const double4 *>(T + (int64_t)k * KP + r0);
-                const double av[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) acc[i][v][c] += av[v] * b[c];
-            }
+            const double2 b = *reinterpret_cast<const double2 *>(&B[k * kTileN + ct * 2]);
+            const double4 a = *reinterpret_cast<const double4 *>(T + (int64_t)k * KP + r0);
+            acc[0][0] += a.x * b.x; acc[0][1] += a.x * b.y;
+            acc[1][0] += a.y * b.x; acc[1][1] += a.y * b.y;
+            acc[2][0] += a.z * b.x; acc[2][1] += a.z * b.y;
+            acc[3][0] += a.w * b.x; acc[3][1] += a.w * b.y;
         }
     }
+    if (!rows_ok) return;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int col = ct * 8 + c;
+    for (int c = 0; c < 2; ++c) {
+        const int col = ct * 2 + c;
         double *dst;
         if (w.w == 0) {
             const int t = tile_targets[(int64_t)w.x * kTileN + col];
@@ -667,19 +661,13 @@ __global__ void __launch_bounds__(256) k_gemm64(const int4 *work, const int32_t 
             dst = partial + ((int64_t)(w.w - 1) * kTileN + col) * KP;
         }
 #pragma unroll
-        for (int i = 0; i < RI; ++i) {
-            const int r0 = rt * 4 + 128 * i;
-            if (r0 >= KP) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                if (ADD && w.w == 0) dst[r0 + v] += acc[i][v][c];
-                else dst[r0 + v] = acc[i][v][c];
-            }
+        for (int v = 0; v < 4; ++v) {
+            if (ADD && w.w == 0) dst[r0 + v] += acc[v][c];
+            else dst[r0 + v] = acc[v][c];
         }
     }
 }
 
-// Partial tiles of the root M2L summed into Ld; blockIdx.y splits the outputs.
 __global__ void k_m2l64_reduce(int64_t ntiles, const int32_t *tile_work, const int32_t *tile_work_idx, const int4 *work,
                                const double *partial, const int32_t *tile_targets, int KP, double *Ld) {
     const int64_t t = blockIdx.x;
@@ -964,6 +952,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     const OpTables &T = op_tables(P);
     const bool mixed = Pl->prec == FMM_PREC_MIXED;
     const int RL = mixed ? kRootLevels : 0;       // levels below RL accumulate in FP64
+    constexpr unsigned kSlabs = (D::KP + kSlab64 - 1) / kSlab64;
     ev_rec(Pl, 2 * PH_P2M, s);
     hipLaunchKernelGGL(k_p2m<P>, (int)((Pl->nleaves + 1) / 2), 64, 0, s, (const int32_t *)Pl->leaves, Pl->nleaves,
                        g, (const float4 *)Pl->bodies, Pl->M);
@@ -983,7 +972,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
         for (int l = std::min(RL - 1, Pl->max_level - 1); l >= 0; --l) {
             const int t0 = Pl->m2m.bucket_tile[l * 8], t1 = Pl->m2m.bucket_tile[l * 8 + 8];
             if (t1 > t0)
-                hipLaunchKernelGGL((k_gemm64<P, false>), t1 - t0, 256, 0, s, (const int4 *)Pl->m2m.work + t0,
+                hipLaunchKernelGGL((k_gemm64<P, false>), dim3(t1 - t0, kSlabs), 256, 0, s, (const int4 *)Pl->m2m.work + t0,
                                    (const int32_t *)Pl->m2m.entry_key, (const int32_t *)Pl->m2m.entry_src,
                                    T.m2m64_ptrs, Pl->nroot, (const float *)Pl->M, (const double *)Pl->Md, Pl->Md,
                                    (double *)nullptr, (const int32_t *)Pl->m2m.tile_targets);
@@ -1011,7 +1000,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
                                (const int32_t *)Pl->tile_targets);
     }
     if (mixed && Pl->nwork64 > 0)
-        hipLaunchKernelGGL((k_gemm64<P, false>), (int)Pl->nwork64, 256, 0, s, (const int4 *)Pl->work64,
+        hipLaunchKernelGGL((k_gemm64<P, false>), dim3((unsigned)Pl->nwork64, kSlabs), 256, 0, s, (const int4 *)Pl->work64,
                            (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src, Pl->key_f64, Pl->nroot,
                            (const float *)Pl->M, (const double *)Pl->Md, Pl->Ld, Pl->partial64,
                            (const int32_t *)Pl->tile_targets);
@@ -1030,7 +1019,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
         for (int l = 1; l <= std::min(RL - 1, Pl->max_level); ++l) {
             const int t0 = Pl->l2l.bucket_tile[l * 8], t1 = Pl->l2l.bucket_tile[l * 8 + 8];
             if (t1 > t0)
-                hipLaunchKernelGGL((k_gemm64<P, true>), t1 - t0, 256, 0, s, (const int4 *)Pl->l2l.work + t0,
+                hipLaunchKernelGGL((k_gemm64<P, true>), dim3(t1 - t0, kSlabs), 256, 0, s, (const int4 *)Pl->l2l.work + t0,
                                    (const int32_t *)Pl->l2l.entry_key, (const int32_t *)Pl->l2l.entry_src,
                                    T.l2l64_ptrs, Pl->nroot, (const float *)Pl->L, (const double *)Pl->Ld, Pl->Ld,
                                    (double *)nullptr, (const int32_t *)Pl->l2l.tile_targets);

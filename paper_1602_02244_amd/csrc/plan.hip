@@ -482,22 +482,22 @@ __global__ void k_target_keys(const int32_t *is_target, const int32_t *ex, int64
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
         if (!is_target[c]) continue;
         int oct = by_octant ? ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1) : 0;
-        tkeys[ex[c]] = ((uint64_t)C.level[c] << 35) | ((uint64_t)oct << 32) | (uint64_t)c;
+        tkeys[ex[c]] = (uint64_t)(C.level[c] * 8 + oct);   // bucket; cells enter in index order
         tvals[ex[c]] = (int32_t)c;
     }
 }
 
 __global__ void k_bucket_starts(const uint64_t *tkeys, int64_t nt, int32_t *bstart) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x) {
-        int b = (int)(tkeys[i] >> 32);
-        if (i == 0 || (int)(tkeys[i - 1] >> 32) != b) bstart[b] = (int32_t)i;
+        int b = (int)tkeys[i];
+        if (i == 0 || (int)tkeys[i - 1] != b) bstart[b] = (int32_t)i;
     }
 }
 
 __global__ void k_assign_tiles(const uint64_t *tkeys, const int32_t *tvals, int64_t nt, const int32_t *bstart,
                                const int32_t *tbase, int32_t *cell_tile, int32_t *cell_lane, int32_t *tile_targets) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x) {
-        int b = (int)(tkeys[i] >> 32);
+        int b = (int)tkeys[i];
         int r = (int)(i - bstart[b]);
         int tile = tbase[b] + r / kTileN, lane = r % kTileN;
         int c = tvals[i];
@@ -684,7 +684,8 @@ static int64_t tile_cells(const CellView &C, int64_t nc, int32_t *flag, bool by_
     int32_t *tv = a.get_n<int32_t>(nt);
     hipLaunchKernelGGL(k_target_keys, grid1(nc), 256, 0, s, (const int32_t *)flag, (const int32_t *)tex, nc, C,
                        by_octant ? 1 : 0, tk, tv);
-    radix_sort_u64(tk, tv, nt, 40, a, s);
+    static_assert(kBuckets <= 256, "one 8-bit pass");
+    radix_sort_u64(tk, tv, nt, 8, a, s);          // stable: Morton (= index) order inside a bucket
     int32_t *bst = a.get_n<int32_t>(kBuckets);
     fill_i32(bst, -1, kBuckets, s);
     hipLaunchKernelGGL(k_bucket_starts, grid1(nt), 256, 0, s, (const uint64_t *)tk, nt, bst);
