@@ -113,14 +113,16 @@ struct Geo {
 
 // ------------------------------------------------------------------ P2M
 // Two leaves per wave, one per half-wave.  Each lane evaluates the harmonics of one
-// body (streamed) and writes q conj(R) into an LDS column; lanes then own
-// coefficients and sum their row over the bodies.
+// body (streamed into registers, times its charge); the 32 lanes of a half-wave then
+// sum their vectors with a reduce-scatter over cross-lane shuffles (five halving
+// steps), after which lane h holds the finished coefficients NF*h .. NF*h + NF - 1.
+// No LDS, so occupancy is set by registers alone.
 template <int P>
 __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, int64_t nleaves, Geo g, const float4 *bodies,
                                             float *M) {
     using D = Dims<P>;
-    constexpr int NR = (D::KP + 31) / 32;
-    __shared__ float sc[2][D::NC][33];
+    constexpr int NV = (D::NC + 31) / 32 * 32;   // register vector length
+    constexpr int NF = NV / 32;                  // coefficients per lane after the reduction
     const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
     const int64_t li = 2 * (int64_t)blockIdx.x + half;
     const bool has = li < nleaves;
@@ -129,9 +131,9 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, int64_t nleav
     double cx, cy, cz, inv;
     cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
     const int nmax = max(n, __shfl_xor(n, 32, 64));
-    float acc[NR];
+    float acc[NF];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = 0.f;
+    for (int i = 0; i < NF; ++i) acc[i] = 0.f;
     for (int base = 0; base < nmax; base += 32) {
         const int j = base + hl;
         float ux = 0.f, uy = 0.f, uz = 0.f, q = 0.f;
@@ -142,33 +144,37 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *leaves, int64_t nleav
             uz = (float)(((double)b.z - cz) * inv);
             q = b.w;
         }
-        __syncthreads();
         // Mt_lm = sum q conj(R_lm(u))
+        float v[NV];
+#pragma unroll
+        for (int d = D::NC; d < NV; ++d) v[d] = 0.f;
         stream_regular<P>(ux, uy, uz, [&](int l, int m, float re, float im) {
             if (m == 0) {
-                sc[half][l * l][hl] = q * re;
+                v[l * l] = q * re;
             } else {
-                sc[half][l * l + 2 * m - 1][hl] = q * re;
-                sc[half][l * l + 2 * m][hl] = -q * im;
+                v[l * l + 2 * m - 1] = q * re;
+                v[l * l + 2 * m] = -q * im;
             }
         });
-        __syncthreads();
-        const int cnt = min(32, n - base);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int d = r * 32 + hl;
-            if (d < D::NC) {
-                float t = 0.f;
-                for (int i = 0; i < cnt; ++i) t += sc[half][d][i];
-                acc[r] += t;
+        for (int st = 0; st < 5; ++st) {
+            const int o = 16 >> st, H = (NV >> st) / 2;
+            const bool upper = (hl & o) != 0;
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const float send = upper ? v[i] : v[i + H];
+                const float keep = upper ? v[i + H] : v[i];
+                v[i] = keep + __shfl_xor(send, o, 64);
             }
         }
+#pragma unroll
+        for (int i = 0; i < NF; ++i) acc[i] += v[i];
     }
     if (!has) return;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int d = r * 32 + hl;
-        if (d < D::KP) M[(int64_t)c * D::KP + d] = d < D::NC ? acc[r] : 0.f;
+    for (int i = 0; i < NF; ++i) {
+        const int d = NF * hl + i;
+        if (d < D::KP) M[(int64_t)c * D::KP + d] = acc[i];
     }
 }
 
@@ -583,18 +589,32 @@ __global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t
     }
 }
 
-__global__ void k_m2l_reduce(int64_t ntiles, const int32_t *tile_work, const int32_t *tile_work_idx, const int4 *work,
-                             const float *partial, const int32_t *tile_targets, int KP, float *L) {
+// Sum of a split tile's partial results.  Grid (tile, element chunk); the tile's partial
+// slots are read once into LDS.
+constexpr int kReduceChunks = 8;
+__global__ void __launch_bounds__(256) k_m2l_reduce(int64_t ntiles, const int32_t *tile_work,
+                                                    const int32_t *tile_work_idx, const int4 *work,
+                                                    const float *partial, const int32_t *tile_targets, int KP,
+                                                    float *L) {
+    constexpr int kMaxSlots = 256;
+    __shared__ int slot[kMaxSlots];
     const int64_t t = blockIdx.x;
     const int w0 = tile_work[t], w1 = tile_work[t + 1];
-    if (w1 - w0 < 2) return;
-    for (int idx = threadIdx.x; idx < kTileN * KP; idx += blockDim.x) {
+    const int ns = w1 - w0;
+    if (ns < 2) return;
+    for (int i = threadIdx.x; i < ns && i < kMaxSlots; i += blockDim.x) slot[i] = work[tile_work_idx[w0 + i]].w - 1;
+    __syncthreads();
+    const int total = kTileN * KP, per = (total + kReduceChunks - 1) / kReduceChunks;
+    const int i0 = blockIdx.y * per, i1 = min(total, i0 + per);
+    for (int idx = i0 + threadIdx.x; idx < i1; idx += blockDim.x) {
         const int col = idx / KP, row = idx % KP;
         const int tg = tile_targets[t * kTileN + col];
         if (tg < 0) continue;
         float s = 0.f;
-        for (int wi = w0; wi < w1; ++wi)
-            s += partial[((int64_t)(work[tile_work_idx[wi]].w - 1) * kTileN + col) * KP + row];
+        for (int q = 0; q < ns; ++q) {
+            const int sl = q < kMaxSlots ? slot[q] : work[tile_work_idx[w0 + q]].w - 1;
+            s += partial[((int64_t)sl * kTileN + col) * KP + row];
+        }
         L[(int64_t)tg * KP + row] = s;
     }
 }
@@ -699,7 +719,7 @@ __global__ void k_root_to32(int64_t nroot, int KP, const double *in, float *out)
 // ------------------------------------------------------------------ L2P
 template <int P>
 __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const float4 *bodies, const float *L,
-                                            float *phi, float *grad) {
+                                            float4 *out) {
     using D = Dims<P>;
     constexpr int KP = D::KP;
     __shared__ float sL[KP];
@@ -747,12 +767,8 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
                 gz += wgt * (zr * rr + zi * ri);
             }
         });
-        const int64_t o = s + j;
-        phi[o] = f * finv;
         const float g2 = finv * finv;
-        grad[3 * o] = gx * g2;
-        grad[3 * o + 1] = gy * g2;
-        grad[3 * o + 2] = gz * g2;
+        out[s + j] = make_float4(f * finv, gx * g2, gy * g2, gz * g2);   // potential, gradient
     }
 }
 
@@ -809,7 +825,7 @@ __device__ __forceinline__ void p2p_batch_comp(const float4 *src, int ns, int g,
 template <bool COMP>
 __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, const int32_t *c_start, const int32_t *c_count,
                                                      const int32_t *seg_off, const int2 *segs, const float4 *bodies,
-                                                     float *out_phi, float *out_grad) {
+                                                     float4 *out) {
     __shared__ float4 src[kP2PBatch];
     __shared__ float4 red[kP2PThreads];
     __shared__ float4 redl[COMP ? kP2PThreads : 1];
@@ -896,11 +912,7 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, cons
                     acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
                 }
             }
-            const int64_t o = ts + t0 + tid;
-            out_phi[o] = acc.x;
-            out_grad[3 * o] = acc.y;
-            out_grad[3 * o + 1] = acc.z;
-            out_grad[3 * o + 2] = acc.w;
+            out[ts + t0 + tid] = acc;                // potential, gradient
         }
     }
 }
@@ -911,15 +923,18 @@ __global__ void k_set_charges(const float *q, const int32_t *perm, int64_t n, fl
         bodies[i].w = q[perm[i]];
 }
 
-__global__ void k_combine(const int32_t *perm, int64_t n, const float *fphi, const float *fgrad, const float *nphi,
-                          const float *ngrad, float *phi, float *grad) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t o = perm[i];
-        if (phi) phi[o] = fphi[i] + nphi[i];
+// Far + near field back to input order: one thread per output (coalesced writes), the
+// sorted-order inputs are gathered through the inverse permutation.
+__global__ void k_combine(const int32_t *iperm, int64_t n, const float4 *far, const float4 *near, float *phi,
+                          float *grad) {
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = iperm[o];
+        const float4 f = far[i], c = near[i];
+        if (phi) phi[o] = f.x + c.x;
         if (grad) {
-            grad[3 * o] = fgrad[3 * i] + ngrad[3 * i];
-            grad[3 * o + 1] = fgrad[3 * i + 1] + ngrad[3 * i + 1];
-            grad[3 * o + 2] = fgrad[3 * i + 2] + ngrad[3 * i + 2];
+            grad[3 * o] = f.y + c.y;
+            grad[3 * o + 1] = f.z + c.z;
+            grad[3 * o + 2] = f.w + c.w;
         }
     }
 }
@@ -1007,7 +1022,8 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     ev_rec(Pl, 2 * PH_M2L + 1, s);
     ev_rec(Pl, 2 * PH_L2L, s);
     if (Pl->npartial > 0)
-        hipLaunchKernelGGL(k_m2l_reduce, (int)Pl->ntiles, 256, 0, s, Pl->ntiles, (const int32_t *)Pl->tile_work,
+        hipLaunchKernelGGL(k_m2l_reduce, dim3((unsigned)Pl->ntiles, kReduceChunks), 256, 0, s, Pl->ntiles,
+                           (const int32_t *)Pl->tile_work,
                            (const int32_t *)Pl->tile_work_idx, (const int4 *)Pl->work, (const float *)Pl->partial,
                            (const int32_t *)Pl->tile_targets, D::KP, Pl->L);
     if (mixed && Pl->partial64)
@@ -1038,7 +1054,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     ev_rec(Pl, 2 * PH_L2L + 1, s);
     ev_rec(Pl, 2 * PH_L2P, s);
     hipLaunchKernelGGL(k_l2p<P>, (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g, (const float4 *)Pl->bodies,
-                       (const float *)Pl->L, Pl->far_phi, Pl->far_grad);
+                       (const float *)Pl->L, Pl->far4);
     ev_rec(Pl, 2 * PH_L2P + 1, s);
 }
 
@@ -1060,14 +1076,13 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phase
         if (Pl->prec == FMM_PREC_MIXED)
             hipLaunchKernelGGL(k_p2p<true>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
                                (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near_phi, Pl->near_grad);
+                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
         else
             hipLaunchKernelGGL(k_p2p<false>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
                                (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near_phi, Pl->near_grad);
+                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
     } else {
-        fill_f32(Pl->near_phi, 0.f, n, Pl->side);
-        fill_f32(Pl->near_grad, 0.f, 3 * n, Pl->side);
+        fill_f32(reinterpret_cast<float *>(Pl->near4), 0.f, 4 * n, Pl->side);
     }
     ev_rec(Pl, 2 * PH_P2P + 1, Pl->side);
     HIP_CHECK(hipEventRecord(Pl->ev_join, Pl->side));
@@ -1080,13 +1095,12 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phase
         }
     } else {
         for (int ph = PH_P2M; ph <= PH_L2P; ++ph) { ev_rec(Pl, 2 * ph, s); ev_rec(Pl, 2 * ph + 1, s); }
-        fill_f32(Pl->far_phi, 0.f, n, s);
-        fill_f32(Pl->far_grad, 0.f, 3 * n, s);
+        fill_f32(reinterpret_cast<float *>(Pl->far4), 0.f, 4 * n, s);
     }
     HIP_CHECK(hipStreamWaitEvent(s, Pl->ev_join, 0));
     ev_rec(Pl, 2 * PH_COMB, s);
-    hipLaunchKernelGGL(k_combine, grid1(n), 256, 0, s, (const int32_t *)Pl->perm, n, (const float *)Pl->far_phi,
-                       (const float *)Pl->far_grad, (const float *)Pl->near_phi, (const float *)Pl->near_grad, phi, grad);
+    hipLaunchKernelGGL(k_combine, grid1(n), 256, 0, s, (const int32_t *)Pl->iperm, n, (const float4 *)Pl->far4,
+                       (const float4 *)Pl->near4, phi, grad);
     ev_rec(Pl, 2 * PH_COMB + 1, s);
     ev_rec(Pl, 2 * PH_TOTAL + 1, s);
     HIP_CHECK(hipGetLastError());

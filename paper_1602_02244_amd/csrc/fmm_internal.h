@@ -129,6 +129,7 @@ struct fmm_plan_s {
 
     // bodies in Morton order
     int32_t *perm = nullptr;     // sorted position -> input index
+    int32_t *iperm = nullptr;    // input index -> sorted position
     float4 *bodies = nullptr;    // (x, y, z, q) ; q written by each eval
     uint64_t *keys = nullptr;    // sorted keys
 
@@ -177,7 +178,7 @@ struct fmm_plan_s {
     _Float16 *Mh = nullptr, *Ml = nullptr;      // [ncells][KP] split FP16 multipoles (normalised)
     float *Msinv = nullptr;                     // [ncells] inverse power-of-two scale of each cell
     float *partial = nullptr;                   // [nwork][kTileN][KP]
-    float *far_phi = nullptr, *far_grad = nullptr, *near_phi = nullptr, *near_grad = nullptr;
+    float4 *far4 = nullptr, *near4 = nullptr;   // sorted order: (potential, gradient) of far and near field
     float *tmp_phi = nullptr, *tmp_grad = nullptr, *tmp_gfwd = nullptr;   // adjoint scratch (input order)
     std::vector<hipStream_t> streams_used;       // every stream the plan's memory was used on
     int fp64_levels = 0;                        // levels 0..fp64_levels-1 kept in FP64 (mixed)

@@ -123,6 +123,11 @@ __global__ void k_keys(const float *pts, int64_t n, double x0x, double x0y, doub
     }
 }
 
+__global__ void k_invert_perm(const int32_t *perm, int64_t n, int32_t *iperm) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        iperm[perm[i]] = (int32_t)i;
+}
+
 __global__ void k_gather_bodies(const float *pts, const int32_t *perm, int64_t n, float4 *bodies) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t j = perm[i];
@@ -759,6 +764,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     radix_sort_u64(keys, perm, n, 3 * kMaxLevel, a, s);
     P->keys = keys;
     P->perm = perm;
+    P->iperm = a.get_n<int32_t>(n);
+    hipLaunchKernelGGL(k_invert_perm, grid1(n), 256, 0, s, (const int32_t *)perm, n, P->iperm);
     P->bodies = a.get_n<float4>(n);
     hipLaunchKernelGGL(k_gather_bodies, grid1(n), 256, 0, s, points, (const int32_t *)perm, n, P->bodies);
 
@@ -1167,10 +1174,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     P->M = a.get_n<float>(nc * KP);
     P->L = a.get_n<float>(nc * KP);
     if (P->npartial > 0) P->partial = a.get_n<float>(P->npartial * kTileN * KP);
-    P->far_phi = a.get_n<float>(n);
-    P->far_grad = a.get_n<float>(3 * n);
-    P->near_phi = a.get_n<float>(n);
-    P->near_grad = a.get_n<float>(3 * n);
+    P->far4 = a.get_n<float4>(n);
+    P->near4 = a.get_n<float4>(n);
     if (P->prec == FMM_PREC_MIXED) {
         P->Mh = a.get_n<_Float16>(nc * KP);
         P->Ml = a.get_n<_Float16>(nc * KP);
