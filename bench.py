@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-accuracy", action="store_true")
+    ap.add_argument("--accuracy-sweep", default=None, metavar="P_LIST",
+                    help="instead of the benchmark line: error against the direct sum and throughput for each "
+                         "order in P_LIST (e.g. 2,4,6,8,10,12) at theta 0.4 and 0.5, one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -57,6 +60,64 @@ def m2l_traffic(workload, p, theta):
     if sha == t["eval_sha256"] and (workload, p, theta) == (t["workload"], t["p"], t["theta"]):
         return t["bytes"]
     return None
+
+
+def direct_reference(xt, qt, targets, chunk=64):
+    """Exact potential and gradient at the sampled targets: plain FP64 direct summation
+    (torch on the device; skips the target itself and coincident points)."""
+    import torch
+    x = xt.double()
+    q = qt.double()
+    phi = np.empty(len(targets))
+    grad = np.empty((len(targets), 3))
+    for c0 in range(0, len(targets), chunk):
+        idx = torch.as_tensor(np.asarray(targets[c0:c0 + chunk]), device=x.device)
+        d = x[idx][:, None, :] - x[None, :, :]
+        r2 = (d * d).sum(-1)
+        rinv = torch.where(r2 > 0, r2.rsqrt(), torch.zeros_like(r2))
+        phi[c0:c0 + chunk] = (rinv * q).sum(1).cpu().numpy()
+        grad[c0:c0 + chunk] = (-(rinv ** 3 * q)[:, :, None] * d).sum(1).cpu().numpy()
+    return phi, grad
+
+
+def accuracy_sweep(args, xt, qt, wt, n, ncrit, reps=5):
+    """Error against the exact direct sum (1000 sampled targets) and throughput of the forward
+    (plan + eval) and forward + adjoint (plan + eval + plan + adjoint) steps, per (theta, p)."""
+    import torch
+    from paper_1602_02244_amd import FMM, inputs
+    samp = inputs.sample_targets(n, 1000)
+    dphi, dgrad = direct_reference(xt, qt, samp)
+    rows = []
+    for theta in (0.4, 0.5):
+        for p in (int(v) for v in args.accuracy_sweep.split(",")):
+            FMM(xt, ncrit, p, theta, args.precision).close()          # operator tables for this (p, theta)
+            fwd, step = [], []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan = FMM(xt, ncrit, p, theta, args.precision)
+                phi, grad = plan.eval(qt)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                plan.close()
+                plan2 = FMM(xt, ncrit, p, theta, args.precision)
+                plan2.adjoint(qt, wt, gradient_fwd=grad)
+                plan2.close()
+                torch.cuda.synchronize()
+                fwd.append(t1 - t0)
+                step.append(time.perf_counter() - t0)
+            e_phi = rel_l2(phi.cpu().numpy()[samp], dphi)
+            e_grad = rel_l2(grad.cpu().numpy()[samp], dgrad)
+            rows.append({"theta": theta, "p": p, "err_phi": e_phi, "err_grad": e_grad,
+                         "fwd_particles_per_s": n / float(np.median(fwd)),
+                         "step_particles_per_s": n / float(np.median(step))})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    best = {}
+    for th in (0.4, 0.5):
+        ok = [r for r in rows if r["theta"] == th and max(r["err_phi"], r["err_grad"]) <= 1e-4]
+        if ok:
+            best[str(th)] = min(ok, key=lambda r: r["p"])["p"]
+    return {"sweep": rows, "smallest_p_at_1e-4": best, "workload": args.workload, "precision": args.precision}
 
 
 def rel_l2(a, b):
@@ -90,6 +151,9 @@ def main():
         dst.copy_(src)
         del src, dst, evict
     torch.cuda.synchronize()
+    if args.accuracy_sweep:
+        print(json.dumps(accuracy_sweep(args, xt, qt, wt, n, ncrit)), flush=True)
+        return
 
     def step(record):
         t0 = time.perf_counter()
@@ -183,11 +247,9 @@ def main():
     }
 
     if not args.skip_accuracy:
-        import oracle
-        oracle.set_threads(0)
         samp = inputs.sample_targets(n, 1000)
-        dphi, dgrad = oracle.direct(x.astype(np.float64), q.astype(np.float64), samp)
-        dpsi, _ = oracle.direct(x.astype(np.float64), w.astype(np.float64), samp)
+        dphi, dgrad = direct_reference(xt, qt, samp)
+        dpsi, _ = direct_reference(xt, wt, samp)
         ph_np, g_np, dq_np = phi.cpu().numpy()[samp], grad.cpu().numpy()[samp], dq.cpu().numpy()[samp]
         err = {"phi": rel_l2(ph_np, dphi), "grad": rel_l2(g_np, dgrad), "dL_dq": rel_l2(dq_np, dpsi)}
         result["rel_err_vs_direct_1000"] = err
