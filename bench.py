@@ -62,12 +62,14 @@ def m2l_traffic(workload, p, theta):
     return None
 
 
-def direct_reference(xt, qt, targets, chunk=64):
+def direct_reference(xt, qt, targets, chunk=None):
     """Exact potential and gradient at the sampled targets: plain FP64 direct summation
     (torch on the device; skips the target itself and coincident points)."""
     import torch
     x = xt.double()
     q = qt.double()
+    if chunk is None:
+        chunk = max(1, min(64, int(2e8 // x.shape[0])))     # bounds the pairwise temporaries
     phi = np.empty(len(targets))
     grad = np.empty((len(targets), 3))
     for c0 in range(0, len(targets), chunk):

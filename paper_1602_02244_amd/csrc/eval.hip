@@ -202,7 +202,7 @@ typedef __attribute__((address_space(1))) const floatx4 gfloatx4;   // global-me
 // targets share an octant, the source is the parent; ADD accumulates onto the
 // M2L result).
 template <int P, bool ADD, bool MASKED>
-__global__ void __launch_bounds__(256) k_gemm(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 12 ? 2 : 1))) k_gemm(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                               const uint8_t *entry_mask, const uint64_t *key_ptr, const float *M,
                                               float *L, float *partial, const int32_t *tile_targets) {
     using D = Dims<P>;
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(64) k_split_m(const float *M, const float *nu,
 // ahead, gathered sources one entry ahead spread over the k steps, operator one k step
 // ahead, global loads only) are those of k_gemm.
 template <int P>
-__global__ void __launch_bounds__(256) k_m2l_f16(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 2 : 1))) k_m2l_f16(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                                  const uint8_t *entry_mask, const uint64_t *key_ptr,
                                                  const _Float16 *Mh, const _Float16 *Ml, const float *sinv, float *L,
                                                  float *partial, const int32_t *tile_targets) {
