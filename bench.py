@@ -26,9 +26,10 @@ import numpy as np  # noqa: E402
 
 MFMA_FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 MFMA
 # HBM bytes of one M2L launch on the uniform-1M workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
-# factors from a 1 GiB plain copy), measured with rocprofv3 on the kernel source whose
-# sha256 prefix is given; reported only while the source is unchanged.
-M2L_TRAFFIC = {"eval_sha256": "284b126a1c49deeb", "workload": "uniform-1M", "p": 10, "theta": 0.4, "bytes": 15.80e9}
+# factors from a 1 GiB plain copy), measured with rocprofv3 on the M2L kernel source whose
+# sha256 prefix is given (the text of k_gemm in eval.hip); reported only while that source
+# is unchanged.
+M2L_TRAFFIC = {"kernel_sha256": "", "workload": "uniform-1M", "p": 10, "theta": 0.4, "bytes": None}
 VALU_FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X FP32 vector with packed (2-wide) FMA
 VALU_FP32_PEAK_TFLOPS = 78.6           # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 not used
 P2P_ISSUE_PEAK_TFLOPS = 46.3           # the same lanes at 17 issue slots per 20-flop interaction
@@ -53,11 +54,17 @@ def parse():
     return ap.parse_args()
 
 
+def m2l_kernel_sha():
+    """sha256 prefix of the M2L kernel's source text (the k_gemm template in eval.hip)."""
+    src = open(os.path.join(ROOT, "paper_1602_02244_amd", "csrc", "eval.hip")).read()
+    a = src.index("template <int P, bool ADD, bool MASKED>")
+    b = src.index("// ---", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
 def m2l_traffic(workload, p, theta):
-    src = os.path.join(ROOT, "paper_1602_02244_amd", "csrc", "eval.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     t = M2L_TRAFFIC
-    if sha == t["eval_sha256"] and (workload, p, theta) == (t["workload"], t["p"], t["theta"]):
+    if m2l_kernel_sha() == t["kernel_sha256"] and (workload, p, theta) == (t["workload"], t["p"], t["theta"]):
         return t["bytes"]
     return None
 
