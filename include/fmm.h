@@ -88,6 +88,23 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
                     fmm_precision prec, void *stream, fmm_plan_t *out);
 
 /*
+ * fmm_plan with a variable-order M2L (the paper notes that expansions whose order varies
+ * with the separation, or low-rank (SVD) operators, cut the M2L work; Sec. 2.2).
+ *   m2l_tol >= 0  every M2L operator is applied in 16 x 16 blocks; a block is left out
+ *                 when it is among the smallest blocks of that operator whose summed
+ *                 size stays within m2l_tol, the size of a block being what it can add to
+ *                 a potential (entries weighted by the bounds h^n / sqrt((n+m)!(n-m)!) of
+ *                 the source's multipole and the target's local coefficients, h = sqrt(3)/2)
+ *                 relative to the interaction's monopole-to-monopole term.  So every M2L
+ *                 pair's potential changes by at most m2l_tol of its monopole term.
+ *                 0 keeps every block (same result as fmm_plan).  FP32 precision only.
+ * Other arguments, ownership and errors as fmm_plan; EINVAL for a negative, NaN or
+ * infinite m2l_tol, or m2l_tol > 0 with FMM_PREC_MIXED.
+ */
+fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta,
+                       fmm_precision prec, double m2l_tol, void *stream, fmm_plan_t *out);
+
+/*
  * Apply the plan to charges q (device [n]): potential (device [n]) and, when
  * `gradient` is not NULL, grad phi (device [n][3]).  Outputs are in input order.
  * Calls that share one plan must not overlap (the plan holds the work buffers).
@@ -128,6 +145,8 @@ struct fmm_stats {
     double m2l_flops;                       /* 2 (p+1)^4 per M2L pair */
     double p2p_flops;                       /* 20 per interaction (stated convention) */
     int64_t workspace_bytes;
+    double m2l_tol;                         /* variable-order tolerance (0: every block) */
+    double m2l_kept_fraction;               /* pair-weighted fraction of operator blocks applied */
 };
 fmm_status fmm_plan_stats(fmm_plan_t plan, struct fmm_stats *out);
 

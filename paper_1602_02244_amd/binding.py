@@ -44,6 +44,7 @@ class FmmStats(C.Structure):
         ("m2l_flops", C.c_double),
         ("p2p_flops", C.c_double),
         ("workspace_bytes", C.c_int64),
+        ("m2l_tol", C.c_double), ("m2l_kept_fraction", C.c_double),
     ]
 
 
@@ -70,6 +71,8 @@ def load_library():
     lib.fmm_last_error.argtypes = []
     lib.fmm_set_allocator.argtypes = [_vp, _vp, _vp]
     lib.fmm_plan.argtypes = [_vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, _vp, C.POINTER(_vp)]
+    lib.fmm_plan_ex.argtypes = [_vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, C.c_double, _vp,
+                                C.POINTER(_vp)]
     lib.fmm_eval.argtypes = [_vp, _vp, _vp, _vp, _vp]
     lib.fmm_eval_ex.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp]
     lib.fmm_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -79,7 +82,7 @@ def load_library():
     lib.fmm_plan_phase_times.argtypes = [_vp, C.POINTER(C.c_float)]
     lib.fmm_plan_destroy.argtypes = [_vp]
     lib.fmm_plan_destroy.restype = None
-    for f in ("fmm_set_allocator", "fmm_plan", "fmm_eval", "fmm_eval_ex", "fmm_adjoint", "fmm_plan_stats",
+    for f in ("fmm_set_allocator", "fmm_plan", "fmm_plan_ex", "fmm_eval", "fmm_eval_ex", "fmm_adjoint", "fmm_plan_stats",
               "fmm_plan_export", "fmm_plan_set_timing", "fmm_plan_phase_times"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -121,9 +124,11 @@ class FMM:
     """A plan (octree + interaction lists) for a fixed point set on the device.
 
     points: float32 device tensor [n, 3].  The plan is built on the current stream.
+    m2l_tol > 0 selects the variable-order M2L (operator blocks below that relative size
+    are left out; FP32 only), 0 the dense operators.
     """
 
-    def __init__(self, points, ncrit=64, p=10, theta=0.4, precision="fp32"):
+    def __init__(self, points, ncrit=64, p=10, theta=0.4, precision="fp32", m2l_tol=0.0):
         lib = load_library()
         if points.dim() != 2 or points.shape[1] != 3:
             raise ValueError("points must have shape [n, 3]")
@@ -134,10 +139,11 @@ class FMM:
         if precision not in _PREC:
             raise ValueError(f"precision must be one of {list(_PREC)}")
         self.ncrit, self.p, self.theta, self.precision = int(ncrit), int(p), float(theta), precision
+        self.m2l_tol = float(m2l_tol)
         self.device = points.device
         h = _vp()
-        _check(lib.fmm_plan(ptr, self.n, self.ncrit, self.p, C.c_float(self.theta), _PREC[precision],
-                            _stream_handle(), C.byref(h)))
+        _check(lib.fmm_plan_ex(ptr, self.n, self.ncrit, self.p, C.c_float(self.theta), _PREC[precision],
+                               C.c_double(self.m2l_tol), _stream_handle(), C.byref(h)))
         self._h = h
 
     # -------------------------------------------------------------- lifetime

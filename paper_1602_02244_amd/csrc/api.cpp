@@ -141,6 +141,8 @@ void fill_stats(fmm_plan_s *P) {
     st.m2l_flops = 2.0 * nc * nc * (double)P->nm2l;
     st.p2p_flops = 20.0 * (double)P->p2p_interactions;
     st.workspace_bytes = P->mem.bytes;
+    st.m2l_tol = P->m2l_tol;
+    st.m2l_kept_fraction = P->m2l_kept;
 }
 }  // namespace
 
@@ -159,6 +161,11 @@ fmm_status fmm_set_allocator(fmm_alloc_fn alloc, fmm_free_fn release, void *ctx)
 
 fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec, void *stream,
                     fmm_plan_t *out) {
+    return fmm_plan_ex(points, n, ncrit, p, theta, prec, 0.0, stream, out);
+}
+
+fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec,
+                       double m2l_tol, void *stream, fmm_plan_t *out) {
     if (!out) return set_err(FMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!points) return set_err(FMM_EINVAL, "points is NULL");
@@ -169,6 +176,9 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
     if (!std::isfinite(theta) || !(theta > 0.f) || !(3.0 * (double)theta * (double)theta < 1.0))
         return set_err(FMM_EINVAL, "theta must be in (0, 1/sqrt(3))");
     if (prec != FMM_PREC_FP32 && prec != FMM_PREC_MIXED) return set_err(FMM_EINVAL, "unknown precision");
+    if (!std::isfinite(m2l_tol) || m2l_tol < 0.0) return set_err(FMM_EINVAL, "m2l_tol must be finite and >= 0");
+    if (m2l_tol > 0.0 && prec != FMM_PREC_FP32)
+        return set_err(FMM_EINVAL, "a variable-order M2L (m2l_tol > 0) needs FMM_PREC_FP32");
     fmm_plan_s *P = new (std::nothrow) fmm_plan_s();
     if (!P) return set_err(FMM_ENOMEM, "host allocation failed");
     P->n = n;
@@ -176,6 +186,7 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
     P->p = p;
     P->theta = theta;
     P->prec = prec;
+    P->m2l_tol = m2l_tol;
     P->KP = ncoef_pad(p);
     {
         std::lock_guard<std::mutex> lk(g_alloc_mu);

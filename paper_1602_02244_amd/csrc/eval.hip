@@ -190,9 +190,9 @@ typedef __attribute__((address_space(1))) const floatx4 gfloatx4;   // global-me
 // Software pipeline, with no branch on loaded data so that every wait is a counted one:
 //   entry e+2: source indices (lane = column), operator key and column mask are loaded;
 //   entry e+1: the operator pointer is resolved, and its 64 gathered source vectors are
-//              loaded one piece per k chunk of entry e (the source index reaches the
-//              loading lane by a cross-lane shuffle; empty columns load row 0 and are
-//              zeroed when stored to LDS);
+//              loaded one k chunk (16 coefficients of every source) per k chunk of entry e
+//              (the source index reaches the loading lane by a cross-lane shuffle; empty
+//              columns load row 0 and are zeroed when stored to LDS);
 //   entry e:   T streams one k chunk ahead of its MFMAs, and the last chunk prefetches
 //              chunk 0 of entry e+1's operator.
 // Column blocks with no source in an entry (mask bit clear; MASKED only) are skipped.
@@ -201,10 +201,11 @@ typedef __attribute__((address_space(1))) const floatx4 gfloatx4;   // global-me
 // level: targets are parents, one entry per child octant) and L2L (per level:
 // targets share an octant, the source is the parent; ADD accumulates onto the
 // M2L result).
-template <int P, bool ADD, bool MASKED>
+template <int P, bool ADD, bool MASKED, bool VARORD = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 12 ? 2 : 1))) k_gemm(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                               const uint8_t *entry_mask, const uint64_t *key_ptr, const float *M,
-                                              float *L, float *partial, const int32_t *tile_targets) {
+                                              float *L, float *partial, const int32_t *tile_targets,
+                                              const uint32_t *key_rows = nullptr) {
     using D = Dims<P>;
     constexpr int KP = D::KP;
     constexpr int KPS = KP + 4;                  // LDS row stride (bank spread)
@@ -213,7 +214,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
     constexpr int NKC = KP / 16;                 // k chunks
     constexpr int NQ = KP / 4;                   // float4 per coefficient vector
     constexpr int NPF = kTileN * NQ / 256;       // gathered float4 per thread per entry
-    static_assert(kTileN == 64 && (kTileN * NQ) % 256 == 0 && NPF == NKC, "one gather piece per k chunk");
+    static_assert(kTileN == 64 && (kTileN * NQ) % 256 == 0 && NPF == NKC && NQ == 4 * NKC,
+                  "one gather piece per k chunk");
     __shared__ __attribute__((aligned(16))) float Ms[kTileN * KPS];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar branches
@@ -228,36 +230,57 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     auto clampe = [&](int e) { return min(e, e1 - 1); };
+    // gather layout: thread tid copies column tid/4, and piece i is k chunk i (coefficients
+    // 16 i .. 16 i + 15, one float4 per thread)
+    const int gcol = tid >> 2, gsub = tid & 3;
+    float4 pre[NPF];
+    int src = -1;
+    auto gather_src = [&](int idxv) { src = __shfl(idxv, gcol, 64); };
+    auto gather_piece = [&](int i, uint32_t used) {
+        // a chunk no row of the operator uses re-reads chunk 0 (cached) instead
+        const int q4 = (!VARORD || ((used >> i) & 1u)) ? 4 * i + gsub : gsub;
+        pre[i] = reinterpret_cast<const float4 *>(M + (int64_t)max(src, 0) * KP)[q4];
+    };
+    auto mask_of = [&](int e) { return MASKED ? (int)entry_mask[e] : 15; };
+
+    // variable order: per row block of the wave, the k chunks of the operator that are kept;
+    // word NRB of a key holds the union over all its row blocks
+    uint32_t rm[RBW], rmn[RBW];
+    auto rows_of = [&](int key, uint32_t *dst) {
+#pragma unroll
+        for (int r = 0; r < RBW; ++r)
+            dst[r] = VARORD ? key_rows[(int64_t)key * (NRB + 1) + min(wave + 4 * r, NRB - 1)] : ~0u;
+    };
+    auto used_of = [&](int key) { return VARORD ? key_rows[(int64_t)key * (NRB + 1) + NRB] : ~0u; };
     // operators are reached through a pointer table: global loads, not flat ones (a flat
-    // load also counts against the LDS wait counter)
-    auto t_chunk = [&](const float *T, int kc, floatx4 *dst) {
+    // load also counts against the LDS wait counter).  A chunk the variable order leaves out
+    // is not skipped but re-reads chunk 0 (already in cache): no branch around a load, so
+    // every wait stays a counted one.
+    auto t_chunk_v = [&](const float *T, int kc, const uint32_t *msk, floatx4 *dst) {
         const gfloatx4 *Tg = (const gfloatx4 *)(T);
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
             const int rb = min(wave + 4 * r, NRB - 1);
-            dst[r] = Tg[((rb * 16 + li) * KP + kc * 16 + 4 * lg) / 4];
+            const int kk = (!VARORD || ((msk[r] >> kc) & 1u)) ? kc : 0;
+            dst[r] = Tg[((rb * 16 + li) * KP + kk * 16 + 4 * lg) / 4];
         }
     };
-    float4 pre[NPF];
-    int srcs[NPF];
-    auto gather_src = [&](int idxv) {            // the source behind each of this lane's pieces
-#pragma unroll
-        for (int i = 0; i < NPF; ++i) srcs[i] = __shfl(idxv, (tid + 256 * i) / NQ, 64);
-    };
-    auto gather_piece = [&](int i) {
-        const int q4 = (tid + 256 * i) % NQ;
-        pre[i] = reinterpret_cast<const float4 *>(M + (int64_t)max(srcs[i], 0) * KP)[q4];
-    };
-    auto mask_of = [&](int e) { return MASKED ? (int)entry_mask[e] : 15; };
 
     // prologue: entry e0's sources and operator chunk 0; entry e0+1's indices, key and mask
+    const int key0 = entry_key[e0];
     gather_src(entry_src[(int64_t)e0 * kTileN + lane]);
+    {
+        const uint32_t used0 = used_of(key0);
 #pragma unroll
-    for (int i = 0; i < NPF; ++i) gather_piece(i);
-    const float *Tc = reinterpret_cast<const float *>(key_ptr[entry_key[e0]]);
+        for (int i = 0; i < NPF; ++i) gather_piece(i, used0);
+    }
+    const float *Tc = reinterpret_cast<const float *>(key_ptr[key0]);
+    rows_of(key0, rm);
     int mask = mask_of(e0);
     floatx4 a[RBW], an[RBW];
-    t_chunk(Tc, 0, a);
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) a[r] = an[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    t_chunk_v(Tc, 0, rm, a);
     int idx = entry_src[(int64_t)clampe(e0 + 1) * kTileN + lane];
     int key_n = entry_key[clampe(e0 + 1)];
     int mask_n = mask_of(clampe(e0 + 1));
@@ -267,9 +290,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NPF; ++i) {
-            const int g = tid + 256 * i, col = g / NQ, q4 = g % NQ;
-            const float4 v = srcs[i] >= 0 ? pre[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-            *reinterpret_cast<float4 *>(&Ms[col * KPS + 4 * q4]) = v;
+            const float4 v = src >= 0 ? pre[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            *reinterpret_cast<float4 *>(&Ms[gcol * KPS + 16 * i + 4 * gsub]) = v;
         }
         gather_src(idx);                         // entry e+1
         const int m = __builtin_amdgcn_readfirstlane(mask);
@@ -278,14 +300,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         __syncthreads();
         // next entry's operator; the entry after that: indices, key, mask
         const float *Tn = reinterpret_cast<const float *>(key_ptr[kn]);
+        rows_of(kn, rmn);
+        const uint32_t used_n = used_of(kn);
         idx = entry_src[(int64_t)clampe(e + 2) * kTileN + lane];
         key_n = entry_key[clampe(e + 2)];
         mask_n = mask_of(clampe(e + 2));
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
-            if (kc + 1 < NKC) t_chunk(Tc, kc + 1, an);
-            else t_chunk(Tn, 0, an);
-            gather_piece(kc);                    // entry e+1 (a repeat of the last entry at the end)
+            if (kc + 1 < NKC) t_chunk_v(Tc, kc + 1, rm, an);
+            else t_chunk_v(Tn, 0, rmn, an);
+            gather_piece(kc, used_n);            // entry e+1 (a repeat of the last entry at the end)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 if (!((m >> cb) & 1)) continue;
@@ -293,6 +317,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
 #pragma unroll
                 for (int r = 0; r < RBW; ++r) {
                     if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
+                    if (VARORD && !((rm[r] >> kc) & 1u)) continue;
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, acc[r][cb], 0, 0, 0);
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, acc[r][cb], 0, 0, 0);
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b.z, acc[r][cb], 0, 0, 0);
@@ -303,6 +328,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
             for (int r = 0; r < RBW; ++r) a[r] = an[r];
         }
         Tc = Tn;
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) rm[r] = rmn[r];
     }
     // output: lane holds D[4*lg + v][li] of each 16x16 block
 #pragma unroll
@@ -1008,6 +1035,11 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
                                (const uint8_t *)Pl->entry_mask, Pl->key_f16, (const _Float16 *)Pl->Mh,
                                (const _Float16 *)Pl->Ml, (const float *)Pl->Msinv, Pl->L, Pl->partial,
                                (const int32_t *)Pl->tile_targets);
+        else if (Pl->key_rows)
+            hipLaunchKernelGGL((k_gemm<P, false, true, true>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
+                               (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
+                               (const uint8_t *)Pl->entry_mask, Pl->key_f32, (const float *)Pl->M, Pl->L, Pl->partial,
+                               (const int32_t *)Pl->tile_targets, (const uint32_t *)Pl->key_rows);
         else
             hipLaunchKernelGGL((k_gemm<P, false, true>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
                                (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,

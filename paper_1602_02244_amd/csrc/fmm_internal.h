@@ -77,6 +77,12 @@ const OpTables &op_tables(int p);
 // keys: packed (level difference, offset) keys.  Creates missing operators.
 void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f32_ptrs,
                        std::vector<uint64_t> &f16_ptrs, bool need_f16);
+// Variable-order M2L: for every key (whose operator exists), the 16x16 blocks of the
+// operator that are kept at tolerance tol, as one row mask per row block (bit c: k chunk c
+// is kept) followed by their union ([nkeys][KP/16 + 1]), and the kept fraction of blocks.  Blocks are dropped smallest first while
+// their summed weighted size stays within tol of the interaction's monopole term.
+void m2l_block_rows(int p, const std::vector<uint64_t> &keys, double tol, std::vector<uint32_t> &rows,
+                    std::vector<float> &kept);
 // FP64 M2L operators ([KP in][KP out], transposed) of the given keys.
 void m2l_operator_ptrs64(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f64_ptrs);
 constexpr int kRootLevels = 4;     // mixed precision: levels 0..3 keep FP64 coefficients
@@ -113,6 +119,9 @@ struct LevelGemm {
 
 // --------------------------------------------------------------------- the plan
 struct fmm_plan_s {
+    double m2l_tol = 0.0;        // variable-order M2L tolerance (0: dense operators)
+    double m2l_kept = 1.0;       // pair-weighted fraction of operator blocks applied
+    uint32_t *key_rows = nullptr; // [nkeys][KP/16 + 1] kept k-chunk masks per row block, then their union
     int device = 0;
     int64_t n = 0;
     int ncrit = 0, p = 0;

@@ -208,6 +208,32 @@ void split16(const std::vector<double> &A, int p, int KP, std::vector<char> &out
     for (int i = 0; i < KP; ++i) rsf[i] = (float)rs[i];
 }
 
+// Size of every 16 x 16 block of an M2L operator A ([KP][KP], rows = local coefficient of
+// the target, columns = multipole coefficient of the source), measured by what the block
+// can add to a potential: a multipole coefficient of degree n is at most h^n / nu_nm
+// times the source cell's total |charge| (its bodies lie within h = sqrt(3)/2 of the
+// centre, in units of the side), and a local coefficient of degree j reaches the
+// potential with a weight of at most h^j / nu_jk.  Returned: for every block, the sum of
+// |w_r A_rc w_c| over the block, divided by |w_0 A_00 w_0| (the monopole-to-monopole
+// term, i.e. the size of the whole interaction).
+std::vector<float> block_sums(const std::vector<double> &A, int p, int KP) {
+    const int NB = KP / 16;
+    const double h = std::sqrt(3.0) / 2;
+    std::vector<double> nu = nu_vector(p, KP), w(KP, 0.0);
+    for (int l = 0; l <= p; ++l)
+        for (int m = 0; m <= l; ++m) {
+            w[ridx(l, m, 0)] = std::pow(h, l) / nu[ridx(l, m, 0)];
+            if (m > 0) w[ridx(l, m, 1)] = std::pow(h, l) / nu[ridx(l, m, 1)];
+        }
+    std::vector<double> b((size_t)NB * NB, 0.0);
+    for (int r = 0; r < KP; ++r)
+        for (int c = 0; c < KP; ++c) b[(size_t)(r / 16) * NB + c / 16] += std::fabs(w[r] * A[(size_t)r * KP + c] * w[c]);
+    const double ref = std::fabs(A[0]);
+    std::vector<float> out(b.size());
+    for (size_t i = 0; i < b.size(); ++i) out[i] = ref > 0 ? (float)(b[i] / ref) : 1.f;
+    return out;
+}
+
 // ------------------------------------------------------------------ device store
 constexpr int kChunk = 64;   // matrices per device allocation (never moved)
 
@@ -234,6 +260,7 @@ struct Store {
     std::unordered_map<uint64_t, uint64_t> f32;   // key -> device pointer
     std::unordered_map<uint64_t, uint64_t> f16;   // key -> device pointer (split FP16 form)
     std::unordered_map<uint64_t, uint64_t> f64;   // key -> device pointer (FP64, transposed)
+    std::unordered_map<uint64_t, std::vector<float>> bsum;   // key -> weighted block sums (see block_sums)
     BlockPool pool32, pool16, pool64;
     OpTables tables;
     float *alloc_matrix() { return static_cast<float *>(pool32.take()); }
@@ -340,6 +367,7 @@ void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uin
             float *d = s.alloc_matrix();
             HIP_CHECK(hipMemcpy(d, host.data(), sizeof(float) * s.mat_floats, hipMemcpyHostToDevice));
             it = s.f32.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
+            s.bsum[keys[i]] = block_sums(A, p, ncoef_pad(p));
         }
         f32_ptrs[i] = it->second;
         if (need_f16) {
@@ -354,6 +382,32 @@ void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uin
             }
             f16_ptrs[i] = jt->second;
         }
+    }
+}
+
+void m2l_block_rows(int p, const std::vector<uint64_t> &keys, double tol, std::vector<uint32_t> &rows,
+                    std::vector<float> &kept) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Store &s = store_for(p);
+    const int NB = ncoef_pad(p) / 16;
+    rows.assign(keys.size() * (NB + 1), 0u);
+    kept.assign(keys.size(), 1.f);
+    std::vector<std::pair<float, int>> order;
+    for (size_t i = 0; i < keys.size(); ++i) {
+        const std::vector<float> &b = s.bsum.at(keys[i]);
+        order.clear();
+        for (int q = 0; q < NB * NB; ++q) order.emplace_back(b[q], q);
+        std::sort(order.begin(), order.end());
+        // drop the smallest blocks while their total stays within tol
+        double dropped = 0;
+        size_t nd = 0;
+        while (nd < order.size() && dropped + order[nd].first <= tol) dropped += order[nd++].first;
+        for (size_t q = nd; q < order.size(); ++q) {
+            const int blk = order[q].second;
+            rows[i * (NB + 1) + blk / NB] |= 1u << (blk % NB);
+            rows[i * (NB + 1) + NB] |= 1u << (blk % NB);      // chunks used by any row block
+        }
+        kept[i] = (float)(order.size() - nd) / (float)order.size();
     }
 }
 

@@ -453,16 +453,19 @@ __global__ void k_entry_keys(const int32_t *present, const int32_t *entry_of, in
         if (present[i]) entry_key[entry_of[i]] = (int32_t)(i % nkeys);
 }
 
-// Column-block mask of every entry: bit cb set iff one of its columns 16cb..16cb+15 has a source.
-__global__ void k_entry_masks(const int32_t *entry_src, int64_t ne, uint8_t *m8) {
+// Column-block mask of every entry: bit cb set iff one of its columns 16cb..16cb+15 has a
+// source; optionally the entry's number of sources.
+__global__ void k_entry_masks(const int32_t *entry_src, int64_t ne, uint8_t *m8, int32_t *nsrc) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
         const int4 *row = reinterpret_cast<const int4 *>(entry_src + e * kTileN);
-        int m = 0;
+        int m = 0, c = 0;
         for (int q = 0; q < kTileN / 4; ++q) {
             const int4 v = row[q];
             if (v.x >= 0 || v.y >= 0 || v.z >= 0 || v.w >= 0) m |= 1 << (q / 4);
+            c += (v.x >= 0) + (v.y >= 0) + (v.z >= 0) + (v.w >= 0);
         }
         m8[e] = (uint8_t)m;
+        if (nsrc) nsrc[e] = c;
     }
 }
 
@@ -988,6 +991,14 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             HIP_CHECK(hipMemcpyAsync(d16, p16.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
             P->key_f16 = d16;
         }
+        std::vector<float> key_kept;
+        if (P->m2l_tol > 0) {
+            std::vector<uint32_t> rows;
+            m2l_block_rows(P->p, hkeys, P->m2l_tol, rows, key_kept);
+            P->key_rows = a.get_n<uint32_t>((int64_t)rows.size());
+            HIP_CHECK(hipMemcpyAsync(P->key_rows, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, s));
+            HIP_CHECK(hipStreamSynchronize(s));   // the host vector goes out of scope
+        }
         int32_t *slot_id = a.get_n<int32_t>((int64_t)H);
         HIP_CHECK(hipMemcpyAsync(slot_id, hslot.data(), 4 * H, hipMemcpyHostToDevice, s));
         int32_t *dsame = a.get_n<int32_t>(nkeys);
@@ -1016,7 +1027,22 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         hipLaunchKernelGGL(k_entry_keys, grid1(ntk), 256, 0, s, (const int32_t *)present, (const int32_t *)entry_of, ntk,
                            nkeys, P->entry_key);
         P->entry_mask = a.get_n<uint8_t>(ne);
-        hipLaunchKernelGGL(k_entry_masks, grid1(ne), 256, 0, s, (const int32_t *)P->entry_src, ne, P->entry_mask);
+        int32_t *nsrc = P->m2l_tol > 0 ? a.get_n<int32_t>(ne) : nullptr;
+        hipLaunchKernelGGL(k_entry_masks, grid1(ne), 256, 0, s, (const int32_t *)P->entry_src, ne, P->entry_mask, nsrc);
+        if (nsrc) {
+            // pair-weighted fraction of operator blocks the variable-order M2L applies
+            std::vector<int32_t> hn(ne), hk(ne);
+            HIP_CHECK(hipMemcpyAsync(hn.data(), nsrc, 4 * ne, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(hk.data(), P->entry_key, 4 * ne, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            double num = 0, den = 0;
+            for (int64_t e2 = 0; e2 < ne; ++e2) {
+                num += (double)hn[e2] * key_kept[hk[e2]];
+                den += (double)hn[e2];
+            }
+            P->m2l_kept = den > 0 ? num / den : 1.0;
+            a.put(nsrc);
+        }
         int32_t *tile_first = a.get_n<int32_t>(ntiles);
         hipLaunchKernelGGL(k_tile_first, grid1(ntiles), 256, 0, s, (const int32_t *)entry_of, ntiles, nkeys, tile_first);
         std::vector<int32_t> htf(ntiles);

@@ -32,7 +32,7 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for want in ("fmm_plan", "fmm_eval", "fmm_eval_ex", "fmm_adjoint", "fmm_plan_stats", "fmm_plan_export",
+    for want in ("fmm_plan", "fmm_plan_ex", "fmm_eval", "fmm_eval_ex", "fmm_adjoint", "fmm_plan_stats", "fmm_plan_export",
                  "fmm_plan_destroy", "fmm_last_error", "fmm_set_allocator", "fmm_plan_set_timing",
                  "fmm_plan_phase_times"):
         assert want in names
@@ -63,6 +63,16 @@ def test_plan_rejects_invalid_arguments_before_any_device_call(lib, n, ncrit, p,
     assert st == FMM_EINVAL and out.value is None
     lib.fmm_last_error.restype = C.c_char_p
     assert len(lib.fmm_last_error()) > 0
+
+
+@pytest.mark.parametrize("tol,prec", [(-1e-3, 0), (float("nan"), 0), (float("inf"), 0), (1e-6, 1)])
+def test_plan_ex_rejects_bad_tolerance_before_any_device_call(lib, tol, prec):
+    lib.fmm_plan_ex.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, C.c_double, C.c_void_p,
+                                C.POINTER(C.c_void_p)]
+    lib.fmm_plan_ex.restype = C.c_int
+    out = C.c_void_p(1234)
+    st = lib.fmm_plan_ex(C.c_void_p(0x1000), 10, 64, 4, 0.4, prec, tol, None, C.byref(out))
+    assert st == FMM_EINVAL and out.value is None
 
 
 def test_null_pointers_rejected(lib):
