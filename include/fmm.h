@@ -98,11 +98,19 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
  *                 relative to the interaction's monopole-to-monopole term.  So every M2L
  *                 pair's potential changes by at most m2l_tol of its monopole term.
  *                 0 keeps every block (same result as fmm_plan).  FP32 precision only.
+ *   lists         FMM_LISTS_DUAL: the dual traversal of fmm_plan (a pair of cells at the same
+ *                 level that fails the MAC is replaced by all pairs of their children);
+ *                 FMM_LISTS_LEVEL_SKIP: only the cell with the smaller Morton prefix is split,
+ *                 so that distant members of a list can be served by their parent (the
+ *                 paper's level-skip remark, Sec. 2.2); fewer M2L pairs, same MAC, pair sets
+ *                 still symmetric.
  * Other arguments, ownership and errors as fmm_plan; EINVAL for a negative, NaN or
- * infinite m2l_tol, or m2l_tol > 0 with FMM_PREC_MIXED.
+ * infinite m2l_tol, m2l_tol > 0 with FMM_PREC_MIXED, or an unknown lists value.
  */
+#define FMM_LISTS_DUAL 0
+#define FMM_LISTS_LEVEL_SKIP 1
 fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta,
-                       fmm_precision prec, double m2l_tol, void *stream, fmm_plan_t *out);
+                       fmm_precision prec, double m2l_tol, int lists, void *stream, fmm_plan_t *out);
 
 /*
  * Apply the plan to charges q (device [n]): potential (device [n]) and, when
@@ -147,6 +155,7 @@ struct fmm_stats {
     int64_t workspace_bytes;
     double m2l_tol;                         /* variable-order tolerance (0: every block) */
     double m2l_kept_fraction;               /* pair-weighted fraction of operator blocks applied */
+    int64_t lists;                          /* FMM_LISTS_DUAL or FMM_LISTS_LEVEL_SKIP */
 };
 fmm_status fmm_plan_stats(fmm_plan_t plan, struct fmm_stats *out);
 

@@ -44,7 +44,7 @@ def _load():
     lib.oracle_l2l.argtypes = [C.c_int, _dp, _dp, _dp]
     lib.oracle_l2p.argtypes = [C.c_int, _dp, _dp, C.c_int64, _dp, _dp, _dp]
     lib.oracle_multipole_eval.argtypes = [C.c_int, _dp, _dp, C.c_int64, _dp, _dp]
-    lib.oracle_plan_create.argtypes = [C.c_int64, _dp, C.c_int, C.c_float]
+    lib.oracle_plan_create.argtypes = [C.c_int64, _dp, C.c_int, C.c_float, C.c_int]
     lib.oracle_plan_create.restype = C.c_void_p
     lib.oracle_plan_destroy.argtypes = [C.c_void_p]
     lib.oracle_plan_counts.argtypes = [C.c_void_p, _i64p]
@@ -157,13 +157,14 @@ NEAR, FAR, BOTH = 1, 2, 3
 class Plan:
     """Oracle octree + interaction lists for a fixed point set (FP32 values held in FP64)."""
 
-    def __init__(self, points, ncrit: int, theta: float):
+    def __init__(self, points, ncrit: int, theta: float, lists: int = 0):
         lib = _load()
         self.points = _d(points).reshape(-1, 3)
         self.n = self.points.shape[0]
         self.ncrit = int(ncrit)
         self.theta = float(np.float32(theta))
-        h = lib.oracle_plan_create(self.n, _ptr(self.points, _dp), self.ncrit, C.c_float(self.theta))
+        self.lists = int(lists)
+        h = lib.oracle_plan_create(self.n, _ptr(self.points, _dp), self.ncrit, C.c_float(self.theta), self.lists)
         if not h:
             raise ValueError("oracle: invalid plan arguments")
         self._h = h

@@ -402,6 +402,7 @@ typedef struct {
     int64_t n;
     int ncrit;
     float theta;
+    int lists;           /* 0: dual traversal (split both); 1: one cell at a time (level skip) */
     int k;               /* root side = 2^k */
     double x0[3];        /* root corner */
     double *pts;         /* [n][3] input order (copy) */
@@ -579,6 +580,12 @@ static int mac_accept(const oplan *P, const ocell *A, const ocell *B, double the
  *   4. else split the coarser cell (lower level; on a tie the non-leaf one)
  *      if it is not a leaf, otherwise the other one.
  * The rules do not depend on the order of A and B, so the lists are symmetric.
+ *
+ * Level-skip variant (lists = 1; the paper's remark that distant members of an
+ * interaction list can be served by their parent): rule 3 splits only one of the two
+ * cells, the one with the smaller Morton prefix, so that a target's children can take
+ * the other cell's multipole whole when the MAC allows it.  The choice depends on the
+ * unordered pair only, so the lists stay symmetric.
  */
 static void traverse(oplan *P) {
     double theta2 = (double)P->theta * (double)P->theta;
@@ -601,9 +608,17 @@ static void traverse(oplan *P) {
         /* children pairs to push */
         int64_t ca[8], cb[8];
         int na = 0, nb = 0;
-        if (!la && !lb && A->level == B->level) {
+        if (!la && !lb && A->level == B->level && P->lists == 0) {
             for (int o = 0; o < 8; ++o) if (A->child[o] >= 0) ca[na++] = A->child[o];
             for (int o = 0; o < 8; ++o) if (B->child[o] >= 0) cb[nb++] = B->child[o];
+        } else if (!la && !lb && A->level == B->level) {
+            if (A->prefix <= B->prefix) {
+                for (int o = 0; o < 8; ++o) if (A->child[o] >= 0) ca[na++] = A->child[o];
+                cb[0] = bi; nb = 1;
+            } else {
+                ca[0] = ai; na = 1;
+                for (int o = 0; o < 8; ++o) if (B->child[o] >= 0) cb[nb++] = B->child[o];
+            }
         } else {
             int splitA;
             if (A->level < B->level) splitA = !la;
@@ -633,12 +648,13 @@ static void traverse(oplan *P) {
 }
 
 /* Returns NULL on invalid arguments. pts is [n][3] doubles (FP32 values). */
-void *oracle_plan_create(int64_t n, const double *pts, int ncrit, float theta) {
-    if (n < 1 || ncrit < 1 || !(theta > 0.0f)) return NULL;
+void *oracle_plan_create(int64_t n, const double *pts, int ncrit, float theta, int lists) {
+    if (n < 1 || ncrit < 1 || !(theta > 0.0f) || lists < 0 || lists > 1) return NULL;
     oplan *P = (oplan *)calloc(1, sizeof(oplan));
     P->n = n;
     P->ncrit = ncrit;
     P->theta = theta;
+    P->lists = lists;
     P->pts = (double *)malloc(sizeof(double) * 3 * n);
     memcpy(P->pts, pts, sizeof(double) * 3 * n);
     root_cube(n, P->pts, &P->k, P->x0);

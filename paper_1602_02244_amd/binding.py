@@ -44,7 +44,7 @@ class FmmStats(C.Structure):
         ("m2l_flops", C.c_double),
         ("p2p_flops", C.c_double),
         ("workspace_bytes", C.c_int64),
-        ("m2l_tol", C.c_double), ("m2l_kept_fraction", C.c_double),
+        ("m2l_tol", C.c_double), ("m2l_kept_fraction", C.c_double), ("lists", C.c_int64),
     ]
 
 
@@ -71,7 +71,7 @@ def load_library():
     lib.fmm_last_error.argtypes = []
     lib.fmm_set_allocator.argtypes = [_vp, _vp, _vp]
     lib.fmm_plan.argtypes = [_vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, _vp, C.POINTER(_vp)]
-    lib.fmm_plan_ex.argtypes = [_vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, C.c_double, _vp,
+    lib.fmm_plan_ex.argtypes = [_vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, C.c_double, C.c_int, _vp,
                                 C.POINTER(_vp)]
     lib.fmm_eval.argtypes = [_vp, _vp, _vp, _vp, _vp]
     lib.fmm_eval_ex.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp]
@@ -118,6 +118,7 @@ def _stream_handle():
 
 
 _PREC = {"fp32": FMM_PREC_FP32, "mixed": FMM_PREC_MIXED}
+_LISTS = {"dual": 0, "level-skip": 1}
 
 
 class FMM:
@@ -125,10 +126,11 @@ class FMM:
 
     points: float32 device tensor [n, 3].  The plan is built on the current stream.
     m2l_tol > 0 selects the variable-order M2L (operator blocks below that relative size
-    are left out; FP32 only), 0 the dense operators.
+    are left out; FP32 only), 0 the dense operators.  lists: "dual" (the dual traversal)
+    or "level-skip" (one cell of a same-level pair split at a time).
     """
 
-    def __init__(self, points, ncrit=64, p=10, theta=0.4, precision="fp32", m2l_tol=0.0):
+    def __init__(self, points, ncrit=64, p=10, theta=0.4, precision="fp32", m2l_tol=0.0, lists="dual"):
         lib = load_library()
         if points.dim() != 2 or points.shape[1] != 3:
             raise ValueError("points must have shape [n, 3]")
@@ -140,10 +142,13 @@ class FMM:
             raise ValueError(f"precision must be one of {list(_PREC)}")
         self.ncrit, self.p, self.theta, self.precision = int(ncrit), int(p), float(theta), precision
         self.m2l_tol = float(m2l_tol)
+        if lists not in _LISTS:
+            raise ValueError(f"lists must be one of {list(_LISTS)}")
+        self.lists = lists
         self.device = points.device
         h = _vp()
         _check(lib.fmm_plan_ex(ptr, self.n, self.ncrit, self.p, C.c_float(self.theta), _PREC[precision],
-                               C.c_double(self.m2l_tol), _stream_handle(), C.byref(h)))
+                               C.c_double(self.m2l_tol), _LISTS[lists], _stream_handle(), C.byref(h)))
         self._h = h
 
     # -------------------------------------------------------------- lifetime

@@ -143,6 +143,7 @@ void fill_stats(fmm_plan_s *P) {
     st.workspace_bytes = P->mem.bytes;
     st.m2l_tol = P->m2l_tol;
     st.m2l_kept_fraction = P->m2l_kept;
+    st.lists = P->lists;
 }
 }  // namespace
 
@@ -161,11 +162,11 @@ fmm_status fmm_set_allocator(fmm_alloc_fn alloc, fmm_free_fn release, void *ctx)
 
 fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec, void *stream,
                     fmm_plan_t *out) {
-    return fmm_plan_ex(points, n, ncrit, p, theta, prec, 0.0, stream, out);
+    return fmm_plan_ex(points, n, ncrit, p, theta, prec, 0.0, FMM_LISTS_DUAL, stream, out);
 }
 
 fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec,
-                       double m2l_tol, void *stream, fmm_plan_t *out) {
+                       double m2l_tol, int lists, void *stream, fmm_plan_t *out) {
     if (!out) return set_err(FMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!points) return set_err(FMM_EINVAL, "points is NULL");
@@ -179,6 +180,7 @@ fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float t
     if (!std::isfinite(m2l_tol) || m2l_tol < 0.0) return set_err(FMM_EINVAL, "m2l_tol must be finite and >= 0");
     if (m2l_tol > 0.0 && prec != FMM_PREC_FP32)
         return set_err(FMM_EINVAL, "a variable-order M2L (m2l_tol > 0) needs FMM_PREC_FP32");
+    if (lists != FMM_LISTS_DUAL && lists != FMM_LISTS_LEVEL_SKIP) return set_err(FMM_EINVAL, "unknown lists value");
     fmm_plan_s *P = new (std::nothrow) fmm_plan_s();
     if (!P) return set_err(FMM_ENOMEM, "host allocation failed");
     P->n = n;
@@ -187,6 +189,7 @@ fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float t
     P->theta = theta;
     P->prec = prec;
     P->m2l_tol = m2l_tol;
+    P->lists = lists;
     P->KP = ncoef_pad(p);
     {
         std::lock_guard<std::mutex> lk(g_alloc_mu);

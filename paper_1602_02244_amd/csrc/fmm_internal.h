@@ -120,6 +120,7 @@ struct LevelGemm {
 // --------------------------------------------------------------------- the plan
 struct fmm_plan_s {
     double m2l_tol = 0.0;        // variable-order M2L tolerance (0: dense operators)
+    int lists = 0;               // 0: dual traversal; 1: level skip (one cell split at a time)
     double m2l_kept = 1.0;       // pair-weighted fraction of operator blocks applied
     uint32_t *key_rows = nullptr; // [nkeys][KP/16 + 1] kept k-chunk masks per row block, then their union
     int device = 0;

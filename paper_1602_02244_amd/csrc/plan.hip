@@ -210,6 +210,8 @@ __global__ void k_init_root(int32_t n, uint64_t *prefix, int32_t *ix, int32_t *i
 // ----------------------------------------------------------------- dual traversal
 struct CellView {
     const int32_t *level, *ix, *iy, *iz, *child0, *nchild;
+    const uint64_t *prefix;   // Morton prefix (key >> 3 (21 - level))
+    int lists;                // 0: rule 3 splits both cells; 1: only the smaller prefix (level skip)
 };
 
 // MAC: accept A <- B iff A != B and theta*|c_A - c_B| >= R_A + R_B (R = half side),
@@ -225,32 +227,6 @@ __device__ inline bool mac_accept(const CellView &C, int a, int b, double theta2
     int64_t d2 = dx * dx + dy * dy + dz * dz;
     int64_t s = sa + sb;
     return theta2 * (double)d2 >= (double)(s * s);
-}
-
-// Traversal rules for the pair (A, B):
-//   1. MAC accepted                    -> M2L        (action 0)
-//   2. else both leaves                -> P2P        (action 1)
-//   3. else both split, same level     -> all child pairs
-//   4. else split the coarser cell (on a tie the non-leaf) if it is not a leaf,
-//      otherwise the other one.
-// For a split, the new pairs are [a0, a0+na) x [b0, b0+nb).
-__device__ inline int classify(const CellView &C, int a, int b, double theta2, int &a0, int &na, int &b0, int &nb) {
-    if (mac_accept(C, a, b, theta2)) return 0;
-    int nca = C.nchild[a], ncb = C.nchild[b];
-    if (nca == 0 && ncb == 0) return 1;
-    int la = C.level[a], lb = C.level[b];
-    bool splitA, splitB;
-    if (nca > 0 && ncb > 0 && la == lb) {
-        splitA = splitB = true;
-    } else {
-        if (la < lb) splitA = nca > 0;
-        else if (lb < la) splitA = ncb == 0;
-        else splitA = nca > 0;
-        splitB = !splitA;
-    }
-    if (splitA) { a0 = C.child0[a]; na = nca; } else { a0 = a; na = 1; }
-    if (splitB) { b0 = C.child0[b]; nb = ncb; } else { b0 = b; nb = 1; }
-    return 2;
 }
 
 __device__ inline int wave_incl_scan(int v) {
@@ -288,12 +264,25 @@ __device__ inline void block_scan3(int v0, int v1, int v2, int &e0, int &e1, int
 // per list reserve the ranges, then the lane writes.  Writes past a list's capacity are
 // dropped; the counters still advance, so the host sees the exact sizes and repeats
 // the step with larger lists.
+//
+// Traversal rules for the pair (A, B):
+//   1. MAC accepted                    -> M2L        (action 0)
+//   2. else both leaves                -> P2P        (action 1)
+//   3. else both split, same level     -> all child pairs; with level skip (lists = 1) only
+//      the cell with the smaller Morton prefix is split, so that the other one can serve
+//      the children whole when the MAC allows (the choice depends on the unordered pair,
+//      which keeps the lists symmetric)
+//   4. else split the coarser cell (on a tie the non-leaf) if it is not a leaf,
+//      otherwise the other one.
 __device__ inline void split_ranges(const CellView &C, int a, int b, int &a0, int &na, int &b0, int &nb) {
     int nca = C.nchild[a], ncb = C.nchild[b];
     int la = C.level[a], lb = C.level[b];
     bool splitA, splitB;
-    if (nca > 0 && ncb > 0 && la == lb) {
+    if (nca > 0 && ncb > 0 && la == lb && C.lists == 0) {
         splitA = splitB = true;
+    } else if (nca > 0 && ncb > 0 && la == lb) {
+        splitA = C.prefix[a] <= C.prefix[b];
+        splitB = !splitA;
     } else {
         if (la < lb) splitA = nca > 0;
         else if (lb < la) splitA = ncb == 0;
@@ -831,7 +820,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     }
 
     lg("leaves");
-    CellView C{P->c_level, P->c_ix, P->c_iy, P->c_iz, P->c_child0, P->c_nchild};
+    CellView C{P->c_level, P->c_ix, P->c_iy, P->c_iz, P->c_child0, P->c_nchild, P->c_prefix_dev, P->lists};
 
     // ---- M2M and L2L as grouped GEMMs: per-level tiles of parents (M2M) and of
     // same-octant children (L2L)

@@ -65,13 +65,14 @@ def test_plan_rejects_invalid_arguments_before_any_device_call(lib, n, ncrit, p,
     assert len(lib.fmm_last_error()) > 0
 
 
-@pytest.mark.parametrize("tol,prec", [(-1e-3, 0), (float("nan"), 0), (float("inf"), 0), (1e-6, 1)])
-def test_plan_ex_rejects_bad_tolerance_before_any_device_call(lib, tol, prec):
-    lib.fmm_plan_ex.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, C.c_double, C.c_void_p,
-                                C.POINTER(C.c_void_p)]
+@pytest.mark.parametrize("tol,prec,lists", [(-1e-3, 0, 0), (float("nan"), 0, 0), (float("inf"), 0, 0), (1e-6, 1, 0),
+                                            (0.0, 0, 2), (0.0, 0, -1)])
+def test_plan_ex_rejects_bad_arguments_before_any_device_call(lib, tol, prec, lists):
+    lib.fmm_plan_ex.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, C.c_double, C.c_int,
+                                C.c_void_p, C.POINTER(C.c_void_p)]
     lib.fmm_plan_ex.restype = C.c_int
     out = C.c_void_p(1234)
-    st = lib.fmm_plan_ex(C.c_void_p(0x1000), 10, 64, 4, 0.4, prec, tol, None, C.byref(out))
+    st = lib.fmm_plan_ex(C.c_void_p(0x1000), 10, 64, 4, 0.4, prec, tol, lists, None, C.byref(out))
     assert st == FMM_EINVAL and out.value is None
 
 

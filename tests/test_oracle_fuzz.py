@@ -33,10 +33,10 @@ def _cloud(kind, n, seed):
 @settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow], derandomize=True)
 @given(kind=st.sampled_from(["cube", "clusters", "plane", "line", "dups", "far"]),
        n=st.integers(2, 700), ncrit=st.integers(1, 40), theta=st.sampled_from([0.3, 0.4, 0.5]),
-       seed=st.integers(0, 10 ** 6))
-def test_pairs_partition_all_interactions(kind, n, ncrit, theta, seed):
+       seed=st.integers(0, 10 ** 6), lists=st.sampled_from([0, 1]))
+def test_pairs_partition_all_interactions(kind, n, ncrit, theta, seed, lists):
     x = _cloud(kind, n, seed)
-    pl = oracle.Plan(x, ncrit, theta)
+    pl = oracle.Plan(x, ncrit, theta, lists)
     c = pl.cells()
     m2l, p2p = pl.pairs()
     cov = np.zeros((n, n), np.int16)

@@ -305,3 +305,40 @@ def test_root_cube_is_the_closed_box():
     y = x.copy()
     y[-1, 0] = np.nextafter(1.0, 2.0)
     assert oracle.Plan(y, 4, 0.5).k == 1
+
+
+@pytest.mark.parametrize("dist,theta,ncrit", [("cube", 0.4, 16), ("plummer", 0.5, 10), ("sphere", 0.35, 12)])
+def test_level_skip_lists_cover_every_pair_once(dist, theta, ncrit):
+    """Level skip (one cell of a same-level pair split at a time): still an exact partition
+    of all ordered point pairs, symmetric, the MAC holds for every M2L pair (including the
+    mixed-level ones it creates), and fewer M2L pairs than the dual traversal."""
+    x, q = inputs.make(dist, 1500, 23)
+    pl = oracle.Plan(x.astype(np.float64), ncrit, theta, lists=1)
+    cov = _coverage(pl)
+    assert cov.min() == 1 and cov.max() == 1
+    m2l, p2p = pl.pairs()
+    s1 = set(map(tuple, m2l)); s2 = set(map(tuple, p2p))
+    assert s1 == {(b, a) for a, b in s1} and s2 == {(b, a) for a, b in s2}
+    c = pl.cells()
+    side = 2.0 ** (pl.k - c["level"].astype(np.float64))
+    ctr = np.zeros((pl.ncells, 3))
+    for i in range(pl.ncells):
+        l, pref = int(c["level"][i]), int(c["prefix"][i])
+        ic = [sum(((pref >> (3 * bb + 2 - a)) & 1) << bb for bb in range(l)) for a in range(3)]
+        ctr[i] = pl.x0 + (np.array(ic) + 0.5) * side[i]
+    d = np.linalg.norm(ctr[m2l[:, 0]] - ctr[m2l[:, 1]], axis=1)
+    assert np.all(theta * d >= 0.5 * (side[m2l[:, 0]] + side[m2l[:, 1]]) * (1 - 1e-6))
+    assert np.any(c["level"][m2l[:, 0]] != c["level"][m2l[:, 1]])
+    assert pl.nm2l < oracle.Plan(x.astype(np.float64), ncrit, theta).nm2l
+
+
+def test_level_skip_fmm_converges():
+    x, q = inputs.make("cube", 3000, 24)
+    x = x.astype(np.float64); q = q.astype(np.float64)
+    pl = oracle.Plan(x, 16, 0.4, lists=1)
+    ref, _ = oracle.direct(x, q)
+    errs = []
+    for p in (4, 8, 12):
+        phi, _, _ = pl.eval(q, p)
+        errs.append(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+    assert errs[2] < 1e-6 and errs[2] < errs[1] < errs[0]
