@@ -52,7 +52,8 @@ def _load():
     lib.oracle_plan_cells.argtypes = [C.c_void_p, _i32p, _u64p, _i64p, _i64p, _i64p, _i32p]
     lib.oracle_plan_pairs.argtypes = [C.c_void_p, _i64p, _i64p]
     lib.oracle_plan_order.argtypes = [C.c_void_p, _i64p, _u64p]
-    lib.oracle_fmm_eval.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp, _dp]
+    lib.oracle_fmm_eval.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp, _dp, _dp]
+    lib.oracle_direct_hessian.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _i64p, _dp]
     _lib = lib
     return lib
 
@@ -68,6 +69,22 @@ def _ptr(a, t):
 def set_threads(n: int = 0) -> int:
     """Set the OpenMP thread count (n <= 0 keeps it); returns the count in use."""
     return _load().oracle_set_threads(int(n))
+
+
+def direct_hessian(points, q, targets=None):
+    """Exact Hessian of phi at the targets (FP64), [nt][6] in the order xx, yy, zz, xy, xz, yz."""
+    lib = _load()
+    pts = _d(points).reshape(-1, 3)
+    qq = _d(q).reshape(-1)
+    n = pts.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        tp = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tp.shape[0]
+    hess = np.zeros((nt, 6))
+    lib.oracle_direct_hessian(n, _ptr(pts, _dp), _ptr(qq, _dp), nt, _ptr(tp, _i64p), _ptr(hess, _dp))
+    return hess
 
 
 def direct(points, q, targets=None):
@@ -210,8 +227,9 @@ class Plan:
         _load().oracle_plan_order(self._h, _ptr(order, _i64p), _ptr(keys, _u64p))
         return order, keys
 
-    def eval(self, q, p: int, mode: int = BOTH, sample=None):
-        """FMM potential and gradient (FP64).  Returns (phi, grad, timing[4])."""
+    def eval(self, q, p: int, mode: int = BOTH, sample=None, hessian=False):
+        """FMM potential and gradient (FP64).  Returns (phi, grad, timing[4]), and the
+        Hessian [nt][6] (xx, yy, zz, xy, xz, yz) as a fourth item when hessian=True."""
         qq = _d(q).reshape(-1)
         assert qq.shape[0] == self.n
         if sample is None:
@@ -222,6 +240,9 @@ class Plan:
         phi = np.zeros(nt)
         grad = np.zeros((nt, 3))
         timing = np.zeros(4)
+        hess = np.zeros((nt, 6)) if hessian else None
         _load().oracle_fmm_eval(self._h, int(p), _ptr(qq, _dp), int(mode), ns, _ptr(sp, _i64p),
-                                _ptr(phi, _dp), _ptr(grad, _dp), _ptr(timing, _dp))
+                                _ptr(phi, _dp), _ptr(grad, _dp), _ptr(hess, _dp), _ptr(timing, _dp))
+        if hessian:
+            return phi, grad, timing, hess
         return phi, grad, timing

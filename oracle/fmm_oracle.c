@@ -106,6 +106,35 @@ void oracle_direct(int64_t n, const double *pts, const double *q,
     }
 }
 
+/*
+ * Hessian of phi (second derivatives in x_i) at every target:
+ *   H_i = sum_{j != i, x_j != x_i} q_j (3 d d^T / |d|^5 - I / |d|^3),  d = x_i - x_j
+ * hess is [nt][6] in the order xx, yy, zz, xy, xz, yz.
+ */
+void oracle_direct_hessian(int64_t n, const double *pts, const double *q, int64_t nt, const int64_t *targ,
+                           double *hess) {
+    if (!targ) nt = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = targ ? targ[t] : t;
+        double h[6] = {0, 0, 0, 0, 0, 0}, hc[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3] = {pts[3 * i] - pts[3 * j], pts[3 * i + 1] - pts[3 * j + 1], pts[3 * i + 2] - pts[3 * j + 2]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2), ir3 = q[j] / (r2 * r), ir5 = 3.0 * ir3 / r2;
+            neumaier_add(&h[0], &hc[0], ir5 * d[0] * d[0] - ir3);
+            neumaier_add(&h[1], &hc[1], ir5 * d[1] * d[1] - ir3);
+            neumaier_add(&h[2], &hc[2], ir5 * d[2] * d[2] - ir3);
+            neumaier_add(&h[3], &hc[3], ir5 * d[0] * d[1]);
+            neumaier_add(&h[4], &hc[4], ir5 * d[0] * d[2]);
+            neumaier_add(&h[5], &hc[5], ir5 * d[1] * d[2]);
+        }
+        for (int a = 0; a < 6; ++a) hess[6 * t + a] = h[a] + hc[a];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Cartesian multi-indices                                                   */
 /* ------------------------------------------------------------------------ */
@@ -294,22 +323,42 @@ static void l2l_acc(const expctx *e, const double *Lp, const double d[3], double
     }
 }
 
-/* L2P: phi += sum_b L_b t^b, grad += d/dt of the same polynomial,  t = x - c */
-static void l2p_one(const expctx *e, const double *L, const double c[3], const double x[3],
-                    double *phi, double *grad) {
+/* L2P: phi += sum_b L_b t^b, grad and hess (xx, yy, zz, xy, xz, yz) += the first and
+ * second derivatives of the same polynomial,  t = x - c */
+static double dpow(const double *tp, int b, int k) {   /* d^k/dt^k of t^b */
+    if (b < k) return 0.0;
+    double f = 1.0;
+    for (int i = 0; i < k; ++i) f *= (double)(b - i);
+    return f * tp[b - k];
+}
+static void l2p_one_h(const expctx *e, const double *L, const double c[3], const double x[3],
+                      double *phi, double *grad, double *hess) {
     int p = e->p;
     double tx[32], ty[32], tz[32];
     powers(x[0] - c[0], p, tx); powers(x[1] - c[1], p, ty); powers(x[2] - c[2], p, tz);
-    double s = 0, gx = 0, gy = 0, gz = 0;
+    double s = 0, gx = 0, gy = 0, gz = 0, h[6] = {0, 0, 0, 0, 0, 0};
     for (int k = 0; k < e->mp.n; ++k) {
         const int *b = e->mp.a + 3 * k;
         s += L[k] * tx[b[0]] * ty[b[1]] * tz[b[2]];
         if (b[0] > 0) gx += L[k] * b[0] * tx[b[0] - 1] * ty[b[1]] * tz[b[2]];
         if (b[1] > 0) gy += L[k] * b[1] * tx[b[0]] * ty[b[1] - 1] * tz[b[2]];
         if (b[2] > 0) gz += L[k] * b[2] * tx[b[0]] * ty[b[1]] * tz[b[2] - 1];
+        if (hess) {
+            h[0] += L[k] * dpow(tx, b[0], 2) * ty[b[1]] * tz[b[2]];
+            h[1] += L[k] * tx[b[0]] * dpow(ty, b[1], 2) * tz[b[2]];
+            h[2] += L[k] * tx[b[0]] * ty[b[1]] * dpow(tz, b[2], 2);
+            h[3] += L[k] * dpow(tx, b[0], 1) * dpow(ty, b[1], 1) * tz[b[2]];
+            h[4] += L[k] * dpow(tx, b[0], 1) * ty[b[1]] * dpow(tz, b[2], 1);
+            h[5] += L[k] * tx[b[0]] * dpow(ty, b[1], 1) * dpow(tz, b[2], 1);
+        }
     }
     *phi += s;
     if (grad) { grad[0] += gx; grad[1] += gy; grad[2] += gz; }
+    if (hess) for (int a = 0; a < 6; ++a) hess[a] += h[a];
+}
+static void l2p_one(const expctx *e, const double *L, const double c[3], const double x[3],
+                    double *phi, double *grad) {
+    l2p_one_h(e, L, c, x, phi, grad, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -752,7 +801,7 @@ static void group_by_target(int64_t ncell, const int64_t *pairs, int64_t np, int
  * timing (nullable) receives seconds: [upward, m2l, downward+l2p, p2p].
  */
 void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample, const int64_t *sample,
-                     double *phi, double *grad, double *timing) {
+                     double *phi, double *grad, double *hess, double *timing) {
     oplan *P = (oplan *)h;
     int64_t nc = P->ncells, n = P->n;
     expctx e;
@@ -795,6 +844,7 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
 
     double *ophi = (double *)calloc((size_t)nt, sizeof(double));
     double *ograd = (double *)calloc((size_t)nt * 3, sizeof(double));
+    double *ohess = hess ? (double *)calloc((size_t)nt * 6, sizeof(double)) : NULL;
 
     int maxlev = 0;
     for (int64_t c = 0; c < nc; ++c) if (P->cells[c].level > maxlev) maxlev = P->cells[c].level;
@@ -863,7 +913,8 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
         for (int64_t t = 0; t < nt; ++t) {
             int64_t s = tpos[t];
             int64_t c = leaf_of[s];
-            l2p_one(&e, L + (size_t)c * nk, ctr + 3 * c, sp + 3 * s, ophi + t, ograd + 3 * t);
+            l2p_one_h(&e, L + (size_t)c * nk, ctr + 3 * c, sp + 3 * s, ophi + t, ograd + 3 * t,
+                      ohess ? ohess + 6 * t : NULL);
         }
         free(M); free(L);
 #ifdef _OPENMP
@@ -880,7 +931,7 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
             int64_t s = tpos[t];
             int64_t c = leaf_of[s];
             double xi = sp[3 * s], yi = sp[3 * s + 1], zi = sp[3 * s + 2];
-            double f = 0, gx = 0, gy = 0, gz = 0;
+            double f = 0, gx = 0, gy = 0, gz = 0, hh[6] = {0, 0, 0, 0, 0, 0};
             for (int64_t k = off[c]; k < off[c + 1]; ++k) {
                 const ocell *B = &P->cells[src[k]];
                 for (int64_t j = B->start; j < B->start + B->count; ++j) {
@@ -891,9 +942,15 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
                     double r = sqrt(r2);
                     double v = sq[j] / r, w = v / r2;
                     f += v; gx -= w * dx; gy -= w * dy; gz -= w * dz;
+                    if (ohess) {
+                        double w5 = 3.0 * w / r2;      /* 3 q / r^5 */
+                        hh[0] += w5 * dx * dx - w; hh[1] += w5 * dy * dy - w; hh[2] += w5 * dz * dz - w;
+                        hh[3] += w5 * dx * dy; hh[4] += w5 * dx * dz; hh[5] += w5 * dy * dz;
+                    }
                 }
             }
             ophi[t] += f; ograd[3 * t] += gx; ograd[3 * t + 1] += gy; ograd[3 * t + 2] += gz;
+            if (ohess) for (int a = 0; a < 6; ++a) ohess[6 * t + a] += hh[a];
         }
         free(off); free(src);
     }
@@ -903,6 +960,7 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
     for (int64_t t = 0; t < nt; ++t) {
         phi[t] = ophi[t];
         if (grad) { grad[3 * t] = ograd[3 * t]; grad[3 * t + 1] = ograd[3 * t + 1]; grad[3 * t + 2] = ograd[3 * t + 2]; }
+        if (hess) for (int a = 0; a < 6; ++a) hess[6 * t + a] = ohess[6 * t + a];
     }
     if (timing) {
         timing[0] = t1 - t0;
@@ -910,6 +968,6 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
         timing[2] = t3 - t2;
         timing[3] = t4 - t3;
     }
-    free(ophi); free(ograd); free(ctr); free(sp); free(sq); free(need); free(tpos); free(leaf_of); free(pos_of);
+    free(ophi); free(ograd); free(ohess); free(ctr); free(sp); free(sq); free(need); free(tpos); free(leaf_of); free(pos_of);
     exp_free(&e);
 }

@@ -342,3 +342,92 @@ def test_level_skip_fmm_converges():
         phi, _, _ = pl.eval(q, p)
         errs.append(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
     assert errs[2] < 1e-6 and errs[2] < errs[1] < errs[0]
+
+
+# ---------------------------------------------------------------- Hessian (losses through grad phi)
+def test_direct_hessian_closed_form_and_laplace():
+    """Two bodies: H = q (3 d d^T - |d|^2 I) / |d|^5; any cloud: H symmetric by layout and
+    traceless away from the sources (phi is harmonic)."""
+    x = np.array([[0.1, 0.2, 0.3], [0.7, -0.5, 1.3]])
+    q = np.array([0.0, 2.5])
+    h = oracle.direct_hessian(x, q)[0]
+    d = x[0] - x[1]
+    r = np.linalg.norm(d)
+    H = 2.5 * (3 * np.outer(d, d) - r * r * np.eye(3)) / r ** 5
+    assert np.allclose(h, [H[0, 0], H[1, 1], H[2, 2], H[0, 1], H[0, 2], H[1, 2]], rtol=1e-13,
+                       atol=1e-14 * np.abs(H).max())
+    x, q = inputs.make("plummer", 400, 31)
+    hh = oracle.direct_hessian(x.astype(np.float64), q.astype(np.float64))
+    scale = np.abs(hh).max(axis=1)
+    assert np.all(np.abs(hh[:, 0] + hh[:, 1] + hh[:, 2]) <= 1e-9 * scale)
+
+
+def test_direct_hessian_is_the_derivative_of_the_gradient():
+    x, q = inputs.make("cube", 300, 32)
+    x = x.astype(np.float64); q = q.astype(np.float64)
+    t = np.array([5, 77, 200])
+    h = oracle.direct_hessian(x, q, t)
+    eps = 1e-5
+    for a, (i, j) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        for r, ti in enumerate(t):                 # one target moved at a time
+            xp = x.copy(); xm = x.copy()
+            xp[ti, j] += eps; xm[ti, j] -= eps
+            gp = oracle.direct(xp, q, [ti])[1]; gm = oracle.direct(xm, q, [ti])[1]
+            fd = (gp[0, i] - gm[0, i]) / (2 * eps)
+            assert abs(h[r, a] - fd) <= 1e-6 * np.abs(h[r]).max()
+
+
+def test_fmm_hessian_converges_to_direct():
+    x, q = inputs.make("cube", 3000, 33)
+    x = x.astype(np.float64); q = q.astype(np.float64)
+    pl = oracle.Plan(x, 16, 0.4)
+    ref = oracle.direct_hessian(x, q)
+    errs = []
+    for p in (4, 8, 12):
+        _, _, _, h = pl.eval(q, p, hessian=True)
+        errs.append(np.linalg.norm(h - ref) / np.linalg.norm(ref))
+    assert errs[2] < 1e-5 and errs[2] < errs[1] < errs[0]
+
+
+def _grad_loss_adjoint_direct(x, q, w, g):
+    """dL/dq and dL/dx of L = sum w phi + sum g . grad phi, from exact direct sums:
+    dL/dq_j = psi_j + chi_j, chi_j = -sum_a d_a phi^(g_a)(x_j);
+    dL/dx_k = w_k E_k + q_k grad psi_k + H_k g_k - q_k sum_a H^(g_a)_k e_a."""
+    idx = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+
+    def full(h):
+        H = np.zeros((h.shape[0], 3, 3))
+        for a, (i, j) in enumerate(idx):
+            H[:, i, j] = H[:, j, i] = h[:, a]
+        return H
+    psi, gpsi = oracle.direct(x, w)
+    _, E = oracle.direct(x, q)
+    H = full(oracle.direct_hessian(x, q))
+    dq = psi.copy()
+    dx = w[:, None] * E + q[:, None] * gpsi + np.einsum("kab,kb->ka", H, g)
+    for a in range(3):
+        _, ga = oracle.direct(x, g[:, a])
+        dq -= ga[:, a]
+        Ha = full(oracle.direct_hessian(x, g[:, a]))
+        dx -= q[:, None] * Ha[:, :, a]
+    return dq, dx
+
+
+def test_adjoint_through_grad_phi_matches_finite_differences():
+    """The adjoint formula for losses through grad phi, checked on the exact loss."""
+    rng = np.random.default_rng(34)
+    n = 60
+    x = rng.random((n, 3)); q = rng.uniform(-1, 1, n); w = rng.standard_normal(n); g = rng.standard_normal((n, 3))
+
+    def loss(xx, qq):
+        phi, E = oracle.direct(xx, qq)
+        return float(np.dot(w, phi) + np.sum(g * E))
+    dq, dx = _grad_loss_adjoint_direct(x, q, w, g)
+    eps = 1e-6
+    for j in (0, 17, 59):
+        qp = q.copy(); qp[j] += eps; qm = q.copy(); qm[j] -= eps
+        assert abs((loss(x, qp) - loss(x, qm)) / (2 * eps) - dq[j]) <= 1e-6 * (1 + abs(dq[j]))
+        for a in range(3):
+            xp = x.copy(); xp[j, a] += eps; xm = x.copy(); xm[j, a] -= eps
+            fd = (loss(xp, q) - loss(xm, q)) / (2 * eps)
+            assert abs(fd - dx[j, a]) <= 1e-5 * (1 + abs(dx[j, a]))
