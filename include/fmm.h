@@ -133,6 +133,30 @@ fmm_status fmm_eval_ex(fmm_plan_t plan, const float *charges, float *potential, 
 fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradient_fwd,
                        const float *dL_dphi, float *dL_dq, float *dL_dx, void *stream);
 
+/*
+ * Potential, gradient and Hessian of the potential at every point (the Hessian is what
+ * the adjoint of a loss through grad phi needs).  hessian: device [n][6], order xx, yy,
+ * zz, xy, xz, yz (symmetric); potential and gradient may be NULL.  The second derivatives
+ * come from the same tree and lists: L2P differentiates the local expansions twice
+ * (degree <= p-2 terms), the near field uses the exact kernel q (3 d d^T/r^5 - I/r^3).
+ * FP32 near field for both precisions.
+ */
+fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potential, float *gradient, float *hessian,
+                            void *stream);
+
+/*
+ * Adjoint of a loss L(phi, grad phi) (the spec adjoint extended to losses through
+ * the gradient output): given w = dL/dphi [n] and g = dL/d(grad phi) [n][3],
+ *   dL/dq_j = psi_j - sum_a d_a phi^(a)(x_j),
+ *   dL/dx_k = w_k grad phi_k + q_k grad psi_k + H_k g_k - q_k sum_a H^(a)_k e_a,
+ * where psi is the FMM of the charges w, grad phi and H the gradient and Hessian of the
+ * FMM of the charges q, and phi^(a) the FMM of the charges g_a (the approximation is
+ * symmetric, so its transpose is itself).  Five evaluations on the plan.  dL_dq [n] and
+ * dL_dx [n][3] may each be NULL.
+ */
+fmm_status fmm_adjoint_ex(fmm_plan_t plan, const float *charges, const float *dL_dphi, const float *dL_dgrad,
+                          float *dL_dq, float *dL_dx, void *stream);
+
 /* Plan statistics (host struct, filled synchronously from host-side copies). */
 #define FMM_MAX_LEVELS 22
 struct fmm_stats {

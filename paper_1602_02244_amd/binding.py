@@ -76,13 +76,16 @@ def load_library():
     lib.fmm_eval.argtypes = [_vp, _vp, _vp, _vp, _vp]
     lib.fmm_eval_ex.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp]
     lib.fmm_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.fmm_eval_hessian.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    lib.fmm_adjoint_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.fmm_plan_stats.argtypes = [_vp, C.POINTER(FmmStats)]
     lib.fmm_plan_export.argtypes = [_vp] + [_vp] * 8
     lib.fmm_plan_set_timing.argtypes = [_vp, C.c_int]
     lib.fmm_plan_phase_times.argtypes = [_vp, C.POINTER(C.c_float)]
     lib.fmm_plan_destroy.argtypes = [_vp]
     lib.fmm_plan_destroy.restype = None
-    for f in ("fmm_set_allocator", "fmm_plan", "fmm_plan_ex", "fmm_eval", "fmm_eval_ex", "fmm_adjoint", "fmm_plan_stats",
+    for f in ("fmm_set_allocator", "fmm_plan", "fmm_plan_ex", "fmm_eval", "fmm_eval_ex", "fmm_adjoint",
+              "fmm_eval_hessian", "fmm_adjoint_ex", "fmm_plan_stats",
               "fmm_plan_export", "fmm_plan_set_timing", "fmm_plan_phase_times"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -189,8 +192,29 @@ class FMM:
                                           _stream_handle()))
         return phi, grad
 
-    def adjoint(self, charges, dL_dphi, gradient_fwd=None, want_dq=True, want_dx=True):
-        """(dL/dq [n], dL/dx [n, 3]) of L = sum_i w_i phi_i, w = dL_dphi, for the frozen plan."""
+    def eval_hessian(self, charges):
+        """(phi [n], grad phi [n, 3], Hessian [n, 6] in the order xx, yy, zz, xy, xz, yz)."""
+        q = _dev_ptr(charges, "charges", (), self.n)
+        phi = torch.empty(self.n, device=self.device, dtype=torch.float32)
+        grad = torch.empty(self.n, 3, device=self.device, dtype=torch.float32)
+        hess = torch.empty(self.n, 6, device=self.device, dtype=torch.float32)
+        _check(load_library().fmm_eval_hessian(self._handle(), q, _vp(phi.data_ptr()), _vp(grad.data_ptr()),
+                                               _vp(hess.data_ptr()), _stream_handle()))
+        return phi, grad, hess
+
+    def adjoint(self, charges, dL_dphi, gradient_fwd=None, want_dq=True, want_dx=True, dL_dgrad=None):
+        """(dL/dq [n], dL/dx [n, 3]) of L(phi, grad phi) with w = dL_dphi and, when given,
+        g = dL_dgrad [n, 3], for the frozen plan."""
+        if dL_dgrad is not None:
+            q = _dev_ptr(charges, "charges", (), self.n)
+            w = _dev_ptr(dL_dphi, "dL_dphi", (), self.n)
+            g = _dev_ptr(dL_dgrad, "dL_dgrad", (3,), self.n)
+            dq = torch.empty(self.n, device=self.device, dtype=torch.float32) if want_dq else None
+            dx = torch.empty(self.n, 3, device=self.device, dtype=torch.float32) if want_dx else None
+            _check(load_library().fmm_adjoint_ex(self._handle(), q, w, g,
+                                                 _vp(dq.data_ptr()) if dq is not None else None,
+                                                 _vp(dx.data_ptr()) if dx is not None else None, _stream_handle()))
+            return dq, dx
         q = _dev_ptr(charges, "charges", (), self.n)
         w = _dev_ptr(dL_dphi, "dL_dphi", (), self.n)
         gf = _dev_ptr(gradient_fwd, "gradient_fwd", (3,), self.n) if gradient_fwd is not None else None
@@ -255,14 +279,20 @@ class FMMFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_phi, g_grad):
         points, charges, grad = ctx.saved_tensors
-        if g_grad is not None and bool(torch.count_nonzero(g_grad)):
-            raise NotImplementedError("gradients through grad(phi) need a Hessian FMM, which this library does not provide")
         need_x, need_q = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        if g_phi is None or not (need_x or need_q):
+        through_grad = g_grad is not None and bool(torch.count_nonzero(g_grad))
+        if (g_phi is None and not through_grad) or not (need_x or need_q):
             return None, None, None, None, None, None
+        if g_phi is None:
+            g_phi = torch.zeros(charges.shape[0], device=charges.device, dtype=torch.float32)
         plan = FMM(points.detach(), *ctx.cfg)
-        dq, dx = plan.adjoint(charges.detach().contiguous(), g_phi.contiguous(), gradient_fwd=grad,
-                              want_dq=need_q, want_dx=need_x)
+        if through_grad:
+            # losses through grad phi: the Hessian FMM (five evaluations on the plan)
+            dq, dx = plan.adjoint(charges.detach().contiguous(), g_phi.contiguous(), want_dq=need_q,
+                                  want_dx=need_x, dL_dgrad=g_grad.contiguous())
+        else:
+            dq, dx = plan.adjoint(charges.detach().contiguous(), g_phi.contiguous(), gradient_fwd=grad,
+                                  want_dq=need_q, want_dx=need_x)
         plan.close()
         return dx, dq, None, None, None, None
 

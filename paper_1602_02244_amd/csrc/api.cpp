@@ -13,7 +13,9 @@
 
 namespace fmm {
 void build_plan(fmm_plan_s *P, const float *points, hipStream_t s);
-void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phases, hipStream_t s);
+void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *hess, int phases, hipStream_t s);
+void run_adjoint_grad(fmm_plan_s *Pl, const float *q, const float *w, const float *g, float *dq, float *dx,
+                      hipStream_t s);
 void run_adjoint_combine(fmm_plan_s *Pl, const float *w, const float *gphi, const float *q, const float *gpsi, float *dx,
                          hipStream_t s);
 }  // namespace fmm
@@ -226,7 +228,7 @@ fmm_status fmm_eval_ex(fmm_plan_t plan, const float *charges, float *potential, 
     hipStream_t s = (hipStream_t)stream;
     return guarded([&] {
         note_stream(plan, s);
-        run_eval(plan, charges, potential, gradient, phases, s);
+        run_eval(plan, charges, potential, gradient, nullptr, phases, s);
     });
 }
 
@@ -253,17 +255,48 @@ fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradi
             P->mem.stream = keep;
         }
         // psi = A w and grad psi: the same FMM with charges w (A is symmetric)
-        run_eval(P, dL_dphi, dL_dq ? dL_dq : P->tmp_phi, dL_dx ? P->tmp_grad : nullptr, FMM_ALL, s);
+        run_eval(P, dL_dphi, dL_dq ? dL_dq : P->tmp_phi, dL_dx ? P->tmp_grad : nullptr, nullptr, FMM_ALL, s);
         if (dL_dx) {
             const float *gphi = gradient_fwd;
             if (!gphi) {
                 float *scratch_phi = dL_dq ? P->tmp_phi : P->tmp_gfwd;   // potential is not needed
                 (void)scratch_phi;
-                run_eval(P, charges, nullptr, P->tmp_gfwd, FMM_ALL, s);
+                run_eval(P, charges, nullptr, P->tmp_gfwd, nullptr, FMM_ALL, s);
                 gphi = P->tmp_gfwd;
             }
             run_adjoint_combine(P, dL_dphi, gphi, charges, P->tmp_grad, dL_dx, s);
         }
+    });
+}
+
+fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potential, float *gradient, float *hessian,
+                            void *stream) {
+    if (!plan || !charges || !hessian) return set_err(FMM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        note_stream(plan, s);
+        run_eval(plan, charges, potential, gradient, hessian, FMM_ALL, s);
+    });
+}
+
+fmm_status fmm_adjoint_ex(fmm_plan_t plan, const float *charges, const float *dL_dphi, const float *dL_dgrad,
+                          float *dL_dq, float *dL_dx, void *stream) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    if (!charges || !dL_dphi || !dL_dgrad) return set_err(FMM_EINVAL, "NULL argument");
+    if (!dL_dq && !dL_dx) return FMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        fmm_plan_s *P = plan;
+        note_stream(P, s);
+        if (!P->tmp_phi) {
+            hipStream_t keep = P->mem.stream;
+            P->mem.stream = s;
+            P->tmp_phi = P->mem.get_n<float>(P->n);
+            P->tmp_grad = P->mem.get_n<float>(3 * P->n);
+            P->tmp_gfwd = P->mem.get_n<float>(3 * P->n);
+            P->mem.stream = keep;
+        }
+        run_adjoint_grad(P, charges, dL_dphi, dL_dgrad, dL_dq, dL_dx, s);
     });
 }
 

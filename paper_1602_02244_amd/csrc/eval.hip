@@ -744,12 +744,21 @@ __global__ void k_root_to32(int64_t nroot, int KP, const double *in, float *out)
 }
 
 // ------------------------------------------------------------------ L2P
-template <int P>
+// One wave per leaf; the local coefficients are broadcast from LDS.  With HESS the second
+// derivatives are also evaluated: the gradient of a local expansion is again a local
+// expansion (coefficients of degree l from those of degree l+1: x: (L_{l+1,m-1} -
+// L_{l+1,m+1})/2, y: i (L_{l+1,m+1} + L_{l+1,m-1})/2, z: L_{l+1,m}), so the six Hessian
+// expansions (degree <= p-2) are built once per leaf in LDS by applying that map twice.
+template <int P, bool HESS>
 __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const float4 *bodies, const float *L,
-                                            float4 *out) {
+                                            float4 *out, float *out_h) {
     using D = Dims<P>;
     constexpr int KP = D::KP;
+    constexpr int NT1 = P >= 1 ? P * (P + 1) / 2 : 1;          // (l, m >= 0) pairs with l <= P-1
+    constexpr int NT2 = P >= 2 ? (P - 1) * P / 2 : 1;          // l <= P-2
     __shared__ float sL[KP];
+    __shared__ float cre[HESS ? 3 : 1][NT1], cim[HESS ? 3 : 1][NT1];
+    __shared__ float hre[HESS ? 6 : 1][NT2], him[HESS ? 6 : 1][NT2];
     const int c = leaves[blockIdx.x];
     const int lane = threadIdx.x;
     for (int d = lane; d < KP; d += 64) sL[d] = L[(int64_t)c * KP + d];
@@ -771,6 +780,50 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
         if (m > 0) return vL[j * j + 2 * m];
         return vL[j * j + 2];
     };
+    if (HESS && P >= 2) {
+        // gradient expansions C^a, degree <= P-1
+        for (int e = lane; e < NT1; e += 64) {
+            int l = 0;
+            while ((l + 1) * (l + 2) / 2 <= e) ++l;
+            const int m = e - l * (l + 1) / 2;
+            const float zr = lre(l + 1, m), zi = lim(l + 1, m);
+            const float pr = lre(l + 1, m + 1), pi = lim(l + 1, m + 1);
+            const float mr = lre(l + 1, m - 1), mi = lim(l + 1, m - 1);
+            cre[0][e] = 0.5f * (mr - pr); cim[0][e] = 0.5f * (mi - pi);
+            cre[1][e] = -0.5f * (pi + mi); cim[1][e] = 0.5f * (pr + mr);
+            cre[2][e] = zr; cim[2][e] = zi;
+        }
+        __syncthreads();
+        // Hessian expansions H^{ab} = d_b C^a, degree <= P-2, order xx yy zz xy xz yz
+        for (int e = lane; e < 6 * NT2; e += 64) {
+            const int comp = e / NT2, t = e % NT2;
+            int l = 0;
+            while ((l + 1) * (l + 2) / 2 <= t) ++l;
+            const int m = t - l * (l + 1) / 2;
+            const int A = comp < 3 ? comp : (comp < 5 ? 0 : 1);
+            const int B = comp < 3 ? comp : (comp == 3 ? 1 : 2);
+            auto cr = [&](int j, int mm) -> float {
+                if (mm > j) return 0.f;
+                if (mm >= 0) return cre[A][j * (j + 1) / 2 + mm];
+                return -cre[A][j * (j + 1) / 2 + 1];           // C_{j,-1} = -conj(C_{j,1})
+            };
+            auto ci = [&](int j, int mm) -> float {
+                if (mm > j) return 0.f;
+                if (mm >= 0) return cim[A][j * (j + 1) / 2 + mm];
+                return cim[A][j * (j + 1) / 2 + 1];
+            };
+            const float zr = cr(l + 1, m), zi = ci(l + 1, m);
+            const float pr = cr(l + 1, m + 1), pi = ci(l + 1, m + 1);
+            const float mr = cr(l + 1, m - 1), mi = ci(l + 1, m - 1);
+            float hr, hi;
+            if (B == 0) { hr = 0.5f * (mr - pr); hi = 0.5f * (mi - pi); }
+            else if (B == 1) { hr = -0.5f * (pi + mi); hi = 0.5f * (pr + mr); }
+            else { hr = zr; hi = zi; }
+            hre[comp][t] = hr;
+            him[comp][t] = hi;
+        }
+        __syncthreads();
+    }
     for (int base = 0; base < n; base += 64) {
         const int j = base + lane;
         if (j >= n) break;
@@ -779,6 +832,7 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
         const float uy = (float)(((double)b.y - cy) * inv);
         const float uz = (float)(((double)b.z - cz) * inv);
         float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        float h[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         stream_regular<P>(ux, uy, uz, [&](int l, int m, float rr, float ri) {
             const float wgt = m == 0 ? 1.f : 2.f;
             f += wgt * (lre(l, m) * rr + lim(l, m) * ri);
@@ -793,9 +847,23 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
                 gy += wgt * (yr * rr + yi * ri);
                 gz += wgt * (zr * rr + zi * ri);
             }
+            if (HESS && l + 2 <= P) {
+                const int t = l * (l + 1) / 2 + m;
+                h[0] += wgt * (hre[0][t] * rr + him[0][t] * ri);
+                h[1] += wgt * (hre[1][t] * rr + him[1][t] * ri);
+                h[2] += wgt * (hre[2][t] * rr + him[2][t] * ri);
+                h[3] += wgt * (hre[3][t] * rr + him[3][t] * ri);
+                h[4] += wgt * (hre[4][t] * rr + him[4][t] * ri);
+                h[5] += wgt * (hre[5][t] * rr + him[5][t] * ri);
+            }
         });
         const float g2 = finv * finv;
         out[s + j] = make_float4(f * finv, gx * g2, gy * g2, gz * g2);   // potential, gradient
+        if (HESS) {
+            const float g3 = g2 * finv;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) out_h[(int64_t)(s + j) * 6 + q] = h[q] * g3;
+        }
     }
 }
 
@@ -944,6 +1012,93 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, cons
     }
 }
 
+// Near field with the Hessian of the potential as well (losses through grad phi):
+// per interaction H += q (3 d d^T / r^5 - I / r^3), d = x_i - x_j.  Same layout and
+// batching as k_p2p; FP32 accumulation.
+template <bool CHECK>
+__device__ __forceinline__ void p2p_batch_h(const float4 *src, int ns, int g, int G, float xi, float yi, float zi,
+                                            float *a) {
+    for (int jj = g; jj < ns; jj += G) {
+        const float4 sj = src[jj];
+        const float dx = xi - sj.x, dy = yi - sj.y, dz = zi - sj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float inv = __builtin_amdgcn_rsqf(r2);
+        if (CHECK) inv = r2 > 0.f ? inv : 0.f;
+        const float inv2 = inv * inv;
+        const float qi = sj.w * inv, qi3 = qi * inv2, qi5 = 3.f * qi3 * inv2;
+        a[0] += qi;
+        a[1] -= dx * qi3; a[2] -= dy * qi3; a[3] -= dz * qi3;
+        a[4] += qi5 * dx * dx - qi3; a[5] += qi5 * dy * dy - qi3; a[6] += qi5 * dz * dz - qi3;
+        a[7] += qi5 * dx * dy; a[8] += qi5 * dx * dz; a[9] += qi5 * dy * dz;
+    }
+}
+
+__global__ void __launch_bounds__(kP2PThreads) k_p2p_hess(const int32_t *leaves, const int32_t *c_start,
+                                                          const int32_t *c_count, const int32_t *seg_off,
+                                                          const int2 *segs, const float4 *bodies, float4 *out,
+                                                          float *out_h) {
+    __shared__ float4 src[kP2PBatch];
+    __shared__ float red[10][kP2PThreads];
+    const int li = blockIdx.x;
+    const int c = leaves[li];
+    const int ts = c_start[c], tn = c_count[c];
+    const int tid = threadIdx.x;
+    const int sg0 = seg_off[li], sg1 = seg_off[li + 1];
+    for (int t0 = 0; t0 < tn; t0 += kP2PThreads) {
+        const int nt = min(kP2PThreads, tn - t0);
+        const int G = kP2PThreads / nt;
+        const bool active = tid < nt * G;
+        const int t = tid % nt, g = tid / nt;
+        float xi = 0.f, yi = 0.f, zi = 0.f;
+        if (active) {
+            float4 b = bodies[ts + t0 + t];
+            xi = b.x; yi = b.y; zi = b.z;
+        }
+        float a[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int s0 = 0; s0 < tn; s0 += kP2PBatch) {     // the target leaf itself
+            const int ns = min(kP2PBatch, tn - s0);
+            __syncthreads();
+            for (int i = tid; i < ns; i += kP2PThreads) src[i] = bodies[ts + s0 + i];
+            __syncthreads();
+            if (active) p2p_batch_h<true>(src, ns, g, G, xi, yi, zi, a);
+        }
+        int pos = 0;
+        for (int sg = sg0; sg < sg1; ++sg) {
+            int2 run = segs[sg];
+            int st = run.x, cnt = run.y;
+            while (cnt > 0) {
+                const int take = min(cnt, kP2PBatch - pos);
+                if (pos == 0) __syncthreads();
+                for (int i = tid; i < take; i += kP2PThreads) src[pos + i] = bodies[st + i];
+                pos += take;
+                st += take;
+                cnt -= take;
+                if (pos == kP2PBatch) {
+                    __syncthreads();
+                    if (active) p2p_batch_h<false>(src, pos, g, G, xi, yi, zi, a);
+                    pos = 0;
+                }
+            }
+        }
+        if (pos > 0) {
+            __syncthreads();
+            if (active) p2p_batch_h<false>(src, pos, g, G, xi, yi, zi, a);
+        }
+        __syncthreads();
+        for (int q = 0; q < 10; ++q) red[q][tid] = a[q];
+        __syncthreads();
+        if (tid < nt) {
+            float acc[10];
+            for (int q = 0; q < 10; ++q) {
+                acc[q] = red[q][tid];
+                for (int gg = 1; gg < G; ++gg) acc[q] += red[q][gg * nt + tid];
+            }
+            out[ts + t0 + tid] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            for (int q = 0; q < 6; ++q) out_h[(int64_t)(ts + t0 + tid) * 6 + q] = acc[4 + q];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ permutes
 __global__ void k_set_charges(const float *q, const int32_t *perm, int64_t n, float4 *bodies) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -966,6 +1121,14 @@ __global__ void k_combine(const int32_t *iperm, int64_t n, const float4 *far, co
     }
 }
 
+__global__ void k_combine_hess(const int32_t *iperm, int64_t n, const float *farh, const float *nearh, float *hess) {
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = iperm[o];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) hess[6 * o + q] = farh[6 * i + q] + nearh[6 * i + q];
+    }
+}
+
 // dL/dx_i = w_i grad phi_i + q_i grad psi_i (input order)
 __global__ void k_adjoint_combine(int64_t n, const float *w, const float *gphi, const float *q, const float *gpsi,
                                   float *dx) {
@@ -974,6 +1137,34 @@ __global__ void k_adjoint_combine(int64_t n, const float *w, const float *gphi, 
         dx[3 * i] = wi * gphi[3 * i] + qi * gpsi[3 * i];
         dx[3 * i + 1] = wi * gphi[3 * i + 1] + qi * gpsi[3 * i + 1];
         dx[3 * i + 2] = wi * gphi[3 * i + 2] + qi * gpsi[3 * i + 2];
+    }
+}
+
+// Adjoint through grad phi (see run_adjoint_grad): component a of a [n][3] array.
+__global__ void k_column(const float *v3, int a, int64_t n, float *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = v3[3 * i + a];
+}
+// dq -= d_a phi^(a);  col += column a of the Hessian of phi^(a)
+__global__ void k_adjoint_grad_acc(int64_t n, int a, const float *grad_a, const float *hess_a, float *dq, float *col) {
+    // symmetric 3x3 from (xx, yy, zz, xy, xz, yz): entry (r, a)
+    const int idx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (dq) dq[i] -= grad_a[3 * i + a];
+        if (col)
+            for (int r = 0; r < 3; ++r) col[3 * i + r] += hess_a[6 * i + idx[r][a]];
+    }
+}
+// dL/dx = w E + q grad psi + H g - q col
+__global__ void k_adjoint_grad_final(int64_t n, const float *w, const float *E, const float *q, const float *gpsi,
+                                     const float *H, const float *g, const float *col, float *dx) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float *h = H + 6 * i;
+        const float gx = g[3 * i], gy = g[3 * i + 1], gz = g[3 * i + 2];
+        const float hg[3] = {h[0] * gx + h[3] * gy + h[4] * gz, h[3] * gx + h[1] * gy + h[5] * gz,
+                             h[4] * gx + h[5] * gy + h[2] * gz};
+        for (int r = 0; r < 3; ++r)
+            dx[3 * i + r] = w[i] * E[3 * i + r] + q[i] * gpsi[3 * i + r] + hg[r] - q[i] * col[3 * i + r];
     }
 }
 
@@ -1085,15 +1276,27 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     }
     ev_rec(Pl, 2 * PH_L2L + 1, s);
     ev_rec(Pl, 2 * PH_L2P, s);
-    hipLaunchKernelGGL(k_l2p<P>, (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g, (const float4 *)Pl->bodies,
-                       (const float *)Pl->L, Pl->far4);
+    if (Pl->hess_on)
+        hipLaunchKernelGGL((k_l2p<P, true>), (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g,
+                           (const float4 *)Pl->bodies, (const float *)Pl->L, Pl->far4, Pl->farh);
+    else
+        hipLaunchKernelGGL((k_l2p<P, false>), (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g,
+                           (const float4 *)Pl->bodies, (const float *)Pl->L, Pl->far4, (float *)nullptr);
     ev_rec(Pl, 2 * PH_L2P + 1, s);
 }
 
 #define FMM_CASE(PP) case PP: far_field<PP>(Pl, g, s); break;
 
-void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phases, hipStream_t s) {
+void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *hess, int phases, hipStream_t s) {
     const int64_t n = Pl->n;
+    Pl->hess_on = hess != nullptr;
+    if (hess && !Pl->farh) {
+        hipStream_t keep = Pl->mem.stream;
+        Pl->mem.stream = s;
+        Pl->farh = Pl->mem.get_n<float>(6 * n);
+        Pl->nearh = Pl->mem.get_n<float>(6 * n);
+        Pl->mem.stream = keep;
+    }
     Geo g{Pl->c_start, Pl->c_count, Pl->c_level, Pl->c_ix, Pl->c_iy, Pl->c_iz, Pl->c_parent, Pl->c_child0, Pl->c_nchild,
           Pl->x0[0], Pl->x0[1], Pl->x0[2], Pl->k};
     ev_rec(Pl, 2 * PH_TOTAL, s);
@@ -1104,7 +1307,11 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phase
     HIP_CHECK(hipEventRecord(Pl->ev_fork, s));
     HIP_CHECK(hipStreamWaitEvent(Pl->side, Pl->ev_fork, 0));
     ev_rec(Pl, 2 * PH_P2P, Pl->side);
-    if (phases & FMM_NEAR) {
+    if ((phases & FMM_NEAR) && hess) {
+        hipLaunchKernelGGL(k_p2p_hess, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
+                           (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
+                           (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4, Pl->nearh);
+    } else if (phases & FMM_NEAR) {
         if (Pl->prec == FMM_PREC_MIXED)
             hipLaunchKernelGGL(k_p2p<true>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
                                (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
@@ -1115,6 +1322,7 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phase
                                (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
     } else {
         fill_f32(reinterpret_cast<float *>(Pl->near4), 0.f, 4 * n, Pl->side);
+        if (hess) fill_f32(Pl->nearh, 0.f, 6 * n, Pl->side);
     }
     ev_rec(Pl, 2 * PH_P2P + 1, Pl->side);
     HIP_CHECK(hipEventRecord(Pl->ev_join, Pl->side));
@@ -1128,15 +1336,55 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, int phase
     } else {
         for (int ph = PH_P2M; ph <= PH_L2P; ++ph) { ev_rec(Pl, 2 * ph, s); ev_rec(Pl, 2 * ph + 1, s); }
         fill_f32(reinterpret_cast<float *>(Pl->far4), 0.f, 4 * n, s);
+        if (hess) fill_f32(Pl->farh, 0.f, 6 * n, s);
     }
     HIP_CHECK(hipStreamWaitEvent(s, Pl->ev_join, 0));
     ev_rec(Pl, 2 * PH_COMB, s);
     hipLaunchKernelGGL(k_combine, grid1(n), 256, 0, s, (const int32_t *)Pl->iperm, n, (const float4 *)Pl->far4,
                        (const float4 *)Pl->near4, phi, grad);
+    if (hess)
+        hipLaunchKernelGGL(k_combine_hess, grid1(n), 256, 0, s, (const int32_t *)Pl->iperm, n, (const float *)Pl->farh,
+                           (const float *)Pl->nearh, hess);
     ev_rec(Pl, 2 * PH_COMB + 1, s);
     ev_rec(Pl, 2 * PH_TOTAL + 1, s);
     HIP_CHECK(hipGetLastError());
     Pl->ev_valid = Pl->timing;
+}
+
+// Adjoint of L(phi, grad phi) with w = dL/dphi and g = dL/d(grad phi) ([n][3]):
+//   dL/dq_j = psi_j - sum_a d_a phi^(a)(x_j)
+//   dL/dx_k = w_k E_k + q_k grad psi_k + H_k g_k - q_k sum_a H^(a)_k e_a
+// with psi the FMM of charges w, E and H the gradient and Hessian of the FMM of the charges
+// q, and phi^(a) the FMM of the charges g_a (grad phi is the transpose of that map; the
+// operator's symmetry turns it into these three evaluations).
+void run_adjoint_grad(fmm_plan_s *Pl, const float *q, const float *w, const float *g, float *dq, float *dx,
+                      hipStream_t s) {
+    const int64_t n = Pl->n;
+    if (!Pl->tmp_h) {
+        hipStream_t keep = Pl->mem.stream;
+        Pl->mem.stream = s;
+        Pl->tmp_h = Pl->mem.get_n<float>(6 * n);
+        Pl->tmp_h2 = Pl->mem.get_n<float>(6 * n);
+        Pl->tmp_col = Pl->mem.get_n<float>(3 * n);
+        Pl->tmp_ga = Pl->mem.get_n<float>(n);
+        Pl->tmp_gg = Pl->mem.get_n<float>(3 * n);
+        Pl->mem.stream = keep;
+    }
+    run_eval(Pl, w, dq ? dq : Pl->tmp_phi, dx ? Pl->tmp_grad : nullptr, nullptr, FMM_ALL, s);
+    if (dx) {
+        run_eval(Pl, q, nullptr, Pl->tmp_gfwd, Pl->tmp_h, FMM_ALL, s);
+        fill_f32(Pl->tmp_col, 0.f, 3 * n, s);
+    }
+    for (int a = 0; a < 3; ++a) {
+        hipLaunchKernelGGL(k_column, grid1(n), 256, 0, s, g, a, n, Pl->tmp_ga);
+        run_eval(Pl, Pl->tmp_ga, nullptr, Pl->tmp_gg, dx ? Pl->tmp_h2 : nullptr, FMM_ALL, s);
+        hipLaunchKernelGGL(k_adjoint_grad_acc, grid1(n), 256, 0, s, n, a, (const float *)Pl->tmp_gg,
+                           (const float *)Pl->tmp_h2, dq, dx ? Pl->tmp_col : nullptr);
+    }
+    if (dx)
+        hipLaunchKernelGGL(k_adjoint_grad_final, grid1(n), 256, 0, s, n, w, (const float *)Pl->tmp_gfwd, q,
+                           (const float *)Pl->tmp_grad, (const float *)Pl->tmp_h, g, (const float *)Pl->tmp_col, dx);
+    HIP_CHECK(hipGetLastError());
 }
 
 void run_adjoint_combine(fmm_plan_s *Pl, const float *w, const float *gphi, const float *q, const float *gpsi, float *dx,

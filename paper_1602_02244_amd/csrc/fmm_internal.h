@@ -189,7 +189,10 @@ struct fmm_plan_s {
     float *Msinv = nullptr;                     // [ncells] inverse power-of-two scale of each cell
     float *partial = nullptr;                   // [nwork][kTileN][KP]
     float4 *far4 = nullptr, *near4 = nullptr;   // sorted order: (potential, gradient) of far and near field
+    float *farh = nullptr, *nearh = nullptr;    // sorted order: Hessian (xx yy zz xy xz yz), allocated on first use
+    bool hess_on = false;                       // the running evaluation also produces the Hessian
     float *tmp_phi = nullptr, *tmp_grad = nullptr, *tmp_gfwd = nullptr;   // adjoint scratch (input order)
+    float *tmp_h = nullptr, *tmp_h2 = nullptr, *tmp_col = nullptr, *tmp_ga = nullptr, *tmp_gg = nullptr;   // adjoint through grad phi
     std::vector<hipStream_t> streams_used;       // every stream the plan's memory was used on
     int fp64_levels = 0;                        // levels 0..fp64_levels-1 kept in FP64 (mixed)
 
