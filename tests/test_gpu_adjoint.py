@@ -65,11 +65,14 @@ def test_autograd_function_matches_adjoint():
     plan = FMM(_dev(x), 48, 7, 0.4)
     dq, dx = plan.adjoint(_dev(q), w)
     assert torch.equal(qt.grad, dq) and torch.equal(xt.grad, dx)
-    # a loss through grad phi needs a Hessian FMM, which is not provided
+    # a loss through grad phi goes through the Hessian FMM (fmm_adjoint_ex)
     xt.grad = None
+    qt.grad = None
     phi, grad = fmm_apply(xt, qt, ncrit=48, p=7, theta=0.4)
-    with pytest.raises(NotImplementedError):
-        grad.sum().backward()
+    gw = _dev(np.random.default_rng(45).standard_normal((20000, 3)))
+    ((w * phi).sum() + (gw * grad).sum()).backward()
+    dq2, dx2 = plan.adjoint(_dev(q), w, dL_dgrad=gw)
+    assert torch.equal(qt.grad, dq2) and torch.equal(xt.grad, dx2)
 
 
 def _exact_loss_delta_fd(x, q, w, k, axis, h):
