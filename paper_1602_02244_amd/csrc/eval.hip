@@ -1180,12 +1180,43 @@ static inline void ev_rec(fmm_plan_s *Pl, int slot, hipStream_t s) {
     if (Pl->timing) HIP_CHECK(hipEventRecord(Pl->ev[slot], s));
 }
 
-template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t s) {
+// Near field on the side stream, forked from the main stream at the point where this is
+// called; the main stream joins it (ev_join) before the outputs are combined.
+static void launch_near(fmm_plan_s *Pl, int phases, bool hess, hipStream_t s) {
+    HIP_CHECK(hipEventRecord(Pl->ev_fork, s));
+    HIP_CHECK(hipStreamWaitEvent(Pl->side, Pl->ev_fork, 0));
+    ev_rec(Pl, 2 * PH_P2P, Pl->side);
+    if ((phases & FMM_NEAR) && hess) {
+        hipLaunchKernelGGL(k_p2p_hess, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
+                           (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
+                           (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4, Pl->nearh);
+    } else if (phases & FMM_NEAR) {
+        if (Pl->prec == FMM_PREC_MIXED)
+            hipLaunchKernelGGL(k_p2p<true>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
+                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
+                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
+        else
+            hipLaunchKernelGGL(k_p2p<false>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
+                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
+                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
+    } else {
+        fill_f32(reinterpret_cast<float *>(Pl->near4), 0.f, 4 * Pl->n, Pl->side);
+        if (hess) fill_f32(Pl->nearh, 0.f, 6 * Pl->n, Pl->side);
+    }
+    ev_rec(Pl, 2 * PH_P2P + 1, Pl->side);
+    HIP_CHECK(hipEventRecord(Pl->ev_join, Pl->side));
+}
+
+// The near field (near(), on the side stream) is forked before P2M and runs beside P2M and
+// the M2M levels.  Forking it right before M2L instead frees those small launches but
+// slows M2L by about the P2P time: the two kernels do not overlap on a compute unit.
+template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t s, const Near &near) {
     using D = Dims<P>;
     const OpTables &T = op_tables(P);
     const bool mixed = Pl->prec == FMM_PREC_MIXED;
     const int RL = mixed ? kRootLevels : 0;       // levels below RL accumulate in FP64
     constexpr unsigned kSlabs = (D::KP + kSlab64 - 1) / kSlab64;
+    near();
     ev_rec(Pl, 2 * PH_P2M, s);
     hipLaunchKernelGGL(k_p2m<P>, (int)((Pl->nleaves + 1) / 2), 64, 0, s, (const int32_t *)Pl->leaves, Pl->nleaves,
                        g, (const float4 *)Pl->bodies, Pl->M);
@@ -1285,7 +1316,7 @@ template <int P> static void far_field(fmm_plan_s *Pl, const Geo &g, hipStream_t
     ev_rec(Pl, 2 * PH_L2P + 1, s);
 }
 
-#define FMM_CASE(PP) case PP: far_field<PP>(Pl, g, s); break;
+#define FMM_CASE(PP) case PP: far_field<PP>(Pl, g, s, near); break;
 
 void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *hess, int phases, hipStream_t s) {
     const int64_t n = Pl->n;
@@ -1303,29 +1334,7 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *he
     ev_rec(Pl, 2 * PH_PERM, s);
     hipLaunchKernelGGL(k_set_charges, grid1(n), 256, 0, s, q, (const int32_t *)Pl->perm, n, Pl->bodies);
     ev_rec(Pl, 2 * PH_PERM + 1, s);
-    // near field on the side stream, concurrent with the far-field chain
-    HIP_CHECK(hipEventRecord(Pl->ev_fork, s));
-    HIP_CHECK(hipStreamWaitEvent(Pl->side, Pl->ev_fork, 0));
-    ev_rec(Pl, 2 * PH_P2P, Pl->side);
-    if ((phases & FMM_NEAR) && hess) {
-        hipLaunchKernelGGL(k_p2p_hess, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
-                           (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                           (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4, Pl->nearh);
-    } else if (phases & FMM_NEAR) {
-        if (Pl->prec == FMM_PREC_MIXED)
-            hipLaunchKernelGGL(k_p2p<true>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
-                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
-        else
-            hipLaunchKernelGGL(k_p2p<false>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
-                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
-    } else {
-        fill_f32(reinterpret_cast<float *>(Pl->near4), 0.f, 4 * n, Pl->side);
-        if (hess) fill_f32(Pl->nearh, 0.f, 6 * n, Pl->side);
-    }
-    ev_rec(Pl, 2 * PH_P2P + 1, Pl->side);
-    HIP_CHECK(hipEventRecord(Pl->ev_join, Pl->side));
+    auto near = [&]() { launch_near(Pl, phases, hess != nullptr, s); };
     if ((phases & FMM_FAR) && Pl->nm2l > 0) {
         switch (Pl->p) {
             FMM_CASE(0) FMM_CASE(1) FMM_CASE(2) FMM_CASE(3) FMM_CASE(4) FMM_CASE(5) FMM_CASE(6) FMM_CASE(7)
@@ -1334,6 +1343,7 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *he
             default: fail(FMM_EINVAL, "unsupported order");
         }
     } else {
+        near();
         for (int ph = PH_P2M; ph <= PH_L2P; ++ph) { ev_rec(Pl, 2 * ph, s); ev_rec(Pl, 2 * ph + 1, s); }
         fill_f32(reinterpret_cast<float *>(Pl->far4), 0.f, 4 * n, s);
         if (hess) fill_f32(Pl->farh, 0.f, 6 * n, s);

@@ -29,6 +29,51 @@ struct Error {
 void check_hip(hipError_t e, const char *what);
 #define HIP_CHECK(x) ::fmm::check_hip((x), #x)
 
+// Host-visible results without a staging copy.  A mailbox is pinned, coherent host
+// memory mapped into the device address space: a kernel writes its small result there
+// and then, after a system-scope fence, a ticket; the host spins on the ticket.  Uploads
+// go through the same pinned memory (an arena reset at the start of each plan build).
+struct Mailbox {
+    static constexpr int64_t kPostBytes = int64_t(64) << 10;   // area kernels post to
+    static constexpr int64_t kDataBytes = int64_t(2) << 20;    // post area, then the fetch area
+    static constexpr int64_t kUploadBytes = int64_t(4) << 20;  // upload arena
+    volatile uint64_t *host = nullptr;   // word 0: ticket; data from byte 64
+    uint64_t *dev = nullptr;             // the same memory as seen by the device
+    char *upload_host = nullptr;         // pinned upload arena
+    int64_t upload_used = 0;
+    uint64_t ticket = 0;
+    uint64_t *flag_dev() const { return dev; }
+    template <class T> T *data_dev() const { return reinterpret_cast<T *>(reinterpret_cast<char *>(dev) + 64); }
+    template <class T> const T *data_host() const {   // read only after wait() returned
+        return reinterpret_cast<const T *>(const_cast<const char *>(reinterpret_cast<const volatile char *>(host)) + 64);
+    }
+    uint64_t next_ticket() { return ++ticket; }
+    // Spin until the ticket arrives; fails if the stream reports an error or completes
+    // without delivering it.
+    void wait(uint64_t t, hipStream_t s);
+    // Copy n bytes of host data into the upload arena and queue their transfer to dst.
+    void upload(void *dst, const void *src, size_t n, hipStream_t s);
+    // Device-to-host copy of n bytes (at most kDataBytes - kPostBytes) into the fetch area
+    // (pinned: no staging), then a stream synchronisation; returns the host copy, valid
+    // until the next fetch.
+    const void *fetch(const void *src, size_t n, hipStream_t s);
+};
+Mailbox *mailbox_acquire();        // from a process-wide pool
+void mailbox_release(Mailbox *m);
+struct MailboxLease {               // scope guard
+    Mailbox *m = mailbox_acquire();
+    ~MailboxLease() { mailbox_release(m); }
+};
+
+// Device side of a mailbox post: the data stores of this thread are made visible at
+// system scope, then the ticket is written.  Every thread that wrote data must call
+// mailbox_fence() before a barrier that precedes the post.
+__device__ inline void mailbox_fence() { __threadfence_system(); }
+__device__ inline void mailbox_post(uint64_t *flag, uint64_t ticket) {
+    __threadfence_system();
+    __hip_atomic_store(flag, ticket, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Workspace allocation through the plan's allocator; everything is released at destroy.
 struct Alloc {
     fmm_alloc_fn alloc = nullptr;
@@ -37,6 +82,7 @@ struct Alloc {
     hipStream_t stream = nullptr;
     std::vector<void *> live;
     int64_t bytes = 0;
+    Mailbox *mb = nullptr;   // set while a plan is built: scan totals come back through it
     void *get(size_t bytes);
     template <class T> T *get_n(int64_t n) { return static_cast<T *>(get(sizeof(T) * (size_t)(n > 0 ? n : 1))); }
     void put(void *p);       // release one allocation early
@@ -44,11 +90,19 @@ struct Alloc {
 };
 
 // ---------------------------------------------------------------- primitives
-// Exclusive scan of n values; returns the total (reads it back, synchronising the stream).
+// Exclusive scan of n values; returns the total (waits for it: through the allocator's
+// mailbox when it has one, else by a read-back).
 int64_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, Alloc &a, hipStream_t s);
 int64_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Alloc &a, hipStream_t s);
-// Stable LSD radix sort of (key, value) on the low `bits` key bits; results in keys/vals.
-void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Alloc &a, hipStream_t s);
+// The same without waiting: the total is written to device memory.
+void exclusive_scan_i32_to(const int32_t *in, int32_t *out, int64_t n, int64_t *tot_dev, Alloc &a, hipStream_t s);
+// Stable LSD radix sort of (key, value) on the low `bits` key bits.  The sorted data end
+// in one of two buffer pairs; keys/vals are updated to point at it and the other pair
+// goes back to the allocator (no copy).
+void radix_sort_u64(uint64_t *&keys, int32_t *&vals, int64_t n, int bits, Alloc &a, hipStream_t s);
+// Copy `bytes` (a multiple of 4, at most kPostBytes) of device memory into the mailbox's
+// post area and post the ticket.
+void publish(const void *src, int64_t bytes, Mailbox &m, uint64_t ticket, hipStream_t s);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);

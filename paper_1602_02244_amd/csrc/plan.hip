@@ -47,7 +47,8 @@ __global__ void __launch_bounds__(256) k_bbox_partial(const float *pts, int64_t 
     if (threadIdx.x < 7) part[blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void __launch_bounds__(256) k_bbox_final(const float *part, int nb, float *out) {
+__global__ void __launch_bounds__(256) k_bbox_final(const float *part, int nb, float *out, uint64_t *flag,
+                                                    uint64_t ticket) {
     __shared__ float sh[7][256];
     float r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.f};
     for (int b = threadIdx.x; b < nb; b += 256) {
@@ -69,7 +70,12 @@ __global__ void __launch_bounds__(256) k_bbox_final(const float *part, int nb, f
         }
         __syncthreads();
     }
-    if (threadIdx.x < 7) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 7) {
+        out[threadIdx.x] = sh[threadIdx.x][0];
+        mailbox_fence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) mailbox_post(flag, ticket);
 }
 
 // Root cube: side 2^k, the smallest power of two with hi_a - x0_a <= 2^k on every axis
@@ -263,7 +269,8 @@ __device__ inline void block_scan3(int v0, int v1, int v2, int &e0, int &e1, int
 // split to `next`.  Each lane classifies one child pair, one block scan and one atomic
 // per list reserve the ranges, then the lane writes.  Writes past a list's capacity are
 // dropped; the counters still advance, so the host sees the exact sizes and repeats
-// the step with larger lists.
+// the step with larger lists.  cnt = (M2L pairs, P2P pairs, next frontier); k_trav_post
+// hands them to the host after the step and clears the frontier count.
 //
 // Traversal rules for the pair (A, B):
 //   1. MAC accepted                    -> M2L        (action 0)
@@ -291,6 +298,23 @@ __device__ inline void split_ranges(const CellView &C, int a, int b, int &a0, in
     }
     if (splitA) { a0 = C.child0[a]; na = nca; } else { a0 = a; na = 1; }
     if (splitB) { b0 = C.child0[b]; nb = ncb; } else { b0 = b; nb = 1; }
+}
+
+__global__ void k_trav_post(unsigned long long *cnt, unsigned long long *post, uint64_t *flag, uint64_t ticket) {
+    if (threadIdx.x == 0) {
+        post[0] = cnt[0];
+        post[1] = cnt[1];
+        post[2] = cnt[2];
+        cnt[2] = 0;
+        mailbox_post(flag, ticket);
+    }
+}
+__global__ void k_set_counters(unsigned long long *cnt, int64_t nm, int64_t np) {
+    if (threadIdx.x == 0) {
+        cnt[0] = (unsigned long long)nm;
+        cnt[1] = (unsigned long long)np;
+        cnt[2] = 0;
+    }
 }
 
 __device__ inline int action(const CellView &C, int a, int b, double theta2) {
@@ -474,29 +498,54 @@ __global__ void k_mark_targets(const int2 *pairs, int64_t np, int32_t *is_target
         is_target[pairs[i].x] = 1;
 }
 
+// Boundary class of a cell: per axis, its distance (in cells of its octant, capped at 2)
+// to the low and to the high face of the root cube, 9 values per axis.  Cells of one
+// class and octant have the same interaction offsets in a uniform region, so ordering a
+// tile's targets by class first fills the MFMA column blocks of an M2L entry better.
+constexpr int kClassBits = 10;   // 9^3 = 729 classes
+__device__ inline int boundary_class(const CellView &C, int c) {
+    const int l = C.level[c];
+    if (l == 0) return 0;
+    const int nl = 1 << (l - 1);   // cells of one octant per axis
+    auto axis = [&](int v) {
+        v >>= 1;
+        return min(v, 2) * 3 + min(nl - 1 - v, 2);
+    };
+    return (axis(C.ix[c]) * 9 + axis(C.iy[c])) * 9 + axis(C.iz[c]);
+}
+
+// Sort key of a tile target: (level, octant) bucket above `cls_bits` bits of boundary
+// class (0 or kClassBits); equal keys keep the cell (Morton) order.
 __global__ void k_target_keys(const int32_t *is_target, const int32_t *ex, int64_t nc, CellView C, int by_octant,
-                              uint64_t *tkeys, int32_t *tvals) {
+                              int cls_bits, uint64_t *tkeys, int32_t *tvals) {
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
         if (!is_target[c]) continue;
         int oct = by_octant ? ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1) : 0;
-        tkeys[ex[c]] = (uint64_t)(C.level[c] * 8 + oct);   // bucket; cells enter in index order
+        uint64_t k = (uint64_t)(C.level[c] * 8 + oct) << cls_bits;
+        if (cls_bits) k |= (uint64_t)boundary_class(C, (int)c);
+        tkeys[ex[c]] = k;
         tvals[ex[c]] = (int32_t)c;
     }
 }
 
-__global__ void k_bucket_starts(const uint64_t *tkeys, int64_t nt, int32_t *bstart) {
+__global__ void k_bucket_starts(const uint64_t *tkeys, int64_t nt, int cls_bits, int32_t *bstart) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x) {
-        int b = (int)tkeys[i];
-        if (i == 0 || (int)tkeys[i - 1] != b) bstart[b] = (int32_t)i;
+        int b = (int)(tkeys[i] >> cls_bits);
+        if (i == 0 || (int)(tkeys[i - 1] >> cls_bits) != b) bstart[b] = (int32_t)i;
     }
 }
 
-__global__ void k_assign_tiles(const uint64_t *tkeys, const int32_t *tvals, int64_t nt, const int32_t *bstart,
-                               const int32_t *tbase, int32_t *cell_tile, int32_t *cell_lane, int32_t *tile_targets) {
+constexpr int kBuckets = (kMaxLevel + 1) * 8;
+struct BucketBase {   // first tile of every (level, octant) bucket, passed by value
+    int32_t v[kBuckets];
+};
+__global__ void k_assign_tiles(const uint64_t *tkeys, const int32_t *tvals, int64_t nt, int cls_bits,
+                               const int32_t *bstart, BucketBase tbase, int32_t *cell_tile, int32_t *cell_lane,
+                               int32_t *tile_targets) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x) {
-        int b = (int)tkeys[i];
+        int b = (int)(tkeys[i] >> cls_bits);
         int r = (int)(i - bstart[b]);
-        int tile = tbase[b] + r / kTileN, lane = r % kTileN;
+        int tile = tbase.v[b] + r / kTileN, lane = r % kTileN;
         int c = tvals[i];
         cell_tile[c] = tile;
         cell_lane[c] = lane;
@@ -625,17 +674,18 @@ __global__ void k_p2p_run_write(const int2 *pairs, int64_t np, const int32_t *c_
     }
 }
 
-__global__ void k_p2p_run_len(int2 *segs, int64_t nseg) {
+__global__ void k_p2p_run_len(int2 *segs, const int64_t *nseg_dev) {
+    const int64_t nseg = *nseg_dev;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nseg; i += (int64_t)gridDim.x * blockDim.x) {
         int2 r = segs[i];
         segs[i] = make_int2(r.x, r.y - r.x);
     }
 }
 
-__global__ void k_p2p_seg_off(int64_t nl, const int32_t *pair_off, const int32_t *run_id, int32_t nseg,
+__global__ void k_p2p_seg_off(int64_t nl, const int32_t *pair_off, const int32_t *run_id, const int64_t *nseg,
                               int32_t *seg_off) {
     for (int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; li <= nl; li += (int64_t)gridDim.x * blockDim.x)
-        seg_off[li] = li < nl ? run_id[pair_off[li]] : nseg;
+        seg_off[li] = li < nl ? run_id[pair_off[li]] : (int32_t)*nseg;
 }
 
 // ----------------------------------------------------------------- host side
@@ -661,13 +711,14 @@ static void grow(Alloc &a, T *&buf, int64_t &cap, int64_t used, int64_t need, hi
 }
 
 // Tiles of kTileN cells: the flagged cells grouped by level (and octant when
-// by_octant), Morton order inside a group.  Returns the number of tiles; fills
-// tile_targets ([ntiles][kTileN], -1 = empty lane), cell -> (tile, lane) maps and the
-// first tile of every (level, octant) bucket (host, size kBuckets + 1).
-constexpr int kBuckets = (kMaxLevel + 1) * 8;
-static int64_t tile_cells(const CellView &C, int64_t nc, int32_t *flag, bool by_octant, Alloc &a, hipStream_t s,
-                          int32_t *&tile_targets, int32_t *cell_tile, int32_t *cell_lane, std::vector<int32_t> &bucket_tile,
-                          int64_t &ntargets) {
+// by_octant), inside a group by boundary class (when by_class) and then in Morton order.
+// Returns the number of tiles; fills tile_targets ([ntiles][kTileN], -1 = empty lane),
+// cell -> (tile, lane) maps and the first tile of every (level, octant) bucket (host,
+// size kBuckets + 1).
+static int64_t tile_cells(const CellView &C, int64_t nc, int32_t *flag, bool by_octant, bool by_class, Alloc &a,
+                          hipStream_t s, int32_t *&tile_targets, int32_t *cell_tile, int32_t *cell_lane,
+                          std::vector<int32_t> &bucket_tile, int64_t &ntargets) {
+    const int cls_bits = by_class ? kClassBits : 0;
     int32_t *tex = a.get_n<int32_t>(nc);
     int64_t nt = exclusive_scan_i32(flag, tex, nc, a, s);
     ntargets = nt;
@@ -680,18 +731,24 @@ static int64_t tile_cells(const CellView &C, int64_t nc, int32_t *flag, bool by_
     uint64_t *tk = a.get_n<uint64_t>(nt);
     int32_t *tv = a.get_n<int32_t>(nt);
     hipLaunchKernelGGL(k_target_keys, grid1(nc), 256, 0, s, (const int32_t *)flag, (const int32_t *)tex, nc, C,
-                       by_octant ? 1 : 0, tk, tv);
-    static_assert(kBuckets <= 256, "one 8-bit pass");
-    radix_sort_u64(tk, tv, nt, 8, a, s);          // stable: Morton (= index) order inside a bucket
+                       by_octant ? 1 : 0, cls_bits, tk, tv);
+    static_assert(kBuckets <= 256, "buckets fit 8 bits");
+    radix_sort_u64(tk, tv, nt, 8 + cls_bits, a, s);   // stable: Morton (= index) order among equal keys
     int32_t *bst = a.get_n<int32_t>(kBuckets);
     fill_i32(bst, -1, kBuckets, s);
-    hipLaunchKernelGGL(k_bucket_starts, grid1(nt), 256, 0, s, (const uint64_t *)tk, nt, bst);
-    std::vector<int32_t> hb_start(kBuckets), hb_base(kBuckets, 0);
-    HIP_CHECK(hipMemcpyAsync(hb_start.data(), bst, 4 * kBuckets, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(k_bucket_starts, grid1(nt), 256, 0, s, (const uint64_t *)tk, nt, cls_bits, bst);
+    std::vector<int32_t> hb_start(kBuckets);
+    BucketBase hb_base{};
+    {
+        Mailbox &mb = *a.mb;
+        const uint64_t t = mb.next_ticket();
+        publish(bst, 4 * kBuckets, mb, t, s);
+        mb.wait(t, s);
+        std::memcpy(hb_start.data(), mb.data_host<int32_t>(), 4 * kBuckets);
+    }
     int64_t ntiles = 0;
     for (int b = 0; b < kBuckets; ++b) {
-        hb_base[b] = (int32_t)ntiles;
+        hb_base.v[b] = (int32_t)ntiles;
         bucket_tile[b] = (int32_t)ntiles;
         if (hb_start[b] < 0) continue;
         int64_t end = nt;
@@ -700,14 +757,11 @@ static int64_t tile_cells(const CellView &C, int64_t nc, int32_t *flag, bool by_
         ntiles += (end - hb_start[b] + kTileN - 1) / kTileN;
     }
     bucket_tile[kBuckets] = (int32_t)ntiles;
-    int32_t *tbase = a.get_n<int32_t>(kBuckets);
-    HIP_CHECK(hipMemcpyAsync(tbase, hb_base.data(), 4 * kBuckets, hipMemcpyHostToDevice, s));
     tile_targets = a.get_n<int32_t>(ntiles * kTileN);
     fill_i32(tile_targets, -1, ntiles * kTileN, s);
-    hipLaunchKernelGGL(k_assign_tiles, grid1(nt), 256, 0, s, (const uint64_t *)tk, (const int32_t *)tv, nt,
-                       (const int32_t *)bst, (const int32_t *)tbase, cell_tile, cell_lane, tile_targets);
-    HIP_CHECK(hipStreamSynchronize(s));   // hb_base is read by the copy above
-    a.put(tex); a.put(tk); a.put(tv); a.put(bst); a.put(tbase);
+    hipLaunchKernelGGL(k_assign_tiles, grid1(nt), 256, 0, s, (const uint64_t *)tk, (const int32_t *)tv, nt, cls_bits,
+                       (const int32_t *)bst, hb_base, cell_tile, cell_lane, tile_targets);
+    a.put(tex); a.put(tk); a.put(tv); a.put(bst);
     return ntiles;
 }
 
@@ -732,18 +786,36 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     lg.s = s;
     Alloc &a = P->mem;
     const int64_t n = P->n;
+    // small results come back through a mailbox; the stream is drained before it is
+    // handed back (its upload arena may still be read by queued copies after a failure)
+    MailboxLease lease;
+    Mailbox &mb = *lease.m;
+    struct Drain {
+        Alloc &a;
+        hipStream_t s;
+        ~Drain() {
+            (void)hipStreamSynchronize(s);
+            a.mb = nullptr;
+        }
+    } drain{a, s};
+    a.mb = &mb;
+    // counted on the device, read once at the end: same-level M2L pairs, P2P interactions,
+    // near-field runs
+    unsigned long long *counts = a.get_n<unsigned long long>(3);
+    fill_i32(reinterpret_cast<int32_t *>(counts), 0, 6, s);
 
     // ---- a1: root cube and keys
     int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
     float *bpart = a.get_n<float>(8 * nb);
-    float *bbox = a.get_n<float>(8);
     hipLaunchKernelGGL(k_bbox_partial, nb, 256, 0, s, points, n, bpart);
-    hipLaunchKernelGGL(k_bbox_final, 1, 256, 0, s, (const float *)bpart, nb, bbox);
     float hb[8];
-    HIP_CHECK(hipMemcpyAsync(hb, bbox, sizeof(float) * 7, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    {
+        const uint64_t t = mb.next_ticket();
+        hipLaunchKernelGGL(k_bbox_final, 1, 256, 0, s, (const float *)bpart, nb, mb.data_dev<float>(), mb.flag_dev(), t);
+        mb.wait(t, s);
+        std::memcpy(hb, mb.data_host<float>(), sizeof(float) * 7);
+    }
     a.put(bpart);
-    a.put(bbox);
     if (hb[6] != 0.f) fail(FMM_ENONFINITE, "a coordinate is NaN or infinite");
     root_cube(hb, hb + 3, P->k, P->x0);
 
@@ -829,7 +901,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         int32_t *ct = a.get_n<int32_t>(nc), *cl = a.get_n<int32_t>(nc);
         int64_t ntg = 0;
         hipLaunchKernelGGL(k_flag_internal, grid1(nc), 256, 0, s, (const int32_t *)P->c_nchild, nc, flag);
-        P->m2m.ntiles = tile_cells(C, nc, flag, false, a, s, P->m2m.tile_targets, ct, cl, P->m2m.bucket_tile, ntg);
+        P->m2m.ntiles = tile_cells(C, nc, flag, false, false, a, s, P->m2m.tile_targets, ct, cl, P->m2m.bucket_tile, ntg);
         if (P->m2m.ntiles > 0) {
             P->m2m.entry_src = a.get_n<int32_t>(P->m2m.ntiles * 8 * kTileN);
             fill_i32(P->m2m.entry_src, -1, P->m2m.ntiles * 8 * kTileN, s);
@@ -841,7 +913,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                                P->m2m.work);
         }
         hipLaunchKernelGGL(k_flag_nonroot, grid1(nc), 256, 0, s, (const int32_t *)P->c_level, nc, flag);
-        P->l2l.ntiles = tile_cells(C, nc, flag, true, a, s, P->l2l.tile_targets, ct, cl, P->l2l.bucket_tile, ntg);
+        P->l2l.ntiles = tile_cells(C, nc, flag, true, false, a, s, P->l2l.tile_targets, ct, cl, P->l2l.bucket_tile, ntg);
         if (P->l2l.ntiles > 0) {
             P->l2l.entry_src = a.get_n<int32_t>(P->l2l.ntiles * kTileN);
             fill_i32(P->l2l.entry_src, -1, P->l2l.ntiles * kTileN, s);
@@ -852,7 +924,6 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             hipLaunchKernelGGL(k_work_uniform, grid1(P->l2l.ntiles), 256, 0, s, P->l2l.ntiles, 1, (int32_t *)nullptr,
                                P->l2l.work);
         }
-        HIP_CHECK(hipStreamSynchronize(s));
         a.put(flag); a.put(ct); a.put(cl);
     }
 
@@ -860,41 +931,42 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     // ---- a4: dual traversal, one fused step per level of the pair tree
     const double theta2 = (double)P->theta * (double)P->theta;
     unsigned long long *cnt = a.get_n<unsigned long long>(3);
+    fill_i32(reinterpret_cast<int32_t *>(cnt), 0, 6, s);
     int2 *m2l = nullptr, *p2p = nullptr;
     int64_t m2l_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
     if (nc == 1) {               // the root is a leaf: one P2P pair
         grow(a, p2p, p2p_cap, 0, 1, s);
-        int2 rr = make_int2(0, 0);
-        HIP_CHECK(hipMemcpyAsync(p2p, &rr, sizeof(int2), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        fill_i32(reinterpret_cast<int32_t *>(p2p), 0, 2, s);
         np2p = 1;
     } else {
+        // first guess of the list sizes (a uniform cloud at theta = 0.4 has ~450 M2L
+        // pairs per cell and ~75 P2P pairs per leaf); a step that overflows is repeated
+        grow(a, m2l, m2l_cap, 0, 512 * nc, s);
+        grow(a, p2p, p2p_cap, 0, 96 * P->nleaves + 64, s);
         int2 *front = a.get_n<int2>(1);
-        int2 rr = make_int2(0, 0);
-        HIP_CHECK(hipMemcpyAsync(front, &rr, sizeof(int2), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        fill_i32(reinterpret_cast<int32_t *>(front), 0, 2, s);
         int64_t nf = 1;
         while (nf > 0) {
             // steady state of a uniform tree: ~8 split pairs, ~56 M2L and ~8 P2P pairs per split pair
             int64_t cap_n = std::max<int64_t>(1024, std::min<int64_t>(64 * nf, 10 * nf));
-            grow(a, m2l, m2l_cap, nm2l, nm2l + std::min<int64_t>(64 * nf, 70 * nf), s);
-            grow(a, p2p, p2p_cap, np2p, np2p + std::min<int64_t>(64 * nf, 12 * nf), s);
+            grow(a, m2l, m2l_cap, nm2l, nm2l + 64 * nf, s);
+            grow(a, p2p, p2p_cap, np2p, np2p + 12 * nf, s);
             int2 *next = a.get_n<int2>(cap_n);
-            unsigned long long h3[3];
+            uint64_t h3[3];
             for (int attempt = 0;; ++attempt) {
-                unsigned long long base[3] = {(unsigned long long)nm2l, (unsigned long long)np2p, 0ull};
-                HIP_CHECK(hipMemcpyAsync(cnt, base, sizeof(base), hipMemcpyHostToDevice, s));
                 const int64_t per_block = 4 * kTravPerWave;
                 const int64_t tb = (nf + per_block - 1) / per_block;
                 if (tb >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "traversal frontier too large");
+                const uint64_t t = mb.next_ticket();
                 hipLaunchKernelGGL(k_trav_step, (int)tb, 256, 0, s, C, (const int2 *)front, nf, theta2,
-                                   cnt, m2l,
-                                   m2l_cap, p2p, p2p_cap, next, cap_n);
-                HIP_CHECK(hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipStreamSynchronize(s));
+                                   cnt, m2l, m2l_cap, p2p, p2p_cap, next, cap_n);
+                hipLaunchKernelGGL(k_trav_post, 1, 64, 0, s, cnt, mb.data_dev<unsigned long long>(), mb.flag_dev(), t);
+                mb.wait(t, s);
+                std::memcpy(h3, mb.data_host<uint64_t>(), sizeof(h3));
                 bool ok = (int64_t)h3[0] <= m2l_cap && (int64_t)h3[1] <= p2p_cap && (int64_t)h3[2] <= cap_n;
                 if (ok) break;
                 if (attempt > 0) fail(FMM_EDEVICE, "traversal step overflowed twice");
+                hipLaunchKernelGGL(k_set_counters, 1, 64, 0, s, cnt, nm2l, np2p);
                 grow(a, m2l, m2l_cap, nm2l, (int64_t)h3[0], s);
                 grow(a, p2p, p2p_cap, np2p, (int64_t)h3[1], s);
                 if ((int64_t)h3[2] > cap_n) {
@@ -916,6 +988,55 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     P->np2p = np2p;
     P->m2l_pairs = m2l;
 
+    // ---- P2P lists, on the side stream while the host builds the M2L grouping: no host
+    // waits (the run count stays on the device; the run array is sized for one run per
+    // pair).  Temporaries come from an allocator bound to the side stream; everything it
+    // still holds joins the plan's workspace when the build ends.
+    struct SideAlloc {
+        Alloc &main;
+        Alloc as;
+        ~SideAlloc() {
+            main.live.insert(main.live.end(), as.live.begin(), as.live.end());
+            main.bytes += as.bytes;
+        }
+    } side{a, Alloc{}};
+    {
+        Alloc &as = side.as;
+        as.alloc = a.alloc;
+        as.release = a.release;
+        as.ctx = a.ctx;
+        as.stream = P->side;
+        hipStream_t ss = P->side;
+        HIP_CHECK(hipEventRecord(P->ev_fork, s));
+        HIP_CHECK(hipStreamWaitEvent(ss, P->ev_fork, 0));
+        uint64_t *comp = as.get_n<uint64_t>(np2p);
+        int32_t *dummy = as.get_n<int32_t>(np2p);
+        const int lbits = bits_for(P->nleaves);
+        hipLaunchKernelGGL(k_p2p_composite, grid1(np2p), 256, 0, ss, (const int2 *)p2p, np2p,
+                           (const int32_t *)P->leaf_id, lbits, comp, dummy);
+        radix_sort_u64(comp, dummy, np2p, 2 * lbits, as, ss);
+        P->p2p_pairs = as.get_n<int2>(np2p);
+        int32_t *pair_off = as.get_n<int32_t>(P->nleaves);
+        hipLaunchKernelGGL(k_p2p_csr, std::min(grid1(np2p), 1024), 256, 0, ss, (const uint64_t *)comp,
+                           (const int32_t *)dummy, np2p, lbits, (const int32_t *)P->leaves, P->p2p_pairs, pair_off,
+                           (const int32_t *)P->c_count, &counts[1]);
+        // runs: open flags in `dummy` (free after the CSR pass), run ids in `comp`'s storage
+        int32_t *open = dummy, *run_id = reinterpret_cast<int32_t *>(comp);
+        hipLaunchKernelGGL(k_p2p_run_flags, grid1(np2p), 256, 0, ss, (const int2 *)P->p2p_pairs, np2p,
+                           (const int32_t *)P->c_start, (const int32_t *)P->c_count, open);
+        int64_t *nseg_dev = reinterpret_cast<int64_t *>(&counts[2]);
+        exclusive_scan_i32_to(open, run_id, np2p, nseg_dev, as, ss);
+        P->seg_off = as.get_n<int32_t>(P->nleaves + 1);
+        P->segs = as.get_n<int2>(np2p);
+        hipLaunchKernelGGL(k_p2p_run_write, grid1(np2p), 256, 0, ss, (const int2 *)P->p2p_pairs, np2p,
+                           (const int32_t *)P->c_start, (const int32_t *)P->c_count, (const int32_t *)open,
+                           (const int32_t *)run_id, P->segs);
+        hipLaunchKernelGGL(k_p2p_run_len, grid1(np2p), 256, 0, ss, P->segs, (const int64_t *)nseg_dev);
+        hipLaunchKernelGGL(k_p2p_seg_off, grid1(P->nleaves + 1), 256, 0, ss, (int64_t)P->nleaves,
+                           (const int32_t *)pair_off, (const int32_t *)run_id, (const int64_t *)nseg_dev, P->seg_off);
+        as.put(comp); as.put(dummy); as.put(pair_off);
+    }
+
     lg("traversal");
     // ---- M2L keys, operators, tiles, entries
     if (nm2l > 0) {
@@ -926,28 +1047,35 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         hipLaunchKernelGGL(k_mark_targets, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, is_t);
         int32_t *cell_tile = a.get_n<int32_t>(nc), *cell_lane = a.get_n<int32_t>(nc);
         std::vector<int32_t> btile;
-        int64_t ntiles = tile_cells(C, nc, is_t, true, a, s, P->tile_targets, cell_tile, cell_lane, btile, P->ntargets);
+        int64_t ntiles = tile_cells(C, nc, is_t, true, true, a, s, P->tile_targets, cell_tile, cell_lane, btile, P->ntargets);
         P->ntiles = ntiles;
         a.put(is_t);
         lg("m2l target tiles");
 
         // distinct operator keys through a device hash table; every pair keeps its slot
+        // (the table's last word holds the two flags: key out of range, table full)
         uint64_t H = 1 << 15;
-        int32_t *flags = a.get_n<int32_t>(2);
         int32_t *pkid = a.get_n<int32_t>(nm2l);
         uint64_t *table = nullptr;
         std::vector<uint64_t> htab;
         for (;;) {
-            table = a.get_n<uint64_t>((int64_t)H);
+            table = a.get_n<uint64_t>((int64_t)H + 1);
             HIP_CHECK(hipMemsetAsync(table, 0xff, 8 * H, s));
+            int32_t *flags = reinterpret_cast<int32_t *>(table + H);
             fill_i32(flags, 0, 2, s);
             hipLaunchKernelGGL(k_key_insert, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, table, H - 1, pkid,
                                flags);
             int32_t hf[2];
-            HIP_CHECK(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
             htab.resize(H);
-            HIP_CHECK(hipMemcpyAsync(htab.data(), table, 8 * H, hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
+            if ((int64_t)(8 * (H + 1)) <= Mailbox::kDataBytes - Mailbox::kPostBytes) {
+                const uint64_t *ht = static_cast<const uint64_t *>(mb.fetch(table, 8 * (H + 1), s));
+                std::memcpy(htab.data(), ht, 8 * H);
+                std::memcpy(hf, ht + H, 8);
+            } else {
+                HIP_CHECK(hipMemcpyAsync(htab.data(), table, 8 * H, hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+            }
             if (hf[0]) fail(FMM_EUNSUPPORTED, "an M2L offset exceeds the key range");
             int64_t used = 0;
             for (uint64_t v : htab) used += v != ~0ull;
@@ -973,11 +1101,11 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         std::vector<uint64_t> p32, p16;
         m2l_operator_ptrs(P->p, hkeys, p32, p16, P->prec == FMM_PREC_MIXED);
         uint64_t *d32 = a.get_n<uint64_t>(nkeys);
-        HIP_CHECK(hipMemcpyAsync(d32, p32.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
+        mb.upload(d32, p32.data(), 8 * nkeys, s);
         P->key_f32 = d32;
         if (P->prec == FMM_PREC_MIXED) {
             uint64_t *d16 = a.get_n<uint64_t>(nkeys);
-            HIP_CHECK(hipMemcpyAsync(d16, p16.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
+            mb.upload(d16, p16.data(), 8 * nkeys, s);
             P->key_f16 = d16;
         }
         std::vector<float> key_kept;
@@ -985,27 +1113,23 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             std::vector<uint32_t> rows;
             m2l_block_rows(P->p, hkeys, P->m2l_tol, rows, key_kept);
             P->key_rows = a.get_n<uint32_t>((int64_t)rows.size());
-            HIP_CHECK(hipMemcpyAsync(P->key_rows, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, s));
-            HIP_CHECK(hipStreamSynchronize(s));   // the host vector goes out of scope
+            mb.upload(P->key_rows, rows.data(), 4 * rows.size(), s);
         }
         int32_t *slot_id = a.get_n<int32_t>((int64_t)H);
-        HIP_CHECK(hipMemcpyAsync(slot_id, hslot.data(), 4 * H, hipMemcpyHostToDevice, s));
+        mb.upload(slot_id, hslot.data(), 4 * H, s);
         int32_t *dsame = a.get_n<int32_t>(nkeys);
-        HIP_CHECK(hipMemcpyAsync(dsame, hsame.data(), 4 * nkeys, hipMemcpyHostToDevice, s));
+        mb.upload(dsame, hsame.data(), 4 * nkeys, s);
         lg("m2l keys+operators");
 
         // (tile, key) entries: dense presence table, scanned tile-major
         const int64_t ntk = ntiles * nkeys;
         if (ntk >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "M2L tile x key table exceeds 2^31 entries");
         int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk);
-        unsigned long long *same = a.get_n<unsigned long long>(1);
-        HIP_CHECK(hipMemsetAsync(same, 0, 8, s));
         fill_i32(present, 0, ntk, s);
         hipLaunchKernelGGL(k_key_ids, std::min(grid1(nm2l), 4096), 256, 0, s, (const int2 *)m2l, nm2l,
                            (const int32_t *)slot_id, (const int32_t *)dsame, (const int32_t *)cell_tile, nkeys, pkid,
-                           present, same);
+                           present, &counts[0]);
         const int64_t ne = exclusive_scan_i32(present, entry_of, ntk, a, s);
-        P->nm2l_same = (int64_t)read_back(same, s);
         P->nentries = ne;
         P->entry_key = a.get_n<int32_t>(ne);
         P->entry_src = a.get_n<int32_t>(ne * kTileN);
@@ -1035,11 +1159,14 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         int32_t *tile_first = a.get_n<int32_t>(ntiles);
         hipLaunchKernelGGL(k_tile_first, grid1(ntiles), 256, 0, s, (const int32_t *)entry_of, ntiles, nkeys, tile_first);
         std::vector<int32_t> htf(ntiles);
-        HIP_CHECK(hipMemcpyAsync(htf.data(), tile_first, 4 * ntiles, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        a.put(same);
+        if ((int64_t)(4 * ntiles) <= Mailbox::kDataBytes - Mailbox::kPostBytes) {
+            std::memcpy(htf.data(), mb.fetch(tile_first, 4 * ntiles, s), 4 * ntiles);
+        } else {
+            HIP_CHECK(hipMemcpyAsync(htf.data(), tile_first, 4 * ntiles, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+        }
         a.put(dsame);
-        a.put(flags); a.put(table); a.put(slot_id); a.put(present); a.put(entry_of); a.put(pkid);
+        a.put(table); a.put(slot_id); a.put(present); a.put(entry_of); a.put(pkid);
         a.put(tile_first); a.put(cell_tile); a.put(cell_lane);
         lg("m2l entries");
 
@@ -1068,6 +1195,13 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         for (int64_t k2 = 0; k2 < maxp; ++k2)
             for (int64_t t = 0; t < ntiles; ++t)
                 if (k2 < (int64_t)tp[t].size()) order.push_back(tp[t][k2]);
+        {
+            // the last quarter of the items, longest first: the final workgroups of the launch
+            // are the short ones, so the chip drains evenly
+            const size_t k0 = order.size() - order.size() / 4;
+            std::stable_sort(order.begin() + k0, order.end(),
+                             [](const int4 &u, const int4 &v) { return u.z - u.y > v.z - v.y; });
+        }
         std::vector<int4> hw;
         std::vector<std::vector<int32_t>> per_tile(ntiles);
         int64_t nsplit = 0;
@@ -1086,11 +1220,10 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         P->work = a.get_n<int4>(P->nwork);
         P->tile_work = a.get_n<int32_t>(ntiles + 1);
         P->tile_work_idx = a.get_n<int32_t>(P->nwork);
-        HIP_CHECK(hipMemcpyAsync(P->work, hw.data(), sizeof(int4) * hw.size(), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(P->tile_work, htw.data(), 4 * (ntiles + 1), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(P->tile_work_idx, htwi.data(), 4 * P->nwork, hipMemcpyHostToDevice, s));
+        mb.upload(P->work, hw.data(), sizeof(int4) * hw.size(), s);
+        mb.upload(P->tile_work, htw.data(), 4 * (ntiles + 1), s);
+        mb.upload(P->tile_work_idx, htwi.data(), 4 * P->nwork, s);
         P->npartial = nsplit;
-        HIP_CHECK(hipStreamSynchronize(s));
 
         // mixed precision: the root levels accumulate in FP64, with FP64 operators for the
         // keys their tiles use and their own split into small work items
@@ -1116,7 +1249,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                 m2l_operator_ptrs64(P->p, rkeys, rp);
                 for (size_t q2 = 0; q2 < rid.size(); ++q2) all[rid[q2]] = rp[q2];
                 uint64_t *d64 = a.get_n<uint64_t>(nkeys);
-                HIP_CHECK(hipMemcpyAsync(d64, all.data(), 8 * nkeys, hipMemcpyHostToDevice, s));
+                mb.upload(d64, all.data(), 8 * nkeys, s);
                 P->key_f64 = d64;
                 constexpr int64_t kPiece64 = 24;
                 std::vector<int4> w64;
@@ -1136,54 +1269,20 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                 P->work64 = a.get_n<int4>(P->nwork64);
                 P->tile_work64 = a.get_n<int32_t>(tr + 1);
                 P->tile_work_idx64 = a.get_n<int32_t>(P->nwork64);
-                HIP_CHECK(hipMemcpyAsync(P->work64, w64.data(), sizeof(int4) * w64.size(), hipMemcpyHostToDevice, s));
-                HIP_CHECK(hipMemcpyAsync(P->tile_work64, tw.data(), 4 * (tr + 1), hipMemcpyHostToDevice, s));
-                HIP_CHECK(hipMemcpyAsync(P->tile_work_idx64, twi.data(), 4 * P->nwork64, hipMemcpyHostToDevice, s));
+                mb.upload(P->work64, w64.data(), sizeof(int4) * w64.size(), s);
+                mb.upload(P->tile_work64, tw.data(), 4 * (tr + 1), s);
+                mb.upload(P->tile_work_idx64, twi.data(), 4 * P->nwork64, s);
                 if (slot > 0) P->partial64 = a.get_n<double>(slot * kTileN * P->KP);
-                HIP_CHECK(hipStreamSynchronize(s));
             }
         }
     }
 
     lg("m2l work items");
-    // ---- P2P lists
-    {
-        uint64_t *comp = a.get_n<uint64_t>(np2p);
-        int32_t *dummy = a.get_n<int32_t>(np2p);
-        const int lbits = bits_for(P->nleaves);
-        hipLaunchKernelGGL(k_p2p_composite, grid1(np2p), 256, 0, s, (const int2 *)p2p, np2p, (const int32_t *)P->leaf_id,
-                           lbits, comp, dummy);
-        radix_sort_u64(comp, dummy, np2p, 2 * lbits, a, s);
-        lg("p2p sort");
-        P->p2p_pairs = a.get_n<int2>(np2p);
-        int32_t *pair_off = a.get_n<int32_t>(P->nleaves);
-        unsigned long long *inter = a.get_n<unsigned long long>(1);
-        HIP_CHECK(hipMemsetAsync(inter, 0, 8, s));
-        hipLaunchKernelGGL(k_p2p_csr, std::min(grid1(np2p), 1024), 256, 0, s, (const uint64_t *)comp,
-                           (const int32_t *)dummy, np2p, lbits, (const int32_t *)P->leaves, P->p2p_pairs, pair_off,
-                           (const int32_t *)P->c_count, inter);
-        P->p2p_interactions = (int64_t)read_back(inter, s);
-        lg("p2p csr");
-        // runs: open flags in `dummy` (free after the CSR pass), run ids in `comp`'s storage
-        int32_t *open = dummy, *run_id = reinterpret_cast<int32_t *>(comp);
-        hipLaunchKernelGGL(k_p2p_run_flags, grid1(np2p), 256, 0, s, (const int2 *)P->p2p_pairs, np2p,
-                           (const int32_t *)P->c_start, (const int32_t *)P->c_count, open);
-        P->nseg = exclusive_scan_i32(open, run_id, np2p, a, s);
-        lg("p2p run flags");
-        if (P->nseg >= (int64_t)INT32_MAX) fail(FMM_EUNSUPPORTED, "near-field run count exceeds 2^31");
-        P->seg_off = a.get_n<int32_t>(P->nleaves + 1);
-        P->segs = a.get_n<int2>(std::max<int64_t>(P->nseg, 1));
-        hipLaunchKernelGGL(k_p2p_run_write, grid1(np2p), 256, 0, s, (const int2 *)P->p2p_pairs, np2p,
-                           (const int32_t *)P->c_start, (const int32_t *)P->c_count, (const int32_t *)open,
-                           (const int32_t *)run_id, P->segs);
-        hipLaunchKernelGGL(k_p2p_run_len, grid1(P->nseg), 256, 0, s, P->segs, P->nseg);
-        hipLaunchKernelGGL(k_p2p_seg_off, grid1(P->nleaves + 1), 256, 0, s, (int64_t)P->nleaves,
-                           (const int32_t *)pair_off, (const int32_t *)run_id, (int32_t)P->nseg, P->seg_off);
-        HIP_CHECK(hipStreamSynchronize(s));
-        a.put(comp); a.put(dummy); a.put(pair_off); a.put(inter); a.put(p2p);
-    }
-
-    lg("p2p lists");
+    // join the near-field lists built on the side stream
+    HIP_CHECK(hipEventRecord(P->ev_join, P->side));
+    HIP_CHECK(hipStreamWaitEvent(s, P->ev_join, 0));
+    a.put(p2p);
+    lg("p2p lists (joined)");
     // ---- evaluation workspace
     const int KP = P->KP;
     P->M = a.get_n<float>(nc * KP);
@@ -1196,6 +1295,16 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         P->Ml = a.get_n<_Float16>(nc * KP);
         P->Msinv = a.get_n<float>(nc);
     }
+    {
+        const uint64_t t = mb.next_ticket();
+        publish(counts, 24, mb, t, s);
+        mb.wait(t, s);
+        P->nm2l_same = (int64_t)mb.data_host<uint64_t>()[0];
+        P->p2p_interactions = (int64_t)mb.data_host<uint64_t>()[1];
+        P->nseg = (int64_t)mb.data_host<uint64_t>()[2];
+        if (P->nseg >= (int64_t)INT32_MAX) fail(FMM_EUNSUPPORTED, "near-field run count exceeds 2^31");
+    }
+    a.put(counts);
     HIP_CHECK(hipStreamSynchronize(s));
     lg("workspace");
 }

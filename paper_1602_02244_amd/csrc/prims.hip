@@ -108,6 +108,90 @@ void Alloc::release_all() {
     live.clear();
 }
 
+// ------------------------------------------------------------------ mailbox
+namespace {
+std::mutex g_mb_mu;
+std::vector<Mailbox *> g_mb_free;   // kept for the life of the process
+}  // namespace
+
+Mailbox *mailbox_acquire() {
+    {
+        std::lock_guard<std::mutex> lk(g_mb_mu);
+        if (!g_mb_free.empty()) {
+            Mailbox *m = g_mb_free.back();
+            g_mb_free.pop_back();
+            m->upload_used = 0;
+            return m;
+        }
+    }
+    void *h = nullptr, *d = nullptr, *u = nullptr;
+    HIP_CHECK(hipHostMalloc(&h, 64 + Mailbox::kDataBytes,
+                            hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable));
+    std::memset(h, 0, 64);
+    HIP_CHECK(hipHostGetDevicePointer(&d, h, 0));
+    HIP_CHECK(hipHostMalloc(&u, Mailbox::kUploadBytes, hipHostMallocPortable));
+    Mailbox *m = new Mailbox;
+    m->host = static_cast<volatile uint64_t *>(h);
+    m->dev = static_cast<uint64_t *>(d);
+    m->upload_host = static_cast<char *>(u);
+    return m;
+}
+
+void mailbox_release(Mailbox *m) {
+    if (!m) return;
+    std::lock_guard<std::mutex> lk(g_mb_mu);
+    g_mb_free.push_back(m);
+}
+
+void Mailbox::wait(uint64_t t, hipStream_t s) {
+    for (uint64_t it = 1;; ++it) {
+        if (__atomic_load_n(&host[0], __ATOMIC_ACQUIRE) == t) return;
+        if ((it & 255) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {   // the stream has drained: the ticket must be there
+                if (__atomic_load_n(&host[0], __ATOMIC_ACQUIRE) == t) return;
+                fail(FMM_EDEVICE, "a device result was not delivered to the host");
+            }
+            if (e != hipErrorNotReady) check_hip(e, "hipStreamQuery");
+        }
+    }
+}
+
+void Mailbox::upload(void *dst, const void *src, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    const int64_t off = (upload_used + 255) & ~int64_t(255);
+    if (off + (int64_t)n > kUploadBytes) {   // does not fit: a staged copy, completed before returning
+        HIP_CHECK(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        return;
+    }
+    std::memcpy(upload_host + off, src, n);
+    HIP_CHECK(hipMemcpyAsync(dst, upload_host + off, n, hipMemcpyHostToDevice, s));
+    upload_used = off + (int64_t)n;
+}
+
+const void *Mailbox::fetch(const void *src, size_t n, hipStream_t s) {
+    if ((int64_t)n > kDataBytes - kPostBytes) fail(FMM_EUNSUPPORTED, "read-back larger than the mailbox");
+    void *dst = const_cast<void *>(static_cast<const void *>(data_host<char>() + kPostBytes));
+    if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return dst;
+}
+
+__global__ void __launch_bounds__(256) k_publish(const uint32_t *src, int64_t words, uint32_t *dst, uint64_t *flag,
+                                                 uint64_t ticket) {
+    for (int64_t i = threadIdx.x; i < words; i += 256) dst[i] = src[i];
+    mailbox_fence();
+    __syncthreads();
+    if (threadIdx.x == 0) mailbox_post(flag, ticket);
+}
+
+void publish(const void *src, int64_t bytes, Mailbox &m, uint64_t ticket, hipStream_t s) {
+    if (bytes % 4 != 0 || bytes > Mailbox::kPostBytes) fail(FMM_EINVAL, "publish: bad size");
+    hipLaunchKernelGGL(k_publish, 1, 256, 0, s, static_cast<const uint32_t *>(src), bytes / 4,
+                       m.data_dev<uint32_t>(), m.flag_dev(), ticket);
+}
+
 // ------------------------------------------------------------------ fills
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
@@ -135,9 +219,58 @@ void iota_i32(int32_t *p, int64_t n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ scan
-// Three-phase exclusive scan: per-block scan (256 threads x 8 items), scan of block
-// totals (recursive), add block offsets.
+// Up to kSingleMax values: one workgroup walks the input in tiles of 4096 and carries
+// the running total.  Larger inputs: per-block scan (256 threads x 8 items), scan of the
+// block totals, add block offsets.  The grand total is written to tot_dst when given,
+// followed by a mailbox ticket when flag is given.
 constexpr int kScanThreads = 256, kScanItems = 8, kScanTile = kScanThreads * kScanItems;
+constexpr int kSingleThreads = 1024, kSingleItems = 4, kSingleTile = kSingleThreads * kSingleItems;
+constexpr int64_t kSingleMax = 65536;
+
+template <class T>
+__global__ void __launch_bounds__(kSingleThreads) k_scan_single(const T *in, T *out, int64_t n, int64_t *tot_dst,
+                                                                 uint64_t *flag, uint64_t ticket) {
+    __shared__ T wsum[kSingleThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    T carry = 0;
+    for (int64_t base = 0; base < n; base += kSingleTile) {
+        T v[kSingleItems];
+        T sum = 0;
+#pragma unroll
+        for (int j = 0; j < kSingleItems; ++j) {
+            const int64_t g = base + (int64_t)tid * kSingleItems + j;
+            v[j] = g < n ? in[g] : T(0);
+            sum += v[j];
+        }
+        T incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T t = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += t;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        T wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kSingleThreads / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        T run = carry + wpre + incl - sum;
+#pragma unroll
+        for (int j = 0; j < kSingleItems; ++j) {
+            const int64_t g = base + (int64_t)tid * kSingleItems + j;
+            if (g < n) out[g] = run;
+            run += v[j];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (tid == 0 && tot_dst) {
+        *tot_dst = (int64_t)carry;
+        if (flag) mailbox_post(flag, ticket);
+    }
+}
 
 template <class T>
 __global__ void __launch_bounds__(kScanThreads) k_scan_block(const T *in, T *out, T *block_tot, int64_t n) {
@@ -177,42 +310,51 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_block(const T *in, T *out
 }
 
 template <class T>
-__global__ void k_scan_add(T *out, const T *block_off, int64_t n) {
+__global__ void k_scan_add(T *out, const T *in, const T *block_off, int64_t n, int64_t *tot_dst, uint64_t *flag,
+                           uint64_t ticket) {
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     T add = block_off[blockIdx.x];
     for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
         int64_t g = base + i;
-        if (g < n) out[g] += add;
+        if (g < n) {
+            const T v = out[g] + add;
+            out[g] = v;
+            if (g == n - 1 && tot_dst) {
+                *tot_dst = (int64_t)v + (int64_t)in[g];
+                if (flag) mailbox_post(flag, ticket);
+            }
+        }
     }
 }
 
 template <class T>
-static void scan_rec(const T *in, T *out, int64_t n, Alloc &a, hipStream_t s) {
-    int64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (nb <= 1) {
-        hipLaunchKernelGGL(k_scan_block<T>, 1, kScanThreads, 0, s, in, out, (T *)nullptr, n);
+static void scan_rec(const T *in, T *out, int64_t n, Alloc &a, hipStream_t s, int64_t *tot_dst = nullptr,
+                     uint64_t *flag = nullptr, uint64_t ticket = 0) {
+    if (n <= kSingleMax) {
+        hipLaunchKernelGGL(k_scan_single<T>, 1, kSingleThreads, 0, s, in, out, n, tot_dst, flag, ticket);
         return;
     }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
     T *tot = a.get_n<T>(nb);
     T *off = a.get_n<T>(nb);
     hipLaunchKernelGGL(k_scan_block<T>, (int)nb, kScanThreads, 0, s, in, out, tot, n);
     scan_rec<T>(tot, off, nb, a, s);
-    hipLaunchKernelGGL(k_scan_add<T>, (int)nb, kScanThreads, 0, s, out, (const T *)off, n);
+    hipLaunchKernelGGL(k_scan_add<T>, (int)nb, kScanThreads, 0, s, out, in, (const T *)off, n, tot_dst, flag, ticket);
     a.put(tot);
     a.put(off);
 }
 
 template <class T>
-__global__ void k_total(const T *in, const T *ex, int64_t n, int64_t *tot) {
-    *tot = (int64_t)ex[n - 1] + (int64_t)in[n - 1];
-}
-
-template <class T>
 static int64_t scan_impl(const T *in, T *out, int64_t n, Alloc &a, hipStream_t s) {
     if (n <= 0) return 0;
-    scan_rec<T>(in, out, n, a, s);
+    if (Mailbox *m = a.mb) {
+        const uint64_t t = m->next_ticket();
+        scan_rec<T>(in, out, n, a, s, m->data_dev<int64_t>(), m->flag_dev(), t);
+        m->wait(t, s);
+        return m->data_host<int64_t>()[0];
+    }
     int64_t *tot = a.get_n<int64_t>(1);
-    hipLaunchKernelGGL(k_total<T>, 1, 1, 0, s, in, (const T *)out, n, tot);
+    scan_rec<T>(in, out, n, a, s, tot);
     int64_t r = read_back(tot, s);
     a.put(tot);
     return r;
@@ -223,6 +365,13 @@ int64_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, Alloc &a,
 }
 int64_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Alloc &a, hipStream_t s) {
     return scan_impl<int32_t>(in, out, n, a, s);
+}
+void exclusive_scan_i32_to(const int32_t *in, int32_t *out, int64_t n, int64_t *tot_dev, Alloc &a, hipStream_t s) {
+    if (n <= 0) {
+        fill_i32(reinterpret_cast<int32_t *>(tot_dev), 0, 2, s);
+        return;
+    }
+    scan_rec<int32_t>(in, out, n, a, s, tot_dev);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -290,7 +439,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint64_t *k
     }
 }
 
-void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Alloc &a, hipStream_t s) {
+void radix_sort_u64(uint64_t *&keys, int32_t *&vals, int64_t n, int bits, Alloc &a, hipStream_t s) {
     if (n <= 1 || bits <= 0) return;
     int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     uint64_t *k2 = a.get_n<uint64_t>(n);
@@ -309,12 +458,15 @@ void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Alloc &a
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
-    if (ki != keys) {
-        HIP_CHECK(hipMemcpyAsync(keys, ki, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
-        HIP_CHECK(hipMemcpyAsync(vals, vi, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (ki != keys) {   // odd number of passes: the result is in the second pair
+        a.put(keys);
+        a.put(vals);
+        keys = ki;
+        vals = vi;
+    } else {
+        a.put(k2);
+        a.put(v2);
     }
-    a.put(k2);
-    a.put(v2);
     a.put(hist);
     a.put(off);
 }
