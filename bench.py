@@ -27,9 +27,10 @@ import numpy as np  # noqa: E402
 MFMA_FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 MFMA
 # HBM bytes of one M2L launch on the uniform-1M workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
 # factors from a 1 GiB plain copy), measured with rocprofv3 on the M2L kernel source whose
-# sha256 prefix is given (the text of k_gemm in eval.hip); reported only while that source
-# is unchanged.
-M2L_TRAFFIC = {"kernel_sha256": "c30bb87874966155", "workload": "uniform-1M", "p": 10, "theta": 0.4, "bytes": 17.73e9}
+# sha256 prefix is given (the text of k_gemm in eval.hip) and on the plan's grouping (its
+# entry and work-item counts); reported only while both are unchanged.
+M2L_TRAFFIC = {"kernel_sha256": "c30bb87874966155", "workload": "uniform-1M", "p": 10, "theta": 0.4,
+               "entries": 285444, "work_items": 4556, "bytes": 18.18e9}
 VALU_FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X FP32 vector with packed (2-wide) FMA
 VALU_FP32_PEAK_TFLOPS = 78.6           # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 not used
 P2P_ISSUE_PEAK_TFLOPS = 46.3           # the same lanes at 17 issue slots per 20-flop interaction
@@ -64,9 +65,10 @@ def m2l_kernel_sha():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def m2l_traffic(workload, p, theta):
+def m2l_traffic(workload, p, theta, st):
     t = M2L_TRAFFIC
-    if m2l_kernel_sha() == t["kernel_sha256"] and (workload, p, theta) == (t["workload"], t["p"], t["theta"]):
+    if (m2l_kernel_sha() == t["kernel_sha256"] and (workload, p, theta) == (t["workload"], t["p"], t["theta"])
+            and (st["m2l_entries"], st["m2l_work_items"]) == (t["entries"], t["work_items"])):
         return t["bytes"]
     return None
 
@@ -242,6 +244,8 @@ def main():
         "p2p_interactions": st["p2p_interactions"],
         "m2l_pairs": st["m2l_pairs"],
         "m2l_keys": st["m2l_keys"],
+        "m2l_entries": st["m2l_entries"],
+        "m2l_work_items": st["m2l_work_items"],
         "m2l_kept_fraction": st["m2l_kept_fraction"],
         "ncells": st["ncells"],
         "roofline": {
@@ -251,7 +255,7 @@ def main():
             "peak": MFMA_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": m2l_tflops / MFMA_FP32_PEAK_TFLOPS,
-            "traffic": m2l_traffic(args.workload, p, theta),
+            "traffic": m2l_traffic(args.workload, p, theta, st),
         },
         "p2p_roofline": {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_tflops, "peak": VALU_FP32_PEAK_TFLOPS,
                          "unit": "TFLOP/s (20 flop/interaction)", "frac": p2p_tflops / VALU_FP32_PEAK_TFLOPS,

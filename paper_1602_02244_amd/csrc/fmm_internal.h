@@ -34,11 +34,12 @@ void check_hip(hipError_t e, const char *what);
 // and then, after a system-scope fence, a ticket; the host spins on the ticket.  Uploads
 // go through the same pinned memory (an arena reset at the start of each plan build).
 struct Mailbox {
-    static constexpr int64_t kPostBytes = int64_t(64) << 10;   // area kernels post to
-    static constexpr int64_t kDataBytes = int64_t(2) << 20;    // post area, then the fetch area
-    static constexpr int64_t kUploadBytes = int64_t(4) << 20;  // upload arena
+    static constexpr int64_t kPostBytes = int64_t(64) << 10;   // area kernels post to (coherent)
+    static constexpr int64_t kFetchBytes = int64_t(4) << 20;   // copy destination (pinned, cached)
+    static constexpr int64_t kUploadBytes = int64_t(4) << 20;  // upload arena (pinned, cached)
     volatile uint64_t *host = nullptr;   // word 0: ticket; data from byte 64
     uint64_t *dev = nullptr;             // the same memory as seen by the device
+    char *fetch_host = nullptr;          // pinned read-back area
     char *upload_host = nullptr;         // pinned upload arena
     int64_t upload_used = 0;
     uint64_t ticket = 0;
@@ -53,9 +54,9 @@ struct Mailbox {
     void wait(uint64_t t, hipStream_t s);
     // Copy n bytes of host data into the upload arena and queue their transfer to dst.
     void upload(void *dst, const void *src, size_t n, hipStream_t s);
-    // Device-to-host copy of n bytes (at most kDataBytes - kPostBytes) into the fetch area
-    // (pinned: no staging), then a stream synchronisation; returns the host copy, valid
-    // until the next fetch.
+    // Device-to-host copy of n bytes (at most kFetchBytes) into the fetch area (pinned: no
+    // staging), then a stream synchronisation; returns the host copy, valid until the next
+    // fetch.
     const void *fetch(const void *src, size_t n, hipStream_t s);
 };
 Mailbox *mailbox_acquire();        // from a process-wide pool

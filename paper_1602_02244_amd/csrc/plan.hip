@@ -1067,7 +1067,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                                flags);
             int32_t hf[2];
             htab.resize(H);
-            if ((int64_t)(8 * (H + 1)) <= Mailbox::kDataBytes - Mailbox::kPostBytes) {
+            if ((int64_t)(8 * (H + 1)) <= Mailbox::kFetchBytes) {
                 const uint64_t *ht = static_cast<const uint64_t *>(mb.fetch(table, 8 * (H + 1), s));
                 std::memcpy(htab.data(), ht, 8 * H);
                 std::memcpy(hf, ht + H, 8);
@@ -1159,7 +1159,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         int32_t *tile_first = a.get_n<int32_t>(ntiles);
         hipLaunchKernelGGL(k_tile_first, grid1(ntiles), 256, 0, s, (const int32_t *)entry_of, ntiles, nkeys, tile_first);
         std::vector<int32_t> htf(ntiles);
-        if ((int64_t)(4 * ntiles) <= Mailbox::kDataBytes - Mailbox::kPostBytes) {
+        if ((int64_t)(4 * ntiles) <= Mailbox::kFetchBytes) {
             std::memcpy(htf.data(), mb.fetch(tile_first, 4 * ntiles, s), 4 * ntiles);
         } else {
             HIP_CHECK(hipMemcpyAsync(htf.data(), tile_first, 4 * ntiles, hipMemcpyDeviceToHost, s));
@@ -1171,9 +1171,9 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         lg("m2l entries");
 
         // work items: split each tile's entries into pieces so that there are enough items
-        // to fill the chip.  Items are ordered piece-major: the workgroups in flight work
-        // on the same part of the key range (entries are key-sorted inside a tile), so the
-        // operators they stream stay in L2.
+        // to fill the chip.  Items are ordered piece-major, then by their first operator key:
+        // the workgroups in flight work on the same part of the key range (entries are
+        // key-sorted inside a tile), so the operators they stream stay in L2.
         htf.push_back((int32_t)ne);
         int64_t piece = kEntriesPerWork, items = 4096;   // tuning knobs, overridable from the environment
         if (const char *ev = getenv("FMM_M2L_PIECE")) piece = std::max<int64_t>(1, atoll(ev));
@@ -1195,6 +1195,13 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         for (int64_t k2 = 0; k2 < maxp; ++k2)
             for (int64_t t = 0; t < ntiles; ++t)
                 if (k2 < (int64_t)tp[t].size()) order.push_back(tp[t][k2]);
+        if ((int64_t)(4 * ne) <= Mailbox::kFetchBytes) {
+            // then by the operator key of the first entry: tiles of different boundary
+            // classes hold different key sets, and the workgroups in flight should stream
+            // the same operators
+            const int32_t *hk = static_cast<const int32_t *>(mb.fetch(P->entry_key, 4 * ne, s));
+            std::stable_sort(order.begin(), order.end(), [&](const int4 &u, const int4 &v) { return hk[u.y] < hk[v.y]; });
+        }
         {
             // the last quarter of the items, longest first: the final workgroups of the launch
             // are the short ones, so the chip drains evenly

@@ -124,15 +124,17 @@ Mailbox *mailbox_acquire() {
             return m;
         }
     }
-    void *h = nullptr, *d = nullptr, *u = nullptr;
-    HIP_CHECK(hipHostMalloc(&h, 64 + Mailbox::kDataBytes,
+    void *h = nullptr, *d = nullptr, *f = nullptr, *u = nullptr;
+    HIP_CHECK(hipHostMalloc(&h, 64 + Mailbox::kPostBytes,
                             hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable));
     std::memset(h, 0, 64);
     HIP_CHECK(hipHostGetDevicePointer(&d, h, 0));
+    HIP_CHECK(hipHostMalloc(&f, Mailbox::kFetchBytes, hipHostMallocPortable));
     HIP_CHECK(hipHostMalloc(&u, Mailbox::kUploadBytes, hipHostMallocPortable));
     Mailbox *m = new Mailbox;
     m->host = static_cast<volatile uint64_t *>(h);
     m->dev = static_cast<uint64_t *>(d);
+    m->fetch_host = static_cast<char *>(f);
     m->upload_host = static_cast<char *>(u);
     return m;
 }
@@ -171,8 +173,8 @@ void Mailbox::upload(void *dst, const void *src, size_t n, hipStream_t s) {
 }
 
 const void *Mailbox::fetch(const void *src, size_t n, hipStream_t s) {
-    if ((int64_t)n > kDataBytes - kPostBytes) fail(FMM_EUNSUPPORTED, "read-back larger than the mailbox");
-    void *dst = const_cast<void *>(static_cast<const void *>(data_host<char>() + kPostBytes));
+    if ((int64_t)n > kFetchBytes) fail(FMM_EUNSUPPORTED, "read-back larger than the mailbox");
+    void *dst = fetch_host;
     if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     return dst;
