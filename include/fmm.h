@@ -180,6 +180,9 @@ struct fmm_stats {
     double m2l_tol;                         /* variable-order tolerance (0: every block) */
     double m2l_kept_fraction;               /* pair-weighted fraction of operator blocks applied */
     int64_t lists;                          /* FMM_LISTS_DUAL or FMM_LISTS_LEVEL_SKIP */
+    int64_t p2p_work_items;                 /* near-field workgroups per evaluation: one per target
+                                               leaf, more for leaves split into pieces */
+    int64_t p2p_split_pieces;               /* pieces of split leaves (0: no leaf is split) */
 };
 fmm_status fmm_plan_stats(fmm_plan_t plan, struct fmm_stats *out);
 

@@ -45,6 +45,7 @@ class FmmStats(C.Structure):
         ("p2p_flops", C.c_double),
         ("workspace_bytes", C.c_int64),
         ("m2l_tol", C.c_double), ("m2l_kept_fraction", C.c_double), ("lists", C.c_int64),
+        ("p2p_work_items", C.c_int64), ("p2p_split_pieces", C.c_int64),
     ]
 
 

@@ -146,6 +146,8 @@ void fill_stats(fmm_plan_s *P) {
     st.m2l_tol = P->m2l_tol;
     st.m2l_kept_fraction = P->m2l_kept;
     st.lists = P->lists;
+    st.p2p_work_items = P->np2p_items;
+    st.p2p_split_pieces = P->np2p_part;
 }
 }  // namespace
 

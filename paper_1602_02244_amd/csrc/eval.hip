@@ -868,7 +868,7 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
 }
 
 // ------------------------------------------------------------------ P2P
-constexpr int kP2PThreads = 256, kP2PBatch = 1024;
+constexpr int kP2PBatch = 1024;
 
 template <bool CHECK>
 __device__ __forceinline__ void p2p_batch(const float4 *src, int ns, int g, int G, float xi, float yi, float zi, float &f,
@@ -917,18 +917,129 @@ __device__ __forceinline__ void p2p_batch_comp(const float4 *src, int ns, int g,
     }
 }
 
+// Source runs of a target leaf, streamed through the LDS batch `src`: the run descriptors
+// are read kP2PThreads at a time (one per thread) and their lengths scanned, so that the
+// bodies of many short runs are copied in one parallel pass (an adaptive tree can give a
+// coarse leaf tens of thousands of small source leaves).  Only the sources whose position
+// in the leaf's concatenated source list lies in [lo, hi) are taken (run_pre: exclusive
+// prefix of all run lengths, base = its value at the leaf's first run).  flush(n)
+// consumes the n staged sources; it is called when the batch is full and at the end.
+// Every thread of the block calls this with the same arguments.
+struct RunStage {
+    int st[kP2PThreads];        // first body of each run of the chunk
+    int off[kP2PThreads + 1];   // exclusive prefix of the run lengths
+    int wsum[kP2PThreads / 64];
+};
+template <class Flush>
+__device__ __forceinline__ void p2p_stream_runs(const int2 *segs, const int64_t *run_pre, int sg0, int sg1, int64_t base,
+                                                int64_t lo, int64_t hi, const float4 *bodies, float4 *src,
+                                                RunStage &rs, Flush flush) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int pos = 0;
+    for (int c0 = sg0; c0 < sg1; c0 += kP2PThreads) {
+        const int nr = min(kP2PThreads, sg1 - c0);
+        int st = 0, len = 0;
+        if (tid < nr) {
+            const int2 r = segs[c0 + tid];
+            const int64_t pre = run_pre[c0 + tid] - base, a = max(pre, lo), b = min(pre + r.y, hi);
+            st = r.x + (int)(a - pre);
+            len = b > a ? (int)(b - a) : 0;
+        }
+        int incl = len;   // block-wide inclusive scan of the lengths
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) rs.wsum[wave] = incl;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) incl += rs.wsum[w];
+        rs.st[tid] = st;
+        rs.off[tid + 1] = incl;
+        if (tid == 0) rs.off[0] = 0;
+        __syncthreads();
+        const int total = rs.off[nr];
+        for (int b0 = 0; b0 < total;) {
+            const int take = min(total - b0, kP2PBatch - pos);
+            if (pos == 0) __syncthreads();   // the previous batch has been consumed
+            for (int i = tid; i < take; i += kP2PThreads) {
+                const int e = b0 + i;
+                int l = 0, h = nr - 1;       // the run holding element e: last r with off[r] <= e
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (rs.off[mid] <= e) l = mid;
+                    else h = mid - 1;
+                }
+                src[pos + i] = bodies[rs.st[l] + (e - rs.off[l])];
+            }
+            pos += take;
+            b0 += take;
+            if (pos == kP2PBatch) {
+                __syncthreads();
+                flush(pos);
+                pos = 0;
+            }
+        }
+        __syncthreads();   // rs is rewritten by the next chunk
+    }
+    if (pos > 0) {
+        __syncthreads();
+        flush(pos);
+    }
+}
+
+// A near-field work item (leaf, piece j of k, first partial block): a leaf whose list
+// holds more than kP2PPieceWork interactions is cut into k pieces of about equal source
+// counts, each written as a partial result and summed by k_p2p_join in piece order
+// (deterministic); k = 1 leaves write their result directly.  The run range of piece j:
+struct P2PPiece {
+    int sg0, sg1;          // runs that overlap the piece
+    int64_t base, lo, hi;  // run_pre at the leaf's first run, and the piece's source range
+};
+__device__ inline P2PPiece p2p_piece(const int32_t *seg_off, const int64_t *run_pre, int li, int j, int k) {
+    P2PPiece pc;
+    pc.sg0 = seg_off[li];
+    pc.sg1 = seg_off[li + 1];
+    pc.base = run_pre[pc.sg0];
+    const int64_t S = run_pre[pc.sg1] - pc.base;
+    pc.lo = S * j / k;
+    pc.hi = S * (j + 1) / k;
+    if (k > 1) {   // the first run ending after lo, the first run starting at or after hi
+        int l = pc.sg0, h = pc.sg1;
+        while (l < h) {
+            const int m = (l + h) >> 1;
+            if (run_pre[m + 1] - pc.base <= pc.lo) l = m + 1;
+            else h = m;
+        }
+        const int a = l;
+        l = a;
+        h = pc.sg1;
+        while (l < h) {
+            const int m = (l + h) >> 1;
+            if (run_pre[m] - pc.base < pc.hi) l = m + 1;
+            else h = m;
+        }
+        pc.sg0 = a;
+        pc.sg1 = l;
+    }
+    return pc;
+}
+
 template <bool COMP>
-__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, const int32_t *c_start, const int32_t *c_count,
-                                                     const int32_t *seg_off, const int2 *segs, const float4 *bodies,
-                                                     float4 *out) {
+__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int4 *items, const int32_t *leaves, const int32_t *c_start,
+                                                     const int32_t *c_count, const int32_t *seg_off, const int2 *segs,
+                                                     const int64_t *run_pre, const float4 *bodies, float4 *out,
+                                                     float4 *part) {
     __shared__ float4 src[kP2PBatch];
     __shared__ float4 red[kP2PThreads];
     __shared__ float4 redl[COMP ? kP2PThreads : 1];
-    const int li = blockIdx.x;
+    __shared__ RunStage rs;
+    const int4 item = items[blockIdx.x];
+    const int li = item.x, piece = item.y, npieces = item.z;
     const int c = leaves[li];
     const int ts = c_start[c], tn = c_count[c];
     const int tid = threadIdx.x;
-    const int sg0 = seg_off[li], sg1 = seg_off[li + 1];
+    const P2PPiece pc = p2p_piece(seg_off, run_pre, li, piece, npieces);
     for (int t0 = 0; t0 < tn; t0 += kP2PThreads) {
         const int nt = min(kP2PThreads, tn - t0);
         const int G = kP2PThreads / nt;
@@ -941,8 +1052,8 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, cons
         }
         float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         Comp4 cmp;
-        // the target leaf itself: skip j == i and coincident points
-        for (int s0 = 0; s0 < tn; s0 += kP2PBatch) {
+        // the target leaf itself (first piece): skip j == i and coincident points
+        for (int s0 = 0; piece == 0 && s0 < tn; s0 += kP2PBatch) {
             const int ns = min(kP2PBatch, tn - s0);
             __syncthreads();
             for (int i = tid; i < ns; i += kP2PThreads) src[i] = bodies[ts + s0 + i];
@@ -953,34 +1064,12 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, cons
             }
         }
         // neighbouring leaves, batched through LDS
-        int pos = 0;
-        for (int sg = sg0; sg < sg1; ++sg) {
-            int2 run = segs[sg];
-            int st = run.x, cnt = run.y;
-            while (cnt > 0) {
-                const int take = min(cnt, kP2PBatch - pos);
-                if (pos == 0) __syncthreads();
-                for (int i = tid; i < take; i += kP2PThreads) src[pos + i] = bodies[st + i];
-                pos += take;
-                st += take;
-                cnt -= take;
-                if (pos == kP2PBatch) {
-                    __syncthreads();
-                    if (active) {
-                        if (COMP) p2p_batch_comp<false>(src, pos, g, G, xi, yi, zi, cmp);
-                        else p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
-                    }
-                    pos = 0;
-                }
-            }
-        }
-        if (pos > 0) {
-            __syncthreads();
+        p2p_stream_runs(segs, run_pre, pc.sg0, pc.sg1, pc.base, pc.lo, pc.hi, bodies, src, rs, [&](int ns) {
             if (active) {
-                if (COMP) p2p_batch_comp<false>(src, pos, g, G, xi, yi, zi, cmp);
-                else p2p_batch<false>(src, pos, g, G, xi, yi, zi, f, gx, gy, gz);
+                if (COMP) p2p_batch_comp<false>(src, ns, g, G, xi, yi, zi, cmp);
+                else p2p_batch<false>(src, ns, g, G, xi, yi, zi, f, gx, gy, gz);
             }
-        }
+        });
         __syncthreads();
         if (COMP) {
             red[tid] = make_float4(cmp.h[0], cmp.h[1], cmp.h[2], cmp.h[3]);
@@ -1007,9 +1096,34 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int32_t *leaves, cons
                     acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
                 }
             }
-            out[ts + t0 + tid] = acc;                // potential, gradient
+            if (npieces == 1) out[ts + t0 + tid] = acc;   // potential, gradient
+            else part[(int64_t)(item.w + piece) * kP2PThreads + tid] = acc;   // split leaves have tn <= kP2PThreads
         }
     }
+}
+
+// Sum of the pieces of every split leaf, in piece order.
+__global__ void __launch_bounds__(kP2PThreads) k_p2p_join(const int4 *items, const int32_t *leaves,
+                                                          const int32_t *c_start, const int32_t *c_count,
+                                                          const float4 *part, float4 *out, const float *part_h,
+                                                          float *out_h) {
+    const int4 item = items[blockIdx.x];
+    if (item.y != 0 || item.z == 1) return;
+    const int c = leaves[item.x];
+    const int ts = c_start[c], tn = c_count[c], t = threadIdx.x;
+    if (t >= tn) return;
+    Comp4 acc;   // compensated, so that splitting keeps the mixed-precision near field's accuracy
+    float h[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < item.z; ++j) {
+        const int64_t b = (int64_t)(item.w + j) * kP2PThreads + t;
+        const float4 v = part[b];
+        acc.add(0, v.x); acc.add(1, v.y); acc.add(2, v.z); acc.add(3, v.w);
+        if (out_h)
+            for (int q = 0; q < 6; ++q) h[q] += part_h[b * 6 + q];
+    }
+    out[ts + t] = make_float4(acc.h[0] + acc.l[0], acc.h[1] + acc.l[1], acc.h[2] + acc.l[2], acc.h[3] + acc.l[3]);
+    if (out_h)
+        for (int q = 0; q < 6; ++q) out_h[(int64_t)(ts + t) * 6 + q] = h[q];
 }
 
 // Near field with the Hessian of the potential as well (losses through grad phi):
@@ -1033,17 +1147,20 @@ __device__ __forceinline__ void p2p_batch_h(const float4 *src, int ns, int g, in
     }
 }
 
-__global__ void __launch_bounds__(kP2PThreads) k_p2p_hess(const int32_t *leaves, const int32_t *c_start,
-                                                          const int32_t *c_count, const int32_t *seg_off,
-                                                          const int2 *segs, const float4 *bodies, float4 *out,
-                                                          float *out_h) {
+__global__ void __launch_bounds__(kP2PThreads) k_p2p_hess(const int4 *items, const int32_t *leaves,
+                                                          const int32_t *c_start, const int32_t *c_count,
+                                                          const int32_t *seg_off, const int2 *segs,
+                                                          const int64_t *run_pre, const float4 *bodies, float4 *out,
+                                                          float *out_h, float4 *part, float *part_h) {
     __shared__ float4 src[kP2PBatch];
     __shared__ float red[10][kP2PThreads];
-    const int li = blockIdx.x;
+    __shared__ RunStage rs;
+    const int4 item = items[blockIdx.x];
+    const int li = item.x, piece = item.y, npieces = item.z;
     const int c = leaves[li];
     const int ts = c_start[c], tn = c_count[c];
     const int tid = threadIdx.x;
-    const int sg0 = seg_off[li], sg1 = seg_off[li + 1];
+    const P2PPiece pc = p2p_piece(seg_off, run_pre, li, piece, npieces);
     for (int t0 = 0; t0 < tn; t0 += kP2PThreads) {
         const int nt = min(kP2PThreads, tn - t0);
         const int G = kP2PThreads / nt;
@@ -1055,35 +1172,16 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_hess(const int32_t *leaves,
             xi = b.x; yi = b.y; zi = b.z;
         }
         float a[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (int s0 = 0; s0 < tn; s0 += kP2PBatch) {     // the target leaf itself
+        for (int s0 = 0; piece == 0 && s0 < tn; s0 += kP2PBatch) {     // the target leaf itself
             const int ns = min(kP2PBatch, tn - s0);
             __syncthreads();
             for (int i = tid; i < ns; i += kP2PThreads) src[i] = bodies[ts + s0 + i];
             __syncthreads();
             if (active) p2p_batch_h<true>(src, ns, g, G, xi, yi, zi, a);
         }
-        int pos = 0;
-        for (int sg = sg0; sg < sg1; ++sg) {
-            int2 run = segs[sg];
-            int st = run.x, cnt = run.y;
-            while (cnt > 0) {
-                const int take = min(cnt, kP2PBatch - pos);
-                if (pos == 0) __syncthreads();
-                for (int i = tid; i < take; i += kP2PThreads) src[pos + i] = bodies[st + i];
-                pos += take;
-                st += take;
-                cnt -= take;
-                if (pos == kP2PBatch) {
-                    __syncthreads();
-                    if (active) p2p_batch_h<false>(src, pos, g, G, xi, yi, zi, a);
-                    pos = 0;
-                }
-            }
-        }
-        if (pos > 0) {
-            __syncthreads();
-            if (active) p2p_batch_h<false>(src, pos, g, G, xi, yi, zi, a);
-        }
+        p2p_stream_runs(segs, run_pre, pc.sg0, pc.sg1, pc.base, pc.lo, pc.hi, bodies, src, rs, [&](int ns) {
+            if (active) p2p_batch_h<false>(src, ns, g, G, xi, yi, zi, a);
+        });
         __syncthreads();
         for (int q = 0; q < 10; ++q) red[q][tid] = a[q];
         __syncthreads();
@@ -1093,8 +1191,15 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_hess(const int32_t *leaves,
                 acc[q] = red[q][tid];
                 for (int gg = 1; gg < G; ++gg) acc[q] += red[q][gg * nt + tid];
             }
-            out[ts + t0 + tid] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-            for (int q = 0; q < 6; ++q) out_h[(int64_t)(ts + t0 + tid) * 6 + q] = acc[4 + q];
+            const float4 v = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            if (npieces == 1) {
+                out[ts + t0 + tid] = v;
+                for (int q = 0; q < 6; ++q) out_h[(int64_t)(ts + t0 + tid) * 6 + q] = acc[4 + q];
+            } else {
+                const int64_t b = (int64_t)(item.w + piece) * kP2PThreads + tid;
+                part[b] = v;
+                for (int q = 0; q < 6; ++q) part_h[b * 6 + q] = acc[4 + q];
+            }
         }
     }
 }
@@ -1187,18 +1292,29 @@ static void launch_near(fmm_plan_s *Pl, int phases, bool hess, hipStream_t s) {
     HIP_CHECK(hipStreamWaitEvent(Pl->side, Pl->ev_fork, 0));
     ev_rec(Pl, 2 * PH_P2P, Pl->side);
     if ((phases & FMM_NEAR) && hess) {
-        hipLaunchKernelGGL(k_p2p_hess, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
-                           (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                           (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4, Pl->nearh);
+        hipLaunchKernelGGL(k_p2p_hess, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
+                           (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
+                           (const int32_t *)Pl->seg_off, (const int2 *)Pl->segs, (const int64_t *)Pl->run_pre,
+                           (const float4 *)Pl->bodies, Pl->near4, Pl->nearh, Pl->p2p_part, Pl->p2p_part_h);
+        if (Pl->np2p_part > 0)
+            hipLaunchKernelGGL(k_p2p_join, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
+                               (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
+                               (const float4 *)Pl->p2p_part, Pl->near4, (const float *)Pl->p2p_part_h, Pl->nearh);
     } else if (phases & FMM_NEAR) {
         if (Pl->prec == FMM_PREC_MIXED)
-            hipLaunchKernelGGL(k_p2p<true>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
-                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
+            hipLaunchKernelGGL(k_p2p<true>, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
+                               (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
+                               (const int32_t *)Pl->seg_off, (const int2 *)Pl->segs, (const int64_t *)Pl->run_pre,
+                               (const float4 *)Pl->bodies, Pl->near4, Pl->p2p_part);
         else
-            hipLaunchKernelGGL(k_p2p<false>, (int)Pl->nleaves, kP2PThreads, 0, Pl->side, (const int32_t *)Pl->leaves,
-                               (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count, (const int32_t *)Pl->seg_off,
-                               (const int2 *)Pl->segs, (const float4 *)Pl->bodies, Pl->near4);
+            hipLaunchKernelGGL(k_p2p<false>, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
+                               (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
+                               (const int32_t *)Pl->seg_off, (const int2 *)Pl->segs, (const int64_t *)Pl->run_pre,
+                               (const float4 *)Pl->bodies, Pl->near4, Pl->p2p_part);
+        if (Pl->np2p_part > 0)
+            hipLaunchKernelGGL(k_p2p_join, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
+                               (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
+                               (const float4 *)Pl->p2p_part, Pl->near4, (const float *)nullptr, (float *)nullptr);
     } else {
         fill_f32(reinterpret_cast<float *>(Pl->near4), 0.f, 4 * Pl->n, Pl->side);
         if (hess) fill_f32(Pl->nearh, 0.f, 6 * Pl->n, Pl->side);
@@ -1326,6 +1442,7 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *he
         Pl->mem.stream = s;
         Pl->farh = Pl->mem.get_n<float>(6 * n);
         Pl->nearh = Pl->mem.get_n<float>(6 * n);
+        if (Pl->np2p_part > 0) Pl->p2p_part_h = Pl->mem.get_n<float>(Pl->np2p_part * kP2PThreads * 6);
         Pl->mem.stream = keep;
     }
     Geo g{Pl->c_start, Pl->c_count, Pl->c_level, Pl->c_ix, Pl->c_iy, Pl->c_iz, Pl->c_parent, Pl->c_child0, Pl->c_nchild,

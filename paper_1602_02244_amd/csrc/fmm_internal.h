@@ -15,6 +15,9 @@ constexpr int kMaxLevel = 21;       // 63-bit Morton keys, 21 bits per axis
 constexpr int kMaxP = 16;
 constexpr int kTileN = 64;          // M2L target cells per tile (GEMM N dimension)
 constexpr int kEntriesPerWork = 48; // M2L (tile, operator) entries per work item (split-K)
+constexpr int kP2PThreads = 256;    // near-field workgroup; a split leaf has at most this many targets
+constexpr int64_t kP2PPieceWork = int64_t(1) << 20;   // near-field interactions per piece of a split leaf
+constexpr int kP2PMaxPieces = 4096;
 
 // Coefficient count of order p and its padded length (multiple of 16: MFMA 16x16x4 blocking).
 inline int ncoef(int p) { return (p + 1) * (p + 1); }
@@ -97,6 +100,7 @@ int64_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, Alloc &a,
 int64_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Alloc &a, hipStream_t s);
 // The same without waiting: the total is written to device memory.
 void exclusive_scan_i32_to(const int32_t *in, int32_t *out, int64_t n, int64_t *tot_dev, Alloc &a, hipStream_t s);
+void exclusive_scan_i64_to(const int64_t *in, int64_t *out, int64_t n, int64_t *tot_dev, Alloc &a, hipStream_t s);
 // Stable LSD radix sort of (key, value) on the low `bits` key bits.  The sorted data end
 // in one of two buffer pairs; keys/vals are updated to point at it and the other pair
 // goes back to the allocator (no copy).
@@ -230,6 +234,11 @@ struct fmm_plan_s {
     int2 *p2p_pairs = nullptr;       // (target leaf cell, source leaf cell), sorted
     int32_t *seg_off = nullptr;      // [nleaves + 1] per target leaf (leaf order)
     int2 *segs = nullptr;            // (body start, body count) runs of source bodies, self excluded
+    int64_t *run_pre = nullptr;      // [nseg + 1] exclusive prefix of the run lengths
+    int4 *p2p_items = nullptr;       // (leaf, piece, pieces, first partial block or -1), leaf order
+    int64_t np2p_items = 0, np2p_part = 0;   // work items; partial blocks of split leaves
+    float4 *p2p_part = nullptr;      // [np2p_part][kP2PThreads] partial (potential, gradient)
+    float *p2p_part_h = nullptr;     // [np2p_part][kP2PThreads][6] partial Hessian (allocated on first use)
 
     // eval workspace
     float *M = nullptr, *L = nullptr;          // [ncells][KP]

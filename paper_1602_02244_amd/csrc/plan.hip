@@ -688,6 +688,34 @@ __global__ void k_p2p_seg_off(int64_t nl, const int32_t *pair_off, const int32_t
         seg_off[li] = li < nl ? run_id[pair_off[li]] : (int32_t)*nseg;
 }
 
+// Near-field work items: a target leaf whose list holds more than kP2PPieceWork
+// interactions (and at most kP2PThreads targets) is cut into pieces of about equal source
+// counts; lens[r] is the length of run r (0 past the last run).
+__global__ void k_p2p_run_len64(const int2 *segs, const int64_t *nseg, int64_t n, int64_t *lens) {
+    const int64_t ns = *nseg;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        lens[r] = r < ns ? (int64_t)segs[r].y : 0;
+}
+__global__ void k_p2p_split(int64_t nl, const int32_t *leaves, const int32_t *c_count, const int32_t *seg_off,
+                            const int64_t *run_pre, int32_t *pieces, int32_t *part_len) {
+    for (int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; li < nl; li += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tn = c_count[leaves[li]];
+        const int64_t S = run_pre[seg_off[li + 1]] - run_pre[seg_off[li]];
+        int64_t k = 1;
+        if (tn <= kP2PThreads && tn * S > kP2PPieceWork)
+            k = std::min<int64_t>(std::min<int64_t>(kP2PMaxPieces, S), (tn * S + kP2PPieceWork - 1) / kP2PPieceWork);
+        pieces[li] = (int32_t)k;
+        part_len[li] = k > 1 ? (int32_t)k : 0;
+    }
+}
+__global__ void k_p2p_items(int64_t nl, const int32_t *pieces, const int32_t *item_off, const int32_t *part_off,
+                            int4 *items) {
+    for (int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; li < nl; li += (int64_t)gridDim.x * blockDim.x) {
+        const int k = pieces[li], o = item_off[li], pb = k > 1 ? part_off[li] : -1;
+        for (int j = 0; j < k; ++j) items[o + j] = make_int4((int)li, j, k, pb);
+    }
+}
+
 // ----------------------------------------------------------------- host side
 static int grid1(int64_t n, int bs = 256) {
     int64_t g = (n + bs - 1) / bs;
@@ -800,9 +828,9 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     } drain{a, s};
     a.mb = &mb;
     // counted on the device, read once at the end: same-level M2L pairs, P2P interactions,
-    // near-field runs
-    unsigned long long *counts = a.get_n<unsigned long long>(3);
-    fill_i32(reinterpret_cast<int32_t *>(counts), 0, 6, s);
+    // near-field runs, near-field work items, partial blocks, total run length
+    unsigned long long *counts = a.get_n<unsigned long long>(6);
+    fill_i32(reinterpret_cast<int32_t *>(counts), 0, 12, s);
 
     // ---- a1: root cube and keys
     int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
@@ -1000,6 +1028,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             main.bytes += as.bytes;
         }
     } side{a, Alloc{}};
+    int32_t *p2p_pieces = nullptr, *p2p_part_len = nullptr, *p2p_item_off = nullptr, *p2p_part_off = nullptr;
     {
         Alloc &as = side.as;
         as.alloc = a.alloc;
@@ -1035,6 +1064,23 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         hipLaunchKernelGGL(k_p2p_seg_off, grid1(P->nleaves + 1), 256, 0, ss, (int64_t)P->nleaves,
                            (const int32_t *)pair_off, (const int32_t *)run_id, (const int64_t *)nseg_dev, P->seg_off);
         as.put(comp); as.put(dummy); as.put(pair_off);
+        // work items of the near field (heavy leaves split into pieces): counts of items and
+        // partial blocks go to counts[3], counts[4]; the items are written after the join
+        int64_t *lens = as.get_n<int64_t>(np2p + 1);
+        hipLaunchKernelGGL(k_p2p_run_len64, grid1(np2p + 1), 256, 0, ss, (const int2 *)P->segs,
+                           (const int64_t *)nseg_dev, np2p + 1, lens);
+        P->run_pre = as.get_n<int64_t>(np2p + 1);
+        exclusive_scan_i64_to(lens, P->run_pre, np2p + 1, reinterpret_cast<int64_t *>(&counts[5]), as, ss);
+        as.put(lens);
+        p2p_pieces = as.get_n<int32_t>(P->nleaves);
+        p2p_part_len = as.get_n<int32_t>(P->nleaves);
+        p2p_item_off = as.get_n<int32_t>(P->nleaves);
+        p2p_part_off = as.get_n<int32_t>(P->nleaves);
+        hipLaunchKernelGGL(k_p2p_split, grid1(P->nleaves), 256, 0, ss, (int64_t)P->nleaves, (const int32_t *)P->leaves,
+                           (const int32_t *)P->c_count, (const int32_t *)P->seg_off, (const int64_t *)P->run_pre,
+                           p2p_pieces, p2p_part_len);
+        exclusive_scan_i32_to(p2p_pieces, p2p_item_off, P->nleaves, reinterpret_cast<int64_t *>(&counts[3]), as, ss);
+        exclusive_scan_i32_to(p2p_part_len, p2p_part_off, P->nleaves, reinterpret_cast<int64_t *>(&counts[4]), as, ss);
     }
 
     lg("traversal");
@@ -1304,13 +1350,20 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     }
     {
         const uint64_t t = mb.next_ticket();
-        publish(counts, 24, mb, t, s);
+        publish(counts, 48, mb, t, s);
         mb.wait(t, s);
         P->nm2l_same = (int64_t)mb.data_host<uint64_t>()[0];
         P->p2p_interactions = (int64_t)mb.data_host<uint64_t>()[1];
         P->nseg = (int64_t)mb.data_host<uint64_t>()[2];
+        P->np2p_items = (int64_t)mb.data_host<uint64_t>()[3];
+        P->np2p_part = (int64_t)mb.data_host<uint64_t>()[4];
         if (P->nseg >= (int64_t)INT32_MAX) fail(FMM_EUNSUPPORTED, "near-field run count exceeds 2^31");
+        if (P->np2p_items >= (int64_t)INT32_MAX) fail(FMM_EUNSUPPORTED, "near-field work items exceed 2^31");
     }
+    P->p2p_items = a.get_n<int4>(P->np2p_items);
+    hipLaunchKernelGGL(k_p2p_items, grid1(P->nleaves), 256, 0, s, (int64_t)P->nleaves, (const int32_t *)p2p_pieces,
+                       (const int32_t *)p2p_item_off, (const int32_t *)p2p_part_off, P->p2p_items);
+    if (P->np2p_part > 0) P->p2p_part = a.get_n<float4>(P->np2p_part * kP2PThreads);
     a.put(counts);
     HIP_CHECK(hipStreamSynchronize(s));
     lg("workspace");

@@ -375,6 +375,13 @@ void exclusive_scan_i32_to(const int32_t *in, int32_t *out, int64_t n, int64_t *
     }
     scan_rec<int32_t>(in, out, n, a, s, tot_dev);
 }
+void exclusive_scan_i64_to(const int64_t *in, int64_t *out, int64_t n, int64_t *tot_dev, Alloc &a, hipStream_t s) {
+    if (n <= 0) {
+        fill_i32(reinterpret_cast<int32_t *>(tot_dev), 0, 2, s);
+        return;
+    }
+    scan_rec<int64_t>(in, out, n, a, s, tot_dev);
+}
 
 // ------------------------------------------------------------------ radix sort
 // LSD radix sort, 8-bit digits.  Per pass: (1) per-tile digit histogram, stored
