@@ -220,21 +220,6 @@ struct CellView {
     int lists;                // 0: rule 3 splits both cells; 1: only the smaller prefix (level skip)
 };
 
-// MAC: accept A <- B iff A != B and theta*|c_A - c_B| >= R_A + R_B (R = half side),
-// exactly: centres and radii are integers in units of the finer cell's half side.
-__device__ inline bool mac_accept(const CellView &C, int a, int b, double theta2) {
-    if (a == b) return false;
-    int la = C.level[a], lb = C.level[b];
-    int lf = la > lb ? la : lb;
-    int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
-    int64_t dx = (2 * (int64_t)C.ix[a] + 1) * sa - (2 * (int64_t)C.ix[b] + 1) * sb;
-    int64_t dy = (2 * (int64_t)C.iy[a] + 1) * sa - (2 * (int64_t)C.iy[b] + 1) * sb;
-    int64_t dz = (2 * (int64_t)C.iz[a] + 1) * sa - (2 * (int64_t)C.iz[b] + 1) * sb;
-    int64_t d2 = dx * dx + dy * dy + dz * dz;
-    int64_t s = sa + sb;
-    return theta2 * (double)d2 >= (double)(s * s);
-}
-
 __device__ inline int wave_incl_scan(int v) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -262,6 +247,48 @@ __device__ inline void block_scan3(int v0, int v1, int v2, int &e0, int &e1, int
     e1 = p1 + i1 - v1;
     e2 = p2 + i2 - v2;
     __syncthreads();
+}
+
+__device__ inline uint64_t key_hash(uint64_t k) {   // splitmix64 finaliser
+    k ^= k >> 30; k *= 0xbf58476d1ce4e5b9ull;
+    k ^= k >> 27; k *= 0x94d049bb133111ebull;
+    k ^= k >> 31;
+    return k;
+}
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ inline uint64_t pair_key(const CellView &C, int a, int b, int32_t *overflow) {
+    int la = C.level[a], lb = C.level[b];
+    int lf = la > lb ? la : lb;
+    int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
+    // D = c_B - c_A in units of the finer half side
+    int64_t nx = (2 * (int64_t)C.ix[b] + 1) * sb - (2 * (int64_t)C.ix[a] + 1) * sa;
+    int64_t ny = (2 * (int64_t)C.iy[b] + 1) * sb - (2 * (int64_t)C.iy[a] + 1) * sa;
+    int64_t nz = (2 * (int64_t)C.iz[b] + 1) * sb - (2 * (int64_t)C.iz[a] + 1) * sa;
+    if (nx < -kKeyOffBias || nx >= kKeyOffBias || ny < -kKeyOffBias || ny >= kKeyOffBias || nz < -kKeyOffBias ||
+        nz >= kKeyOffBias) {
+        *overflow = 1;
+        return 0;
+    }
+    return pack_key(lb - la, nx, ny, nz);
+}
+
+// Insert a key into the open-addressing table (linear probing, at most `mask + 1`
+// probes; a full table raises flags[1]); returns its slot.
+__device__ inline int32_t key_slot(uint64_t key, uint64_t *table, uint64_t mask, int32_t *flags) {
+    uint64_t h = key_hash(key) & mask;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+        const uint64_t cur = table[h];
+        if (cur == key) return (int32_t)h;
+        if (cur == kEmpty) {
+            const uint64_t prev = atomicCAS((unsigned long long *)&table[h], (unsigned long long)kEmpty,
+                                            (unsigned long long)key);
+            if (prev == kEmpty || prev == key) return (int32_t)h;
+        }
+        h = (h + 1) & mask;
+    }
+    flags[1] = 1;
+    return (int32_t)h;
 }
 
 // One traversal step.  Every pair of `front` needs a split; its child pairs (rules 3-4)
@@ -317,35 +344,80 @@ __global__ void k_set_counters(unsigned long long *cnt, int64_t nm, int64_t np) 
     }
 }
 
-__device__ inline int action(const CellView &C, int a, int b, double theta2) {
-    if (mac_accept(C, a, b, theta2)) return 0;
-    if (C.nchild[a] == 0 && C.nchild[b] == 0) return 1;
-    return 2;
-}
-
 // Each wave takes kTravPerWave frontier pairs in turn, one lane per child pair (at most
-// 8 x 8); the lane keeps its outcomes, the block reserves its output ranges once.
+// 8 x 8); the lane keeps its outcomes, the block reserves its output ranges once.  The
+// frontier pair and its split are wave-uniform; the data of the children are loaded once
+// (lanes 0-7: children of A, lanes 8-15: children of B) and passed on by cross-lane
+// shuffles.  An M2L pair also marks its target and enters its operator key into the key
+// table (the slot is stored beside the pair).
+struct TravOut {
+    int2 *m2l;
+    int32_t *m2l_slot;
+    int64_t cap_m;
+    int2 *p2p;
+    int64_t cap_p;
+    int2 *next;
+    int64_t cap_n;
+    uint64_t *table;      // operator-key table, mask + 1 slots
+    uint64_t mask;
+    int32_t *flags;       // key out of range, table full
+    int32_t *is_target;   // [ncells] the cell is the target of an M2L pair
+};
 constexpr int kTravPerWave = 8;
 __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front, int64_t nf, double theta2,
-                                                   unsigned long long *cnt, int2 *m2l, int64_t cap_m, int2 *p2p,
-                                                   int64_t cap_p, int2 *next, int64_t cap_n) {
-    const int64_t f0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6)) * kTravPerWave;
+                                                   unsigned long long *cnt, TravOut o) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t f0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + wave) * kTravPerWave;
     const int lane = threadIdx.x & 63, x = lane >> 3, y = lane & 7;
     int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave];
+    uint64_t key[kTravPerWave];
     int m = 0, q = 0, nx = 0;
 #pragma unroll
     for (int k = 0; k < kTravPerWave; ++k) {
         const int64_t f = f0 + k;
         pa[k] = pb[k] = 0;
         act[k] = -1;
+        key[k] = 0;
         if (f < nf) {
             int a0, na, b0, nb;
             const int2 pr = front[f];
-            split_ranges(C, pr.x, pr.y, a0, na, b0, nb);
+            split_ranges(C, __builtin_amdgcn_readfirstlane(pr.x), __builtin_amdgcn_readfirstlane(pr.y), a0, na, b0,
+                         nb);
+            const bool ld = lane < 8 ? lane < na : (lane < 16 && lane - 8 < nb);
+            const int cell = lane < 8 ? a0 + lane : b0 + (lane - 8);
+            int lv = 0, cx = 0, cy = 0, cz = 0, ch = 0;
+            if (ld) {
+                lv = C.level[cell];
+                cx = C.ix[cell];
+                cy = C.iy[cell];
+                cz = C.iz[cell];
+                ch = C.nchild[cell];
+            }
+            const int la = __shfl(lv, x, 64), ax = __shfl(cx, x, 64), ay = __shfl(cy, x, 64), az = __shfl(cz, x, 64),
+                      ca = __shfl(ch, x, 64);
+            const int lb = __shfl(lv, 8 + y, 64), bx = __shfl(cx, 8 + y, 64), by = __shfl(cy, 8 + y, 64),
+                      bz = __shfl(cz, 8 + y, 64), cb = __shfl(ch, 8 + y, 64);
             if (x < na && y < nb) {
                 pa[k] = a0 + x;
                 pb[k] = b0 + y;
-                act[k] = action(C, pa[k], pb[k], theta2);
+                // rule 1, the MAC: accept A <- B iff A != B and theta |c_A - c_B| >= R_A + R_B
+                // (R = half side), exactly: centres and radii in units of the finer half side
+                const int lf = la > lb ? la : lb;
+                const int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
+                const int64_t dx = (2 * (int64_t)bx + 1) * sb - (2 * (int64_t)ax + 1) * sa;
+                const int64_t dy = (2 * (int64_t)by + 1) * sb - (2 * (int64_t)ay + 1) * sa;
+                const int64_t dz = (2 * (int64_t)bz + 1) * sb - (2 * (int64_t)az + 1) * sa;
+                const int64_t d2 = dx * dx + dy * dy + dz * dz, sr = sa + sb;
+                if (pa[k] != pb[k] && theta2 * (double)d2 >= (double)(sr * sr)) {
+                    act[k] = 0;
+                    if (dx < -kKeyOffBias || dx >= kKeyOffBias || dy < -kKeyOffBias || dy >= kKeyOffBias ||
+                        dz < -kKeyOffBias || dz >= kKeyOffBias)
+                        o.flags[0] = 1;
+                    else
+                        key[k] = pack_key(lb - la, dx, dy, dz);
+                } else {
+                    act[k] = (ca == 0 && cb == 0) ? 1 : 2;   // rule 2, else rules 3-4 at the next step
+                }
             }
         }
         m += act[k] == 0;
@@ -365,9 +437,20 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
 #pragma unroll
     for (int k = 0; k < kTravPerWave; ++k) {
         const int2 v = make_int2(pa[k], pb[k]);
-        if (act[k] == 0) { if (wm < cap_m) m2l[wm] = v; ++wm; }
-        else if (act[k] == 1) { if (wq < cap_p) p2p[wq] = v; ++wq; }
-        else if (act[k] == 2) { if (wn < cap_n) next[wn] = v; ++wn; }
+        if (act[k] == 0) {
+            if (wm < o.cap_m) {
+                o.m2l[wm] = v;
+                o.m2l_slot[wm] = key_slot(key[k], o.table, o.mask, o.flags);
+            }
+            o.is_target[pa[k]] = 1;
+            ++wm;
+        } else if (act[k] == 1) {
+            if (wq < o.cap_p) o.p2p[wq] = v;
+            ++wq;
+        } else if (act[k] == 2) {
+            if (wn < o.cap_n) o.next[wn] = v;
+            ++wn;
+        }
     }
 }
 
@@ -386,51 +469,13 @@ __device__ inline void block_add_u64(unsigned long long v, unsigned long long *d
     }
 }
 
-__device__ inline uint64_t key_hash(uint64_t k) {   // splitmix64 finaliser
-    k ^= k >> 30; k *= 0xbf58476d1ce4e5b9ull;
-    k ^= k >> 27; k *= 0x94d049bb133111ebull;
-    k ^= k >> 31;
-    return k;
-}
-constexpr uint64_t kEmpty = ~0ull;
-
-__device__ inline uint64_t pair_key(const CellView &C, int a, int b, int32_t *overflow) {
-    int la = C.level[a], lb = C.level[b];
-    int lf = la > lb ? la : lb;
-    int64_t sa = int64_t(1) << (lf - la), sb = int64_t(1) << (lf - lb);
-    // D = c_B - c_A in units of the finer half side
-    int64_t nx = (2 * (int64_t)C.ix[b] + 1) * sb - (2 * (int64_t)C.ix[a] + 1) * sa;
-    int64_t ny = (2 * (int64_t)C.iy[b] + 1) * sb - (2 * (int64_t)C.iy[a] + 1) * sa;
-    int64_t nz = (2 * (int64_t)C.iz[b] + 1) * sb - (2 * (int64_t)C.iz[a] + 1) * sa;
-    if (nx < -kKeyOffBias || nx >= kKeyOffBias || ny < -kKeyOffBias || ny >= kKeyOffBias || nz < -kKeyOffBias ||
-        nz >= kKeyOffBias) {
-        *overflow = 1;
-        return 0;
-    }
-    return pack_key(lb - la, nx, ny, nz);
-}
-
-// Insert the key of every M2L pair into an open-addressing table (linear probing,
-// at most `mask + 1` probes; a full table raises flags[1]) and record the pair's slot.
+// Insert the key of every M2L pair into the table and record the pair's slot.  The
+// traversal does this as it emits the pairs; this pass rebuilds a table that filled up
+// there, at a larger size.
 __global__ void k_key_insert(const int2 *pairs, int64_t np, CellView C, uint64_t *table, uint64_t mask,
                              int32_t *pair_slot, int32_t *flags) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t key = pair_key(C, pairs[i].x, pairs[i].y, flags);
-        uint64_t h = key_hash(key) & mask;
-        bool done = false;
-        for (uint64_t probe = 0; probe <= mask; ++probe) {
-            uint64_t cur = table[h];
-            if (cur == key) { done = true; break; }
-            if (cur == kEmpty) {
-                uint64_t prev = atomicCAS((unsigned long long *)&table[h], (unsigned long long)kEmpty,
-                                          (unsigned long long)key);
-                if (prev == kEmpty || prev == key) { done = true; break; }
-            }
-            h = (h + 1) & mask;
-        }
-        pair_slot[i] = (int32_t)h;
-        if (!done) flags[1] = 1;
-    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+        pair_slot[i] = key_slot(pair_key(C, pairs[i].x, pairs[i].y, flags), table, mask, flags);
 }
 
 // Key id of every pair (from its slot), the (tile, key) presence table, and the number
@@ -492,11 +537,6 @@ __global__ void k_flag_diff(const uint64_t *keys, int64_t n, int shift, int32_t 
         flag[i] = (i == 0 || (keys[i] >> shift) != (keys[i - 1] >> shift)) ? 1 : 0;
 }
 
-
-__global__ void k_mark_targets(const int2 *pairs, int64_t np, int32_t *is_target) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
-        is_target[pairs[i].x] = 1;
-}
 
 // Boundary class of a cell: per axis, its distance (in cells of its octant, capped at 2)
 // to the low and to the high face of the root cube, 9 values per axis.  Cells of one
@@ -961,7 +1001,13 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     unsigned long long *cnt = a.get_n<unsigned long long>(3);
     fill_i32(reinterpret_cast<int32_t *>(cnt), 0, 6, s);
     int2 *m2l = nullptr, *p2p = nullptr;
-    int64_t m2l_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
+    int32_t *m2l_slot = nullptr;
+    int64_t m2l_cap = 0, slot_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
+    // operator-key table filled by the traversal (its last word holds the two flags),
+    // M2L targets marked by it
+    const uint64_t H0 = uint64_t(1) << 16;
+    uint64_t *ktable = nullptr;
+    int32_t *is_t = nullptr;
     if (nc == 1) {               // the root is a leaf: one P2P pair
         grow(a, p2p, p2p_cap, 0, 1, s);
         fill_i32(reinterpret_cast<int32_t *>(p2p), 0, 2, s);
@@ -970,7 +1016,13 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         // first guess of the list sizes (a uniform cloud at theta = 0.4 has ~450 M2L
         // pairs per cell and ~75 P2P pairs per leaf); a step that overflows is repeated
         grow(a, m2l, m2l_cap, 0, 512 * nc, s);
+        grow(a, m2l_slot, slot_cap, 0, m2l_cap, s);
         grow(a, p2p, p2p_cap, 0, 96 * P->nleaves + 64, s);
+        ktable = a.get_n<uint64_t>((int64_t)H0 + 1);
+        HIP_CHECK(hipMemsetAsync(ktable, 0xff, 8 * H0, s));
+        fill_i32(reinterpret_cast<int32_t *>(ktable + H0), 0, 2, s);
+        is_t = a.get_n<int32_t>(nc);
+        fill_i32(is_t, 0, nc, s);
         int2 *front = a.get_n<int2>(1);
         fill_i32(reinterpret_cast<int32_t *>(front), 0, 2, s);
         int64_t nf = 1;
@@ -978,6 +1030,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             // steady state of a uniform tree: ~8 split pairs, ~56 M2L and ~8 P2P pairs per split pair
             int64_t cap_n = std::max<int64_t>(1024, std::min<int64_t>(64 * nf, 10 * nf));
             grow(a, m2l, m2l_cap, nm2l, nm2l + 64 * nf, s);
+            grow(a, m2l_slot, slot_cap, nm2l, m2l_cap, s);
             grow(a, p2p, p2p_cap, np2p, np2p + 12 * nf, s);
             int2 *next = a.get_n<int2>(cap_n);
             uint64_t h3[3];
@@ -986,8 +1039,9 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                 const int64_t tb = (nf + per_block - 1) / per_block;
                 if (tb >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "traversal frontier too large");
                 const uint64_t t = mb.next_ticket();
-                hipLaunchKernelGGL(k_trav_step, (int)tb, 256, 0, s, C, (const int2 *)front, nf, theta2,
-                                   cnt, m2l, m2l_cap, p2p, p2p_cap, next, cap_n);
+                const TravOut to{m2l, m2l_slot, m2l_cap, p2p, p2p_cap, next, cap_n, ktable, H0 - 1,
+                                 reinterpret_cast<int32_t *>(ktable + H0), is_t};
+                hipLaunchKernelGGL(k_trav_step, (int)tb, 256, 0, s, C, (const int2 *)front, nf, theta2, cnt, to);
                 hipLaunchKernelGGL(k_trav_post, 1, 64, 0, s, cnt, mb.data_dev<unsigned long long>(), mb.flag_dev(), t);
                 mb.wait(t, s);
                 std::memcpy(h3, mb.data_host<uint64_t>(), sizeof(h3));
@@ -996,6 +1050,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                 if (attempt > 0) fail(FMM_EDEVICE, "traversal step overflowed twice");
                 hipLaunchKernelGGL(k_set_counters, 1, 64, 0, s, cnt, nm2l, np2p);
                 grow(a, m2l, m2l_cap, nm2l, (int64_t)h3[0], s);
+                grow(a, m2l_slot, slot_cap, nm2l, m2l_cap, s);
                 grow(a, p2p, p2p_cap, np2p, (int64_t)h3[1], s);
                 if ((int64_t)h3[2] > cap_n) {
                     a.put(next);
@@ -1087,10 +1142,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     // ---- M2L keys, operators, tiles, entries
     if (nm2l > 0) {
         if (nm2l >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "more than 2^31 M2L pairs");
-        // target tiles
-        int32_t *is_t = a.get_n<int32_t>(nc);
-        fill_i32(is_t, 0, nc, s);
-        hipLaunchKernelGGL(k_mark_targets, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, is_t);
+        // target tiles (targets marked by the traversal)
         int32_t *cell_tile = a.get_n<int32_t>(nc), *cell_lane = a.get_n<int32_t>(nc);
         std::vector<int32_t> btile;
         int64_t ntiles = tile_cells(C, nc, is_t, true, true, a, s, P->tile_targets, cell_tile, cell_lane, btile, P->ntargets);
@@ -1099,18 +1151,21 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         lg("m2l target tiles");
 
         // distinct operator keys through a device hash table; every pair keeps its slot
-        // (the table's last word holds the two flags: key out of range, table full)
-        uint64_t H = 1 << 15;
-        int32_t *pkid = a.get_n<int32_t>(nm2l);
-        uint64_t *table = nullptr;
+        // (the table's last word holds the two flags: key out of range, table full).  The
+        // traversal has filled the first table; a fuller one is rebuilt larger from the pairs.
+        uint64_t H = H0;
+        int32_t *pkid = m2l_slot;
+        uint64_t *table = ktable;
         std::vector<uint64_t> htab;
         for (;;) {
-            table = a.get_n<uint64_t>((int64_t)H + 1);
-            HIP_CHECK(hipMemsetAsync(table, 0xff, 8 * H, s));
+            if (!table) {
+                table = a.get_n<uint64_t>((int64_t)H + 1);
+                HIP_CHECK(hipMemsetAsync(table, 0xff, 8 * H, s));
+                fill_i32(reinterpret_cast<int32_t *>(table + H), 0, 2, s);
+                hipLaunchKernelGGL(k_key_insert, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, table, H - 1,
+                                   pkid, reinterpret_cast<int32_t *>(table + H));
+            }
             int32_t *flags = reinterpret_cast<int32_t *>(table + H);
-            fill_i32(flags, 0, 2, s);
-            hipLaunchKernelGGL(k_key_insert, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, table, H - 1, pkid,
-                               flags);
             int32_t hf[2];
             htab.resize(H);
             if ((int64_t)(8 * (H + 1)) <= Mailbox::kFetchBytes) {
@@ -1127,6 +1182,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             for (uint64_t v : htab) used += v != ~0ull;
             if (!hf[1] && 2 * used <= (int64_t)H) break;
             a.put(table);
+            table = nullptr;
             H *= 4;
         }
         std::vector<uint64_t> hkeys;
