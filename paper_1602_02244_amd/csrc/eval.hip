@@ -193,8 +193,8 @@ typedef __attribute__((address_space(1))) const floatx4 gfloatx4;   // global-me
 //              loaded one k chunk (16 coefficients of every source) per k chunk of entry e
 //              (the source index reaches the loading lane by a cross-lane shuffle; empty
 //              columns load row 0 and are zeroed when stored to LDS);
-//   entry e:   T streams one k chunk ahead of its MFMAs, and the last chunk prefetches
-//              chunk 0 of entry e+1's operator.
+//   entry e:   T streams two k chunks ahead of its MFMAs (one when there is a single
+//              chunk), and the last chunks prefetch the first ones of entry e+1's operator.
 // Column blocks with no source in an entry (mask bit clear; MASKED only) are skipped.
 //
 // The same kernel runs M2L (all levels at once, split into work items), M2M (per
@@ -277,10 +277,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
     const float *Tc = reinterpret_cast<const float *>(key_ptr[key0]);
     rows_of(key0, rm);
     int mask = mask_of(e0);
-    floatx4 a[RBW], an[RBW];
+    constexpr bool T2 = NKC >= 2;   // the operator streams two k chunks ahead of its MFMAs
+    floatx4 a[RBW], an[RBW], ann[RBW];
 #pragma unroll
-    for (int r = 0; r < RBW; ++r) a[r] = an[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < RBW; ++r) a[r] = an[r] = ann[r] = floatx4{0.f, 0.f, 0.f, 0.f};
     t_chunk_v(Tc, 0, rm, a);
+    if (T2) t_chunk_v(Tc, 1, rm, an);
     int idx = entry_src[(int64_t)clampe(e0 + 1) * kTileN + lane];
     int key_n = entry_key[clampe(e0 + 1)];
     int mask_n = mask_of(clampe(e0 + 1));
@@ -307,8 +309,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         mask_n = mask_of(clampe(e + 2));
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
-            if (kc + 1 < NKC) t_chunk_v(Tc, kc + 1, rm, an);
-            else t_chunk_v(Tn, 0, rmn, an);
+            if (T2) {
+                if (kc + 2 < NKC) t_chunk_v(Tc, kc + 2, rm, ann);
+                else t_chunk_v(Tn, kc + 2 - NKC, rmn, ann);
+            } else {
+                if (kc + 1 < NKC) t_chunk_v(Tc, kc + 1, rm, an);
+                else t_chunk_v(Tn, 0, rmn, an);
+            }
             gather_piece(kc, used_n);            // entry e+1 (a repeat of the last entry at the end)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
@@ -325,7 +332,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
                 }
             }
 #pragma unroll
-            for (int r = 0; r < RBW; ++r) a[r] = an[r];
+            for (int r = 0; r < RBW; ++r) {
+                a[r] = an[r];
+                if (T2) an[r] = ann[r];
+            }
         }
         Tc = Tn;
 #pragma unroll
