@@ -33,7 +33,7 @@ M2L_TRAFFIC = {"kernel_sha256": "705cbab550672744", "workload": "uniform-1M", "p
                "entries": 285444, "work_items": 4556, "bytes": 15.36e9}
 VALU_FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X FP32 vector with packed (2-wide) FMA
 VALU_FP32_PEAK_TFLOPS = 78.6           # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 not used
-P2P_ISSUE_PEAK_TFLOPS = 46.3           # the same lanes at 17 issue slots per 20-flop interaction
+P2P_ISSUE_PEAK_TFLOPS = 47.6           # the same lanes at 16.5 issue slots per 20-flop interaction
 
 
 def parse():
