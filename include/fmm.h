@@ -157,6 +157,33 @@ fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potent
 fmm_status fmm_adjoint_ex(fmm_plan_t plan, const float *charges, const float *dL_dphi, const float *dL_dgrad,
                           float *dL_dq, float *dL_dx, void *stream);
 
+/*
+ * Separate target set: the field of ns charged sources at nt target points that need not
+ * be sources (the potential evaluation of Sec. 1 with distinct source and target sets).
+ *
+ * fmm_plan_targets: sources [ns][3], targets [nt][3] (device, FP32); other arguments as
+ * in fmm_plan.  The plan is built over the union of the two sets (sources first): a
+ * target carries zero charge, so it adds nothing to the field, and a source and a target
+ * at the same position do not interact (the coincident-point rule).  Plans built this way
+ * are used only with the two calls below (FMM_EINVAL otherwise, and for plain plans).
+ *
+ * fmm_eval_targets: charges [ns] -> potential [nt], gradient [nt][3] (either may be NULL,
+ * not both).
+ *
+ * fmm_adjoint_targets: the exact adjoint of L(phi, grad phi at the targets) for the frozen
+ * plan, with dL_dphi [nt] and, optionally, dL_dgrad [nt][3] (NULL: L depends on phi only).
+ * Outputs dL_dq [ns], dL_dx_src [ns][3] (source positions) and dL_dx_tgt [nt][3] (target
+ * positions); each may be NULL.  gradient_fwd [nt][3] is the forward gradient at the
+ * targets (NULL: recomputed); it is not used when dL_dgrad is given.  On the union the
+ * loss weights of the sources are zero, so these are fmm_adjoint and fmm_adjoint_ex of
+ * the union problem restricted to the two sets: two evaluations, or five with dL_dgrad.
+ */
+fmm_status fmm_plan_targets(const float *sources, int64_t ns, const float *targets, int64_t nt, int ncrit, int p,
+                            float theta, fmm_precision prec, void *stream, fmm_plan_t *out);
+fmm_status fmm_eval_targets(fmm_plan_t plan, const float *charges, float *potential, float *gradient, void *stream);
+fmm_status fmm_adjoint_targets(fmm_plan_t plan, const float *charges, const float *gradient_fwd, const float *dL_dphi,
+                               const float *dL_dgrad, float *dL_dq, float *dL_dx_src, float *dL_dx_tgt, void *stream);
+
 /* Plan statistics (host struct, filled synchronously from host-side copies). */
 #define FMM_MAX_LEVELS 22
 struct fmm_stats {

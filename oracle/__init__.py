@@ -104,6 +104,19 @@ def direct(points, q, targets=None):
     return phi, grad
 
 
+def direct_targets(sources, q, targets):
+    """Field of source charges at separate target positions (FP64):
+    phi(y_t) = sum_j q_j / |y_t - x_j| over the sources with x_j != y_t, and its gradient in y_t.
+    The direct sum over the union of the two sets, the targets carrying zero charge, taken
+    at the target rows: target-target terms vanish and j != i never excludes a source."""
+    src = _d(sources).reshape(-1, 3)
+    tgt = _d(targets).reshape(-1, 3)
+    ns, nt = src.shape[0], tgt.shape[0]
+    union = np.concatenate([src, tgt])
+    qu = np.concatenate([_d(q).reshape(-1), np.zeros(nt)])
+    return direct(union, qu, targets=np.arange(ns, ns + nt, dtype=np.int64))
+
+
 # ---- single operators (Cartesian Taylor basis) --------------------------------
 
 def num_coeffs(p: int) -> int:

@@ -79,6 +79,10 @@ def load_library():
     lib.fmm_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.fmm_eval_hessian.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.fmm_adjoint_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.fmm_plan_targets.argtypes = [_vp, C.c_int64, _vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, _vp,
+                                     C.POINTER(_vp)]
+    lib.fmm_eval_targets.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    lib.fmm_adjoint_targets.argtypes = [_vp] + [_vp] * 8
     lib.fmm_plan_stats.argtypes = [_vp, C.POINTER(FmmStats)]
     lib.fmm_plan_export.argtypes = [_vp] + [_vp] * 8
     lib.fmm_plan_set_timing.argtypes = [_vp, C.c_int]
@@ -86,7 +90,8 @@ def load_library():
     lib.fmm_plan_destroy.argtypes = [_vp]
     lib.fmm_plan_destroy.restype = None
     for f in ("fmm_set_allocator", "fmm_plan", "fmm_plan_ex", "fmm_eval", "fmm_eval_ex", "fmm_adjoint",
-              "fmm_eval_hessian", "fmm_adjoint_ex", "fmm_plan_stats",
+              "fmm_eval_hessian", "fmm_adjoint_ex", "fmm_plan_targets", "fmm_eval_targets",
+              "fmm_adjoint_targets", "fmm_plan_stats",
               "fmm_plan_export", "fmm_plan_set_timing", "fmm_plan_phase_times"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -262,6 +267,104 @@ class FMM:
         ms = (C.c_float * FMM_NUM_PHASES)()
         _check(load_library().fmm_plan_phase_times(self._handle(), ms))
         return dict(zip(PHASES, [float(v) for v in ms]))
+
+
+def _opt_ptr(t):
+    return _vp(t.data_ptr()) if t is not None else None
+
+
+class FMMTargets(FMM):
+    """A plan for separate sources [ns, 3] and targets [nt, 3]: the fields of the source
+    charges at the targets (a target at a source's position skips that source).
+
+    The octree and lists are those of the union point set (sources first); the targets carry
+    no charge.  Only eval / adjoint below apply; the introspection calls see the union.
+    """
+
+    def __init__(self, sources, targets, ncrit=64, p=10, theta=0.4, precision="fp32"):
+        lib = load_library()
+        for name, t in (("sources", sources), ("targets", targets)):
+            if t.dim() != 2 or t.shape[1] != 3:
+                raise ValueError(f"{name} must have shape [n, 3]")
+        self.ns, self.nt = int(sources.shape[0]), int(targets.shape[0])
+        if self.ns < 1 or self.nt < 1:
+            raise ValueError("EINVAL: ns and nt must be >= 1")
+        ps = _dev_ptr(sources, "sources", (3,), self.ns)
+        pt = _dev_ptr(targets, "targets", (3,), self.nt)
+        if precision not in _PREC:
+            raise ValueError(f"precision must be one of {list(_PREC)}")
+        self.n = self.ns + self.nt
+        self.ncrit, self.p, self.theta, self.precision = int(ncrit), int(p), float(theta), precision
+        self.m2l_tol, self.lists = 0.0, "dual"
+        self.device = sources.device
+        h = _vp()
+        _check(lib.fmm_plan_targets(ps, self.ns, pt, self.nt, self.ncrit, self.p, C.c_float(self.theta),
+                                    _PREC[precision], _stream_handle(), C.byref(h)))
+        self._h = h
+
+    def eval(self, charges, gradient=True):
+        """Potential [nt] and (optionally) its gradient [nt, 3] at the targets."""
+        q = _dev_ptr(charges, "charges", (), self.ns)
+        phi = torch.empty(self.nt, device=self.device, dtype=torch.float32)
+        grad = torch.empty(self.nt, 3, device=self.device, dtype=torch.float32) if gradient else None
+        _check(load_library().fmm_eval_targets(self._handle(), q, _vp(phi.data_ptr()), _opt_ptr(grad),
+                                               _stream_handle()))
+        return phi, grad
+
+    def eval_hessian(self, charges):
+        raise ValueError("EINVAL: the Hessian at separate targets is not provided")
+
+    def adjoint(self, charges, dL_dphi, gradient_fwd=None, dL_dgrad=None, want_dq=True, want_dx_src=True,
+                want_dx_tgt=True):
+        """(dL/dq [ns], dL/dx_src [ns, 3], dL/dx_tgt [nt, 3]) for L(phi, grad phi) at the
+        targets, with w = dL_dphi [nt] and, when given, g = dL_dgrad [nt, 3]."""
+        q = _dev_ptr(charges, "charges", (), self.ns)
+        w = _dev_ptr(dL_dphi, "dL_dphi", (), self.nt)
+        gf = _dev_ptr(gradient_fwd, "gradient_fwd", (3,), self.nt) if gradient_fwd is not None else None
+        g = _dev_ptr(dL_dgrad, "dL_dgrad", (3,), self.nt) if dL_dgrad is not None else None
+        dq = torch.empty(self.ns, device=self.device, dtype=torch.float32) if want_dq else None
+        dxs = torch.empty(self.ns, 3, device=self.device, dtype=torch.float32) if want_dx_src else None
+        dxt = torch.empty(self.nt, 3, device=self.device, dtype=torch.float32) if want_dx_tgt else None
+        _check(load_library().fmm_adjoint_targets(self._handle(), q, gf, w, g, _opt_ptr(dq), _opt_ptr(dxs),
+                                                  _opt_ptr(dxt), _stream_handle()))
+        return dq, dxs, dxt
+
+
+class FMMTargetsFunction(torch.autograd.Function):
+    """phi_t, grad_phi_t = FMM(sources, charges -> targets); backward through the adjoint on
+    a rebuilt plan."""
+
+    @staticmethod
+    def forward(ctx, sources, charges, targets, ncrit, p, theta, precision):
+        plan = FMMTargets(sources.detach(), targets.detach(), ncrit, p, theta, precision)
+        phi, grad = plan.eval(charges.detach().contiguous())
+        plan.close()
+        ctx.save_for_backward(sources, charges, targets, grad)
+        ctx.cfg = (ncrit, p, theta, precision)
+        return phi, grad
+
+    @staticmethod
+    def backward(ctx, g_phi, g_grad):
+        sources, charges, targets, grad = ctx.saved_tensors
+        need_xs, need_q, need_xt = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        through_grad = g_grad is not None and bool(torch.count_nonzero(g_grad))
+        none = (None,) * 4
+        if (g_phi is None and not through_grad) or not (need_xs or need_q or need_xt):
+            return (None, None, None) + none
+        if g_phi is None:
+            g_phi = torch.zeros(targets.shape[0], device=targets.device, dtype=torch.float32)
+        plan = FMMTargets(sources.detach(), targets.detach(), *ctx.cfg)
+        dq, dxs, dxt = plan.adjoint(charges.detach().contiguous(), g_phi.contiguous(),
+                                    gradient_fwd=None if through_grad else grad,
+                                    dL_dgrad=g_grad.contiguous() if through_grad else None, want_dq=need_q,
+                                    want_dx_src=need_xs, want_dx_tgt=need_xt)
+        plan.close()
+        return (dxs, dq, dxt) + none
+
+
+def fmm_apply_targets(sources, charges, targets, ncrit=64, p=10, theta=0.4, precision="fp32"):
+    """Differentiable FMM at separate targets: returns (phi [nt], grad phi [nt, 3])."""
+    return FMMTargetsFunction.apply(sources, charges, targets, ncrit, p, theta, precision)
 
 
 class FMMFunction(torch.autograd.Function):

@@ -169,12 +169,20 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
     return fmm_plan_ex(points, n, ncrit, p, theta, prec, 0.0, FMM_LISTS_DUAL, stream, out);
 }
 
-fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec,
-                       double m2l_tol, int lists, void *stream, fmm_plan_t *out) {
+// A plan over `points` [n][3], or (targets != NULL) over the union of n sources and nt
+// targets, sources first.
+static fmm_status plan_create(const float *points, int64_t n, const float *targets, int64_t nt, int ncrit, int p,
+                              float theta, fmm_precision prec, double m2l_tol, int lists, void *stream,
+                              fmm_plan_t *out) {
     if (!out) return set_err(FMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!points) return set_err(FMM_EINVAL, "points is NULL");
     if (n < 1) return set_err(FMM_EINVAL, "n must be >= 1");
+    if (targets && nt < 1) return set_err(FMM_EINVAL, "nt must be >= 1");
+    if (targets && n >= (int64_t(1) << 31) - 1 - nt) return set_err(FMM_EUNSUPPORTED, "ns + nt must be below 2^31 - 1");
+    const int64_t nsrc = n;
+    if (targets) n += nt;
+    else nt = 0;
     if (n >= (int64_t(1) << 31) - 1) return set_err(FMM_EUNSUPPORTED, "n must be below 2^31 - 1");
     if (ncrit < 1) return set_err(FMM_EINVAL, "ncrit must be >= 1");
     if (p < 0 || p > kMaxP) return set_err(FMM_EINVAL, "p must be in [0, 16]");
@@ -188,6 +196,8 @@ fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float t
     fmm_plan_s *P = new (std::nothrow) fmm_plan_s();
     if (!P) return set_err(FMM_ENOMEM, "host allocation failed");
     P->n = n;
+    P->nsrc = nsrc;
+    P->ntgt = nt;
     P->ncrit = ncrit;
     P->p = p;
     P->theta = theta;
@@ -210,7 +220,15 @@ fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float t
         P->side = side_stream(P->device);
         HIP_CHECK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
-        build_plan(P, points, s);
+        if (nt > 0) {   // the union point set, sources first
+            float *uni = P->mem.get_n<float>(3 * n);
+            HIP_CHECK(hipMemcpyAsync(uni, points, sizeof(float) * 3 * nsrc, hipMemcpyDeviceToDevice, s));
+            HIP_CHECK(hipMemcpyAsync(uni + 3 * nsrc, targets, sizeof(float) * 3 * nt, hipMemcpyDeviceToDevice, s));
+            build_plan(P, uni, s);   // ends with a synchronisation
+            P->mem.put(uni);
+        } else {
+            build_plan(P, points, s);
+        }
         fill_stats(P);
     });
     if (st != FMM_OK) {
@@ -221,12 +239,27 @@ fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float t
     return FMM_OK;
 }
 
+fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec,
+                       double m2l_tol, int lists, void *stream, fmm_plan_t *out) {
+    return plan_create(points, n, nullptr, 0, ncrit, p, theta, prec, m2l_tol, lists, stream, out);
+}
+
+fmm_status fmm_plan_targets(const float *sources, int64_t ns, const float *targets, int64_t nt, int ncrit, int p,
+                            float theta, fmm_precision prec, void *stream, fmm_plan_t *out) {
+    if (!targets) {
+        if (out) *out = nullptr;
+        return set_err(FMM_EINVAL, "targets is NULL");
+    }
+    return plan_create(sources, ns, targets, nt, ncrit, p, theta, prec, 0.0, FMM_LISTS_DUAL, stream, out);
+}
+
 fmm_status fmm_eval_ex(fmm_plan_t plan, const float *charges, float *potential, float *gradient, int phases,
                        void *stream) {
     if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
     if (!charges) return set_err(FMM_EINVAL, "charges is NULL");
     if (!potential && !gradient) return set_err(FMM_EINVAL, "potential and gradient are both NULL");
     if (phases < 1 || phases > 3) return set_err(FMM_EINVAL, "phases must be a non-empty subset of FMM_NEAR | FMM_FAR");
+    if (plan->ntgt > 0) return set_err(FMM_EINVAL, "a plan with a separate target set takes fmm_eval_targets");
     hipStream_t s = (hipStream_t)stream;
     return guarded([&] {
         note_stream(plan, s);
@@ -238,31 +271,34 @@ fmm_status fmm_eval(fmm_plan_t plan, const float *charges, float *potential, flo
     return fmm_eval_ex(plan, charges, potential, gradient, FMM_ALL, stream);
 }
 
+// Scratch of the adjoint evaluations (allocated on first use, on the calling stream)
+static void adjoint_scratch(fmm_plan_s *P, hipStream_t s) {
+    if (P->tmp_phi) return;
+    hipStream_t keep = P->mem.stream;
+    P->mem.stream = s;
+    P->tmp_phi = P->mem.get_n<float>(P->n);
+    P->tmp_grad = P->mem.get_n<float>(3 * P->n);
+    P->tmp_gfwd = P->mem.get_n<float>(3 * P->n);
+    P->mem.stream = keep;
+}
+
 fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradient_fwd, const float *dL_dphi,
                        float *dL_dq, float *dL_dx, void *stream) {
     if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
     if (!dL_dphi) return set_err(FMM_EINVAL, "dL_dphi is NULL");
     if (dL_dx && !charges) return set_err(FMM_EINVAL, "charges is NULL");
+    if (plan->ntgt > 0) return set_err(FMM_EINVAL, "a plan with a separate target set takes fmm_adjoint_targets");
     if (!dL_dq && !dL_dx) return FMM_OK;
     hipStream_t s = (hipStream_t)stream;
     return guarded([&] {
         fmm_plan_s *P = plan;
         note_stream(P, s);
-        if (!P->tmp_phi) {
-            hipStream_t keep = P->mem.stream;
-            P->mem.stream = s;
-            P->tmp_phi = P->mem.get_n<float>(P->n);
-            P->tmp_grad = P->mem.get_n<float>(3 * P->n);
-            P->tmp_gfwd = P->mem.get_n<float>(3 * P->n);
-            P->mem.stream = keep;
-        }
+        adjoint_scratch(P, s);
         // psi = A w and grad psi: the same FMM with charges w (A is symmetric)
         run_eval(P, dL_dphi, dL_dq ? dL_dq : P->tmp_phi, dL_dx ? P->tmp_grad : nullptr, nullptr, FMM_ALL, s);
         if (dL_dx) {
             const float *gphi = gradient_fwd;
             if (!gphi) {
-                float *scratch_phi = dL_dq ? P->tmp_phi : P->tmp_gfwd;   // potential is not needed
-                (void)scratch_phi;
                 run_eval(P, charges, nullptr, P->tmp_gfwd, nullptr, FMM_ALL, s);
                 gphi = P->tmp_gfwd;
             }
@@ -274,6 +310,7 @@ fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradi
 fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potential, float *gradient, float *hessian,
                             void *stream) {
     if (!plan || !charges || !hessian) return set_err(FMM_EINVAL, "NULL argument");
+    if (plan->ntgt > 0) return set_err(FMM_EINVAL, "a plan with a separate target set takes fmm_eval_targets");
     hipStream_t s = (hipStream_t)stream;
     return guarded([&] {
         note_stream(plan, s);
@@ -285,20 +322,96 @@ fmm_status fmm_adjoint_ex(fmm_plan_t plan, const float *charges, const float *dL
                           float *dL_dq, float *dL_dx, void *stream) {
     if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
     if (!charges || !dL_dphi || !dL_dgrad) return set_err(FMM_EINVAL, "NULL argument");
+    if (plan->ntgt > 0) return set_err(FMM_EINVAL, "a plan with a separate target set takes fmm_adjoint_targets");
     if (!dL_dq && !dL_dx) return FMM_OK;
     hipStream_t s = (hipStream_t)stream;
     return guarded([&] {
         fmm_plan_s *P = plan;
         note_stream(P, s);
-        if (!P->tmp_phi) {
-            hipStream_t keep = P->mem.stream;
-            P->mem.stream = s;
-            P->tmp_phi = P->mem.get_n<float>(P->n);
-            P->tmp_grad = P->mem.get_n<float>(3 * P->n);
-            P->tmp_gfwd = P->mem.get_n<float>(3 * P->n);
-            P->mem.stream = keep;
-        }
+        adjoint_scratch(P, s);
         run_adjoint_grad(P, charges, dL_dphi, dL_dgrad, dL_dq, dL_dx, s);
+    });
+}
+
+// ------------------------------------------------------------ separate target set
+// The union problem: charges [q; 0], loss weights [0; w] (and [0; g]); its evaluation and
+// adjoint restricted to the targets / sources are those of the two-set problem.
+namespace {
+struct TargetScratch {   // union-sized views into the plan's scratch (allocated on first use)
+    float *q, *w, *g, *phi, *grad, *dq, *dx, *gpsi;
+};
+TargetScratch target_scratch(fmm_plan_s *P, hipStream_t s) {
+    const int64_t n = P->n;
+    if (!P->tmp_u) {
+        hipStream_t keep = P->mem.stream;
+        P->mem.stream = s;
+        P->tmp_u = P->mem.get_n<float>(5 * n);   // q, w, g (or the forward gradient)
+        P->tmp_o = P->mem.get_n<float>(11 * n);  // phi, grad, dq, dx, grad psi
+        P->mem.stream = keep;
+    }
+    return TargetScratch{P->tmp_u, P->tmp_u + n, P->tmp_u + 2 * n, P->tmp_o, P->tmp_o + n, P->tmp_o + 4 * n,
+                         P->tmp_o + 5 * n, P->tmp_o + 8 * n};
+}
+// dst[0, n*w) = src placed at items [off, off + cnt), zero elsewhere
+void embed(float *dst, int64_t n, int w, const float *src, int64_t off, int64_t cnt, hipStream_t s) {
+    if (off > 0) fill_f32(dst, 0.f, off * w, s);
+    if (off + cnt < n) fill_f32(dst + (off + cnt) * w, 0.f, (n - off - cnt) * w, s);
+    HIP_CHECK(hipMemcpyAsync(dst + off * w, src, sizeof(float) * cnt * w, hipMemcpyDeviceToDevice, s));
+}
+void extract(float *dst, const float *src, int w, int64_t off, int64_t cnt, hipStream_t s) {
+    if (dst) HIP_CHECK(hipMemcpyAsync(dst, src + off * w, sizeof(float) * cnt * w, hipMemcpyDeviceToDevice, s));
+}
+}  // namespace
+
+fmm_status fmm_eval_targets(fmm_plan_t plan, const float *charges, float *potential, float *gradient, void *stream) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    if (plan->ntgt == 0) return set_err(FMM_EINVAL, "the plan has no separate target set (use fmm_eval)");
+    if (!charges) return set_err(FMM_EINVAL, "charges is NULL");
+    if (!potential && !gradient) return set_err(FMM_EINVAL, "potential and gradient are both NULL");
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        fmm_plan_s *P = plan;
+        note_stream(P, s);
+        const TargetScratch t = target_scratch(P, s);
+        embed(t.q, P->n, 1, charges, 0, P->nsrc, s);
+        run_eval(P, t.q, potential ? t.phi : nullptr, gradient ? t.grad : nullptr, nullptr, FMM_ALL, s);
+        extract(potential, t.phi, 1, P->nsrc, P->ntgt, s);
+        extract(gradient, t.grad, 3, P->nsrc, P->ntgt, s);
+    });
+}
+
+fmm_status fmm_adjoint_targets(fmm_plan_t plan, const float *charges, const float *gradient_fwd, const float *dL_dphi,
+                               const float *dL_dgrad, float *dL_dq, float *dL_dx_src, float *dL_dx_tgt,
+                               void *stream) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    if (plan->ntgt == 0) return set_err(FMM_EINVAL, "the plan has no separate target set (use fmm_adjoint)");
+    if (!charges || !dL_dphi) return set_err(FMM_EINVAL, "NULL argument");
+    if (!dL_dq && !dL_dx_src && !dL_dx_tgt) return FMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        fmm_plan_s *P = plan;
+        note_stream(P, s);
+        const int64_t n = P->n, ns = P->nsrc, nt = P->ntgt;
+        const TargetScratch t = target_scratch(P, s);
+        const bool want_dx = dL_dx_src || dL_dx_tgt;
+        embed(t.q, n, 1, charges, 0, ns, s);
+        embed(t.w, n, 1, dL_dphi, ns, nt, s);
+        if (dL_dgrad) {   // losses through grad phi: the Hessian FMM (five evaluations)
+            adjoint_scratch(P, s);
+            embed(t.g, n, 3, dL_dgrad, ns, nt, s);
+            run_adjoint_grad(P, t.q, t.w, t.g, dL_dq ? t.dq : nullptr, want_dx ? t.dx : nullptr, s);
+        } else {
+            // psi = A w_u and grad psi; dL/dx_u = w_u grad phi + q_u grad psi
+            run_eval(P, t.w, t.dq, want_dx ? t.gpsi : nullptr, nullptr, FMM_ALL, s);
+            if (want_dx) {
+                if (gradient_fwd) embed(t.g, n, 3, gradient_fwd, ns, nt, s);   // zero at sources: w is 0 there
+                else run_eval(P, t.q, nullptr, t.g, nullptr, FMM_ALL, s);
+                run_adjoint_combine(P, t.w, t.g, t.q, t.gpsi, t.dx, s);
+            }
+        }
+        extract(dL_dq, t.dq, 1, 0, ns, s);
+        extract(dL_dx_src, t.dx, 3, 0, ns, s);
+        extract(dL_dx_tgt, t.dx, 3, ns, nt, s);
     });
 }
 

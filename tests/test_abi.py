@@ -94,6 +94,24 @@ def test_null_pointers_rejected(lib):
     lib.fmm_plan_destroy(None)          # no-op
 
 
+def test_target_calls_reject_bad_arguments_before_any_device_call(lib):
+    f = lib.fmm_plan_targets
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, C.c_void_p,
+                  C.POINTER(C.c_void_p)]
+    src, tgt = C.c_void_p(0x1000), C.c_void_p(0x2000)
+    for a in ((src, 10, None, 5), (src, 10, tgt, 0), (src, 0, tgt, 5), (None, 10, tgt, 5)):
+        out = C.c_void_p(0x1)
+        assert f(*a, 64, 4, C.c_float(0.4), 0, None, C.byref(out)) == FMM_EINVAL and out.value is None
+    out = C.c_void_p(0x1)
+    assert f(src, 10, tgt, 5, 64, 4, C.c_float(0.7), 0, None, C.byref(out)) == FMM_EINVAL   # theta
+    for name, nargs in (("fmm_eval_targets", 5), ("fmm_adjoint_targets", 9)):
+        fn = getattr(lib, name)
+        fn.restype = C.c_int
+        fn.argtypes = [C.c_void_p] * nargs
+        assert fn(*([None] * nargs)) == FMM_EINVAL
+
+
 def test_allocator_pair_must_be_complete(lib):
     lib.fmm_set_allocator.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.fmm_set_allocator.restype = C.c_int

@@ -431,3 +431,41 @@ def test_adjoint_through_grad_phi_matches_finite_differences():
             xp = x.copy(); xp[j, a] += eps; xm = x.copy(); xm[j, a] -= eps
             fd = (loss(xp, q) - loss(xm, q)) / (2 * eps)
             assert abs(fd - dx[j, a]) <= 1e-5 * (1 + abs(dx[j, a]))
+
+
+# ---- separate target set ------------------------------------------------------
+
+def test_direct_targets_closed_form_and_brute_force():
+    """One unit source at the origin: phi = 1/r, grad = -y/r^3 (closed form); a target on a
+    source skips it; small random sets against a broadcast sum written out here."""
+    phi, grad = oracle.direct_targets(np.zeros((1, 3)), np.array([2.0]),
+                                      np.array([[3.0, 0, 4.0], [0, 0, 0], [1.0, 2.0, 2.0]]))
+    assert np.allclose(phi, [2 / 5, 0.0, 2 / 3], rtol=1e-15, atol=0)
+    assert np.allclose(grad[0], [-2 * 3 / 125, 0, -2 * 4 / 125], rtol=1e-15)
+    assert np.all(grad[1] == 0)
+    rng = np.random.default_rng(5)
+    x, q, y = rng.random((40, 3)), rng.standard_normal(40), rng.random((25, 3))
+    y[3] = x[7]                     # a target on a source
+    d = y[:, None, :] - x[None, :, :]
+    r = np.sqrt((d * d).sum(-1))
+    inv = np.where(r > 0, 1 / np.where(r > 0, r, 1), 0.0)
+    ephi = (q[None, :] * inv).sum(1)
+    egrad = -(q[None, :, None] * d * inv[:, :, None] ** 3).sum(1)
+    phi, grad = oracle.direct_targets(x, q, y)
+    assert np.allclose(phi, ephi, rtol=1e-13, atol=0) and np.allclose(grad, egrad, rtol=1e-12, atol=1e-12)
+
+
+def test_union_fmm_at_targets_converges_to_direct_targets():
+    """The oracle FMM on the union (zero target charges), sampled at the target rows,
+    approaches the two-set direct sum geometrically in p."""
+    x, q = inputs.make("plummer", 3000, 61)
+    y, _ = inputs.make("cube", 2000, 62)
+    xd, yd, qd = x.astype(np.float64), y.astype(np.float64), q.astype(np.float64)
+    ephi, egrad = oracle.direct_targets(xd, qd, yd)
+    plan = oracle.Plan(np.concatenate([xd, yd]), 32, 0.4)
+    qu = np.concatenate([qd, np.zeros(len(yd))])
+    errs = []
+    for p in (4, 8):
+        phi, grad, _ = plan.eval(qu, p, sample=np.arange(3000, 5000))
+        errs.append(np.linalg.norm(phi - ephi) / np.linalg.norm(ephi))
+    assert errs[1] < 1e-4 and errs[1] < errs[0] / 10
