@@ -411,9 +411,17 @@ __global__ void __launch_bounds__(64) k_split_m(const float *M, const float *nu,
 // result is scaled back (rows by rs, columns by the source's inverse scale) and added in
 // FP32.  Tiling, work items, outputs and the software pipeline (indices two entries
 // ahead, gathered sources one entry ahead spread over the k steps, operator one k step
-// ahead, global loads only) are those of k_gemm.
+// ahead, global loads only) are those of k_gemm, with NW waves: at 11 <= p <= 15 eight,
+// so that the row blocks and gather pieces of a wave fit two waves per SIMD (four waves
+// would hold one per SIMD).  Every output element sums the same terms in the same
+// order whatever NW is.
 template <int P>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 2 : 1))) k_m2l_f16(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+constexpr int f16_waves() {   // waves per workgroup of k_m2l_f16: 8 fit two waves per SIMD for 11 <= p <= 15
+    return P >= 11 && P <= 15 ? 8 : 4;
+}
+
+template <int P, int NW = f16_waves<P>()>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(P <= 10 || NW == 8 ? 2 : 1))) k_m2l_f16(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                                  const uint8_t *entry_mask, const uint64_t *key_ptr,
                                                  const _Float16 *Mh, const _Float16 *Ml, const float *sinv, float *L,
                                                  float *partial, const int32_t *tile_targets) {
@@ -421,13 +429,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
     constexpr int KP = D::KP;
     constexpr int KPH = KP + 8;                  // LDS row stride in halves
     constexpr int NRB = KP / 16;
-    constexpr int RBW = (NRB + 3) / 4;
+    constexpr int NT = 64 * NW;                  // threads
+    constexpr int RBW = (NRB + NW - 1) / NW;     // row blocks per wave (wave w: w, w + NW, ...)
     constexpr int NK32 = KP / 32;                // k steps of 32
     constexpr bool TAIL16 = (KP % 32) != 0;      // one k step of 16 at the end
     constexpr int NKS = NK32 + (TAIL16 ? 1 : 0); // k steps
     constexpr int NQ = KP / 8;                   // 16-byte pieces (8 halves) per vector
     constexpr int NG = kTileN * NQ;              // pieces per entry and half
-    constexpr int NPF = (NG + 255) / 256;
+    constexpr int NPF = (NG + NT - 1) / NT;
     static_assert(kTileN == 64, "64-column tiles");
     __shared__ __attribute__((aligned(16))) _Float16 Bh[kTileN * KPH];
     __shared__ __attribute__((aligned(16))) _Float16 Bl[kTileN * KPH];
@@ -454,7 +463,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         const ghalf8 *Hg = (const ghalf8 *)H, *Lg = (const ghalf8 *)(H + KP * KP);
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
-            const int rb = min(wave + 4 * r, NRB - 1);
+            const int rb = min(wave + NW * r, NRB - 1);
             const int off = ((rb * 16 + li) * KP + kc * 32 + 8 * lg) / 8;
             dh[r] = Hg[off];
             dl[r] = Lg[off];
@@ -466,11 +475,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
     int csrc = -1;                               // this lane's column source (wave 0)
     auto gather_src = [&](int idxv) {
 #pragma unroll
-        for (int i = 0; i < NPF; ++i) srcs[i] = __shfl(idxv, min(tid + 256 * i, NG - 1) / NQ, 64);
+        for (int i = 0; i < NPF; ++i) srcs[i] = __shfl(idxv, min(tid + NT * i, NG - 1) / NQ, 64);
         csrc = idxv;
     };
     auto gather_piece = [&](int i) {
-        const int q = min(tid + 256 * i, NG - 1) % NQ;
+        const int q = min(tid + NT * i, NG - 1) % NQ;
         const int64_t row = (int64_t)max(srcs[i], 0) * KP;
         ph[i] = reinterpret_cast<const float4 *>(Mh + row)[q];
         pl[i] = reinterpret_cast<const float4 *>(Ml + row)[q];
@@ -496,7 +505,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NPF; ++i) {
-            const int g = tid + 256 * i;
+            const int g = tid + NT * i;
             if (g < NG) {
                 const int col = g / NQ, q = g % NQ;
                 const bool ok = srcs[i] >= 0;
@@ -517,7 +526,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
             const gfloat *rs = (const gfloat *)(H + 2 * KP * KP);
 #pragma unroll
             for (int r = 0; r < RBW; ++r) {
-                const int rb = min(wave + 4 * r, NRB - 1);
+                const int rb = min(wave + NW * r, NRB - 1);
                 r4[r] = make_float4(rs[rb * 16 + 4 * lg], rs[rb * 16 + 4 * lg + 1], rs[rb * 16 + 4 * lg + 2],
                                     rs[rb * 16 + 4 * lg + 3]);
             }
@@ -536,7 +545,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
             const ghalf4 *Hg = (const ghalf4 *)H, *Lg = (const ghalf4 *)(H + KP * KP);
 #pragma unroll
             for (int r = 0; r < RBW; ++r) {
-                const int rb = min(wave + 4 * r, NRB - 1);
+                const int rb = min(wave + NW * r, NRB - 1);
                 const int off = ((rb * 16 + li) * KP + k0 + 4 * lg) / 4;
                 th[r] = Hg[off];
                 tl[r] = Lg[off];
@@ -557,7 +566,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
                 const half8 bl = *reinterpret_cast<const half8 *>(&Bl[boff]);
 #pragma unroll
                 for (int r = 0; r < RBW; ++r) {
-                    if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
+                    if (NRB % NW != 0 && wave + NW * r >= NRB) continue;
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bh, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bl, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], bh, tmp[r][cb], 0, 0, 0);
@@ -582,7 +591,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
                 const half4 bl = *reinterpret_cast<const half4 *>(&Bl[boff]);
 #pragma unroll
                 for (int r = 0; r < RBW; ++r) {
-                    if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
+                    if (NRB % NW != 0 && wave + NW * r >= NRB) continue;
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(th[r], bh, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(th[r], bl, tmp[r][cb], 0, 0, 0);
                     tmp[r][cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(tl[r], bh, tmp[r][cb], 0, 0, 0);
@@ -592,7 +601,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         // back to the FP32 basis: rows by rs, columns by the source's inverse scale
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
-            if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
+            if (NRB % NW != 0 && wave + NW * r >= NRB) continue;
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 if (!((m >> cb) & 1)) continue;
@@ -607,7 +616,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
     }
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
-        const int rb = wave + 4 * r;
+        const int rb = wave + NW * r;
         if (rb >= NRB) continue;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
@@ -1378,7 +1387,7 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
     ev_rec(Pl, 2 * PH_M2L, s);
     if (Pl->nwork > 0) {
         if (mixed)
-            hipLaunchKernelGGL(k_m2l_f16<P>, (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
+            hipLaunchKernelGGL(k_m2l_f16<P>, (int)Pl->nwork, 64 * f16_waves<P>(), 0, s, (const int4 *)Pl->work,
                                (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
                                (const uint8_t *)Pl->entry_mask, Pl->key_f16, (const _Float16 *)Pl->Mh,
                                (const _Float16 *)Pl->Ml, (const float *)Pl->Msinv, Pl->L, Pl->partial,
