@@ -478,6 +478,38 @@ __global__ void k_key_insert(const int2 *pairs, int64_t np, CellView C, uint64_t
         pair_slot[i] = key_slot(pair_key(C, pairs[i].x, pairs[i].y, flags), table, mask, flags);
 }
 
+// Occupied slots of the key table, compacted for the host: out[0] = their number,
+// out[1] = the table's flag word, out[2 + i] = the keys in no particular order (the
+// first cap of them; the host sorts them).
+__global__ void k_key_compact(const uint64_t *table, uint64_t H, uint64_t cap, unsigned long long *out) {
+    for (uint64_t h = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; h < H; h += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t v = table[h];
+        if (v != ~0ull) {
+            const unsigned long long i = atomicAdd(&out[0], 1ull);
+            if (i < cap) out[2 + i] = v;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[1] = table[H];
+}
+
+// Key id of every occupied slot: the rank of its key among the sorted distinct keys.
+__global__ void k_slot_ids(const uint64_t *table, uint64_t H, const uint64_t *keys, int64_t nkeys, int32_t *slot_id) {
+    for (uint64_t h = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; h < H; h += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t v = table[h];
+        int32_t id = -1;
+        if (v != ~0ull) {
+            int64_t lo = 0, hi = nkeys;   // first index with keys[i] >= v
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (keys[mid] < v) lo = mid + 1;
+                else hi = mid;
+            }
+            id = (int32_t)lo;
+        }
+        slot_id[h] = id;
+    }
+}
+
 // Key id of every pair (from its slot), the (tile, key) presence table, and the number
 // of pairs whose key joins cells of the same level.
 __global__ void __launch_bounds__(256) k_key_ids(const int2 *pairs, int64_t np, const int32_t *slot_id,
@@ -1156,7 +1188,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         uint64_t H = H0;
         int32_t *pkid = m2l_slot;
         uint64_t *table = ktable;
-        std::vector<uint64_t> htab;
+        std::vector<uint64_t> hkeys;
         for (;;) {
             if (!table) {
                 table = a.get_n<uint64_t>((int64_t)H + 1);
@@ -1165,34 +1197,40 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                 hipLaunchKernelGGL(k_key_insert, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, C, table, H - 1,
                                    pkid, reinterpret_cast<int32_t *>(table + H));
             }
-            int32_t *flags = reinterpret_cast<int32_t *>(table + H);
-            int32_t hf[2];
-            htab.resize(H);
-            if ((int64_t)(8 * (H + 1)) <= Mailbox::kFetchBytes) {
-                const uint64_t *ht = static_cast<const uint64_t *>(mb.fetch(table, 8 * (H + 1), s));
-                std::memcpy(htab.data(), ht, 8 * H);
-                std::memcpy(hf, ht + H, 8);
+            // the distinct keys, compacted on the device (a table holding more than H / 2
+            // of them is rebuilt larger, so cap = H / 2 keeps every key of an accepted one)
+            const uint64_t cap = H / 2;
+            unsigned long long *kc = a.get_n<unsigned long long>((int64_t)cap + 2);
+            fill_i32(reinterpret_cast<int32_t *>(kc), 0, 2, s);
+            hipLaunchKernelGGL(k_key_compact, std::min(grid1((int64_t)H), 1024), 256, 0, s, (const uint64_t *)table, H,
+                               cap, kc);
+            const int64_t kbytes = 8 * ((int64_t)cap + 2);
+            std::vector<unsigned long long> hbuf;
+            const unsigned long long *hk;
+            if (kbytes <= Mailbox::kFetchBytes) {
+                hk = static_cast<const unsigned long long *>(mb.fetch(kc, kbytes, s));
             } else {
-                HIP_CHECK(hipMemcpyAsync(htab.data(), table, 8 * H, hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
+                hbuf.resize(cap + 2);
+                HIP_CHECK(hipMemcpyAsync(hbuf.data(), kc, kbytes, hipMemcpyDeviceToHost, s));
                 HIP_CHECK(hipStreamSynchronize(s));
+                hk = hbuf.data();
             }
+            int32_t hf[2];
+            std::memcpy(hf, &hk[1], 8);
             if (hf[0]) fail(FMM_EUNSUPPORTED, "an M2L offset exceeds the key range");
-            int64_t used = 0;
-            for (uint64_t v : htab) used += v != ~0ull;
-            if (!hf[1] && 2 * used <= (int64_t)H) break;
+            const int64_t used = (int64_t)hk[0];
+            if (!hf[1] && 2 * used <= (int64_t)H) {
+                hkeys.assign(hk + 2, hk + 2 + used);
+                a.put(kc);
+                break;
+            }
+            a.put(kc);
             a.put(table);
             table = nullptr;
             H *= 4;
         }
-        std::vector<uint64_t> hkeys;
-        for (uint64_t v : htab)
-            if (v != ~0ull) hkeys.push_back(v);
         std::sort(hkeys.begin(), hkeys.end());
         const int64_t nkeys = (int64_t)hkeys.size();
-        std::vector<int32_t> hslot(H, -1);
-        for (uint64_t h = 0; h < H; ++h)
-            if (htab[h] != ~0ull) hslot[h] = (int32_t)(std::lower_bound(hkeys.begin(), hkeys.end(), htab[h]) - hkeys.begin());
         P->nkeys = nkeys;
         std::vector<int32_t> hsame(nkeys);
         P->nkeys_same = 0;
@@ -1217,8 +1255,11 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             P->key_rows = a.get_n<uint32_t>((int64_t)rows.size());
             mb.upload(P->key_rows, rows.data(), 4 * rows.size(), s);
         }
+        uint64_t *dkeys = a.get_n<uint64_t>(nkeys);
+        mb.upload(dkeys, hkeys.data(), 8 * nkeys, s);
         int32_t *slot_id = a.get_n<int32_t>((int64_t)H);
-        mb.upload(slot_id, hslot.data(), 4 * H, s);
+        hipLaunchKernelGGL(k_slot_ids, grid1((int64_t)H), 256, 0, s, (const uint64_t *)table, H, (const uint64_t *)dkeys,
+                           nkeys, slot_id);
         int32_t *dsame = a.get_n<int32_t>(nkeys);
         mb.upload(dsame, hsame.data(), 4 * nkeys, s);
         lg("m2l keys+operators");
@@ -1268,7 +1309,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             HIP_CHECK(hipStreamSynchronize(s));
         }
         a.put(dsame);
-        a.put(table); a.put(slot_id); a.put(present); a.put(entry_of); a.put(pkid);
+        a.put(table); a.put(slot_id); a.put(dkeys); a.put(present); a.put(entry_of); a.put(pkid);
         a.put(tile_first); a.put(cell_tile); a.put(cell_lane);
         lg("m2l entries");
 
@@ -1281,28 +1322,37 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         if (const char *ev = getenv("FMM_M2L_PIECE")) piece = std::max<int64_t>(1, atoll(ev));
         if (const char *ev = getenv("FMM_M2L_ITEMS")) items = std::max<int64_t>(1, atoll(ev));
         int64_t per = std::max<int64_t>(piece, (ne + items - 1) / items);
-        std::vector<std::vector<int4>> tp(ntiles);   // pieces of each tile, in entry order
-        int64_t maxp = 0;
+        // pieces of each tile: count and size (a tile split in several pieces sums them)
+        std::vector<int32_t> npc(ntiles), psz(ntiles);
+        int64_t maxp = 0, nitems = 0;
         for (int64_t t = 0; t < ntiles; ++t) {
-            int64_t e0 = htf[t], e1 = htf[t + 1];
-            int64_t cntE = e1 - e0;
-            int64_t chunks = std::max<int64_t>(1, (cntE + per - 1) / per);
-            int64_t sz = std::max<int64_t>(1, (cntE + chunks - 1) / chunks);
-            for (int64_t c0 = e0; c0 < e1; c0 += sz)
-                tp[t].push_back(make_int4((int)t, (int)c0, (int)std::min(e1, c0 + sz), chunks > 1 ? 1 : 0));
-            maxp = std::max<int64_t>(maxp, (int64_t)tp[t].size());
+            const int64_t cntE = htf[t + 1] - htf[t];
+            const int64_t chunks = std::max<int64_t>(1, (cntE + per - 1) / per);
+            const int64_t sz = std::max<int64_t>(1, (cntE + chunks - 1) / chunks);
+            npc[t] = (int32_t)((cntE + sz - 1) / sz);
+            psz[t] = (int32_t)sz;
+            maxp = std::max<int64_t>(maxp, npc[t]);
+            nitems += npc[t];
         }
-        std::vector<int4> order;
-        order.reserve(ne);
+        std::vector<int4> order;   // piece-major
+        order.reserve(nitems);
         for (int64_t k2 = 0; k2 < maxp; ++k2)
             for (int64_t t = 0; t < ntiles; ++t)
-                if (k2 < (int64_t)tp[t].size()) order.push_back(tp[t][k2]);
+                if (k2 < npc[t]) {
+                    const int c0 = htf[t] + (int)k2 * psz[t];
+                    order.push_back(make_int4((int)t, c0, std::min(htf[t + 1], c0 + psz[t]), npc[t] > 1 ? 1 : 0));
+                }
         if ((int64_t)(4 * ne) <= Mailbox::kFetchBytes) {
-            // then by the operator key of the first entry: tiles of different boundary
-            // classes hold different key sets, and the workgroups in flight should stream
-            // the same operators
+            // then by the operator key of the first entry (a stable counting sort): tiles of
+            // different boundary classes hold different key sets, and the workgroups in
+            // flight should stream the same operators
             const int32_t *hk = static_cast<const int32_t *>(mb.fetch(P->entry_key, 4 * ne, s));
-            std::stable_sort(order.begin(), order.end(), [&](const int4 &u, const int4 &v) { return hk[u.y] < hk[v.y]; });
+            std::vector<int32_t> kpos(nkeys + 1, 0);
+            for (const int4 &u : order) ++kpos[hk[u.y] + 1];
+            for (int64_t k2 = 0; k2 < nkeys; ++k2) kpos[k2 + 1] += kpos[k2];
+            std::vector<int4> by_key(order.size());
+            for (const int4 &u : order) by_key[kpos[hk[u.y]]++] = u;
+            order.swap(by_key);
         }
         {
             // the last quarter of the items, longest first: the final workgroups of the launch
@@ -1311,20 +1361,22 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             std::stable_sort(order.begin() + k0, order.end(),
                              [](const int4 &u, const int4 &v) { return u.z - u.y > v.z - v.y; });
         }
-        std::vector<int4> hw;
-        std::vector<std::vector<int32_t>> per_tile(ntiles);
+        // work items in launch order (split pieces numbered in that order), and per tile
+        // the indices of its items in launch order
+        std::vector<int4> hw(order.size());
+        std::vector<int32_t> htw(ntiles + 1, 0), htwi(order.size());
         int64_t nsplit = 0;
-        for (int4 w4 : order) {
+        for (size_t i = 0; i < order.size(); ++i) {
+            int4 w4 = order[i];
             if (w4.w) w4.w = (int)(++nsplit);
-            per_tile[w4.x].push_back((int32_t)hw.size());
-            hw.push_back(w4);
+            hw[i] = w4;
+            ++htw[w4.x + 1];
         }
-        std::vector<int32_t> htw(ntiles + 1), htwi;
-        for (int64_t t = 0; t < ntiles; ++t) {
-            htw[t] = (int32_t)htwi.size();
-            htwi.insert(htwi.end(), per_tile[t].begin(), per_tile[t].end());
+        for (int64_t t = 0; t < ntiles; ++t) htw[t + 1] += htw[t];
+        {
+            std::vector<int32_t> fillp(htw.begin(), htw.end() - 1);
+            for (size_t i = 0; i < hw.size(); ++i) htwi[fillp[hw[i].x]++] = (int32_t)i;
         }
-        htw[ntiles] = (int32_t)htwi.size();
         P->nwork = (int64_t)hw.size();
         P->work = a.get_n<int4>(P->nwork);
         P->tile_work = a.get_n<int32_t>(ntiles + 1);
