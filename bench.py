@@ -25,6 +25,7 @@ import hashlib  # noqa: E402
 import numpy as np  # noqa: E402
 
 MFMA_FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 MFMA
+MFMA_FP16_PEAK_TFLOPS = 2500.0     # MI355X dense FP16 MFMA
 # HBM bytes of one M2L launch on the uniform-1M workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
 # factors from a 1 GiB plain copy), measured with rocprofv3 on the M2L kernel source whose
 # sha256 prefix is given (the text of k_gemm in eval.hip) and on the plan's grouping (its
@@ -63,6 +64,19 @@ def m2l_kernel_sha():
     a = src.index("template <int P, bool ADD, bool MASKED")
     b = src.index("// ---", a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def m2l_roofline(precision, m2l_tflops, traffic):
+    """The M2L kernel against the MFMA peak of the type it computes in.  The split-FP16
+    form runs three FP16 products (hi hi, hi lo, lo hi) per algorithmic one."""
+    if precision == "mixed":
+        achieved = 3.0 * m2l_tflops
+        return {"kernel": "k_m2l_f16 (split-FP16 MFMA grouped GEMM, 3 products)", "bound": "mfma",
+                "achieved": achieved, "peak": MFMA_FP16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK_TFLOPS,
+                "fp32_equivalent": m2l_tflops, "traffic": None}
+    return {"kernel": "k_m2l (FP32 MFMA grouped GEMM)", "bound": "mfma", "achieved": m2l_tflops,
+            "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": m2l_tflops / MFMA_FP32_PEAK_TFLOPS,
+            "traffic": traffic}
 
 
 def m2l_traffic(workload, p, theta, st):
@@ -248,15 +262,7 @@ def main():
         "m2l_work_items": st["m2l_work_items"],
         "m2l_kept_fraction": st["m2l_kept_fraction"],
         "ncells": st["ncells"],
-        "roofline": {
-            "kernel": "k_m2l (FP32 MFMA grouped GEMM)",
-            "bound": "mfma",
-            "achieved": m2l_tflops,
-            "peak": MFMA_FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": m2l_tflops / MFMA_FP32_PEAK_TFLOPS,
-            "traffic": m2l_traffic(args.workload, p, theta, st),
-        },
+        "roofline": m2l_roofline(args.precision, m2l_tflops, m2l_traffic(args.workload, p, theta, st)),
         "p2p_roofline": {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_tflops, "peak": VALU_FP32_PEAK_TFLOPS,
                          "unit": "TFLOP/s (20 flop/interaction)", "frac": p2p_tflops / VALU_FP32_PEAK_TFLOPS,
                          "frac_of_packed_peak": p2p_tflops / VALU_FP32_PACKED_PEAK_TFLOPS,
