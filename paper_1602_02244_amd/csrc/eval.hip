@@ -184,8 +184,11 @@ typedef __attribute__((address_space(1))) const floatx4 gfloatx4;   // global-me
 
 // Workgroup = 4 waves.  Output tile: KP rows x 64 target columns, in 16x16 blocks.
 // Wave w owns row blocks w, w+4, ... and all four column blocks.  The K loop runs in
-// chunks of 16 coefficients; inside a chunk lane l feeds k = 16*kc + 4*(l/16) + s to
-// MFMA step s, for both operands, so each lane reads 4 consecutive k as one float4.
+// chunks of 16 coefficients; inside a chunk lane l feeds k = 16*kc + 4*s + l/16 to MFMA
+// step s, for both operands: the operators are stored with a 4 x 4 transpose inside
+// every 16-wide chunk of columns and the gathered vectors are written to LDS in the same
+// order, so each lane still reads its four k as one float4, and a step whose four k are
+// all padding (k >= NC, in the last chunk) is not issued.
 //
 // Software pipeline, with no branch on loaded data so that every wait is a counted one:
 //   entry e+2: source indices (lane = column), operator key and column mask are loaded;
@@ -292,8 +295,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NPF; ++i) {
+            // coefficients 16 i + 4 gsub + j go to positions 16 i + 4 j + gsub
             const float4 v = src >= 0 ? pre[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-            *reinterpret_cast<float4 *>(&Ms[gcol * KPS + 16 * i + 4 * gsub]) = v;
+            float *row = &Ms[gcol * KPS + 16 * i + gsub];
+            row[0] = v.x;
+            row[4] = v.y;
+            row[8] = v.z;
+            row[12] = v.w;
         }
         gather_src(idx);                         // entry e+1
         const int m = __builtin_amdgcn_readfirstlane(mask);
@@ -325,10 +333,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
                 for (int r = 0; r < RBW; ++r) {
                     if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
                     if (VARORD && !((rm[r] >> kc) & 1u)) continue;
+                    // step s covers k = 16 kc + 4 s .. 16 kc + 4 s + 3 (step 0 always holds a real k)
                     acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, acc[r][cb], 0, 0, 0);
-                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, acc[r][cb], 0, 0, 0);
-                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b.z, acc[r][cb], 0, 0, 0);
-                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, b.w, acc[r][cb], 0, 0, 0);
+                    if (16 * kc + 4 < D::NC)
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, acc[r][cb], 0, 0, 0);
+                    if (16 * kc + 8 < D::NC)
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b.z, acc[r][cb], 0, 0, 0);
+                    if (16 * kc + 12 < D::NC)
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, b.w, acc[r][cb], 0, 0, 0);
                 }
             }
 #pragma unroll

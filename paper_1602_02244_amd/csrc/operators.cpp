@@ -114,6 +114,18 @@ void real_matrix(int p, int RP, int KP, bool transposed, std::vector<double> &A,
             }
 }
 
+// FP32 copy of a KP x KP operator in the layout the MFMA GEMM reads: inside every
+// 16-wide chunk of columns, position 16 c + 4 a + b holds column 16 c + 4 b + a (a 4 x 4
+// transpose), so that each of the GEMM's four k steps of a chunk covers four consecutive
+// columns and a step whose columns are all padding can be left out.
+void to_gemm_layout(const std::vector<double> &A, int KP, float *dst) {
+    for (int r = 0; r < KP; ++r)
+        for (int c = 0; c < KP; c += 16)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    dst[(size_t)r * KP + c + 4 * a + b] = (float)A[(size_t)r * KP + c + 4 * b + a];
+}
+
 void build_m2l(int p, uint64_t key, std::vector<double> &A) {
     int dl;
     int64_t nx, ny, nz;
@@ -289,12 +301,12 @@ Store &store_for(int p) {
         HIP_CHECK(hipMalloc(&ptrs, sizeof(uint64_t) * 16));
         for (int o = 0; o < 8; ++o) {
             build_m2m(p, o, A);
-            for (size_t i = 0; i < A.size(); ++i) host[(size_t)o * KP * KP + i] = (float)A[i];
+            to_gemm_layout(A, KP, host.data() + (size_t)o * KP * KP);
         }
         HIP_CHECK(hipMemcpy(m2m, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice));
         for (int o = 0; o < 8; ++o) {
             build_l2l(p, o, A);
-            for (size_t i = 0; i < A.size(); ++i) host[(size_t)o * KP * KP + i] = (float)A[i];
+            to_gemm_layout(A, KP, host.data() + (size_t)o * KP * KP);
         }
         HIP_CHECK(hipMemcpy(l2l, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice));
         uint64_t hp[16];
@@ -363,7 +375,7 @@ void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uin
         auto it = s.f32.find(keys[i]);
         if (it == s.f32.end()) {
             build_m2l(p, keys[i], A);
-            for (size_t e = 0; e < A.size(); ++e) host[e] = (float)A[e];
+            to_gemm_layout(A, ncoef_pad(p), host.data());
             float *d = s.alloc_matrix();
             HIP_CHECK(hipMemcpy(d, host.data(), sizeof(float) * s.mat_floats, hipMemcpyHostToDevice));
             it = s.f32.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
