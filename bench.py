@@ -30,8 +30,8 @@ MFMA_FP16_PEAK_TFLOPS = 2500.0     # MI355X dense FP16 MFMA
 # factors from a 1 GiB plain copy), measured with rocprofv3 on the M2L kernel source whose
 # sha256 prefix is given (the text of k_gemm in eval.hip) and on the plan's grouping (its
 # entry and work-item counts); reported only while both are unchanged.
-M2L_TRAFFIC = {"kernel_sha256": "705cbab550672744", "workload": "uniform-1M", "p": 10, "theta": 0.4,
-               "entries": 285444, "work_items": 4556, "bytes": 15.36e9}
+M2L_TRAFFIC = {"kernel_sha256": "6a28cdac88939087", "workload": "uniform-1M", "p": 10, "theta": 0.4,
+               "entries": 285444, "work_items": 4556, "bytes": 15.35e9}
 VALU_FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X FP32 vector with packed (2-wide) FMA
 VALU_FP32_PEAK_TFLOPS = 78.6           # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 not used
 P2P_ISSUE_PEAK_TFLOPS = 47.6           # the same lanes at 16.5 issue slots per 20-flop interaction
