@@ -185,8 +185,8 @@ struct fmm_plan_s {
     int device = 0;
     int64_t n = 0;
     int64_t nsrc = 0, ntgt = 0;  // separate target set: n = nsrc + ntgt points, sources first (ntgt = 0: one set)
-    float *tmp_u = nullptr;      // [4n] union-sized inputs of the target-set calls (charges, weights, gradients)
-    float *tmp_o = nullptr;      // [4n] union-sized outputs of the target-set calls
+    float *tmp_u = nullptr;      // [5n] union-sized inputs of the target-set calls (charges, weights, gradients)
+    float *tmp_o = nullptr;      // [11n] union-sized outputs of the target-set calls (phi, grad, dq, dx, grad psi)
     int ncrit = 0, p = 0;
     float theta = 0;
     fmm_precision prec = FMM_PREC_FP32;
