@@ -143,35 +143,42 @@ __global__ void k_gather_bodies(const float *pts, const int32_t *perm, int64_t n
 
 // ----------------------------------------------------------------- octree
 // Leaf rule: a cell splits iff it holds more than ncrit bodies and lies above level 21.
-// Children are the non-empty octants, found by binary search in the sorted keys.
+// Children are the non-empty octants.  Eight lanes per cell: lane o finds the first body
+// of octant o by binary search in the sorted keys (the seven searches run side by side
+// instead of one after another), and the group exchanges its bounds by shuffles.
 __global__ void k_split(int64_t ncl, const int32_t *start, const int32_t *count, const uint64_t *prefix, int level,
                         int ncrit, const uint64_t *keys, int32_t *nchild, int32_t *cstart8, int32_t *ccount8) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    int s = start[i], c = count[i];
-    int nch = 0;
-    if (c > ncrit && level < kMaxLevel) {
-        int shift = 3 * (kMaxLevel - (level + 1));
-        uint64_t base = prefix[i] * 8;
-        int b[9];
-        b[0] = s;
-        b[8] = s + c;
-        for (int o = 1; o < 8; ++o) {
-            uint64_t want = base + (uint64_t)o;
+    // the stride is a multiple of 8, so the eight lanes of a group stay together
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; (t >> 3) < ncl; t += stride) {
+        const int64_t i = t >> 3;
+        const int o = (int)(t & 7);
+        const int s = start[i], c = count[i];
+        const bool split = c > ncrit && level < kMaxLevel;
+        int b = s;                       // first body of octant o
+        if (split && o > 0) {
+            const int shift = 3 * (kMaxLevel - (level + 1));
+            const uint64_t want = prefix[i] * 8 + (uint64_t)o;
             int lo = s, hi = s + c;      // first position with (key >> shift) >= want
             while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if ((keys[mid] >> shift) < want) lo = mid + 1; else hi = mid;
+                const int mid = (lo + hi) >> 1;
+                if ((keys[mid] >> shift) < want) lo = mid + 1;
+                else hi = mid;
             }
-            b[o] = lo;
+            b = lo;
         }
-        for (int o = 0; o < 8; ++o) {
-            cstart8[i * 8 + o] = b[o];
-            ccount8[i * 8 + o] = b[o + 1] - b[o];
-            nch += (b[o + 1] > b[o]);
+        int bn = __shfl_down(b, 1, 8);
+        if (o == 7) bn = s + c;
+        int nz = (split && bn > b) ? 1 : 0;
+        nz += __shfl_xor(nz, 1, 8);
+        nz += __shfl_xor(nz, 2, 8);
+        nz += __shfl_xor(nz, 4, 8);
+        if (split) {
+            cstart8[i * 8 + o] = b;
+            ccount8[i * 8 + o] = bn - b;
         }
+        if (o == 0) nchild[i] = split ? nz : 0;
     }
-    nchild[i] = nch;
 }
 
 __global__ void k_write_children(int64_t ncl, int64_t glob_base, int64_t next_base, const int32_t *nchild,
@@ -957,7 +964,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     for (int l = 0;; ++l) {
         const int64_t o0 = level_off[l], o1 = level_off[l + 1], m = o1 - o0;
         int32_t *cs8 = a.get_n<int32_t>(8 * m), *cc8 = a.get_n<int32_t>(8 * m), *off = a.get_n<int32_t>(m);
-        hipLaunchKernelGGL(k_split, grid1(m), 256, 0, s, m, (const int32_t *)P->c_start + o0,
+        hipLaunchKernelGGL(k_split, grid1(8 * m), 256, 0, s, m, (const int32_t *)P->c_start + o0,
                            (const int32_t *)P->c_count + o0, (const uint64_t *)c_prefix + o0, l, P->ncrit,
                            (const uint64_t *)keys, P->c_nchild + o0, cs8, cc8);
         const int64_t nnext = exclusive_scan_i32(P->c_nchild + o0, off, m, a, s);
