@@ -154,7 +154,7 @@ def rel_l2(a, b):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     import torch

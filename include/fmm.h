@@ -145,8 +145,8 @@ fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potent
                             void *stream);
 
 /*
- * Adjoint of a loss L(phi, grad phi) (the spec adjoint extended to losses through
- * the gradient output): given w = dL/dphi [n] and g = dL/d(grad phi) [n][3],
+ * Adjoint of a loss L(phi, grad phi) (fmm_adjoint extended to losses through the gradient
+ * output): given w = dL/dphi [n] and g = dL/d(grad phi) [n][3],
  *   dL/dq_j = psi_j - sum_a d_a phi^(a)(x_j),
  *   dL/dx_k = w_k grad phi_k + q_k grad psi_k + H_k g_k - q_k sum_a H^(a)_k e_a,
  * where psi is the FMM of the charges w, grad phi and H the gradient and Hessian of the
