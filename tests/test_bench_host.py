@@ -1,0 +1,43 @@
+"""Host logic of bench.py (no GPU): the roofline objects, the gating of the recorded HBM
+traffic figure, and the one-GPU guard."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_fp32_roofline_against_fp32_mfma_peak():
+    r = bench.m2l_roofline("fp32", 104.0, 15.35e9)
+    assert r["bound"] == "mfma" and r["peak"] == 157.3 and r["unit"] == "TFLOP/s"
+    assert r["frac"] == pytest.approx(104.0 / 157.3) and r["traffic"] == 15.35e9
+
+
+def test_mixed_roofline_counts_three_fp16_products():
+    r = bench.m2l_roofline("mixed", 89.0, 15.35e9)
+    assert r["peak"] == 2500.0 and r["achieved"] == pytest.approx(267.0)
+    assert r["fp32_equivalent"] == 89.0 and r["traffic"] is None
+
+
+def test_traffic_only_for_the_measured_kernel_and_grouping(monkeypatch):
+    t = bench.M2L_TRAFFIC
+    st = {"m2l_entries": t["entries"], "m2l_work_items": t["work_items"]}
+    assert len(bench.m2l_kernel_sha()) == 16
+    monkeypatch.setattr(bench, "m2l_kernel_sha", lambda: t["kernel_sha256"])
+    assert bench.m2l_traffic(t["workload"], t["p"], t["theta"], st) == t["bytes"]
+    assert bench.m2l_traffic(t["workload"], t["p"], 0.5, st) is None
+    assert bench.m2l_traffic("sphere-4M", t["p"], t["theta"], st) is None
+    st2 = dict(st, m2l_entries=st["m2l_entries"] + 1)
+    assert bench.m2l_traffic(t["workload"], t["p"], t["theta"], st2) is None
+    monkeypatch.setattr(bench, "m2l_kernel_sha", lambda: "0" * 16)   # the kernel changed since
+    assert bench.m2l_traffic(t["workload"], t["p"], t["theta"], st) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
