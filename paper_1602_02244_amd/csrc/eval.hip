@@ -1397,6 +1397,20 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
     fill_f32(Pl->L, 0.f, Pl->ncells * (int64_t)D::KP, s);
     if (mixed) fill_f32(reinterpret_cast<float *>(Pl->Ld), 0.f, 2 * Pl->nroot * (int64_t)D::KP, s);
     ev_rec(Pl, 2 * PH_M2L, s);
+    // mixed precision: the FP64 root-level M2L is a small launch that writes only Ld (and
+    // its partials), so it runs on the side stream (after the near field queued there)
+    // beside the main M2L launch; the main stream waits for it before reading Ld.  ev_join
+    // recorded after it still covers the near field before it.
+    const bool root_side = mixed && Pl->nwork64 > 0;
+    if (root_side) {
+        HIP_CHECK(hipEventRecord(Pl->ev_fork, s));
+        HIP_CHECK(hipStreamWaitEvent(Pl->side, Pl->ev_fork, 0));
+        hipLaunchKernelGGL((k_gemm64<P, false>), dim3((unsigned)Pl->nwork64, kSlabs), 256, 0, Pl->side,
+                           (const int4 *)Pl->work64, (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
+                           Pl->key_f64, Pl->nroot, (const float *)Pl->M, (const double *)Pl->Md, Pl->Ld, Pl->partial64,
+                           (const int32_t *)Pl->tile_targets);
+        HIP_CHECK(hipEventRecord(Pl->ev_join, Pl->side));
+    }
     if (Pl->nwork > 0) {
         if (mixed)
             hipLaunchKernelGGL(k_m2l_f16<P>, (int)Pl->nwork, 64 * f16_waves<P>(), 0, s, (const int4 *)Pl->work,
@@ -1415,11 +1429,6 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
                                (const uint8_t *)Pl->entry_mask, Pl->key_f32, (const float *)Pl->M, Pl->L, Pl->partial,
                                (const int32_t *)Pl->tile_targets);
     }
-    if (mixed && Pl->nwork64 > 0)
-        hipLaunchKernelGGL((k_gemm64<P, false>), dim3((unsigned)Pl->nwork64, kSlabs), 256, 0, s, (const int4 *)Pl->work64,
-                           (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src, Pl->key_f64, Pl->nroot,
-                           (const float *)Pl->M, (const double *)Pl->Md, Pl->Ld, Pl->partial64,
-                           (const int32_t *)Pl->tile_targets);
     ev_rec(Pl, 2 * PH_M2L + 1, s);
     ev_rec(Pl, 2 * PH_L2L, s);
     if (Pl->npartial > 0)
@@ -1427,6 +1436,7 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
                            (const int32_t *)Pl->tile_work,
                            (const int32_t *)Pl->tile_work_idx, (const int4 *)Pl->work, (const float *)Pl->partial,
                            (const int32_t *)Pl->tile_targets, D::KP, Pl->L);
+    if (root_side) HIP_CHECK(hipStreamWaitEvent(s, Pl->ev_join, 0));
     if (mixed && Pl->partial64)
         hipLaunchKernelGGL(k_m2l64_reduce, dim3((unsigned)Pl->ntiles_root, 16), 256, 0, s, Pl->ntiles_root,
                            (const int32_t *)Pl->tile_work64, (const int32_t *)Pl->tile_work_idx64,
