@@ -469,3 +469,38 @@ def test_union_fmm_at_targets_converges_to_direct_targets():
         phi, grad, _ = plan.eval(qu, p, sample=np.arange(3000, 5000))
         errs.append(np.linalg.norm(phi - ephi) / np.linalg.norm(ephi))
     assert errs[1] < 1e-4 and errs[1] < errs[0] / 10
+
+
+def test_two_set_adjoint_reduction_matches_finite_differences():
+    """L = sum_t w_t phi(y_t) for separate sources x (charges q) and targets y.  Its exact
+    derivatives by central differences of the direct sum against the one-set adjoint on the
+    union with charges [q; 0] and weights [0; w]: dL/dq = psi(x), dL/dx = q grad psi(x),
+    dL/dy = w grad phi(y), psi the field of the weights."""
+    rng = np.random.default_rng(17)
+    x, q = rng.random((12, 3)), rng.standard_normal(12)
+    y, w = rng.random((9, 3)) + 0.05, rng.standard_normal(9)
+
+    def loss(xx, qq, yy):
+        return float(np.dot(w, oracle.direct_targets(xx, qq, yy)[0]))
+
+    union = np.concatenate([x, y])
+    psi, gpsi = oracle.direct(union, np.concatenate([np.zeros(12), w]))
+    _, gphi = oracle.direct(union, np.concatenate([q, np.zeros(9)]))
+    dq, dx, dy = psi[:12], q[:, None] * gpsi[:12], w[:, None] * gphi[12:]
+    h = 1e-5
+    for j in range(12):
+        qp, qm = q.copy(), q.copy()
+        qp[j] += h
+        qm[j] -= h
+        assert (loss(x, qp, y) - loss(x, qm, y)) / (2 * h) == pytest.approx(dq[j], rel=1e-7, abs=1e-9)
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[j, a] += h
+            xm[j, a] -= h
+            assert (loss(xp, q, y) - loss(xm, q, y)) / (2 * h) == pytest.approx(dx[j, a], rel=1e-5, abs=1e-7)
+    for t in range(9):
+        for a in range(3):
+            yp, ym = y.copy(), y.copy()
+            yp[t, a] += h
+            ym[t, a] -= h
+            assert (loss(x, q, yp) - loss(x, q, ym)) / (2 * h) == pytest.approx(dy[t, a], rel=1e-5, abs=1e-7)
