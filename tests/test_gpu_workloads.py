@@ -10,6 +10,7 @@ import pytest
 import oracle
 from paper_1602_02244_amd import inputs
 from fmm_testlib import compare_plans, rel_l2
+from golden.count_lists import read_table
 
 pytestmark = pytest.mark.gpu
 
@@ -47,15 +48,22 @@ def _check(name, theta=None, counts=None, full_plan_check=True, nsample=300):
 
 
 @pytest.mark.timeout(600)
+def _complete_tree(theta):
+    """(cells, M2L pairs, near leaf pairs, distinct offsets) of a complete depth-5 octree,
+    from tests/golden/complete_tree_counts.txt (integer counting, no tree builder)."""
+    row = [r for r in read_table("complete_tree_counts.txt") if r[0] == 5 and abs(r[1] - theta) < 1e-9]
+    return tuple(row[0][2:])
+
+
 def test_uniform_1M_theta04():
     # all leaves at level 5: 37,449 cells; 16,820,208 M2L pairs over 850 offsets; 2,421,064 near pairs
-    _check("uniform-1M", counts=(37449, 16820208, 2421064, 850))
+    _check("uniform-1M", counts=_complete_tree(0.4))
 
 
 @pytest.mark.timeout(600)
 def test_uniform_1M_theta05_classical_lists():
     # theta = 1/2 reproduces the classical interaction list: 316 distinct offsets
-    _check("uniform-1M", theta=0.5, counts=(37449, 6039504, 830584, 316))
+    _check("uniform-1M", theta=0.5, counts=_complete_tree(0.5))
 
 
 @pytest.mark.timeout(900)

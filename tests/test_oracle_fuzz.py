@@ -1,8 +1,11 @@
 """Randomised checks of the oracle's plan and FMM on small, awkward point clouds
 (clusters, planes, lines, duplicates, wide dynamic range), and of the seeded inputs."""
+import os
+import secrets
+
 import numpy as np
 import pytest
-from hypothesis import HealthCheck, given, settings
+from hypothesis import HealthCheck, given, seed, settings
 from hypothesis import strategies as st
 
 import oracle
@@ -73,6 +76,32 @@ def test_fmm_close_to_direct(kind, n, seed):
     rate = (np.sqrt(3) * 0.4) ** 6
     for i in range(2):
         assert err[12][i] <= 2 * rate * err[6][i] + 1e-12
+
+
+def test_partition_and_accuracy_fresh_examples(capsys):
+    """The two checks above on examples drawn afresh at every run (not derandomized).
+    The seed is printed; FMM_FUZZ_SEED=<seed> replays a run."""
+    s = int(os.environ.get("FMM_FUZZ_SEED", secrets.randbits(32)))
+    with capsys.disabled():
+        print(f"\n[fuzz] hypothesis seed {s} (replay: FMM_FUZZ_SEED={s})")
+
+    @seed(s)
+    @settings(max_examples=8, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
+    @given(kind=st.sampled_from(["cube", "clusters", "plane", "line", "dups", "far"]),
+           n=st.integers(2, 500), ncrit=st.integers(1, 40), theta=st.sampled_from([0.3, 0.4, 0.5]),
+           cseed=st.integers(0, 10 ** 6), lists=st.sampled_from([0, 1]))
+    def partition(kind, n, ncrit, theta, cseed, lists):
+        test_pairs_partition_all_interactions.hypothesis.inner_test(kind, n, ncrit, theta, cseed, lists)
+
+    @seed(s + 1)
+    @settings(max_examples=4, deadline=None, database=None)
+    @given(kind=st.sampled_from(["cube", "clusters", "plane", "dups"]), n=st.integers(50, 600),
+           cseed=st.integers(0, 10 ** 6))
+    def accuracy(kind, n, cseed):
+        test_fmm_close_to_direct.hypothesis.inner_test(kind, n, cseed)
+
+    partition()
+    accuracy()
 
 
 def test_inputs_are_seeded_and_shaped():
