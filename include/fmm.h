@@ -61,12 +61,23 @@ typedef enum {
 #define FMM_ALL 3
 
 /*
- * Device allocator used for every plan workspace.  alloc returns NULL on
- * failure (the call then fails with FMM_ENOMEM).  Both are called with the
- * stream of the plan call.  Passing NULL for both restores the default: a
- * process-wide caching allocator over hipMalloc (blocks are kept for reuse and
- * not returned to the driver).  Plans keep the allocator that was current when
- * they were built.
+ * Device allocator used for every plan workspace (the paper stresses that the FMM's memory
+ * is O(N), Sec. 4.1: all of it is workspace of the plan, obtained here).  alloc returns
+ * NULL on failure (the call then fails with FMM_ENOMEM); release takes back a pointer
+ * that alloc returned.  `stream` is the stream the block is first used on, and the block
+ * may be reused by its owner in that stream's order once released:
+ *   - fmm_plan and its variants: the plan call's stream, except the near-field lists,
+ *     which are built on the library's own per-device side stream and allocated (and,
+ *     when they are temporaries, released) with that stream;
+ *   - the scratch that the adjoint and Hessian calls add to a plan on first use: the
+ *     stream of that call.
+ * Blocks still held by a plan are released by fmm_plan_destroy after every stream the
+ * plan was used on has been synchronised.  Passing NULL for both restores the default: a
+ * process-wide caching allocator over hipMalloc (blocks are kept for reuse and not
+ * returned to the driver).  Plans keep the allocator that was current when they were
+ * built.  The Python binding installs PyTorch's caching allocator here.  The operator
+ * tables (a process-wide cache per expansion order) and the pinned host mailboxes are
+ * the library's own and do not go through this allocator.
  */
 typedef void *(*fmm_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*fmm_free_fn)(void *ptr, void *stream, void *ctx);
@@ -203,7 +214,9 @@ struct fmm_stats {
     int64_t ncoef, ncoef_padded;            /* (p+1)^2 and its padded length */
     double m2l_flops;                       /* 2 (p+1)^4 per M2L pair */
     double p2p_flops;                       /* 20 per interaction (stated convention) */
-    int64_t workspace_bytes;
+    int64_t workspace_bytes;                /* device bytes the plan holds from the allocator now (its
+                                               workspace, and scratch added on first use by an adjoint or
+                                               Hessian call) */
     double m2l_tol;                         /* variable-order tolerance (0: every block) */
     double m2l_kept_fraction;               /* pair-weighted fraction of operator blocks applied */
     int64_t lists;                          /* FMM_LISTS_DUAL or FMM_LISTS_LEVEL_SKIP */

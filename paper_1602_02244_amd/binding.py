@@ -1,9 +1,11 @@
 """ctypes binding of the HIP FMM library (include/fmm.h).
 
 Argument marshalling only: every step of the computation runs in the library's
-device kernels.  PyTorch provides device memory and the current stream.  When
-the library has not been built, every entry point raises instead of falling back
-to anything else.
+device kernels.  PyTorch provides device memory and the current stream: when the
+library is loaded, its workspace allocator (fmm_set_allocator) is bound to
+PyTorch's caching allocator, so plan workspace shows in torch.cuda.memory_allocated()
+and returns to PyTorch's pool at close().  When the library has not been built,
+every entry point raises instead of falling back to anything else.
 """
 import ctypes as C
 import os
@@ -57,6 +59,9 @@ class FMMError(RuntimeError):
 
 _lib = None
 _vp = C.c_void_p
+_ALLOC_T = C.CFUNCTYPE(_vp, C.c_size_t, _vp, _vp)     # fmm_alloc_fn
+_FREE_T = C.CFUNCTYPE(None, _vp, _vp, _vp)            # fmm_free_fn
+_installed = None                                     # the callbacks in use (kept alive here)
 
 
 def load_library():
@@ -95,7 +100,55 @@ def load_library():
               "fmm_plan_export", "fmm_plan_set_timing", "fmm_plan_phase_times"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
+    use_torch_allocator()
     return lib
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device workspace through alloc(nbytes, stream) -> address (0 or
+    None: out of memory) and free(address, stream); `stream` is the raw stream handle the
+    library passes.  alloc=None gives the library its own device pool back.  Plans keep
+    the allocator that was installed when they were created."""
+    global _installed
+    lib = load_library()
+    if alloc is None:
+        _check(lib.fmm_set_allocator(None, None, None))
+        _installed = None
+        return
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0)) or 0) or None
+        except Exception:       # an allocation failure of any kind is FMM_ENOMEM for the library
+            return None
+
+    def _f(ptr, stream, ctx):
+        try:
+            free(int(ptr), int(stream or 0))
+        except Exception:
+            pass
+
+    cbs = (_ALLOC_T(_a), _FREE_T(_f))
+    _check(lib.fmm_set_allocator(C.cast(cbs[0], _vp), C.cast(cbs[1], _vp), None))
+    # plans made under an earlier allocator still call it: keep every set of callbacks alive
+    _all_installed.append(cbs)
+    _installed = cbs
+
+
+_all_installed = []
+
+
+def _torch_alloc(nbytes, stream):
+    return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+
+def _torch_free(ptr, stream):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+def use_torch_allocator():
+    """Bind the library's workspace to PyTorch's caching allocator (the default)."""
+    set_allocator(_torch_alloc, _torch_free)
 
 
 def _check(st):

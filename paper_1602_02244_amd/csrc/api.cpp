@@ -63,23 +63,6 @@ void destroy_plan(fmm_plan_s *P) {
     delete P;
 }
 
-// Keep freed stream-ordered allocations in the device's default pool instead of
-// returning them to the driver at every synchronisation (plans allocate and free
-// many work buffers).
-void keep_pool_memory(int dev) {
-    static std::mutex mu;
-    static std::vector<int> done;
-    std::lock_guard<std::mutex> lk(mu);
-    for (int d : done)
-        if (d == dev) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = ~0ull;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    done.push_back(dev);
-}
-
 // One near-field stream per device, shared by all plans (default priority).
 hipStream_t side_stream(int dev) {
     static std::mutex mu;
@@ -216,7 +199,6 @@ static fmm_status plan_create(const float *points, int64_t n, const float *targe
     note_stream(P, s);
     fmm_status st = guarded([&] {
         HIP_CHECK(hipGetDevice(&P->device));
-        keep_pool_memory(P->device);
         P->side = side_stream(P->device);
         HIP_CHECK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));

@@ -84,8 +84,8 @@ struct Alloc {
     fmm_free_fn release = nullptr;
     void *ctx = nullptr;
     hipStream_t stream = nullptr;
-    std::vector<void *> live;
-    int64_t bytes = 0;
+    std::vector<std::pair<void *, size_t>> live;   // blocks held, with their requested sizes
+    int64_t bytes = 0;                              // sum of the sizes of the blocks held
     Mailbox *mb = nullptr;   // set while a plan is built: scan totals come back through it
     void *get(size_t bytes);
     template <class T> T *get_n(int64_t n) { return static_cast<T *>(get(sizeof(T) * (size_t)(n > 0 ? n : 1))); }

@@ -84,16 +84,17 @@ void cache_put(void *p, bool synchronized) {
 void *Alloc::get(size_t nbytes) {
     void *p = alloc ? alloc(nbytes, (void *)stream, ctx) : cache_get(nbytes, stream);
     if (!p) fail(FMM_ENOMEM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
-    live.push_back(p);
+    live.emplace_back(p, nbytes);
     bytes += (int64_t)nbytes;
     return p;
 }
 
 void Alloc::put(void *p) {
     for (size_t i = 0; i < live.size(); ++i)
-        if (live[i] == p) {
+        if (live[i].first == p) {
             if (release) release(p, (void *)stream, ctx);
             else cache_put(p, false);
+            bytes -= (int64_t)live[i].second;
             live[i] = live.back();
             live.pop_back();
             return;
@@ -101,11 +102,12 @@ void Alloc::put(void *p) {
 }
 
 void Alloc::release_all() {
-    for (void *p : live) {
-        if (release) release(p, (void *)stream, ctx);
-        else cache_put(p, true);
+    for (auto &b : live) {
+        if (release) release(b.first, (void *)stream, ctx);
+        else cache_put(b.first, true);
     }
     live.clear();
+    bytes = 0;
 }
 
 // ------------------------------------------------------------------ mailbox
