@@ -135,7 +135,11 @@ fmm_status fmm_eval_ex(fmm_plan_t plan, const float *charges, float *potential, 
                        int phases, void *stream);
 
 /*
- * Adjoint of L = sum_i w_i phi_i with w = dL_dphi (device [n]), for the frozen plan:
+ * Adjoint of L = sum_i w_i phi_i with w = dL_dphi (device [n]), for the frozen plan.  The
+ * paper treats the FMM as a matrix-free application of a fixed (H^2) matrix (Sec. 1); for a
+ * fixed plan that matrix A is symmetric (symmetric pair sets, symmetric truncation), so
+ * its transpose is applied by the same FMM, and the plan is recomputed in the backward
+ * pass rather than stored (the compute-over-memory argument of Sec. 1):
  *   dL_dq[i]  = sum_k w_k A_ki  = (A w)_i            (A is symmetric: the same FMM with charges w)
  *   dL_dx[i]  = w_i grad phi(x_i) + q_i grad psi(x_i),  psi = A w
  * gradient_fwd is grad phi from fmm_eval with `charges` ([n][3]); when NULL it is recomputed.
@@ -224,6 +228,9 @@ struct fmm_stats {
                                                leaf, more for leaves split into pieces */
     int64_t p2p_split_pieces;               /* pieces of split leaves (0: no leaf is split) */
 };
+/* Host copy of the plan's statistics: tree shape, interaction-list sizes (the paper's
+ * list-size count of Sec. 2.2 is m2l_pairs per target box in a uniform region), the work
+ * of one application (M2L and P2P flops) and the memory it holds (O(N), Sec. 4.1). */
 fmm_status fmm_plan_stats(fmm_plan_t plan, struct fmm_stats *out);
 
 /*
