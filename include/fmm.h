@@ -149,6 +149,24 @@ fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradi
                        const float *dL_dphi, float *dL_dq, float *dL_dx, void *stream);
 
 /*
+ * fmm_adjoint for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * results and errors as fmm_adjoint, but the call allocates nothing: the adjoint's
+ * scratch (psi when dL_dq is NULL, grad psi, and grad phi when gradient_fwd is NULL; 7
+ * floats per point) lives in a static device array of the library, FMM_NOALLOC_MAX_N * 7
+ * floats (28 MiB), that each GPU the library runs on holds until the process ends; its
+ * address is looked up once per device on the first call there.  The plan must have been
+ * built beforehand (fmm_plan allocates).  FMM_EINVAL when the plan has more than
+ * FMM_NOALLOC_MAX_N points, or when the current device is not the plan's.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (on different streams,
+ * from different threads or for different plans) race.  Nothing in the array has to start
+ * at zero (every value is written before it is read).
+ */
+#define FMM_NOALLOC_MAX_N ((int64_t)1 << 20)
+fmm_status fmm_adjoint_noalloc(fmm_plan_t plan, const float *charges, const float *gradient_fwd,
+                               const float *dL_dphi, float *dL_dq, float *dL_dx, void *stream);
+
+/*
  * Potential, gradient and Hessian of the potential at every point (the Hessian is what
  * the adjoint of a loss through grad phi needs).  hessian: device [n][6], order xx, yy,
  * zz, xy, xz, yz (symmetric); potential and gradient may be NULL.  The second derivatives

@@ -289,6 +289,63 @@ fmm_status fmm_adjoint(fmm_plan_t plan, const float *charges, const float *gradi
     });
 }
 
+// ---- the adjoint without allocation: scratch in a static device array
+}  // extern "C"
+
+namespace {
+constexpr int64_t kNoallocFloats = 7 * FMM_NOALLOC_MAX_N;   // psi [n], grad psi [n][3], grad phi [n][3]
+__device__ __align__(256) float scratch[kNoallocFloats];
+std::mutex g_scratch_mu;
+std::vector<std::pair<int, float *>> g_scratch_ptr;   // device -> address of `scratch` there
+
+// Address of `scratch` on device `dev` (the current device), looked up once per device.
+// Host code never uses the array's own name as an address.
+float *noalloc_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    for (auto &e : g_scratch_ptr)
+        if (e.first == dev) return e.second;
+    void *ptr = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(FMM_EDEVICE, "hipGetSymbolAddress returned NULL for the static scratch");
+    g_scratch_ptr.emplace_back(dev, static_cast<float *>(ptr));
+    return static_cast<float *>(ptr);
+}
+}  // namespace
+
+extern "C" {
+
+fmm_status fmm_adjoint_noalloc(fmm_plan_t plan, const float *charges, const float *gradient_fwd,
+                               const float *dL_dphi, float *dL_dq, float *dL_dx, void *stream) {
+    if (!plan) return set_err(FMM_EINVAL, "plan is NULL");
+    if (!dL_dphi) return set_err(FMM_EINVAL, "dL_dphi is NULL");
+    if (dL_dx && !charges) return set_err(FMM_EINVAL, "charges is NULL");
+    if (plan->ntgt > 0) return set_err(FMM_EINVAL, "a plan with a separate target set takes fmm_adjoint_targets");
+    if (plan->n > FMM_NOALLOC_MAX_N)
+        return set_err(FMM_EINVAL, "fmm_adjoint_noalloc takes plans of at most 2^20 points (its static scratch); "
+                                   "this plan has " + std::to_string(plan->n));
+    if (!dL_dq && !dL_dx) return FMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        fmm_plan_s *P = plan;
+        int dev = -1;
+        HIP_CHECK(hipGetDevice(&dev));
+        if (dev != P->device) fail(FMM_EINVAL, "the current device is not the plan's device");
+        float *sc = noalloc_scratch(dev);
+        const int64_t n = P->n;
+        float *psi = sc, *gpsi = sc + n, *gfwd = sc + 4 * n;
+        note_stream(P, s);
+        run_eval(P, dL_dphi, dL_dq ? dL_dq : psi, dL_dx ? gpsi : nullptr, nullptr, FMM_ALL, s);
+        if (dL_dx) {
+            const float *gphi = gradient_fwd;
+            if (!gphi) {
+                run_eval(P, charges, nullptr, gfwd, nullptr, FMM_ALL, s);
+                gphi = gfwd;
+            }
+            run_adjoint_combine(P, dL_dphi, gphi, charges, gpsi, dL_dx, s);
+        }
+    });
+}
+
 fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potential, float *gradient, float *hessian,
                             void *stream) {
     if (!plan || !charges || !hessian) return set_err(FMM_EINVAL, "NULL argument");
