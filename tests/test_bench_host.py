@@ -15,6 +15,7 @@ def test_fp32_roofline_against_fp32_mfma_peak():
     r = bench.m2l_roofline("fp32", 104.0, 15.35e9)
     assert r["bound"] == "mfma" and r["peak"] == 157.3 and r["unit"] == "TFLOP/s"
     assert r["frac"] == pytest.approx(104.0 / 157.3) and r["traffic"] == 15.35e9
+    assert r["traffic_source"].startswith("profiles/") and "L2-to-fabric" in r["traffic_kind"]
 
 
 def test_mixed_roofline_counts_three_fp16_products():
@@ -23,8 +24,20 @@ def test_mixed_roofline_counts_three_fp16_products():
     assert r["fp32_equivalent"] == 89.0 and r["traffic"] is None
 
 
+def test_p2p_roofline_has_no_ceiling_above_one():
+    r = bench.p2p_roofline(47.6)
+    assert r["bound"] == "alu" and r["peak"] == 78.6 and r["frac"] == pytest.approx(47.6 / 78.6)
+    assert all(not k.startswith("frac") or v <= 1 for k, v in r.items() if isinstance(v, float))
+
+
+def test_default_workload_is_the_largest_single_gpu_configuration():
+    a = bench.parse([])
+    assert a.workload == "uniform-16M" and a.precision == "fp32" and a.p is None
+
+
 def test_traffic_only_for_the_measured_kernel_and_grouping(monkeypatch):
-    t = bench.M2L_TRAFFIC
+    t = dict(bench.M2L_TRAFFIC, kernel_sha256="ab" * 8, entries=123, work_items=45, bytes=7.5e9)
+    monkeypatch.setattr(bench, "M2L_TRAFFIC", t)
     st = {"m2l_entries": t["entries"], "m2l_work_items": t["work_items"]}
     assert len(bench.m2l_kernel_sha()) == 16
     monkeypatch.setattr(bench, "m2l_kernel_sha", lambda: t["kernel_sha256"])
