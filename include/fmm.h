@@ -245,6 +245,10 @@ struct fmm_stats {
     int64_t p2p_work_items;                 /* near-field workgroups per evaluation: one per target
                                                leaf, more for leaves split into pieces */
     int64_t p2p_split_pieces;               /* pieces of split leaves (0: no leaf is split) */
+    int64_t m2l_pool_pairs;                 /* M2L pairs of sparse (tile, key) cells, regrouped into slots */
+    int64_t m2l_slots;                      /* slots: (target, source-side cell of the split that produced
+                                               the pairs), one partial column each */
+    int64_t m2l_slot_tiles;                 /* tiles of 64 slots with one key sequence */
 };
 /* Host copy of the plan's statistics: tree shape, interaction-list sizes (the paper's
  * list-size count of Sec. 2.2 is m2l_pairs per target box in a uniform region), the work

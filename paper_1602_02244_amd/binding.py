@@ -48,6 +48,7 @@ class FmmStats(C.Structure):
         ("workspace_bytes", C.c_int64),
         ("m2l_tol", C.c_double), ("m2l_kept_fraction", C.c_double), ("lists", C.c_int64),
         ("p2p_work_items", C.c_int64), ("p2p_split_pieces", C.c_int64),
+        ("m2l_pool_pairs", C.c_int64), ("m2l_slots", C.c_int64), ("m2l_slot_tiles", C.c_int64),
     ]
 
 

@@ -131,6 +131,9 @@ void fill_stats(fmm_plan_s *P) {
     st.lists = P->lists;
     st.p2p_work_items = P->np2p_items;
     st.p2p_split_pieces = P->np2p_part;
+    st.m2l_pool_pairs = P->npool;
+    st.m2l_slots = P->nslots;
+    st.m2l_slot_tiles = P->nslot_tiles;
 }
 }  // namespace
 

@@ -677,6 +677,22 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int64_t ntiles, const int32_
     }
 }
 
+// Slot pool: every target with slots adds the partial columns of its slots, in slot order
+// (a fixed order: the result does not depend on the schedule).  One workgroup per run of
+// slots of one target, threads over the coefficients.
+__global__ void __launch_bounds__(256) k_slot_reduce(int64_t nruns, const int32_t *run_first, const int32_t *run_tgt,
+                                                     const int64_t *slot_pos, const float *partial, int KP, float *L) {
+    for (int64_t r = blockIdx.x; r < nruns; r += gridDim.x) {
+        const int q0 = run_first[r], q1 = run_first[r + 1];
+        float *dst = L + (int64_t)run_tgt[r] * KP;
+        for (int row = threadIdx.x; row < KP; row += blockDim.x) {
+            float acc = dst[row];
+            for (int q = q0; q < q1; ++q) acc += partial[slot_pos[q] * KP + row];
+            dst[row] = acc;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ FP64 root levels (mixed precision)
 // Cells [0, nroot) are the cells of the root levels (cells are numbered level by level).
 // Their multipole and local coefficients are accumulated in FP64 (Md, Ld) by one tiled
@@ -1429,19 +1445,25 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
                                (const uint8_t *)Pl->entry_mask, Pl->key_f32, (const float *)Pl->M, Pl->L, Pl->partial,
                                (const int32_t *)Pl->tile_targets);
     }
-    ev_rec(Pl, 2 * PH_M2L + 1, s);
-    ev_rec(Pl, 2 * PH_L2L, s);
+    // the M2L phase ends after the fixed-order sums of split tiles (and, in mixed precision,
+    // after the FP64 root-level M2L on the side stream)
     if (Pl->npartial > 0)
         hipLaunchKernelGGL(k_m2l_reduce, dim3((unsigned)Pl->ntiles, kReduceChunks), 256, 0, s, Pl->ntiles,
                            (const int32_t *)Pl->tile_work,
                            (const int32_t *)Pl->tile_work_idx, (const int4 *)Pl->work, (const float *)Pl->partial,
                            (const int32_t *)Pl->tile_targets, D::KP, Pl->L);
+    if (Pl->nruns > 0)
+        hipLaunchKernelGGL(k_slot_reduce, (int)std::min<int64_t>(Pl->nruns, 1 << 20), D::KP <= 128 ? 128 : 256, 0, s,
+                           Pl->nruns, (const int32_t *)Pl->run_first, (const int32_t *)Pl->run_tgt,
+                           (const int64_t *)Pl->slot_pos, (const float *)Pl->partial, D::KP, Pl->L);
     if (root_side) HIP_CHECK(hipStreamWaitEvent(s, Pl->ev_join, 0));
     if (mixed && Pl->partial64)
         hipLaunchKernelGGL(k_m2l64_reduce, dim3((unsigned)Pl->ntiles_root, 16), 256, 0, s, Pl->ntiles_root,
                            (const int32_t *)Pl->tile_work64, (const int32_t *)Pl->tile_work_idx64,
                            (const int4 *)Pl->work64, (const double *)Pl->partial64, (const int32_t *)Pl->tile_targets,
                            D::KP, Pl->Ld);
+    ev_rec(Pl, 2 * PH_M2L + 1, s);
+    ev_rec(Pl, 2 * PH_L2L, s);
     if (mixed) {
         for (int l = 1; l <= std::min(RL - 1, Pl->max_level); ++l) {
             const int t0 = Pl->l2l.bucket_tile[l * 8], t1 = Pl->l2l.bucket_tile[l * 8 + 8];

@@ -230,6 +230,12 @@ struct fmm_plan_s {
     int32_t *tile_work = nullptr;        // [ntiles + 1] range of each tile in tile_work_idx
     int32_t *tile_work_idx = nullptr;    // [nwork] work items of each tile
     int64_t nkeys_same = 0, nm2l_same = 0;
+    // M2L slot pool: pairs of sparse (tile, key) cells, regrouped by the cell pair that produced
+    // them; every slot writes a partial column, summed per target in slot order
+    int64_t npool = 0, nslots = 0, nslot_tiles = 0, nruns = 0;
+    int64_t *slot_pos = nullptr;         // [nslots] partial column of each slot
+    int32_t *run_first = nullptr;        // [nruns + 1] first slot of each target's run
+    int32_t *run_tgt = nullptr;          // [nruns] target cell of each run
     LevelGemm m2m, l2l;
 
     // P2P

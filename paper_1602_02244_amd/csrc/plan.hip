@@ -360,6 +360,7 @@ __global__ void k_set_counters(unsigned long long *cnt, int64_t nm, int64_t np) 
 struct TravOut {
     int2 *m2l;
     int32_t *m2l_slot;
+    uint8_t *m2l_gen;     // per M2L pair: bit 0 the pair that produced it split its target side, bit 1 its source side
     int64_t cap_m;
     int2 *p2p;
     int64_t cap_p;
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t f0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + wave) * kTravPerWave;
     const int lane = threadIdx.x & 63, x = lane >> 3, y = lane & 7;
-    int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave];
+    int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave], gen[kTravPerWave];
     uint64_t key[kTravPerWave];
     int m = 0, q = 0, nx = 0;
 #pragma unroll
@@ -385,11 +386,13 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
         pa[k] = pb[k] = 0;
         act[k] = -1;
         key[k] = 0;
+        gen[k] = 0;
         if (f < nf) {
             int a0, na, b0, nb;
             const int2 pr = front[f];
-            split_ranges(C, __builtin_amdgcn_readfirstlane(pr.x), __builtin_amdgcn_readfirstlane(pr.y), a0, na, b0,
-                         nb);
+            const int ga = __builtin_amdgcn_readfirstlane(pr.x), gb = __builtin_amdgcn_readfirstlane(pr.y);
+            split_ranges(C, ga, gb, a0, na, b0, nb);
+            gen[k] = (a0 != ga ? 1 : 0) | (b0 != gb ? 2 : 0);
             const bool ld = lane < 8 ? lane < na : (lane < 16 && lane - 8 < nb);
             const int cell = lane < 8 ? a0 + lane : b0 + (lane - 8);
             int lv = 0, cx = 0, cy = 0, cz = 0, ch = 0;
@@ -448,6 +451,7 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
             if (wm < o.cap_m) {
                 o.m2l[wm] = v;
                 o.m2l_slot[wm] = key_slot(key[k], o.table, o.mask, o.flags);
+                o.m2l_gen[wm] = (uint8_t)gen[k];
             }
             o.is_target[pa[k]] = 1;
             ++wm;
@@ -517,31 +521,277 @@ __global__ void k_slot_ids(const uint64_t *table, uint64_t H, const uint64_t *ke
     }
 }
 
-// Key id of every pair (from its slot), the (tile, key) presence table, and the number
-// of pairs whose key joins cells of the same level.
+// Key id of every pair (from its slot), the (tile, key) table of target lanes (bit l: the
+// target in lane l of the tile has a source under that key), and the number of pairs whose
+// key joins cells of the same level.
 __global__ void __launch_bounds__(256) k_key_ids(const int2 *pairs, int64_t np, const int32_t *slot_id,
-                                                 const int32_t *key_same, const int32_t *cell_tile, int64_t nkeys,
-                                                 int32_t *pair_key_id, int32_t *present,
-                                                 unsigned long long *nsame) {
+                                                 const int32_t *key_same, const int32_t *cell_tile,
+                                                 const int32_t *cell_lane, int64_t nkeys, int32_t *pair_key_id,
+                                                 unsigned long long *lanes, unsigned long long *nsame) {
+    static_assert(kTileN == 64, "one 64-bit lane mask per (tile, key)");
     unsigned long long loc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         const int id = slot_id[pair_key_id[i]];
         pair_key_id[i] = id;
-        present[(int64_t)cell_tile[pairs[i].x] * nkeys + id] = 1;
+        const int a = pairs[i].x;
+        atomicOr(&lanes[(int64_t)cell_tile[a] * nkeys + id], 1ull << cell_lane[a]);
         loc += key_same[id] ? 1ull : 0ull;
     }
     block_add_u64(loc, nsame);
 }
 
-// Entries are the present (tile, key) cells in tile-major, key-ascending order.
-__global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pair_key_id, const int32_t *cell_tile,
-                               const int32_t *cell_lane, const int32_t *entry_of, int64_t nkeys, int32_t *entry_src) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        int a = pairs[i].x, k = pair_key_id[i];
-        int e = entry_of[(int64_t)cell_tile[a] * nkeys + k];
-        int lane = cell_lane[a];
-        entry_src[(int64_t)e * kTileN + lane] = pairs[i].y;
+// A (tile, key) cell becomes an entry of the target tile (dense) when its sources fill at
+// least fill_pct percent of the 16-column blocks it touches, or when the tile is one of the
+// first `all_dense` tiles; its pairs go to the slot pool otherwise.
+__global__ void __launch_bounds__(256) k_dense_flags(const unsigned long long *lanes, int64_t ntk, int64_t nkeys,
+                                                     int fill_pct, int64_t all_dense, int32_t *present,
+                                                     unsigned long long *sparse_pairs) {
+    unsigned long long loc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntk; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long m = lanes[i];
+        int f = 0;
+        if (m) {
+            int blocks = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) blocks += ((m >> (16 * b)) & 0xffffull) != 0;
+            f = (i / nkeys < all_dense || 100 * __popcll(m) >= fill_pct * 16 * blocks) ? 1 : 0;
+            if (!f) loc += (unsigned long long)__popcll(m);
+        }
+        present[i] = f;
     }
+    if (sparse_pairs) block_add_u64(loc, sparse_pairs);
+}
+
+// Entries are the dense (tile, key) cells in tile-major, key-ascending order (pairs of the
+// other cells are in the slot pool).
+__global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pair_key_id, const int32_t *cell_tile,
+                               const int32_t *cell_lane, const int32_t *pool, const int32_t *entry_of,
+                               int64_t nkeys, int32_t *entry_src) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        if (pool[i]) continue;
+        const int a = pairs[i].x;
+        const int64_t tk = (int64_t)cell_tile[a] * nkeys + pair_key_id[i];
+        entry_src[(int64_t)entry_of[tk] * kTileN + cell_lane[a]] = pairs[i].y;
+    }
+}
+
+// ---------------------------------------------------------------- M2L slot pool
+// Pairs of sparse (tile, key) cells are regrouped by the pair of cells the traversal split
+// to produce them: a slot is (target t, the source-side cell B of that pair), holding the
+// pairs (t, child of B) -- or the one pair (t, B) when B was not split.  Slots whose pairs
+// have the same key sequence (signature) share tiles of 64 columns, one column per slot,
+// so every column of every entry holds a source; each slot's column is a partial local
+// expansion of its target, and the targets' partials are summed in a fixed order.
+
+__device__ inline int cell_octant(const CellView &C, int c) {
+    return ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1);
+}
+
+// Sort keys of the pool pairs: (target, source, how the producing pair was split) in
+// `cbits`, `cbits` and 2 bits; values = pair index.
+__global__ void k_pool_keys(const int2 *pairs, const uint8_t *gen, int64_t np, const int32_t *pool,
+                            const int32_t *pool_at, int cbits, uint64_t *keys, int32_t *vals) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+        if (pool[i]) {
+            const int64_t j = pool_at[i];
+            keys[j] = ((((uint64_t)pairs[i].x << cbits) | (uint64_t)pairs[i].y) << 2) | (uint64_t)(gen[i] & 3);
+            vals[j] = (int32_t)i;
+        }
+}
+
+struct PoolKey {   // a sorted pool key unpacked
+    int t, s, g;
+};
+__device__ inline PoolKey pool_key(uint64_t k, int cbits) {
+    const uint64_t m = (uint64_t(1) << cbits) - 1;
+    return PoolKey{(int)((k >> (cbits + 2)) & m), (int)((k >> 2) & m), (int)(k & 3)};
+}
+// Source-side cell of the pair that produced a pool pair: the source's parent when that
+// side was split, else the source itself.
+__device__ inline int gen_source(const PoolKey &p, const int32_t *parent) { return (p.g & 2) ? parent[p.s] : p.s; }
+
+// Slot boundaries along the sorted pool: a new slot where the target, the way the
+// producing pair was split, or its source-side cell changes.
+__global__ void k_slot_flags(const uint64_t *pk, int cbits, const int32_t *parent, int64_t npool, int32_t *flag) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npool; j += (int64_t)gridDim.x * blockDim.x) {
+        int f = 1;
+        if (j > 0) {
+            const PoolKey a = pool_key(pk[j], cbits), b = pool_key(pk[j - 1], cbits);
+            f = (a.t != b.t || a.g != b.g || gen_source(a, parent) != gen_source(b, parent)) ? 1 : 0;
+        }
+        flag[j] = f;
+    }
+}
+
+// Per slot: first pool position, pair count, target, and signature = (key id of its first
+// pair, target side split, source side split, target octant when split, octants of its
+// sources when split).  Given how the producing pair was split, the first key, the target
+// octant and the source octants fix that pair's geometry and so every key of the slot in
+// source order: slots with equal signatures have equal key sequences.
+__global__ void k_slot_info(const uint64_t *pk, int cbits, const int32_t *key_id, const int32_t *order,
+                            const int32_t *flag, const int32_t *slot_at, int64_t npool, CellView C,
+                            int32_t *slot_first, int32_t *slot_cnt, int32_t *slot_tgt, uint64_t *slot_sig,
+                            int32_t *err) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npool; j += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[j]) continue;
+        const int64_t q = slot_at[j];
+        const int64_t i0 = order[j];
+        const PoolKey p0 = pool_key(pk[j], cbits);
+        const int t = p0.t, g = p0.g;
+        int c = 0, smask = 0;
+        for (int64_t jj = j; jj < npool && (jj == j || !flag[jj]); ++jj, ++c)
+            if (g & 2) smask |= 1 << cell_octant(C, pool_key(pk[jj], cbits).s);
+        if (c > 8) err[0] = 1;   // a slot holds the pairs of one split cell: never more than 8
+        const uint64_t ot = (g & 1) ? (uint64_t)cell_octant(C, t) : 0;
+        slot_first[q] = (int32_t)j;
+        slot_cnt[q] = c;
+        slot_tgt[q] = t;
+        slot_sig[q] = (uint64_t)(uint32_t)key_id[i0] | ((uint64_t)(g & 1) << 32) | ((uint64_t)((g >> 1) & 1) << 33) |
+                      (ot << 34) | ((uint64_t)smask << 37);
+    }
+}
+
+// Signature table: every slot's signature inserted (its table slot recorded).  Probing
+// stops after kSigProbes slots and flags the table as full, so that a table too small for
+// the signatures costs one bounded pass before it is rebuilt larger.
+constexpr int kSigProbes = 64;
+__global__ void k_sig_insert(const uint64_t *sig, int64_t ns, uint64_t *table, uint64_t mask, int32_t *at,
+                             int32_t *flags) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = sig[q];
+        uint64_t h = key_hash(key) & mask;
+        int32_t got = -1;
+        for (int probe = 0; probe < kSigProbes; ++probe) {
+            const uint64_t cur = table[h];
+            if (cur == key) { got = (int32_t)h; break; }
+            if (cur == kEmpty) {
+                const uint64_t prev = atomicCAS((unsigned long long *)&table[h], (unsigned long long)kEmpty,
+                                                (unsigned long long)key);
+                if (prev == kEmpty || prev == key) { got = (int32_t)h; break; }
+            }
+            h = (h + 1) & mask;
+        }
+        if (got < 0) {
+            flags[1] = 1;
+            got = 0;
+        }
+        at[q] = got;
+    }
+}
+
+// Signature id of every slot, and one representative slot per signature.
+__global__ void k_sig_ids(const int32_t *at, const int32_t *table_id, int64_t ns, int32_t *sig_id, int32_t *rep) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x) {
+        const int id = table_id[at[q]];
+        sig_id[q] = id;
+        atomicMax(&rep[id], (int32_t)q);
+    }
+}
+
+// Key sequence of every signature, from its representative slot ([nsig][8], count in sig_n).
+__global__ void k_sig_keys(const int32_t *rep, int64_t nsig, const int32_t *slot_first, const int32_t *slot_cnt,
+                           const int32_t *order, const int32_t *key_id, int32_t *sig_keys, int32_t *sig_n) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nsig; g += (int64_t)gridDim.x * blockDim.x) {
+        const int q = rep[g], c = slot_cnt[q], j0 = slot_first[q];
+        sig_n[g] = c;
+        for (int e = 0; e < 8; ++e) sig_keys[g * 8 + e] = e < c ? key_id[order[j0 + e]] : 0;
+    }
+}
+
+// Tile order of the slots: (region of the target, signature, target).  The region is the
+// target's ancestor (or, for a coarser target, its descendant corner) at level `rl`, so the
+// workgroups in flight share operators (one signature) and source expansions (one region).
+__global__ void k_slot_sort_keys(const int32_t *slot_tgt, const int32_t *sig_id, int64_t ns, CellView C, int rl,
+                                 int sbits, int tbits, uint64_t *keys, int32_t *vals) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x) {
+        const int t = slot_tgt[q], l = C.level[t];
+        const uint64_t pre = C.prefix[t];
+        const uint64_t reg = l >= rl ? pre >> (3 * (l - rl)) : pre << (3 * (rl - l));
+        keys[q] = (((reg << sbits) | (uint64_t)sig_id[q]) << tbits) | (uint64_t)t;
+        vals[q] = (int32_t)q;
+    }
+}
+
+// Group starts along the sorted slots: (region, signature) changes.
+__global__ void k_group_flags(const uint64_t *keys, int64_t ns, int tbits, int32_t *flag) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x)
+        flag[j] = (j == 0 || (keys[j] >> tbits) != (keys[j - 1] >> tbits)) ? 1 : 0;
+}
+__global__ void k_group_starts(const int32_t *flag, const int32_t *gid, int64_t ns, int32_t *gstart) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x)
+        if (flag[j]) gstart[gid[j]] = (int32_t)j;
+}
+// A tile starts at every 64th slot of a group.
+__global__ void k_tile_flags(const int32_t *flag, const int32_t *gid, const int32_t *gstart, int64_t ns,
+                             int32_t *tflag) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x) {
+        const int g = gid[j] + flag[j] - 1;
+        tflag[j] = ((j - gstart[g]) % kTileN) == 0 ? 1 : 0;
+    }
+}
+// Per slot tile: its signature and number of entries.
+__global__ void k_tile_sig(const int32_t *tflag, const int32_t *tid, const int32_t *sorted, const int32_t *sig_id,
+                           const int32_t *sig_n, int64_t ns, int32_t *tile_sig, int32_t *tile_ne) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x)
+        if (tflag[j]) {
+            const int T = tid[j], g = sig_id[sorted[j]];
+            tile_sig[T] = g;
+            tile_ne[T] = sig_n[g];
+        }
+}
+// Entries of the slot tiles (keys, sources per column) and each slot's partial column:
+// slot tile T is partial tile `part0 + T`.
+__global__ void k_slot_entries(const int32_t *tflag, const int32_t *tid, const int32_t *flag, const int32_t *gid,
+                               const int32_t *gstart, const int32_t *sorted, int64_t ns, const int32_t *slot_first,
+                               const int32_t *slot_cnt, const uint64_t *pk, int cbits, const int32_t *tile_eoff,
+                               int64_t e_base, int64_t part0, int32_t *entry_src, int64_t *slot_pos) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x) {
+        const int T = tid[j] + tflag[j] - 1;
+        const int lane = (int)((j - gstart[gid[j] + flag[j] - 1]) % kTileN);
+        const int q = sorted[j];
+        const int64_t e0 = e_base + tile_eoff[T];
+        for (int e = 0; e < slot_cnt[q]; ++e)
+            entry_src[(e0 + e) * kTileN + lane] = pool_key(pk[slot_first[q] + e], cbits).s;
+        slot_pos[q] = (part0 + T) * kTileN + lane;
+    }
+}
+__global__ void k_slot_entry_keys(const int32_t *tile_sig, const int32_t *tile_eoff, int64_t nt,
+                                  const int32_t *sig_keys, const int32_t *sig_n, int64_t e_base, int32_t *entry_key) {
+    for (int64_t T = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; T < nt; T += (int64_t)gridDim.x * blockDim.x) {
+        const int g = tile_sig[T];
+        for (int e = 0; e < sig_n[g]; ++e) entry_key[e_base + tile_eoff[T] + e] = sig_keys[g * 8 + e];
+    }
+}
+// Work items of the slot tiles, after the dense ones: every slot tile writes its partial.
+__global__ void k_slot_work(const int32_t *tile_eoff, const int32_t *tile_ne, int64_t nt, int64_t e_base,
+                            int64_t part0, int4 *work) {
+    for (int64_t T = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; T < nt; T += (int64_t)gridDim.x * blockDim.x) {
+        const int e0 = (int)(e_base + tile_eoff[T]);
+        work[T] = make_int4(0, e0, e0 + tile_ne[T], (int)(part0 + T + 1));
+    }
+}
+// Runs of slots with one target (slots are numbered in target order).
+__global__ void k_run_flags(const int32_t *slot_tgt, int64_t ns, int32_t *flag) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x)
+        flag[q] = (q == 0 || slot_tgt[q] != slot_tgt[q - 1]) ? 1 : 0;
+}
+// Pool flag of every pair: its (tile, key) cell is not a dense entry.
+__global__ void k_pool_flags(const int2 *pairs, int64_t np, const int32_t *key_id, const int32_t *cell_tile,
+                             const int32_t *present, int64_t nkeys, int32_t *pool) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+        pool[i] = present[(int64_t)cell_tile[pairs[i].x] * nkeys + key_id[i]] ? 0 : 1;
+}
+__global__ void k_shift_pos(int64_t *pos, int64_t n, int64_t by) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        pos[i] += by;
+}
+__global__ void k_run_info(const int32_t *flag, const int32_t *rid, const int32_t *slot_tgt, int64_t ns,
+                           int32_t *run_first, int32_t *run_tgt) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x)
+        if (flag[q]) {
+            run_first[rid[q]] = (int32_t)q;
+            run_tgt[rid[q]] = slot_tgt[q];
+        }
 }
 
 __global__ void k_entry_keys(const int32_t *present, const int32_t *entry_of, int64_t ntk, int64_t nkeys,
@@ -888,6 +1138,259 @@ struct StageLog {
     }
 };
 
+// Slot tiles of the M2L pool (see the slot pool kernels).  Device arrays of the plan's
+// allocator; release() returns the temporaries.
+constexpr int kDenseFillPct = 75;   // a (tile, key) cell stays a dense entry at >= 75% block fill
+constexpr int kSlotRegionLevel = 1; // slot tiles are ordered by the targets' ancestor at this level
+constexpr int kPoolMinPct = 5;      // a pool holding fewer than 5% of the M2L pairs is not built
+constexpr int kSlotsPerSig = 64;    // fewer slots per signature on average: the pool is given up
+struct SlotTiles {
+    bool abandoned = false;                         // the pool's slots were too diverse to tile well
+    int64_t nslots = 0, ntiles = 0, ne = 0, nsig = 0;
+    int cbits = 0;
+    uint64_t *pk = nullptr;                         // sorted pool keys (target, source, split flags)
+    int32_t *order = nullptr;                       // pool position -> pair index (sorted by target, source)
+    int32_t *slot_first = nullptr, *slot_cnt = nullptr, *slot_tgt = nullptr;
+    int32_t *sorted = nullptr;                      // tile order -> slot
+    int32_t *gflag = nullptr, *gid = nullptr, *gstart = nullptr, *tflag = nullptr, *tid = nullptr;
+    int32_t *tile_sig = nullptr, *tile_ne = nullptr, *tile_eoff = nullptr;
+    int32_t *sig_keys = nullptr, *sig_n = nullptr;
+    void release(Alloc &a) {
+        for (int32_t *p : {order, slot_first, slot_cnt, slot_tgt, sorted, gflag, gid, gstart, tflag, tid, tile_sig,
+                           tile_ne, tile_eoff, sig_keys, sig_n})
+            if (p) a.put(p);
+        if (pk) a.put(pk);
+        *this = SlotTiles{};
+    }
+};
+
+// Groups the pool pairs into slots and slot tiles; fills P->slot_pos (partial column of
+// every slot, relative to the first slot tile), P->run_first / P->run_tgt / P->nruns (the
+// slots of each target, for the fixed-order sum) and `st` (what the entry builders need).
+static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64_t nm2l, const int32_t *key_id,
+                        const uint8_t *gen, const int32_t *pool, const int32_t *pool_at, int64_t npool, Alloc &a,
+                        hipStream_t s, SlotTiles &st) {
+    Mailbox &mb = *a.mb;
+    StageLog lg;
+    lg.s = s;
+    const int64_t nc = P->ncells;
+    const int cbits = bits_for(nc);
+    // pool pairs sorted by (target, source): a slot's pairs are consecutive, in source order
+    st.cbits = cbits;
+    st.pk = a.get_n<uint64_t>(npool);
+    st.order = a.get_n<int32_t>(npool);
+    uint64_t *&pk = st.pk;
+    hipLaunchKernelGGL(k_pool_keys, grid1(nm2l), 256, 0, s, m2l, gen, nm2l, pool, pool_at, cbits, pk, st.order);
+    radix_sort_u64(pk, st.order, npool, 2 * cbits + 2, a, s);
+    lg("  slots: pool sort");
+    int32_t *sflag = a.get_n<int32_t>(npool), *sat = a.get_n<int32_t>(npool);
+    hipLaunchKernelGGL(k_slot_flags, grid1(npool), 256, 0, s, (const uint64_t *)pk, cbits, (const int32_t *)P->c_parent,
+                       npool, sflag);
+    const int64_t ns = exclusive_scan_i32(sflag, sat, npool, a, s);
+    st.nslots = ns;
+    st.slot_first = a.get_n<int32_t>(ns);
+    st.slot_cnt = a.get_n<int32_t>(ns);
+    st.slot_tgt = a.get_n<int32_t>(ns);
+    uint64_t *sig = a.get_n<uint64_t>(ns);
+    int32_t *err = a.get_n<int32_t>(1);
+    fill_i32(err, 0, 1, s);
+    hipLaunchKernelGGL(k_slot_info, grid1(npool), 256, 0, s, (const uint64_t *)pk, cbits, key_id,
+                       (const int32_t *)st.order, (const int32_t *)sflag, (const int32_t *)sat, npool, C, st.slot_first,
+                       st.slot_cnt, st.slot_tgt, sig, err);
+    a.put(sflag); a.put(sat);
+    lg("  slots: slot info");
+
+    // distinct signatures through a device hash table (rebuilt larger while more than half full)
+    uint64_t H = uint64_t(1) << 16;
+    while (H < (uint64_t(1) << 20) && (int64_t)H < ns / 8) H <<= 1;
+    int32_t *at = a.get_n<int32_t>(ns);
+    std::vector<uint64_t> hsig;
+    uint64_t *table = nullptr;
+    for (;;) {
+        table = a.get_n<uint64_t>((int64_t)H + 1);
+        HIP_CHECK(hipMemsetAsync(table, 0xff, 8 * H, s));
+        fill_i32(reinterpret_cast<int32_t *>(table + H), 0, 2, s);
+        hipLaunchKernelGGL(k_sig_insert, grid1(ns), 256, 0, s, (const uint64_t *)sig, ns, table, H - 1, at,
+                           reinterpret_cast<int32_t *>(table + H));
+        const uint64_t cap = H / 2;
+        unsigned long long *kc = a.get_n<unsigned long long>((int64_t)cap + 2);
+        fill_i32(reinterpret_cast<int32_t *>(kc), 0, 2, s);
+        hipLaunchKernelGGL(k_key_compact, std::min(grid1((int64_t)H), 1024), 256, 0, s, (const uint64_t *)table, H, cap,
+                           kc);
+        const int64_t kbytes = 8 * ((int64_t)cap + 2);
+        std::vector<unsigned long long> hbuf(cap + 2);
+        if (kbytes <= Mailbox::kFetchBytes) {
+            std::memcpy(hbuf.data(), mb.fetch(kc, kbytes, s), kbytes);
+        } else {
+            HIP_CHECK(hipMemcpyAsync(hbuf.data(), kc, kbytes, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+        }
+        a.put(kc);
+        int32_t hf[2];
+        std::memcpy(hf, &hbuf[1], 8);
+        const int64_t used = (int64_t)hbuf[0];
+        if (!hf[1] && 2 * used <= (int64_t)H) {
+            hsig.assign(hbuf.begin() + 2, hbuf.begin() + 2 + used);
+            break;
+        }
+        a.put(table);
+        H *= 4;
+    }
+    {
+        int32_t herr = 0;
+        std::memcpy(&herr, mb.fetch(err, 4, s), 4);
+        if (herr) fail(FMM_EDEVICE, "internal: an M2L slot with more than eight pairs");
+        a.put(err);
+    }
+    std::sort(hsig.begin(), hsig.end());
+    const int64_t nsig = (int64_t)hsig.size();
+    st.nsig = nsig;
+    if (ns < (int64_t)kSlotsPerSig * nsig) {
+        // slots with this many key sequences fill their tiles poorly: the pairs stay in the
+        // target tiles (the caller rebuilds the dense cells)
+        a.put(table); a.put(at); a.put(sig);
+        st.release(a);
+        st.abandoned = true;
+        lg("  slots: given up (diverse signatures)");
+        return;
+    }
+    uint64_t *dsig = a.get_n<uint64_t>(nsig);
+    mb.upload(dsig, hsig.data(), 8 * nsig, s);
+    int32_t *tslot = a.get_n<int32_t>((int64_t)H);
+    hipLaunchKernelGGL(k_slot_ids, grid1((int64_t)H), 256, 0, s, (const uint64_t *)table, H, (const uint64_t *)dsig,
+                       nsig, tslot);
+    int32_t *sig_id = a.get_n<int32_t>(ns), *rep = a.get_n<int32_t>(nsig);
+    fill_i32(rep, -1, nsig, s);
+    hipLaunchKernelGGL(k_sig_ids, grid1(ns), 256, 0, s, (const int32_t *)at, (const int32_t *)tslot, ns, sig_id, rep);
+    a.put(tslot); a.put(table); a.put(dsig); a.put(at); a.put(sig);
+    st.sig_keys = a.get_n<int32_t>(8 * nsig);
+    st.sig_n = a.get_n<int32_t>(nsig);
+    hipLaunchKernelGGL(k_sig_keys, grid1(nsig), 256, 0, s, (const int32_t *)rep, nsig, (const int32_t *)st.slot_first,
+                       (const int32_t *)st.slot_cnt, (const int32_t *)st.order, key_id, st.sig_keys, st.sig_n);
+    a.put(rep);
+    lg("  slots: signatures");
+
+    // tile order: (region, signature, target); tiles of 64 slots inside each (region, signature)
+    int rl = kSlotRegionLevel;
+    if (const char *ev = getenv("FMM_M2L_REGION_LEVEL")) rl = std::max(0, std::min(6, atoi(ev)));
+    const int sbits = bits_for(nsig), tbits = cbits;
+    if (3 * rl + sbits + tbits > 64) rl = std::max(0, (64 - sbits - tbits) / 3);
+    uint64_t *tk = a.get_n<uint64_t>(ns);
+    st.sorted = a.get_n<int32_t>(ns);
+    hipLaunchKernelGGL(k_slot_sort_keys, grid1(ns), 256, 0, s, (const int32_t *)st.slot_tgt, (const int32_t *)sig_id, ns,
+                       C, rl, sbits, tbits, tk, st.sorted);
+    radix_sort_u64(tk, st.sorted, ns, 3 * rl + sbits + tbits, a, s);
+    st.gflag = a.get_n<int32_t>(ns);
+    st.gid = a.get_n<int32_t>(ns);
+    hipLaunchKernelGGL(k_group_flags, grid1(ns), 256, 0, s, (const uint64_t *)tk, ns, tbits, st.gflag);
+    a.put(tk);
+    const int64_t ngroups = exclusive_scan_i32(st.gflag, st.gid, ns, a, s);
+    st.gstart = a.get_n<int32_t>(ngroups);
+    hipLaunchKernelGGL(k_group_starts, grid1(ns), 256, 0, s, (const int32_t *)st.gflag, (const int32_t *)st.gid, ns,
+                       st.gstart);
+    st.tflag = a.get_n<int32_t>(ns);
+    st.tid = a.get_n<int32_t>(ns);
+    hipLaunchKernelGGL(k_tile_flags, grid1(ns), 256, 0, s, (const int32_t *)st.gflag, (const int32_t *)st.gid,
+                       (const int32_t *)st.gstart, ns, st.tflag);
+    const int64_t nt = exclusive_scan_i32(st.tflag, st.tid, ns, a, s);
+    st.ntiles = nt;
+    st.tile_sig = a.get_n<int32_t>(nt);
+    st.tile_ne = a.get_n<int32_t>(nt);
+    st.tile_eoff = a.get_n<int32_t>(nt);
+    hipLaunchKernelGGL(k_tile_sig, grid1(ns), 256, 0, s, (const int32_t *)st.tflag, (const int32_t *)st.tid,
+                       (const int32_t *)st.sorted, (const int32_t *)sig_id, (const int32_t *)st.sig_n, ns, st.tile_sig,
+                       st.tile_ne);
+    a.put(sig_id);
+    st.ne = exclusive_scan_i32(st.tile_ne, st.tile_eoff, nt, a, s);
+    lg("  slots: tiles");
+    if (st.ne + 1 >= (int64_t(1) << 31) / kTileN) fail(FMM_EUNSUPPORTED, "too many M2L slot entries");
+
+    // the fixed-order sum: runs of slots of one target (slots are numbered in target order)
+    P->slot_pos = a.get_n<int64_t>(ns);
+    int32_t *rflag = a.get_n<int32_t>(ns), *rid = a.get_n<int32_t>(ns);
+    hipLaunchKernelGGL(k_run_flags, grid1(ns), 256, 0, s, (const int32_t *)st.slot_tgt, ns, rflag);
+    const int64_t nr = exclusive_scan_i32(rflag, rid, ns, a, s);
+    P->nruns = nr;
+    P->run_first = a.get_n<int32_t>(nr + 1);
+    P->run_tgt = a.get_n<int32_t>(nr);
+    hipLaunchKernelGGL(k_run_info, grid1(ns), 256, 0, s, (const int32_t *)rflag, (const int32_t *)rid,
+                       (const int32_t *)st.slot_tgt, ns, P->run_first, P->run_tgt);
+    {
+        const int32_t end = (int32_t)ns;
+        mb.upload(P->run_first + nr, &end, 4, s);
+    }
+    a.put(rflag); a.put(rid);
+    lg("  slots: runs");
+    if (lg.on)
+        fprintf(stderr, "[fmm plan]   pool %lld pairs, %lld slots, %lld signatures, %lld groups, %lld tiles, %lld entries\n",
+                (long long)npool, (long long)ns, (long long)nsig, (long long)ngroups, (long long)nt, (long long)st.ne);
+}
+
+// Host-side range checks of the M2L grouping (FMM_VALIDATE_PLAN set): every index an
+// evaluation kernel will follow is checked before any evaluation runs.
+template <class T> static std::vector<T> dl(const T *dev, int64_t n, hipStream_t s) {
+    std::vector<T> h((size_t)std::max<int64_t>(n, 0));
+    if (n > 0) HIP_CHECK(hipMemcpyAsync(h.data(), dev, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return h;
+}
+static void validate_m2l(fmm_plan_s *P, hipStream_t s) {
+    if (P->nm2l == 0) return;
+    const int64_t nc = P->ncells, ne = P->nentries, nw = P->nwork, np = P->npartial, nt = P->ntiles;
+    char msg[256];
+    auto bad = [&](const char *what, int64_t i, int64_t v) {
+        snprintf(msg, sizeof msg, "plan validation: %s at %lld = %lld (nc %lld ne %lld nwork %lld npartial %lld "
+                 "ntiles %lld nkeys %lld nslots %lld nruns %lld)", what, (long long)i, (long long)v, (long long)nc,
+                 (long long)ne, (long long)nw, (long long)np, (long long)nt, (long long)P->nkeys,
+                 (long long)P->nslots, (long long)P->nruns);
+        fail(FMM_EDEVICE, msg);
+    };
+    auto w = dl(P->work, nw, s);
+    for (int64_t i = 0; i < nw; ++i) {
+        if (w[i].y < 0 || w[i].z > ne || w[i].y > w[i].z) bad("work entry range", i, w[i].y);
+        if (w[i].w < 0 || w[i].w > np) bad("work partial", i, w[i].w);
+        if (w[i].w == 0 && (w[i].x < 0 || w[i].x >= nt)) bad("work tile", i, w[i].x);
+    }
+    auto ek = dl(P->entry_key, ne, s);
+    for (int64_t e = 0; e < ne; ++e)
+        if (ek[e] < 0 || ek[e] >= P->nkeys) bad("entry key", e, ek[e]);
+    auto es = dl(P->entry_src, ne * kTileN, s);
+    auto em = dl(P->entry_mask, ne, s);
+    for (int64_t e = 0; e < ne; ++e) {
+        int m = 0;
+        for (int l = 0; l < kTileN; ++l) {
+            const int v = es[e * kTileN + l];
+            if (v < -1 || v >= nc) bad("entry source", e * kTileN + l, v);
+            if (v >= 0) m |= 1 << (l / 16);
+        }
+        if (m != em[e]) bad("entry mask", e, em[e]);
+    }
+    auto tt = dl(P->tile_targets, nt * kTileN, s);
+    for (int64_t i = 0; i < nt * kTileN; ++i)
+        if (tt[i] < -1 || tt[i] >= nc) bad("tile target", i, tt[i]);
+    auto tw = dl(P->tile_work, nt + 1, s);
+    for (int64_t t = 0; t < nt; ++t)
+        if (tw[t] > tw[t + 1]) bad("tile work order", t, tw[t]);
+    if (P->nslots > 0) {
+        auto sp = dl(P->slot_pos, P->nslots, s);
+        for (int64_t q = 0; q < P->nslots; ++q)
+            if (sp[q] < 0 || sp[q] >= np * kTileN) bad("slot position", q, sp[q]);
+        auto rf = dl(P->run_first, P->nruns + 1, s);
+        auto rt = dl(P->run_tgt, P->nruns, s);
+        if (rf[0] != 0 || rf[P->nruns] != P->nslots) bad("run bounds", 0, rf[P->nruns]);
+        for (int64_t r = 0; r < P->nruns; ++r) {
+            if (rf[r] >= rf[r + 1]) bad("run order", r, rf[r]);
+            if (rt[r] < 0 || rt[r] >= nc) bad("run target", r, rt[r]);
+        }
+    }
+    auto kp = dl(P->key_f32, P->nkeys, s);
+    for (int64_t k = 0; k < P->nkeys; ++k)
+        if (!kp[k]) bad("operator pointer", k, 0);
+    fprintf(stderr, "[fmm validate] ok: nc %lld entries %lld work %lld partial %lld tiles %lld pool %lld slots %lld "
+            "slot tiles %lld runs %lld\n", (long long)nc, (long long)ne, (long long)nw, (long long)np, (long long)nt,
+            (long long)P->npool, (long long)P->nslots, (long long)P->nslot_tiles, (long long)P->nruns);
+}
+
 void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     StageLog lg;
     lg.s = s;
@@ -1041,7 +1544,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     fill_i32(reinterpret_cast<int32_t *>(cnt), 0, 6, s);
     int2 *m2l = nullptr, *p2p = nullptr;
     int32_t *m2l_slot = nullptr;
-    int64_t m2l_cap = 0, slot_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
+    uint8_t *m2l_gen = nullptr;
+    int64_t m2l_cap = 0, slot_cap = 0, gen_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
     // operator-key table filled by the traversal (its last word holds the two flags),
     // M2L targets marked by it
     const uint64_t H0 = uint64_t(1) << 16;
@@ -1056,6 +1560,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         // pairs per cell and ~75 P2P pairs per leaf); a step that overflows is repeated
         grow(a, m2l, m2l_cap, 0, 512 * nc, s);
         grow(a, m2l_slot, slot_cap, 0, m2l_cap, s);
+        grow(a, m2l_gen, gen_cap, 0, m2l_cap, s);
         grow(a, p2p, p2p_cap, 0, 96 * P->nleaves + 64, s);
         ktable = a.get_n<uint64_t>((int64_t)H0 + 1);
         HIP_CHECK(hipMemsetAsync(ktable, 0xff, 8 * H0, s));
@@ -1070,6 +1575,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             int64_t cap_n = std::max<int64_t>(1024, std::min<int64_t>(64 * nf, 10 * nf));
             grow(a, m2l, m2l_cap, nm2l, nm2l + 64 * nf, s);
             grow(a, m2l_slot, slot_cap, nm2l, m2l_cap, s);
+            grow(a, m2l_gen, gen_cap, nm2l, m2l_cap, s);
             grow(a, p2p, p2p_cap, np2p, np2p + 12 * nf, s);
             int2 *next = a.get_n<int2>(cap_n);
             uint64_t h3[3];
@@ -1078,7 +1584,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                 const int64_t tb = (nf + per_block - 1) / per_block;
                 if (tb >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "traversal frontier too large");
                 const uint64_t t = mb.next_ticket();
-                const TravOut to{m2l, m2l_slot, m2l_cap, p2p, p2p_cap, next, cap_n, ktable, H0 - 1,
+                const TravOut to{m2l, m2l_slot, m2l_gen, std::min(m2l_cap, gen_cap), p2p, p2p_cap, next, cap_n, ktable, H0 - 1,
                                  reinterpret_cast<int32_t *>(ktable + H0), is_t};
                 hipLaunchKernelGGL(k_trav_step, (int)tb, 256, 0, s, C, (const int2 *)front, nf, theta2, cnt, to);
                 hipLaunchKernelGGL(k_trav_post, 1, 64, 0, s, cnt, mb.data_dev<unsigned long long>(), mb.flag_dev(), t);
@@ -1090,6 +1596,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                 hipLaunchKernelGGL(k_set_counters, 1, 64, 0, s, cnt, nm2l, np2p);
                 grow(a, m2l, m2l_cap, nm2l, (int64_t)h3[0], s);
                 grow(a, m2l_slot, slot_cap, nm2l, m2l_cap, s);
+                grow(a, m2l_gen, gen_cap, nm2l, m2l_cap, s);
                 grow(a, p2p, p2p_cap, np2p, (int64_t)h3[1], s);
                 if ((int64_t)h3[2] > cap_n) {
                     a.put(next);
@@ -1271,24 +1778,82 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         mb.upload(dsame, hsame.data(), 4 * nkeys, s);
         lg("m2l keys+operators");
 
-        // (tile, key) entries: dense presence table, scanned tile-major
+        // (tile, key) cells: the target lanes of each, through a 64-bit mask per cell.  Cells
+        // whose sources fill their 16-column blocks well become entries of their target tile
+        // (tile-major, key-ascending); the pairs of the others go to the slot pool.
         const int64_t ntk = ntiles * nkeys;
         if (ntk >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "M2L tile x key table exceeds 2^31 entries");
-        int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk);
-        fill_i32(present, 0, ntk, s);
+        unsigned long long *lanes = a.get_n<unsigned long long>(ntk);
+        fill_i32(reinterpret_cast<int32_t *>(lanes), 0, 2 * ntk, s);
         hipLaunchKernelGGL(k_key_ids, std::min(grid1(nm2l), 4096), 256, 0, s, (const int2 *)m2l, nm2l,
-                           (const int32_t *)slot_id, (const int32_t *)dsame, (const int32_t *)cell_tile, nkeys, pkid,
-                           present, &counts[0]);
-        const int64_t ne = exclusive_scan_i32(present, entry_of, ntk, a, s);
+                           (const int32_t *)slot_id, (const int32_t *)dsame, (const int32_t *)cell_tile,
+                           (const int32_t *)cell_lane, nkeys, pkid, lanes, &counts[0]);
+        int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk);
+        // in mixed precision the root tiles stay whole: their FP64 path reads their entries
+        const int64_t root_tiles = P->prec == FMM_PREC_MIXED ? btile[(size_t)kRootLevels * 8] : 0;
+        int fill_pct = kDenseFillPct;
+        if (const char *ev = getenv("FMM_M2L_DENSE_PCT")) fill_pct = std::max(0, std::min(101, atoi(ev)));
+        unsigned long long *nsparse = a.get_n<unsigned long long>(1);
+        fill_i32(reinterpret_cast<int32_t *>(nsparse), 0, 2, s);
+        hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes, ntk,
+                           nkeys, fill_pct, root_tiles, present, nsparse);
+        int64_t npool = 0;
+        {
+            const uint64_t t = mb.next_ticket();
+            publish(nsparse, 8, mb, t, s);
+            mb.wait(t, s);
+            npool = (int64_t)mb.data_host<uint64_t>()[0];
+        }
+        a.put(nsparse);
+        int32_t *pool = a.get_n<int32_t>(nm2l);
+        SlotTiles st;
+        if (npool > 0 && 100 * npool >= (int64_t)kPoolMinPct * nm2l) {
+            // ---- slot pool (given up when its slots are too diverse)
+            hipLaunchKernelGGL(k_pool_flags, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
+                               (const int32_t *)cell_tile, (const int32_t *)present, nkeys, pool);
+            int32_t *pool_at = a.get_n<int32_t>(nm2l);
+            npool = exclusive_scan_i32(pool, pool_at, nm2l, a, s);
+            lg("m2l dense cells");
+            build_slots(P, C, m2l, nm2l, pkid, m2l_gen, pool, pool_at, npool, a, s, st);
+            a.put(pool_at);
+        }
+        if (st.ntiles == 0) {
+            // no pool: every (tile, key) cell with a pair is an entry of its target tile
+            if (npool > 0)
+                hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
+                                   ntk, nkeys, 0, (int64_t)0, present, (unsigned long long *)nullptr);
+            fill_i32(pool, 0, nm2l, s);
+            npool = 0;
+        }
+        const int64_t ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
+        P->npool = npool;
+        P->nslots = st.nslots;
+        P->nslot_tiles = st.ntiles;
+        a.put(lanes);
+        a.put(m2l_gen);
+        lg("m2l slot pool");
+
+        const int64_t ne = ne_d + st.ne;
         P->nentries = ne;
         P->entry_key = a.get_n<int32_t>(ne);
         P->entry_src = a.get_n<int32_t>(ne * kTileN);
         fill_i32(P->entry_src, -1, ne * kTileN, s);
         hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
-                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of, nkeys,
-                           P->entry_src);
+                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)pool,
+                           (const int32_t *)entry_of, nkeys, P->entry_src);
         hipLaunchKernelGGL(k_entry_keys, grid1(ntk), 256, 0, s, (const int32_t *)present, (const int32_t *)entry_of, ntk,
                            nkeys, P->entry_key);
+        a.put(pool);
+        if (st.ntiles > 0) {
+            hipLaunchKernelGGL(k_slot_entries, grid1(st.nslots), 256, 0, s, (const int32_t *)st.tflag,
+                               (const int32_t *)st.tid, (const int32_t *)st.gflag, (const int32_t *)st.gid,
+                               (const int32_t *)st.gstart, (const int32_t *)st.sorted, st.nslots,
+                               (const int32_t *)st.slot_first, (const int32_t *)st.slot_cnt, (const uint64_t *)st.pk,
+                               st.cbits, (const int32_t *)st.tile_eoff, ne_d, (int64_t)0, P->entry_src, P->slot_pos);
+            hipLaunchKernelGGL(k_slot_entry_keys, grid1(st.ntiles), 256, 0, s, (const int32_t *)st.tile_sig,
+                               (const int32_t *)st.tile_eoff, st.ntiles, (const int32_t *)st.sig_keys,
+                               (const int32_t *)st.sig_n, ne_d, P->entry_key);
+        }
         P->entry_mask = a.get_n<uint8_t>(ne);
         int32_t *nsrc = P->m2l_tol > 0 ? a.get_n<int32_t>(ne) : nullptr;
         hipLaunchKernelGGL(k_entry_masks, grid1(ne), 256, 0, s, (const int32_t *)P->entry_src, ne, P->entry_mask, nsrc);
@@ -1324,7 +1889,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         // to fill the chip.  Items are ordered piece-major, then by their first operator key:
         // the workgroups in flight work on the same part of the key range (entries are
         // key-sorted inside a tile), so the operators they stream stay in L2.
-        htf.push_back((int32_t)ne);
+        htf.push_back((int32_t)ne_d);
         int64_t piece = kEntriesPerWork, items = 4096;   // tuning knobs, overridable from the environment
         if (const char *ev = getenv("FMM_M2L_PIECE")) piece = std::max<int64_t>(1, atoll(ev));
         if (const char *ev = getenv("FMM_M2L_ITEMS")) items = std::max<int64_t>(1, atoll(ev));
@@ -1344,16 +1909,16 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         std::vector<int4> order;   // piece-major
         order.reserve(nitems);
         for (int64_t k2 = 0; k2 < maxp; ++k2)
-            for (int64_t t = 0; t < ntiles; ++t)
-                if (k2 < npc[t]) {
+            for (int64_t t = root_tiles; t < ntiles; ++t)   // mixed: the root tiles run in FP64 only
+                if (k2 < npc[t] && htf[t + 1] > htf[t]) {
                     const int c0 = htf[t] + (int)k2 * psz[t];
                     order.push_back(make_int4((int)t, c0, std::min(htf[t + 1], c0 + psz[t]), npc[t] > 1 ? 1 : 0));
                 }
-        if ((int64_t)(4 * ne) <= Mailbox::kFetchBytes) {
+        if ((int64_t)(4 * ne_d) <= Mailbox::kFetchBytes && !order.empty()) {
             // then by the operator key of the first entry (a stable counting sort): tiles of
             // different boundary classes hold different key sets, and the workgroups in
             // flight should stream the same operators
-            const int32_t *hk = static_cast<const int32_t *>(mb.fetch(P->entry_key, 4 * ne, s));
+            const int32_t *hk = static_cast<const int32_t *>(mb.fetch(P->entry_key, 4 * ne_d, s));
             std::vector<int32_t> kpos(nkeys + 1, 0);
             for (const int4 &u : order) ++kpos[hk[u.y] + 1];
             for (int64_t k2 = 0; k2 < nkeys; ++k2) kpos[k2 + 1] += kpos[k2];
@@ -1361,9 +1926,9 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             for (const int4 &u : order) by_key[kpos[hk[u.y]]++] = u;
             order.swap(by_key);
         }
-        {
+        if (st.ntiles == 0) {
             // the last quarter of the items, longest first: the final workgroups of the launch
-            // are the short ones, so the chip drains evenly
+            // are the short ones, so the chip drains evenly (slot tiles, short, come last)
             const size_t k0 = order.size() - order.size() / 4;
             std::stable_sort(order.begin() + k0, order.end(),
                              [](const int4 &u, const int4 &v) { return u.z - u.y > v.z - v.y; });
@@ -1384,14 +1949,23 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             std::vector<int32_t> fillp(htw.begin(), htw.end() - 1);
             for (size_t i = 0; i < hw.size(); ++i) htwi[fillp[hw[i].x]++] = (int32_t)i;
         }
-        P->nwork = (int64_t)hw.size();
+        const int64_t nwd = (int64_t)hw.size();
+        P->nwork = nwd + st.ntiles;
         P->work = a.get_n<int4>(P->nwork);
         P->tile_work = a.get_n<int32_t>(ntiles + 1);
-        P->tile_work_idx = a.get_n<int32_t>(P->nwork);
-        mb.upload(P->work, hw.data(), sizeof(int4) * hw.size(), s);
+        P->tile_work_idx = a.get_n<int32_t>(std::max<int64_t>(nwd, 1));
+        if (nwd > 0) mb.upload(P->work, hw.data(), sizeof(int4) * hw.size(), s);
         mb.upload(P->tile_work, htw.data(), 4 * (ntiles + 1), s);
-        mb.upload(P->tile_work_idx, htwi.data(), 4 * P->nwork, s);
-        P->npartial = nsplit;
+        if (nwd > 0) mb.upload(P->tile_work_idx, htwi.data(), 4 * nwd, s);
+        // slot tiles: one work item each, after the dense ones, writing partial tiles
+        // nsplit .. nsplit + st.ntiles - 1; slot q's column is partial column slot_pos[q]
+        if (st.ntiles > 0) {
+            hipLaunchKernelGGL(k_slot_work, grid1(st.ntiles), 256, 0, s, (const int32_t *)st.tile_eoff,
+                               (const int32_t *)st.tile_ne, st.ntiles, ne_d, nsplit, P->work + nwd);
+            hipLaunchKernelGGL(k_shift_pos, grid1(st.nslots), 256, 0, s, P->slot_pos, st.nslots, nsplit * kTileN);
+        }
+        P->npartial = nsplit + st.ntiles;   // before release(), which clears the counts
+        st.release(a);
 
         // mixed precision: the root levels accumulate in FP64, with FP64 operators for the
         // keys their tiles use and their own split into small work items
@@ -1482,6 +2056,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     a.put(counts);
     HIP_CHECK(hipStreamSynchronize(s));
     lg("workspace");
+    if (getenv("FMM_VALIDATE_PLAN")) validate_m2l(P, s);
 }
 
 }  // namespace fmm
