@@ -562,16 +562,17 @@ __global__ void __launch_bounds__(256) k_dense_flags(const unsigned long long *l
     if (sparse_pairs) block_add_u64(loc, sparse_pairs);
 }
 
-// Entries are the dense (tile, key) cells in tile-major, key-ascending order (pairs of the
-// other cells are in the slot pool).
+// Entries are the dense (tile, key) cells in tile-major, key-ascending order; the pairs of
+// the other cells are flagged for the slot pool (when `pool` is given).
 __global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pair_key_id, const int32_t *cell_tile,
-                               const int32_t *cell_lane, const int32_t *pool, const int32_t *entry_of,
-                               int64_t nkeys, int32_t *entry_src) {
+                               const int32_t *cell_lane, const int32_t *present, const int32_t *entry_of,
+                               int64_t nkeys, int32_t *entry_src, int32_t *pool) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        if (pool[i]) continue;
         const int a = pairs[i].x;
         const int64_t tk = (int64_t)cell_tile[a] * nkeys + pair_key_id[i];
-        entry_src[(int64_t)entry_of[tk] * kTileN + cell_lane[a]] = pairs[i].y;
+        const int dense = present[tk];
+        if (pool) pool[i] = dense ? 0 : 1;
+        if (dense) entry_src[(int64_t)entry_of[tk] * kTileN + cell_lane[a]] = pairs[i].y;
     }
 }
 
@@ -628,10 +629,12 @@ __global__ void k_slot_flags(const uint64_t *pk, int cbits, const int32_t *paren
 // sources when split).  Given how the producing pair was split, the first key, the target
 // octant and the source octants fix that pair's geometry and so every key of the slot in
 // source order: slots with equal signatures have equal key sequences.
-__global__ void k_slot_info(const uint64_t *pk, int cbits, const int32_t *key_id, const int32_t *order,
-                            const int32_t *flag, const int32_t *slot_at, int64_t npool, CellView C,
-                            int32_t *slot_first, int32_t *slot_cnt, int32_t *slot_tgt, uint64_t *slot_sig,
-                            int32_t *err) {
+__global__ void __launch_bounds__(256) k_slot_info(const uint64_t *pk, int cbits, const int32_t *key_id,
+                                                   const int32_t *order, const int32_t *flag, const int32_t *slot_at,
+                                                   int64_t npool, CellView C, int32_t *slot_first, int32_t *slot_cnt,
+                                                   int32_t *slot_tgt, uint64_t *slot_sig, int32_t *err,
+                                                   unsigned long long *partial_octants) {
+    unsigned long long part = 0;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npool; j += (int64_t)gridDim.x * blockDim.x) {
         if (!flag[j]) continue;
         const int64_t q = slot_at[j];
@@ -642,6 +645,7 @@ __global__ void k_slot_info(const uint64_t *pk, int cbits, const int32_t *key_id
         for (int64_t jj = j; jj < npool && (jj == j || !flag[jj]); ++jj, ++c)
             if (g & 2) smask |= 1 << cell_octant(C, pool_key(pk[jj], cbits).s);
         if (c > 8) err[0] = 1;   // a slot holds the pairs of one split cell: never more than 8
+        if ((g & 2) && c < 8) ++part;
         const uint64_t ot = (g & 1) ? (uint64_t)cell_octant(C, t) : 0;
         slot_first[q] = (int32_t)j;
         slot_cnt[q] = c;
@@ -649,6 +653,7 @@ __global__ void k_slot_info(const uint64_t *pk, int cbits, const int32_t *key_id
         slot_sig[q] = (uint64_t)(uint32_t)key_id[i0] | ((uint64_t)(g & 1) << 32) | ((uint64_t)((g >> 1) & 1) << 33) |
                       (ot << 34) | ((uint64_t)smask << 37);
     }
+    block_add_u64(part, partial_octants);
 }
 
 // Signature table: every slot's signature inserted (its table slot recorded).  Probing
@@ -774,12 +779,6 @@ __global__ void k_slot_work(const int32_t *tile_eoff, const int32_t *tile_ne, in
 __global__ void k_run_flags(const int32_t *slot_tgt, int64_t ns, int32_t *flag) {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x)
         flag[q] = (q == 0 || slot_tgt[q] != slot_tgt[q - 1]) ? 1 : 0;
-}
-// Pool flag of every pair: its (tile, key) cell is not a dense entry.
-__global__ void k_pool_flags(const int2 *pairs, int64_t np, const int32_t *key_id, const int32_t *cell_tile,
-                             const int32_t *present, int64_t nkeys, int32_t *pool) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
-        pool[i] = present[(int64_t)cell_tile[pairs[i].x] * nkeys + key_id[i]] ? 0 : 1;
 }
 __global__ void k_shift_pos(int64_t *pos, int64_t n, int64_t by) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1192,17 +1191,33 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64
     st.slot_cnt = a.get_n<int32_t>(ns);
     st.slot_tgt = a.get_n<int32_t>(ns);
     uint64_t *sig = a.get_n<uint64_t>(ns);
-    int32_t *err = a.get_n<int32_t>(1);
-    fill_i32(err, 0, 1, s);
-    hipLaunchKernelGGL(k_slot_info, grid1(npool), 256, 0, s, (const uint64_t *)pk, cbits, key_id,
+    int32_t *err = a.get_n<int32_t>(4);   // [0] error flag, [2..3] slots whose split source has empty octants
+    fill_i32(err, 0, 4, s);
+    hipLaunchKernelGGL(k_slot_info, std::min(grid1(npool), 8192), 256, 0, s, (const uint64_t *)pk, cbits, key_id,
                        (const int32_t *)st.order, (const int32_t *)sflag, (const int32_t *)sat, npool, C, st.slot_first,
-                       st.slot_cnt, st.slot_tgt, sig, err);
+                       st.slot_cnt, st.slot_tgt, sig, err, reinterpret_cast<unsigned long long *>(err + 2));
     a.put(sflag); a.put(sat);
+    int64_t partial_oct = 0;
+    {
+        int32_t h4[4];
+        std::memcpy(h4, mb.fetch(err, 16, s), 16);
+        if (h4[0]) fail(FMM_EDEVICE, "internal: an M2L slot with more than eight pairs");
+        std::memcpy(&partial_oct, h4 + 2, 8);
+    }
     lg("  slots: slot info");
+    if (lg.on) fprintf(stderr, "[fmm plan]   %lld of %lld slots from sources with empty octants\n",
+                       (long long)partial_oct, (long long)ns);
+    if (2 * partial_oct > ns) {
+        // most sources miss octants (a surface-like cloud): signatures would be too many
+        a.put(sig); a.put(err);
+        st.release(a);
+        st.abandoned = true;
+        lg("  slots: given up (sources with empty octants)");
+        return;
+    }
 
     // distinct signatures through a device hash table (rebuilt larger while more than half full)
     uint64_t H = uint64_t(1) << 16;
-    while (H < (uint64_t(1) << 20) && (int64_t)H < ns / 8) H <<= 1;
     int32_t *at = a.get_n<int32_t>(ns);
     std::vector<uint64_t> hsig;
     uint64_t *table = nullptr;
@@ -1236,12 +1251,7 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64
         a.put(table);
         H *= 4;
     }
-    {
-        int32_t herr = 0;
-        std::memcpy(&herr, mb.fetch(err, 4, s), 4);
-        if (herr) fail(FMM_EDEVICE, "internal: an M2L slot with more than eight pairs");
-        a.put(err);
-    }
+    a.put(err);
     std::sort(hsig.begin(), hsig.end());
     const int64_t nsig = (int64_t)hsig.size();
     st.nsig = nsig;
@@ -1805,27 +1815,44 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             npool = (int64_t)mb.data_host<uint64_t>()[0];
         }
         a.put(nsparse);
-        int32_t *pool = a.get_n<int32_t>(nm2l);
+        const bool try_pool = npool > 0 && 100 * npool >= (int64_t)kPoolMinPct * nm2l;
+        if (npool > 0 && !try_pool) {
+            // a small pool is not built: every (tile, key) cell with a pair is an entry
+            hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
+                               ntk, nkeys, 0, (int64_t)0, present, (unsigned long long *)nullptr);
+            npool = 0;
+        }
+        // dense entries (their sources in a first array; the slot entries, if any, follow them)
+        int64_t ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
+        int32_t *dsrc = a.get_n<int32_t>(ne_d * kTileN);
+        fill_i32(dsrc, -1, ne_d * kTileN, s);
+        int32_t *pool = try_pool ? a.get_n<int32_t>(nm2l) : nullptr;
+        hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
+                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)present,
+                           (const int32_t *)entry_of, nkeys, dsrc, pool);
         SlotTiles st;
-        if (npool > 0 && 100 * npool >= (int64_t)kPoolMinPct * nm2l) {
-            // ---- slot pool (given up when its slots are too diverse)
-            hipLaunchKernelGGL(k_pool_flags, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
-                               (const int32_t *)cell_tile, (const int32_t *)present, nkeys, pool);
+        if (try_pool) {
+            // ---- slot pool (given up when its slots would tile poorly)
             int32_t *pool_at = a.get_n<int32_t>(nm2l);
             npool = exclusive_scan_i32(pool, pool_at, nm2l, a, s);
             lg("m2l dense cells");
             build_slots(P, C, m2l, nm2l, pkid, m2l_gen, pool, pool_at, npool, a, s, st);
             a.put(pool_at);
         }
-        if (st.ntiles == 0) {
+        if (pool) a.put(pool);
+        if (st.ntiles == 0 && npool > 0) {
             // no pool: every (tile, key) cell with a pair is an entry of its target tile
-            if (npool > 0)
-                hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
-                                   ntk, nkeys, 0, (int64_t)0, present, (unsigned long long *)nullptr);
-            fill_i32(pool, 0, nm2l, s);
-            npool = 0;
+            hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
+                               ntk, nkeys, 0, (int64_t)0, present, (unsigned long long *)nullptr);
+            ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
+            a.put(dsrc);
+            dsrc = a.get_n<int32_t>(ne_d * kTileN);
+            fill_i32(dsrc, -1, ne_d * kTileN, s);
+            hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
+                               (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)present,
+                               (const int32_t *)entry_of, nkeys, dsrc, (int32_t *)nullptr);
         }
-        const int64_t ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
+        if (st.ntiles == 0) npool = 0;
         P->npool = npool;
         P->nslots = st.nslots;
         P->nslot_tiles = st.ntiles;
@@ -1836,14 +1863,17 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         const int64_t ne = ne_d + st.ne;
         P->nentries = ne;
         P->entry_key = a.get_n<int32_t>(ne);
-        P->entry_src = a.get_n<int32_t>(ne * kTileN);
-        fill_i32(P->entry_src, -1, ne * kTileN, s);
-        hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
-                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)pool,
-                           (const int32_t *)entry_of, nkeys, P->entry_src);
+        if (st.ne == 0) {
+            P->entry_src = dsrc;
+        } else {
+            P->entry_src = a.get_n<int32_t>(ne * kTileN);
+            if (ne_d > 0)
+                HIP_CHECK(hipMemcpyAsync(P->entry_src, dsrc, sizeof(int32_t) * ne_d * kTileN, hipMemcpyDeviceToDevice, s));
+            fill_i32(P->entry_src + ne_d * kTileN, -1, st.ne * kTileN, s);
+            a.put(dsrc);
+        }
         hipLaunchKernelGGL(k_entry_keys, grid1(ntk), 256, 0, s, (const int32_t *)present, (const int32_t *)entry_of, ntk,
                            nkeys, P->entry_key);
-        a.put(pool);
         if (st.ntiles > 0) {
             hipLaunchKernelGGL(k_slot_entries, grid1(st.nslots), 256, 0, s, (const int32_t *)st.tflag,
                                (const int32_t *)st.tid, (const int32_t *)st.gflag, (const int32_t *)st.gid,
