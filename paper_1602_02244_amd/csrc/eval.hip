@@ -677,19 +677,42 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int64_t ntiles, const int32_
     }
 }
 
-// Slot pool: every target with slots adds the partial columns of its slots, in slot order
-// (a fixed order: the result does not depend on the schedule).  One workgroup per run of
-// slots of one target, threads over the coefficients.
+// Slot pool: every target with slots adds the partial columns of its slots.  One workgroup
+// per run of slots of one target: the run is dealt to G groups of KP/4 threads (slot q to
+// group (q - q0) mod G, float4 per thread), each group sums its slots in slot order, and the
+// G group sums are added to L in group order -- a fixed order, so the result does not
+// depend on the schedule.
 __global__ void __launch_bounds__(256) k_slot_reduce(int64_t nruns, const int32_t *run_first, const int32_t *run_tgt,
                                                      const int64_t *slot_pos, const float *partial, int KP, float *L) {
+    __shared__ float4 part[256];
+    const int NQ = KP / 4, G = min(256 / NQ, 16);
+    const int g = threadIdx.x / NQ, c = threadIdx.x % NQ;
     for (int64_t r = blockIdx.x; r < nruns; r += gridDim.x) {
         const int q0 = run_first[r], q1 = run_first[r + 1];
-        float *dst = L + (int64_t)run_tgt[r] * KP;
-        for (int row = threadIdx.x; row < KP; row += blockDim.x) {
-            float acc = dst[row];
-            for (int q = q0; q < q1; ++q) acc += partial[slot_pos[q] * KP + row];
-            dst[row] = acc;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (g < G)
+            for (int q = q0 + g; q < q1; q += G) {
+                const float4 v = reinterpret_cast<const float4 *>(partial + slot_pos[q] * KP)[c];
+                acc.x += v.x;
+                acc.y += v.y;
+                acc.z += v.z;
+                acc.w += v.w;
+            }
+        if (g < G) part[g * NQ + c] = acc;
+        __syncthreads();
+        if (threadIdx.x < NQ) {
+            float4 *dst = reinterpret_cast<float4 *>(L + (int64_t)run_tgt[r] * KP) + c;
+            float4 sum = *dst;
+            for (int h = 0; h < G; ++h) {
+                const float4 v = part[h * NQ + c];
+                sum.x += v.x;
+                sum.y += v.y;
+                sum.z += v.z;
+                sum.w += v.w;
+            }
+            *dst = sum;
         }
+        __syncthreads();
     }
 }
 
@@ -1453,7 +1476,7 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
                            (const int32_t *)Pl->tile_work_idx, (const int4 *)Pl->work, (const float *)Pl->partial,
                            (const int32_t *)Pl->tile_targets, D::KP, Pl->L);
     if (Pl->nruns > 0)
-        hipLaunchKernelGGL(k_slot_reduce, (int)std::min<int64_t>(Pl->nruns, 1 << 20), D::KP <= 128 ? 128 : 256, 0, s,
+        hipLaunchKernelGGL(k_slot_reduce, (int)std::min<int64_t>(Pl->nruns, 1 << 20), 256, 0, s,
                            Pl->nruns, (const int32_t *)Pl->run_first, (const int32_t *)Pl->run_tgt,
                            (const int64_t *)Pl->slot_pos, (const float *)Pl->partial, D::KP, Pl->L);
     if (root_side) HIP_CHECK(hipStreamWaitEvent(s, Pl->ev_join, 0));

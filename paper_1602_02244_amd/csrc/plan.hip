@@ -684,13 +684,17 @@ __global__ void k_sig_insert(const uint64_t *sig, int64_t ns, uint64_t *table, u
     }
 }
 
-// Signature id of every slot, and one representative slot per signature.
-__global__ void k_sig_ids(const int32_t *at, const int32_t *table_id, int64_t ns, int32_t *sig_id, int32_t *rep) {
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x) {
-        const int id = table_id[at[q]];
-        sig_id[q] = id;
-        atomicMax(&rep[id], (int32_t)q);
-    }
+// Signature id of every slot.
+__global__ void k_sig_ids(const int32_t *at, const int32_t *table_id, int64_t ns, int32_t *sig_id) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x)
+        sig_id[q] = table_id[at[q]];
+}
+// One representative slot per signature: the first slot of one of its groups (any slot of a
+// signature has the signature's key sequence).
+__global__ void k_group_rep(const int32_t *gflag, const int32_t *sorted, const int32_t *sig_id, int64_t ns,
+                            int32_t *rep) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x)
+        if (gflag[j]) rep[sig_id[sorted[j]]] = sorted[j];
 }
 
 // Key sequence of every signature, from its representative slot ([nsig][8], count in sig_n).
@@ -1269,15 +1273,9 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64
     int32_t *tslot = a.get_n<int32_t>((int64_t)H);
     hipLaunchKernelGGL(k_slot_ids, grid1((int64_t)H), 256, 0, s, (const uint64_t *)table, H, (const uint64_t *)dsig,
                        nsig, tslot);
-    int32_t *sig_id = a.get_n<int32_t>(ns), *rep = a.get_n<int32_t>(nsig);
-    fill_i32(rep, -1, nsig, s);
-    hipLaunchKernelGGL(k_sig_ids, grid1(ns), 256, 0, s, (const int32_t *)at, (const int32_t *)tslot, ns, sig_id, rep);
+    int32_t *sig_id = a.get_n<int32_t>(ns);
+    hipLaunchKernelGGL(k_sig_ids, grid1(ns), 256, 0, s, (const int32_t *)at, (const int32_t *)tslot, ns, sig_id);
     a.put(tslot); a.put(table); a.put(dsig); a.put(at); a.put(sig);
-    st.sig_keys = a.get_n<int32_t>(8 * nsig);
-    st.sig_n = a.get_n<int32_t>(nsig);
-    hipLaunchKernelGGL(k_sig_keys, grid1(nsig), 256, 0, s, (const int32_t *)rep, nsig, (const int32_t *)st.slot_first,
-                       (const int32_t *)st.slot_cnt, (const int32_t *)st.order, key_id, st.sig_keys, st.sig_n);
-    a.put(rep);
     lg("  slots: signatures");
 
     // tile order: (region, signature, target); tiles of 64 slots inside each (region, signature)
@@ -1298,6 +1296,17 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64
     st.gstart = a.get_n<int32_t>(ngroups);
     hipLaunchKernelGGL(k_group_starts, grid1(ns), 256, 0, s, (const int32_t *)st.gflag, (const int32_t *)st.gid, ns,
                        st.gstart);
+    {   // key sequence of every signature, from a representative slot
+        int32_t *rep = a.get_n<int32_t>(nsig);
+        hipLaunchKernelGGL(k_group_rep, grid1(ns), 256, 0, s, (const int32_t *)st.gflag, (const int32_t *)st.sorted,
+                           (const int32_t *)sig_id, ns, rep);
+        st.sig_keys = a.get_n<int32_t>(8 * nsig);
+        st.sig_n = a.get_n<int32_t>(nsig);
+        hipLaunchKernelGGL(k_sig_keys, grid1(nsig), 256, 0, s, (const int32_t *)rep, nsig,
+                           (const int32_t *)st.slot_first, (const int32_t *)st.slot_cnt, (const int32_t *)st.order,
+                           key_id, st.sig_keys, st.sig_n);
+        a.put(rep);
+    }
     st.tflag = a.get_n<int32_t>(ns);
     st.tid = a.get_n<int32_t>(ns);
     hipLaunchKernelGGL(k_tile_flags, grid1(ns), 256, 0, s, (const int32_t *)st.gflag, (const int32_t *)st.gid,
