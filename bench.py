@@ -34,13 +34,13 @@ MFMA_FP16_PEAK_TFLOPS = 2500.0     # MI355X dense FP16 MFMA
 VALU_FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X FP32 vector with packed (2-wide) FMA
 VALU_FP32_PEAK_TFLOPS = 78.6           # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 not used
 ACC_TOL = 1e-4
-# Bytes that one M2L launch moves between L2 and the memory fabric (FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0, factors from a plain 1 GiB copy), read from the rocprofv3 summary
-# named in "source".  Reported only while the M2L kernel's source text (sha256 prefix of
+# Bytes that one M2L step (GEMM + slot sums) moves between L2 and the memory fabric
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a plain 1 GiB copy), read from the
+# rocprofv3 summary named in "source".  Reported only while the M2L kernel's source text (sha256 prefix of
 # the k_gemm template in eval.hip) and the plan's grouping (entry and work-item counts)
 # are the ones the counters were taken on; else null.
-M2L_TRAFFIC = {"kernel_sha256": None, "workload": "uniform-16M", "p": 12, "theta": 0.4,
-               "entries": None, "work_items": None, "bytes": None,
+M2L_TRAFFIC = {"kernel_sha256": "6a28cdac88939087", "workload": "uniform-16M", "p": 12, "theta": 0.4,
+               "entries": 7271803, "work_items": 1040804, "bytes": 796.8e9,
                "source": "profiles/m2l_uniform-16M_hbm_bytes.md"}
 
 
