@@ -55,6 +55,8 @@ def parse(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
     ap.add_argument("--m2l-tol", type=float, default=0.0,
                     help="variable-order M2L tolerance (0: dense operators, the configuration's method)")
+    ap.add_argument("--svd-tol", type=float, default=0.0,
+                    help="SVD-compressed M2L tolerance (0: dense operators, the configuration's method)")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-accuracy", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
@@ -150,7 +152,7 @@ class Refs:
         return out
 
 
-def run_steps(xt, qt, wt, ncrit, p, theta, precision, steps, warmup, m2l_tol=0.0):
+def run_steps(xt, qt, wt, ncrit, p, theta, precision, steps, warmup, m2l_tol=0.0, svd_tol=0.0):
     """Times `steps` whole steps (plan + eval + plan + adjoint) after `warmup` untimed
     ones; per-phase HIP-event times and plan statistics from the timed steps."""
     import torch
@@ -159,7 +161,7 @@ def run_steps(xt, qt, wt, ncrit, p, theta, precision, steps, warmup, m2l_tol=0.0
 
     def step(record):
         t0 = time.perf_counter()
-        plan = FMM(xt, ncrit, p, theta, precision, m2l_tol=m2l_tol)
+        plan = FMM(xt, ncrit, p, theta, precision, m2l_tol=m2l_tol, svd_tol=svd_tol)
         if record is not None:
             torch.cuda.synchronize()
             record["plan"].append(time.perf_counter() - t0)
@@ -171,7 +173,7 @@ def run_steps(xt, qt, wt, ncrit, p, theta, precision, steps, warmup, m2l_tol=0.0
             record["eval_phases"].append(plan.phase_times())
             record["stats"] = plan.stats()
         plan.close()
-        plan2 = FMM(xt, ncrit, p, theta, precision, m2l_tol=m2l_tol)
+        plan2 = FMM(xt, ncrit, p, theta, precision, m2l_tol=m2l_tol, svd_tol=svd_tol)
         if record is not None:
             plan2.set_timing(True)
         dq, dx = plan2.adjoint(qt, wt, gradient_fwd=grad)
@@ -183,7 +185,7 @@ def run_steps(xt, qt, wt, ncrit, p, theta, precision, steps, warmup, m2l_tol=0.0
     # the first plan of a process (per order) also builds the operator tables, a cached constant
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    FMM(xt, ncrit, p, theta, precision, m2l_tol=m2l_tol).close()
+    FMM(xt, ncrit, p, theta, precision, m2l_tol=m2l_tol, svd_tol=svd_tol).close()
     torch.cuda.synchronize()
     first_plan_ms = 1e3 * (time.perf_counter() - t0)
     for _ in range(warmup):
@@ -200,8 +202,8 @@ def run_steps(xt, qt, wt, ncrit, p, theta, precision, steps, warmup, m2l_tol=0.0
     phases = rec["eval_phases"] + rec["adj_phases"]
     ph = {k: float(np.mean([d[k] for d in phases])) for k in phases[0]}
     eval_ms = float(np.mean([d["total"] for d in rec["eval_phases"]]))
-    # the M2L phase spans the grouped GEMM and the fixed-order sum of split tiles; with a
-    # variable-order M2L only the applied operator blocks count as work
+    # the M2L phase spans the grouped GEMM and the fixed-order sums of split tiles and slots;
+    # with a variable-order or SVD-compressed M2L only the applied work counts
     m2l_tflops = st["m2l_flops"] * st["m2l_kept_fraction"] / (ph["m2l"] * 1e-3) / 1e12
     p2p_tflops = st["p2p_flops"] / (ph["p2p"] * 1e-3) / 1e12
     plan_ms = 1e3 * float(np.mean(rec["plan"]))
@@ -222,7 +224,7 @@ def run_steps(xt, qt, wt, ncrit, p, theta, precision, steps, warmup, m2l_tol=0.0
 
 def stats_keys(st):
     return {k: st[k] for k in ("ncells", "m2l_pairs", "m2l_keys", "m2l_entries", "m2l_work_items", "p2p_interactions",
-                               "m2l_kept_fraction", "workspace_bytes")}
+                               "m2l_kept_fraction", "m2l_svd_rank_mean", "m2l_slots", "workspace_bytes")}
 
 
 def accuracy_sweep(args, xt, qt, wt, n, ncrit, reps=5):
@@ -365,7 +367,7 @@ def main():
     print(f"[bench] {args.workload} n={n} p={p} {args.precision}: {args.steps} steps after {args.warmup}",
           file=sys.stderr, flush=True)
     run, (phi, grad, dq, dx) = run_steps(xt, qt, wt, ncrit, p, theta, args.precision, args.steps, args.warmup,
-                                         args.m2l_tol)
+                                         args.m2l_tol, args.svd_tol)
     st = run.pop("stats")
     result = {
         "metric": "Laplace FMM particles/s at 1e-4 rel err (fwd, fwd+adjoint); P2P TFLOP/s",
@@ -381,7 +383,8 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "mixed(f16x3 MFMA, f32, f64)",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "distribution": dist, "p": p, "ncrit": ncrit, "theta": theta,
-                   "precision": args.precision, "m2l_tol": args.m2l_tol, "step": "plan + eval + plan + adjoint"},
+                   "precision": args.precision, "m2l_tol": args.m2l_tol, "svd_tol": args.svd_tol,
+                   "step": "plan + eval + plan + adjoint"},
     }
     result.update({k: v for k, v in run.items() if k not in ("particles_per_s", "ms_per_step")})
     result.update(stats_keys(st))
@@ -399,7 +402,7 @@ def main():
             result["value"] = None
     del phi, grad, dq, dx
 
-    if not args.headline_only and args.precision == "fp32" and args.m2l_tol == 0.0:
+    if not args.headline_only and args.precision == "fp32" and args.m2l_tol == 0.0 and args.svd_tol == 0.0:
         ks, kw = min(args.steps, 5), min(args.warmup, 1)
         # the mixed-precision form on the same workload
         print("[bench] mixed precision", file=sys.stderr, flush=True)

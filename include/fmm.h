@@ -118,6 +118,22 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
  * Other arguments, ownership and errors as fmm_plan; EINVAL for a negative, NaN or
  * infinite m2l_tol, m2l_tol > 0 with FMM_PREC_MIXED, or an unknown lists value.
  */
+/*
+ * fmm_plan with SVD-compressed M2L operators (the paper: an SVD of the translation matrices
+ * gives what expansions of varying order give, systematically; Sec. 2.2, Sec. 5).  Every
+ * operator A (one per relative offset) is replaced by a rank-r product Pf Qf from the SVD of
+ * W A W, W = diag(h^n / sqrt((n+m)!(n-m)!)) with h = sqrt(3)/2 (the bounds of a multipole
+ * coefficient of degree n per unit charge, and of a local coefficient's reach on the
+ * potential): singular values at or below svd_tol times the largest are dropped.  M2L then
+ * applies two products per pair, Qf (r x (p+1)^2) and Pf ((p+1)^2 x r), r rounded up to a
+ * multiple of 16.  0 < svd_tol < 1; FP32 precision; other arguments, ownership and errors
+ * as fmm_plan (EINVAL for svd_tol outside [0, 1)).  svd_tol = 0 is fmm_plan.  The factors
+ * are computed on the host (all cores) on first use of a (p, key, svd_tol) and cached for
+ * the life of the process.
+ */
+fmm_status fmm_plan_svd(const float *points, int64_t n, int ncrit, int p, float theta, double svd_tol,
+                        void *stream, fmm_plan_t *out);
+
 #define FMM_LISTS_DUAL 0
 #define FMM_LISTS_LEVEL_SKIP 1
 fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta,
@@ -249,6 +265,8 @@ struct fmm_stats {
     int64_t m2l_slots;                      /* slots: (target, source-side cell of the split that produced
                                                the pairs), one partial column each */
     int64_t m2l_slot_tiles;                 /* tiles of 64 slots with one key sequence */
+    double svd_tol;                         /* SVD-compressed M2L tolerance (0: dense operators) */
+    double m2l_svd_rank_mean;               /* pair-weighted mean rank of the compressed operators */
 };
 /* Host copy of the plan's statistics: tree shape, interaction-list sizes (the paper's
  * list-size count of Sec. 2.2 is m2l_pairs per target box in a uniform region), the work

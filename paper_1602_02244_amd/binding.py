@@ -49,6 +49,7 @@ class FmmStats(C.Structure):
         ("m2l_tol", C.c_double), ("m2l_kept_fraction", C.c_double), ("lists", C.c_int64),
         ("p2p_work_items", C.c_int64), ("p2p_split_pieces", C.c_int64),
         ("m2l_pool_pairs", C.c_int64), ("m2l_slots", C.c_int64), ("m2l_slot_tiles", C.c_int64),
+        ("svd_tol", C.c_double), ("m2l_svd_rank_mean", C.c_double),
     ]
 
 
@@ -87,6 +88,7 @@ def load_library():
     lib.fmm_adjoint_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.fmm_plan_targets.argtypes = [_vp, C.c_int64, _vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, _vp,
                                      C.POINTER(_vp)]
+    lib.fmm_plan_svd.argtypes = [_vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_double, _vp, C.POINTER(_vp)]
     lib.fmm_eval_targets.argtypes = [_vp, _vp, _vp, _vp, _vp]
     lib.fmm_adjoint_targets.argtypes = [_vp] + [_vp] * 8
     lib.fmm_plan_stats.argtypes = [_vp, C.POINTER(FmmStats)]
@@ -95,7 +97,7 @@ def load_library():
     lib.fmm_plan_phase_times.argtypes = [_vp, C.POINTER(C.c_float)]
     lib.fmm_plan_destroy.argtypes = [_vp]
     lib.fmm_plan_destroy.restype = None
-    for f in ("fmm_set_allocator", "fmm_plan", "fmm_plan_ex", "fmm_eval", "fmm_eval_ex", "fmm_adjoint",
+    for f in ("fmm_set_allocator", "fmm_plan", "fmm_plan_ex", "fmm_plan_svd", "fmm_eval", "fmm_eval_ex", "fmm_adjoint",
               "fmm_eval_hessian", "fmm_adjoint_ex", "fmm_plan_targets", "fmm_eval_targets",
               "fmm_adjoint_targets", "fmm_plan_stats",
               "fmm_plan_export", "fmm_plan_set_timing", "fmm_plan_phase_times"):
@@ -189,11 +191,13 @@ class FMM:
 
     points: float32 device tensor [n, 3].  The plan is built on the current stream.
     m2l_tol > 0 selects the variable-order M2L (operator blocks below that relative size
-    are left out; FP32 only), 0 the dense operators.  lists: "dual" (the dual traversal)
-    or "level-skip" (one cell of a same-level pair split at a time).
+    are left out; FP32 only), 0 the dense operators.  svd_tol > 0 selects SVD-compressed
+    operators (singular values of the bound-weighted operator at or below svd_tol times the
+    largest dropped; FP32 only, not with m2l_tol or level-skip lists).  lists: "dual" (the
+    dual traversal) or "level-skip" (one cell of a same-level pair split at a time).
     """
 
-    def __init__(self, points, ncrit=64, p=10, theta=0.4, precision="fp32", m2l_tol=0.0, lists="dual"):
+    def __init__(self, points, ncrit=64, p=10, theta=0.4, precision="fp32", m2l_tol=0.0, lists="dual", svd_tol=0.0):
         lib = load_library()
         if points.dim() != 2 or points.shape[1] != 3:
             raise ValueError("points must have shape [n, 3]")
@@ -209,9 +213,16 @@ class FMM:
             raise ValueError(f"lists must be one of {list(_LISTS)}")
         self.lists = lists
         self.device = points.device
+        self.svd_tol = float(svd_tol)
         h = _vp()
-        _check(lib.fmm_plan_ex(ptr, self.n, self.ncrit, self.p, C.c_float(self.theta), _PREC[precision],
-                               C.c_double(self.m2l_tol), _LISTS[lists], _stream_handle(), C.byref(h)))
+        if self.svd_tol != 0.0:
+            if self.m2l_tol != 0.0 or lists != "dual":
+                raise ValueError("EINVAL: svd_tol takes the dense dual-traversal plan (m2l_tol = 0, lists = 'dual')")
+            _check(lib.fmm_plan_svd(ptr, self.n, self.ncrit, self.p, C.c_float(self.theta), C.c_double(self.svd_tol),
+                                    _stream_handle(), C.byref(h)))
+        else:
+            _check(lib.fmm_plan_ex(ptr, self.n, self.ncrit, self.p, C.c_float(self.theta), _PREC[precision],
+                                   C.c_double(self.m2l_tol), _LISTS[lists], _stream_handle(), C.byref(h)))
         self._h = h
 
     # -------------------------------------------------------------- lifetime

@@ -134,6 +134,8 @@ void fill_stats(fmm_plan_s *P) {
     st.m2l_pool_pairs = P->npool;
     st.m2l_slots = P->nslots;
     st.m2l_slot_tiles = P->nslot_tiles;
+    st.svd_tol = P->svd_tol;
+    st.m2l_svd_rank_mean = P->svd_rank_mean;
 }
 }  // namespace
 
@@ -159,7 +161,7 @@ fmm_status fmm_plan(const float *points, int64_t n, int ncrit, int p, float thet
 // targets, sources first.
 static fmm_status plan_create(const float *points, int64_t n, const float *targets, int64_t nt, int ncrit, int p,
                               float theta, fmm_precision prec, double m2l_tol, int lists, void *stream,
-                              fmm_plan_t *out) {
+                              fmm_plan_t *out, double svd_tol = 0.0) {
     if (!out) return set_err(FMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!points) return set_err(FMM_EINVAL, "points is NULL");
@@ -179,6 +181,10 @@ static fmm_status plan_create(const float *points, int64_t n, const float *targe
     if (m2l_tol > 0.0 && prec != FMM_PREC_FP32)
         return set_err(FMM_EINVAL, "a variable-order M2L (m2l_tol > 0) needs FMM_PREC_FP32");
     if (lists != FMM_LISTS_DUAL && lists != FMM_LISTS_LEVEL_SKIP) return set_err(FMM_EINVAL, "unknown lists value");
+    if (!std::isfinite(svd_tol) || svd_tol < 0.0 || svd_tol >= 1.0)
+        return set_err(FMM_EINVAL, "svd_tol must be in [0, 1)");
+    if (svd_tol > 0.0 && prec != FMM_PREC_FP32)
+        return set_err(FMM_EINVAL, "an SVD-compressed M2L (svd_tol > 0) needs FMM_PREC_FP32");
     fmm_plan_s *P = new (std::nothrow) fmm_plan_s();
     if (!P) return set_err(FMM_ENOMEM, "host allocation failed");
     P->n = n;
@@ -189,6 +195,7 @@ static fmm_status plan_create(const float *points, int64_t n, const float *targe
     P->theta = theta;
     P->prec = prec;
     P->m2l_tol = m2l_tol;
+    P->svd_tol = svd_tol;
     P->lists = lists;
     P->KP = ncoef_pad(p);
     {
@@ -227,6 +234,12 @@ static fmm_status plan_create(const float *points, int64_t n, const float *targe
 fmm_status fmm_plan_ex(const float *points, int64_t n, int ncrit, int p, float theta, fmm_precision prec,
                        double m2l_tol, int lists, void *stream, fmm_plan_t *out) {
     return plan_create(points, n, nullptr, 0, ncrit, p, theta, prec, m2l_tol, lists, stream, out);
+}
+
+fmm_status fmm_plan_svd(const float *points, int64_t n, int ncrit, int p, float theta, double svd_tol, void *stream,
+                        fmm_plan_t *out) {
+    return plan_create(points, n, nullptr, 0, ncrit, p, theta, FMM_PREC_FP32, 0.0, FMM_LISTS_DUAL, stream, out,
+                       svd_tol);
 }
 
 fmm_status fmm_plan_targets(const float *sources, int64_t ns, const float *targets, int64_t nt, int ncrit, int p,

@@ -378,6 +378,137 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
     }
 }
 
+// ------------------------------------------------------------------ M2L, SVD-compressed operators
+// The same work items, tiles and entries as k_gemm; every key's operator is applied in
+// factored form, A ~ Pf Qf with rank rp (a multiple of 16): per entry Y = Qf Ms (rp x 64,
+// k over the KP coefficients), then acc += Pf Y (k over the rank).  Workgroup = 4 waves; in
+// the first product wave w computes column block w of Y for every row block, in the second
+// it owns output row blocks w, w+4, ... as in k_gemm.  Ms (the gathered source vectors) and
+// then Y share one LDS buffer; no software pipelining.
+template <int P>
+__global__ void __launch_bounds__(256) k_gemm_svd(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
+                                                  const uint8_t *entry_mask, const uint64_t *key_svd,
+                                                  const int32_t *key_rank, const float *M, float *L, float *partial,
+                                                  const int32_t *tile_targets) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP;
+    constexpr int KPS = KP + 4;                  // LDS row stride
+    constexpr int NRB = KP / 16;                 // row blocks of the output (and of Y at full rank)
+    constexpr int RBW = (NRB + 3) / 4;           // output row blocks per wave
+    constexpr int NKC = KP / 16;                 // k chunks of the first product
+    static_assert(kTileN == 64, "four 16-column blocks");
+    __shared__ __attribute__((aligned(16))) float Ms[kTileN * KPS];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int4 w = work[blockIdx.x];
+    const int e0 = w.y, e1 = w.z;
+    if (e0 >= e1) return;
+    floatx4 acc[RBW][4];
+#pragma unroll
+    for (int r = 0; r < RBW; ++r)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int gcol = tid >> 2, gsub = tid & 3;
+    for (int e = e0; e < e1; ++e) {
+        const int key = __builtin_amdgcn_readfirstlane(entry_key[e]);
+        const int rp = __builtin_amdgcn_readfirstlane(key_rank[key]);
+        const int m = __builtin_amdgcn_readfirstlane((int)entry_mask[e]);
+        const gfloatx4 *Qg = (const gfloatx4 *)reinterpret_cast<const float *>(key_svd[2 * key]);
+        const gfloatx4 *Pg = (const gfloatx4 *)reinterpret_cast<const float *>(key_svd[2 * key + 1]);
+        const int src = entry_src[(int64_t)e * kTileN + gcol];
+        __syncthreads();   // the previous entry is done with the buffer
+#pragma unroll
+        for (int i = 0; i < NKC; ++i) {
+            // coefficients 16 i + 4 gsub + j go to positions 16 i + 4 j + gsub
+            const float4 v = src >= 0 ? reinterpret_cast<const float4 *>(M + (int64_t)src * KP)[4 * i + gsub]
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+            float *row = &Ms[gcol * KPS + 16 * i + gsub];
+            row[0] = v.x;
+            row[4] = v.y;
+            row[8] = v.z;
+            row[12] = v.w;
+        }
+        __syncthreads();
+        // first product: column block `wave` of Y for every row block below rp
+        const int nrb = rp / 16;
+        floatx4 y[NRB];
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) y[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const bool mine = (m >> wave) & 1;
+        if (mine) {
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) {
+                const float4 b = *reinterpret_cast<const float4 *>(&Ms[(wave * 16 + li) * KPS + kc * 16 + 4 * lg]);
+#pragma unroll
+                for (int r = 0; r < NRB; ++r) {
+                    if (r >= nrb) break;
+                    const floatx4 a = Qg[((r * 16 + li) * KP + kc * 16 + 4 * lg) / 4];
+                    y[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, y[r], 0, 0, 0);
+                    if (16 * kc + 4 < D::NC) y[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, y[r], 0, 0, 0);
+                    if (16 * kc + 8 < D::NC) y[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, y[r], 0, 0, 0);
+                    if (16 * kc + 12 < D::NC) y[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, y[r], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();   // every wave is done reading Ms
+        // Y into the buffer, in the transposed-chunk order of a B operand: column c of Y is
+        // buffer row c, rank index k at position 16 (k / 16) + 4 (k % 4) + (k % 16) / 4
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) {
+            if (r >= nrb) break;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = r * 16 + 4 * lg + v;
+                Ms[(wave * 16 + li) * KPS + 16 * (k / 16) + 4 * (k % 4) + (k % 16) / 4] = y[r][v];
+            }
+        }
+        __syncthreads();
+        // second product: acc (KP x 64) += Pf (KP x rp) Y (rp x 64)
+        for (int kc = 0; kc < nrb; ++kc) {
+            floatx4 a[RBW];
+#pragma unroll
+            for (int r = 0; r < RBW; ++r) {
+                const int rb = min(wave + 4 * r, NRB - 1);
+                a[r] = Pg[((rb * 16 + li) * rp + kc * 16 + 4 * lg) / 4];
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                if (!((m >> cb) & 1)) continue;
+                const float4 b = *reinterpret_cast<const float4 *>(&Ms[(cb * 16 + li) * KPS + kc * 16 + 4 * lg]);
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) {
+                    if (NRB % 4 != 0 && wave + 4 * r >= NRB) continue;
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, b.z, acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, b.w, acc[r][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // output: lane holds D[4*lg + v][li] of each 16x16 block
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+        const int rb = wave + 4 * r;
+        if (rb >= NRB) continue;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int col = cb * 16 + li;
+            float *dst;
+            if (w.w == 0) {
+                const int t = tile_targets[(int64_t)w.x * kTileN + col];
+                if (t < 0) continue;
+                dst = L + (int64_t)t * KP;
+            } else {
+                dst = partial + ((int64_t)(w.w - 1) * kTileN + col) * KP;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[rb * 16 + 4 * lg + v] = acc[r][cb][v];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ M2L, split FP16 on MFMA
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
@@ -1457,6 +1588,11 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
                                (const uint8_t *)Pl->entry_mask, Pl->key_f16, (const _Float16 *)Pl->Mh,
                                (const _Float16 *)Pl->Ml, (const float *)Pl->Msinv, Pl->L, Pl->partial,
                                (const int32_t *)Pl->tile_targets);
+        else if (Pl->key_svd)
+            hipLaunchKernelGGL(k_gemm_svd<P>, (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
+                               (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,
+                               (const uint8_t *)Pl->entry_mask, Pl->key_svd, (const int32_t *)Pl->key_rank,
+                               (const float *)Pl->M, Pl->L, Pl->partial, (const int32_t *)Pl->tile_targets);
         else if (Pl->key_rows)
             hipLaunchKernelGGL((k_gemm<P, false, true, true>), (int)Pl->nwork, 256, 0, s, (const int4 *)Pl->work,
                                (const int32_t *)Pl->entry_key, (const int32_t *)Pl->entry_src,

@@ -142,6 +142,11 @@ void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uin
 // their summed weighted size stays within tol of the interaction's monopole term.
 void m2l_block_rows(int p, const std::vector<uint64_t> &keys, double tol, std::vector<uint32_t> &rows,
                     std::vector<float> &kept);
+// SVD-compressed M2L: for every key, device pointers of its factors Qf ([rp][KP]) and Pf
+// ([KP][rp]) at ptrs[2 i], ptrs[2 i + 1], the rank kept and its padding to a multiple of 16
+// (singular values of the bound-weighted operator above tol * sigma_1 are kept).
+void m2l_svd_ptrs(int p, const std::vector<uint64_t> &keys, double tol, std::vector<uint64_t> &ptrs,
+                  std::vector<int32_t> &rank_pad, std::vector<int32_t> &rank);
 // FP64 M2L operators ([KP in][KP out], transposed) of the given keys.
 void m2l_operator_ptrs64(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f64_ptrs);
 constexpr int kRootLevels = 4;     // mixed precision: levels 0..3 keep FP64 coefficients
@@ -179,6 +184,10 @@ struct LevelGemm {
 // --------------------------------------------------------------------- the plan
 struct fmm_plan_s {
     double m2l_tol = 0.0;        // variable-order M2L tolerance (0: dense operators)
+    double svd_tol = 0.0;        // SVD-compressed M2L tolerance (0: dense operators)
+    const uint64_t *key_svd = nullptr;  // [nkeys][2] device pointers of the SVD factors (Qf, Pf)
+    int32_t *key_rank = nullptr;        // [nkeys] padded rank of each key's factors
+    double svd_rank_mean = 0.0;         // pair-weighted mean rank kept
     int lists = 0;               // 0: dual traversal; 1: level skip (one cell split at a time)
     double m2l_kept = 1.0;       // pair-weighted fraction of operator blocks applied
     uint32_t *key_rows = nullptr; // [nkeys][KP/16 + 1] kept k-chunk masks per row block, then their union

@@ -30,7 +30,9 @@
 #include <algorithm>
 #include <complex>
 #include <cmath>
+#include <map>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "fmm_internal.h"
@@ -228,8 +230,8 @@ void split16(const std::vector<double> &A, int p, int KP, std::vector<char> &out
 // potential with a weight of at most h^j / nu_jk.  Returned: for every block, the sum of
 // |w_r A_rc w_c| over the block, divided by |w_0 A_00 w_0| (the monopole-to-monopole
 // term, i.e. the size of the whole interaction).
-std::vector<float> block_sums(const std::vector<double> &A, int p, int KP) {
-    const int NB = KP / 16;
+// Bound weights of the coefficients: h^l / nu_lm (h = sqrt(3)/2), zero on the padding.
+std::vector<double> bound_weights(int p, int KP) {
     const double h = std::sqrt(3.0) / 2;
     std::vector<double> nu = nu_vector(p, KP), w(KP, 0.0);
     for (int l = 0; l <= p; ++l)
@@ -237,6 +239,12 @@ std::vector<float> block_sums(const std::vector<double> &A, int p, int KP) {
             w[ridx(l, m, 0)] = std::pow(h, l) / nu[ridx(l, m, 0)];
             if (m > 0) w[ridx(l, m, 1)] = std::pow(h, l) / nu[ridx(l, m, 1)];
         }
+    return w;
+}
+
+std::vector<float> block_sums(const std::vector<double> &A, int p, int KP) {
+    const int NB = KP / 16;
+    std::vector<double> w = bound_weights(p, KP);
     std::vector<double> b((size_t)NB * NB, 0.0);
     for (int r = 0; r < KP; ++r)
         for (int c = 0; c < KP; ++c) b[(size_t)(r / 16) * NB + c / 16] += std::fabs(w[r] * A[(size_t)r * KP + c] * w[c]);
@@ -244,6 +252,168 @@ std::vector<float> block_sums(const std::vector<double> &A, int p, int KP) {
     std::vector<float> out(b.size());
     for (size_t i = 0; i < b.size(); ++i) out[i] = ref > 0 ? (float)(b[i] / ref) : 1.f;
     return out;
+}
+
+// ------------------------------------------------------------------ SVD-compressed M2L
+// Low-rank form of an M2L operator (Sec. 2.2: an SVD of the translation matrices gives what
+// expansions of varying order give, systematically).  The SVD is taken of the weighted
+// operator B = W A W, W = diag(bound weights): a multipole coefficient of degree n is at most
+// h^n / nu_nm times the source's total |charge| and a local coefficient of degree j reaches
+// the potential with at most the same weight, so B's singular values measure what each
+// direction can add to a potential.  Singular values at or below tol * sigma_1 are dropped;
+// A ~ (W^-1 U_r Sigma_r) (V_r^T W^-1) = Pf Qf, applied as two skinny products: Y = Qf M
+// (r x KP times KP), then L += Pf Y.
+//
+// The SVD: Householder QR with column pivoting of B, stopped once every remaining column
+// is below tol * (largest column norm) / sqrt(n) (so the dropped part is below tol * sigma_1),
+// then one-sided Jacobi (Hestenes) rotations on the transposed triangular factor.
+struct SvdFactor {
+    int r = 0;                     // rank kept
+    std::vector<double> Pf, Qf;    // [n][r] and [r][n] (n = coefficient count)
+};
+
+SvdFactor svd_factor(const std::vector<double> &A, int p, int KP, double tol) {
+    const int n = ncoef(p);
+    std::vector<double> w = bound_weights(p, KP);
+    // B column-major (n x n)
+    std::vector<double> B((size_t)n * n);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) B[i + (size_t)j * n] = w[i] * A[(size_t)i * KP + j] * w[j];
+    std::vector<int> piv(n);
+    for (int j = 0; j < n; ++j) piv[j] = j;
+    std::vector<double> cn(n);
+    auto colnorm2 = [&](int j, int from) {
+        double t = 0;
+        for (int i = from; i < n; ++i) t += B[i + (size_t)j * n] * B[i + (size_t)j * n];
+        return t;
+    };
+    double cmax = 0;
+    for (int j = 0; j < n; ++j) { cn[j] = colnorm2(j, 0); cmax = std::max(cmax, cn[j]); }
+    const double stop2 = (tol * std::sqrt(cmax)) * (tol * std::sqrt(cmax)) / n;
+    std::vector<std::vector<double>> refl;   // Householder vectors (length n - j), beta folded in
+    std::vector<double> betas;
+    int k = 0;
+    for (int j = 0; j < n; ++j) {
+        int pc = j;
+        for (int c = j + 1; c < n; ++c)
+            if (cn[c] > cn[pc]) pc = c;
+        if (cn[pc] <= stop2 || cn[pc] == 0) break;
+        if (pc != j) {
+            for (int i = 0; i < n; ++i) std::swap(B[i + (size_t)j * n], B[i + (size_t)pc * n]);
+            std::swap(cn[j], cn[pc]);
+            std::swap(piv[j], piv[pc]);
+        }
+        // reflector zeroing B(j+1:n, j)
+        std::vector<double> v(n - j);
+        double alpha = 0;
+        for (int i = j; i < n; ++i) { v[i - j] = B[i + (size_t)j * n]; alpha += v[i - j] * v[i - j]; }
+        alpha = std::sqrt(alpha);
+        if (v[0] > 0) alpha = -alpha;
+        v[0] -= alpha;
+        double vn = 0;
+        for (double x : v) vn += x * x;
+        const double beta = vn > 0 ? 2.0 / vn : 0.0;
+        for (int c = j; c < n; ++c) {
+            double d = 0;
+            for (int i = j; i < n; ++i) d += v[i - j] * B[i + (size_t)c * n];
+            d *= beta;
+            for (int i = j; i < n; ++i) B[i + (size_t)c * n] -= d * v[i - j];
+        }
+        refl.push_back(std::move(v));
+        betas.push_back(beta);
+        for (int c = j + 1; c < n; ++c) cn[c] = colnorm2(c, j + 1);
+        k = j + 1;
+    }
+    SvdFactor f;
+    if (k == 0) return f;
+    // explicit Q (n x k, column-major): reflectors applied to the first k unit columns
+    std::vector<double> Q((size_t)n * k, 0.0);
+    for (int c = 0; c < k; ++c) {
+        Q[c + (size_t)c * n] = 1.0;
+        for (int j = k - 1; j >= 0; --j) {
+            const std::vector<double> &v = refl[j];
+            double d = 0;
+            for (int i = j; i < n; ++i) d += v[i - j] * Q[i + (size_t)c * n];
+            d *= betas[j];
+            for (int i = j; i < n; ++i) Q[i + (size_t)c * n] -= d * v[i - j];
+        }
+    }
+    // X = R^T (n x k, column-major; row index = pivoted column position), V = I (k x k)
+    std::vector<double> X((size_t)n * k, 0.0), V((size_t)k * k, 0.0);
+    for (int c = 0; c < k; ++c)
+        for (int i = c; i < n; ++i) X[i + (size_t)c * n] = B[c + (size_t)i * n];
+    for (int c = 0; c < k; ++c) V[c + (size_t)c * k] = 1.0;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        bool rotated = false;
+        for (int a = 0; a < k - 1; ++a)
+            for (int b = a + 1; b < k; ++b) {
+                double al = 0, be = 0, ga = 0;
+                for (int i = 0; i < n; ++i) {
+                    const double xa = X[i + (size_t)a * n], xb = X[i + (size_t)b * n];
+                    al += xa * xa;
+                    be += xb * xb;
+                    ga += xa * xb;
+                }
+                if (std::fabs(ga) <= 1e-15 * std::sqrt(al * be) || ga == 0) continue;
+                rotated = true;
+                const double zeta = (be - al) / (2 * ga);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1 + zeta * zeta));
+                const double cs = 1 / std::sqrt(1 + t * t), sn = cs * t;
+                for (int i = 0; i < n; ++i) {
+                    const double xa = X[i + (size_t)a * n], xb = X[i + (size_t)b * n];
+                    X[i + (size_t)a * n] = cs * xa - sn * xb;
+                    X[i + (size_t)b * n] = sn * xa + cs * xb;
+                }
+                for (int i = 0; i < k; ++i) {
+                    const double va = V[i + (size_t)a * k], vb = V[i + (size_t)b * k];
+                    V[i + (size_t)a * k] = cs * va - sn * vb;
+                    V[i + (size_t)b * k] = sn * va + cs * vb;
+                }
+            }
+        if (!rotated) break;
+    }
+    // X V = U Sigma: sigma_c = |X_c|; R = V Sigma U^T; B ~ (Q V) Sigma (Pi U)^T
+    std::vector<std::pair<double, int>> sig(k);
+    for (int c = 0; c < k; ++c) {
+        double t = 0;
+        for (int i = 0; i < n; ++i) t += X[i + (size_t)c * n] * X[i + (size_t)c * n];
+        sig[c] = {std::sqrt(t), c};
+    }
+    std::sort(sig.begin(), sig.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+        return x.first > y.first;
+    });
+    int r = 0;
+    while (r < k && sig[r].first > tol * sig[0].first) ++r;
+    f.r = r;
+    f.Pf.assign((size_t)n * r, 0.0);
+    f.Qf.assign((size_t)r * n, 0.0);
+    for (int q = 0; q < r; ++q) {
+        const int c = sig[q].second;
+        const double sv = sig[q].first;
+        // left vector: Q V_c (n), scaled by sigma and un-weighted
+        for (int i = 0; i < n; ++i) {
+            double t = 0;
+            for (int j = 0; j < k; ++j) t += Q[i + (size_t)j * n] * V[j + (size_t)c * k];
+            f.Pf[(size_t)i * r + q] = t * sv / w[i];
+        }
+        // right vector: U_c = X_c / sigma in pivoted positions, back to column order, un-weighted
+        for (int i = 0; i < n; ++i) f.Qf[(size_t)q * n + piv[i]] = X[i + (size_t)c * n] / sv / w[piv[i]];
+    }
+    return f;
+}
+
+// GEMM layouts of a factor pair with the rank padded to rp (a multiple of 16): Qf as
+// [rp][KP] and Pf as [KP][rp], both with the 4 x 4 transpose inside every 16-wide chunk of
+// columns (see to_gemm_layout); padding is zero.
+void svd_gemm_layout(const SvdFactor &f, int p, int KP, int rp, float *dst) {
+    const int n = ncoef(p), r = f.r;
+    float *q = dst, *pp = dst + (size_t)rp * KP;
+    std::fill(dst, dst + (size_t)2 * rp * KP, 0.f);
+    auto tpos = [](int c) { return 16 * (c / 16) + 4 * (c % 4) + (c % 16) / 4; };
+    for (int a = 0; a < r; ++a)
+        for (int c = 0; c < n; ++c) q[(size_t)a * KP + tpos(c)] = (float)f.Qf[(size_t)a * n + c];
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < r; ++a) pp[(size_t)i * rp + tpos(a)] = (float)f.Pf[(size_t)i * r + a];
 }
 
 // ------------------------------------------------------------------ device store
@@ -266,9 +436,37 @@ struct BlockPool {
     }
 };
 
+// Device memory for variable-size blocks (SVD factors): bump allocation inside 64 MB
+// chunks that are never moved or freed.
+struct Arena {
+    std::vector<char *> chunks;
+    size_t used = 0, cap = 0;
+    void *take(size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        if (chunks.empty() || used + bytes > cap) {
+            const size_t sz = std::max(bytes, size_t(64) << 20);
+            char *c = nullptr;
+            HIP_CHECK(hipMalloc(&c, sz));
+            chunks.push_back(c);
+            used = 0;
+            cap = sz;
+        }
+        void *r = chunks.back() + used;
+        used += bytes;
+        return r;
+    }
+};
+
+struct SvdEntry {
+    uint64_t q = 0, pp = 0;   // device pointers of Qf [rp][KP] and Pf [KP][rp]
+    int32_t r = 0, rp = 0;
+};
+
 struct Store {
     int p = -1;
     size_t mat_floats = 0;
+    std::map<std::pair<uint64_t, double>, SvdEntry> svd;   // (key, tolerance) -> factors
+    Arena svd_arena;
     std::unordered_map<uint64_t, uint64_t> f32;   // key -> device pointer
     std::unordered_map<uint64_t, uint64_t> f16;   // key -> device pointer (split FP16 form)
     std::unordered_map<uint64_t, uint64_t> f64;   // key -> device pointer (FP64, transposed)
@@ -420,6 +618,55 @@ void m2l_block_rows(int p, const std::vector<uint64_t> &keys, double tol, std::v
             rows[i * (NB + 1) + NB] |= 1u << (blk % NB);      // chunks used by any row block
         }
         kept[i] = (float)(order.size() - nd) / (float)order.size();
+    }
+}
+
+void m2l_svd_ptrs(int p, const std::vector<uint64_t> &keys, double tol, std::vector<uint64_t> &ptrs,
+                  std::vector<int32_t> &rank_pad, std::vector<int32_t> &rank) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Store &s = store_for(p);
+    const int KP = ncoef_pad(p);
+    const size_t nk = keys.size();
+    // factors missing from the cache, computed on all host cores
+    std::vector<size_t> todo;
+    for (size_t i = 0; i < nk; ++i)
+        if (!s.svd.count({keys[i], tol})) todo.push_back(i);
+    std::vector<SvdFactor> fac(todo.size());
+    {
+        const unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 64));
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t] {
+                std::vector<double> A;
+                for (size_t j = t; j < todo.size(); j += nt) {
+                    build_m2l(p, keys[todo[j]], A);
+                    fac[j] = svd_factor(A, p, KP, tol);
+                }
+            });
+        for (auto &x : th) x.join();
+    }
+    std::vector<float> host;
+    for (size_t j = 0; j < todo.size(); ++j) {
+        SvdEntry e;
+        e.r = fac[j].r;
+        e.rp = std::max(16, (e.r + 15) / 16 * 16);
+        host.assign((size_t)2 * e.rp * KP, 0.f);
+        svd_gemm_layout(fac[j], p, KP, e.rp, host.data());
+        char *d = static_cast<char *>(s.svd_arena.take(sizeof(float) * host.size()));
+        HIP_CHECK(hipMemcpy(d, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice));
+        e.q = (uint64_t)(uintptr_t)d;
+        e.pp = (uint64_t)(uintptr_t)(d + sizeof(float) * (size_t)e.rp * KP);
+        s.svd[{keys[todo[j]], tol}] = e;
+    }
+    ptrs.resize(2 * nk);
+    rank_pad.resize(nk);
+    rank.resize(nk);
+    for (size_t i = 0; i < nk; ++i) {
+        const SvdEntry &e = s.svd.at({keys[i], tol});
+        ptrs[2 * i] = e.q;
+        ptrs[2 * i + 1] = e.pp;
+        rank_pad[i] = e.rp;
+        rank[i] = e.r;
     }
 }
 

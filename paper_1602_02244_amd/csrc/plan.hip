@@ -1170,9 +1170,10 @@ struct SlotTiles {
 // Groups the pool pairs into slots and slot tiles; fills P->slot_pos (partial column of
 // every slot, relative to the first slot tile), P->run_first / P->run_tgt / P->nruns (the
 // slots of each target, for the fixed-order sum) and `st` (what the entry builders need).
+// Unless `keep`, gives the pool up (st.abandoned, no tiles) when its slots would tile poorly.
 static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64_t nm2l, const int32_t *key_id,
                         const uint8_t *gen, const int32_t *pool, const int32_t *pool_at, int64_t npool, Alloc &a,
-                        hipStream_t s, SlotTiles &st) {
+                        hipStream_t s, SlotTiles &st, bool keep) {
     Mailbox &mb = *a.mb;
     StageLog lg;
     lg.s = s;
@@ -1211,7 +1212,7 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64
     lg("  slots: slot info");
     if (lg.on) fprintf(stderr, "[fmm plan]   %lld of %lld slots from sources with empty octants\n",
                        (long long)partial_oct, (long long)ns);
-    if (2 * partial_oct > ns) {
+    if (!keep && 2 * partial_oct > ns) {
         // most sources miss octants (a surface-like cloud): signatures would be too many
         a.put(sig); a.put(err);
         st.release(a);
@@ -1259,7 +1260,7 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64
     std::sort(hsig.begin(), hsig.end());
     const int64_t nsig = (int64_t)hsig.size();
     st.nsig = nsig;
-    if (ns < (int64_t)kSlotsPerSig * nsig) {
+    if (!keep && ns < (int64_t)kSlotsPerSig * nsig) {
         // slots with this many key sequences fill their tiles poorly: the pairs stay in the
         // target tiles (the caller rebuilds the dense cells)
         a.put(table); a.put(at); a.put(sig);
@@ -1781,12 +1782,25 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             mb.upload(d16, p16.data(), 8 * nkeys, s);
             P->key_f16 = d16;
         }
-        std::vector<float> key_kept;
+        std::vector<float> key_kept;   // per key: fraction of the dense operator's flops applied
+        std::vector<int32_t> svd_rank;
         if (P->m2l_tol > 0) {
             std::vector<uint32_t> rows;
             m2l_block_rows(P->p, hkeys, P->m2l_tol, rows, key_kept);
             P->key_rows = a.get_n<uint32_t>((int64_t)rows.size());
             mb.upload(P->key_rows, rows.data(), 4 * rows.size(), s);
+        } else if (P->svd_tol > 0) {
+            // SVD-compressed operators: two products of rank r cost 4 r NC flop per pair
+            std::vector<uint64_t> sp;
+            std::vector<int32_t> rpad;
+            m2l_svd_ptrs(P->p, hkeys, P->svd_tol, sp, rpad, svd_rank);
+            uint64_t *dsp = a.get_n<uint64_t>(2 * nkeys);
+            mb.upload(dsp, sp.data(), 8 * sp.size(), s);
+            P->key_svd = dsp;
+            P->key_rank = a.get_n<int32_t>(nkeys);
+            mb.upload(P->key_rank, rpad.data(), 4 * nkeys, s);
+            key_kept.resize(nkeys);
+            for (int64_t k2 = 0; k2 < nkeys; ++k2) key_kept[k2] = (float)(2.0 * svd_rank[k2] / ncoef(P->p));
         }
         uint64_t *dkeys = a.get_n<uint64_t>(nkeys);
         mb.upload(dkeys, hkeys.data(), 8 * nkeys, s);
@@ -1824,7 +1838,9 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             npool = (int64_t)mb.data_host<uint64_t>()[0];
         }
         a.put(nsparse);
-        const bool try_pool = npool > 0 && 100 * npool >= (int64_t)kPoolMinPct * nm2l;
+        // fill_pct above 100 pools every pair and keeps the pool whatever its shape (a test mode)
+        const bool force_pool = fill_pct > 100;
+        const bool try_pool = npool > 0 && (force_pool || 100 * npool >= (int64_t)kPoolMinPct * nm2l);
         if (npool > 0 && !try_pool) {
             // a small pool is not built: every (tile, key) cell with a pair is an entry
             hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
@@ -1845,7 +1861,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             int32_t *pool_at = a.get_n<int32_t>(nm2l);
             npool = exclusive_scan_i32(pool, pool_at, nm2l, a, s);
             lg("m2l dense cells");
-            build_slots(P, C, m2l, nm2l, pkid, m2l_gen, pool, pool_at, npool, a, s, st);
+            build_slots(P, C, m2l, nm2l, pkid, m2l_gen, pool, pool_at, npool, a, s, st, force_pool);
             a.put(pool_at);
         }
         if (pool) a.put(pool);
@@ -1894,7 +1910,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
                                (const int32_t *)st.sig_n, ne_d, P->entry_key);
         }
         P->entry_mask = a.get_n<uint8_t>(ne);
-        int32_t *nsrc = P->m2l_tol > 0 ? a.get_n<int32_t>(ne) : nullptr;
+        int32_t *nsrc = !key_kept.empty() ? a.get_n<int32_t>(ne) : nullptr;
         hipLaunchKernelGGL(k_entry_masks, grid1(ne), 256, 0, s, (const int32_t *)P->entry_src, ne, P->entry_mask, nsrc);
         if (nsrc) {
             // pair-weighted fraction of operator blocks the variable-order M2L applies
@@ -1902,12 +1918,14 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             HIP_CHECK(hipMemcpyAsync(hn.data(), nsrc, 4 * ne, hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipMemcpyAsync(hk.data(), P->entry_key, 4 * ne, hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
-            double num = 0, den = 0;
+            double num = 0, den = 0, rk = 0;
             for (int64_t e2 = 0; e2 < ne; ++e2) {
                 num += (double)hn[e2] * key_kept[hk[e2]];
                 den += (double)hn[e2];
+                if (!svd_rank.empty()) rk += (double)hn[e2] * svd_rank[hk[e2]];
             }
             P->m2l_kept = den > 0 ? num / den : 1.0;
+            P->svd_rank_mean = den > 0 ? rk / den : 0.0;
             a.put(nsrc);
         }
         int32_t *tile_first = a.get_n<int32_t>(ntiles);

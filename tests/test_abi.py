@@ -76,6 +76,16 @@ def test_plan_ex_rejects_bad_arguments_before_any_device_call(lib, tol, prec, li
     assert st == FMM_EINVAL and out.value is None
 
 
+@pytest.mark.parametrize("tol", [-1e-3, 1.0, 2.0, float("nan"), float("inf")])
+def test_plan_svd_rejects_bad_tolerance_before_any_device_call(lib, tol):
+    lib.fmm_plan_svd.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_double, C.c_void_p,
+                                 C.POINTER(C.c_void_p)]
+    lib.fmm_plan_svd.restype = C.c_int
+    out = C.c_void_p(1234)
+    st = lib.fmm_plan_svd(C.c_void_p(0x1000), 10, 64, 4, 0.4, tol, None, C.byref(out))
+    assert st == FMM_EINVAL and out.value is None
+
+
 def test_null_pointers_rejected(lib):
     st, _ = _plan(lib, None, 10, 64, 4, 0.4)
     assert st == FMM_EINVAL
