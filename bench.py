@@ -10,8 +10,9 @@ uniform in the unit cube, p = 12, ncrit = 64, theta = 0.4); the forward-only and
 evaluation-only rates are reported beside it.  Inputs are resident in device memory
 before timing starts.
 
-Beside the headline the same run reports: the mixed-precision form on the same
-workload, the throughput at the smallest order p whose result still meets 1e-4, the
+Beside the headline the same run reports: the mixed-precision form and the
+SVD-compressed M2L (tolerance 1e-5) on the same workload, the throughput at the smallest
+order p whose result still meets 1e-4, the
 uniform 2^20-point workload at p = 10, and the FP64 oracle timed on the host cores on a
 bounded sample.  Accuracy is checked against the exact FP64 direct sum on 1000
 sampled targets (phi, grad phi, dL/dq, dL/dx); `value` is null unless all four are
@@ -416,6 +417,21 @@ def main():
         mixed["speedup_vs_fp32_step"] = run["ms_per_step"] / mr["ms_per_step"]
         del mphi, mgrad, mdq, mdx, mst
         result["mixed"] = mixed
+        # the SVD-compressed M2L at a tolerance that keeps the FP32 accuracy
+        print("[bench] SVD-compressed M2L", file=sys.stderr, flush=True)
+        sv_tol = 1e-5
+        vr, (vphi, vgrad, vdq, vdx) = run_steps(xt, qt, wt, ncrit, p, theta, "fp32", ks, kw, svd_tol=sv_tol)
+        vst = vr.pop("stats")
+        svd = {k: vr[k] for k in ("particles_per_s", "ms_per_step", "fwd_particles_per_s", "eval_particles_per_s",
+                                  "plan_ms", "table_build_ms", "phase_ms")}
+        svd.update(svd_tol=sv_tol, steps=ks, warmup=kw, m2l_svd_rank_mean=vst["m2l_svd_rank_mean"],
+                   m2l_factored_tflops=vr["m2l_tflops"],
+                   m2l_dense_equivalent_tflops=vst["m2l_flops"] / (vr["phase_ms"]["m2l"] * 1e-3) / 1e12,
+                   speedup_vs_fp32_step=run["ms_per_step"] / vr["ms_per_step"])
+        if refs is not None:
+            svd["rel_err_vs_direct_1000"] = refs.errors(vphi, vgrad, vdq, vdx)
+        del vphi, vgrad, vdq, vdx
+        result["svd"] = svd
         # throughput at the smallest order that still meets 1e-4
         if refs is not None:
             p_star, tried = smallest_order(xt, qt, wt, ncrit, theta, refs, p)

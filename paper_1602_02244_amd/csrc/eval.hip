@@ -384,7 +384,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 1
 // k over the KP coefficients), then acc += Pf Y (k over the rank).  Workgroup = 4 waves; in
 // the first product wave w computes column block w of Y for every row block, in the second
 // it owns output row blocks w, w+4, ... as in k_gemm.  Ms (the gathered source vectors) and
-// then Y share one LDS buffer; no software pipelining.
+// then Y share one LDS buffer.  The next entry's source vectors are loaded into registers
+// while the second product runs (every load is consumed before the next is issued).
 template <int P>
 __global__ void __launch_bounds__(256) k_gemm_svd(const int4 *work, const int32_t *entry_key, const int32_t *entry_src,
                                                   const uint8_t *entry_mask, const uint64_t *key_svd,
@@ -410,25 +411,33 @@ __global__ void __launch_bounds__(256) k_gemm_svd(const int4 *work, const int32_
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int gcol = tid >> 2, gsub = tid & 3;
+    // source vectors of the current entry, in registers until they are stored to LDS
+    float4 pre[NKC];
+    int src = entry_src[(int64_t)e0 * kTileN + gcol];
+    auto gather = [&](int sv) {
+#pragma unroll
+        for (int i = 0; i < NKC; ++i) pre[i] = reinterpret_cast<const float4 *>(M + (int64_t)max(sv, 0) * KP)[4 * i + gsub];
+    };
+    gather(src);
     for (int e = e0; e < e1; ++e) {
         const int key = __builtin_amdgcn_readfirstlane(entry_key[e]);
         const int rp = __builtin_amdgcn_readfirstlane(key_rank[key]);
         const int m = __builtin_amdgcn_readfirstlane((int)entry_mask[e]);
         const gfloatx4 *Qg = (const gfloatx4 *)reinterpret_cast<const float *>(key_svd[2 * key]);
         const gfloatx4 *Pg = (const gfloatx4 *)reinterpret_cast<const float *>(key_svd[2 * key + 1]);
-        const int src = entry_src[(int64_t)e * kTileN + gcol];
+        const int src_next = entry_src[(int64_t)min(e + 1, e1 - 1) * kTileN + gcol];
         __syncthreads();   // the previous entry is done with the buffer
 #pragma unroll
         for (int i = 0; i < NKC; ++i) {
             // coefficients 16 i + 4 gsub + j go to positions 16 i + 4 j + gsub
-            const float4 v = src >= 0 ? reinterpret_cast<const float4 *>(M + (int64_t)src * KP)[4 * i + gsub]
-                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 v = src >= 0 ? pre[i] : make_float4(0.f, 0.f, 0.f, 0.f);
             float *row = &Ms[gcol * KPS + 16 * i + gsub];
             row[0] = v.x;
             row[4] = v.y;
             row[8] = v.z;
             row[12] = v.w;
         }
+        src = src_next;
         __syncthreads();
         // first product: column block `wave` of Y for every row block below rp
         const int nrb = rp / 16;
@@ -464,6 +473,7 @@ __global__ void __launch_bounds__(256) k_gemm_svd(const int4 *work, const int32_
             }
         }
         __syncthreads();
+        gather(src);   // the next entry's sources (a repeat of the last entry's at the end)
         // second product: acc (KP x 64) += Pf (KP x rp) Y (rp x 64)
         for (int kc = 0; kc < nrb; ++kc) {
             floatx4 a[RBW];
