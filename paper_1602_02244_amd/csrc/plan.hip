@@ -227,32 +227,21 @@ struct CellView {
     int lists;                // 0: rule 3 splits both cells; 1: only the smaller prefix (level skip)
 };
 
-__device__ inline int wave_incl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int t = __shfl_up(v, off, 64);
-        if (lane >= off) v += t;
-    }
-    return v;
-}
-
-// Block-wide exclusive scan of three counters (256 threads).
-__device__ inline void block_scan3(int v0, int v1, int v2, int &e0, int &e1, int &e2, int &t0, int &t1, int &t2) {
-    __shared__ int ws[3][4];
+// Exclusive scan of four wave-uniform counters over the four waves of a 256-thread
+// block: `off` = the counts of the waves before this one, `tot` = the block's totals.
+__device__ inline void block_scan_waves4(const int (&v)[4], int (&off)[4], int (&tot)[4]) {
+    __shared__ int ws[4][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int i0 = wave_incl_scan(v0), i1 = wave_incl_scan(v1), i2 = wave_incl_scan(v2);
-    if (lane == 63) { ws[0][wave] = i0; ws[1][wave] = i1; ws[2][wave] = i2; }
+    if (lane == 0)
+        for (int c = 0; c < 4; ++c) ws[c][wave] = v[c];
     __syncthreads();
-    int p0 = 0, p1 = 0, p2 = 0;
-    t0 = t1 = t2 = 0;
-    for (int w = 0; w < 4; ++w) {
-        if (w < wave) { p0 += ws[0][w]; p1 += ws[1][w]; p2 += ws[2][w]; }
-        t0 += ws[0][w]; t1 += ws[1][w]; t2 += ws[2][w];
+    for (int c = 0; c < 4; ++c) {
+        off[c] = tot[c] = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wave) off[c] += ws[c][w];
+            tot[c] += ws[c][w];
+        }
     }
-    e0 = p0 + i0 - v0;
-    e1 = p1 + i1 - v1;
-    e2 = p2 + i2 - v2;
     __syncthreads();
 }
 
@@ -339,29 +328,35 @@ __global__ void k_trav_post(unsigned long long *cnt, unsigned long long *post, u
         post[0] = cnt[0];
         post[1] = cnt[1];
         post[2] = cnt[2];
+        post[3] = cnt[3];
         cnt[2] = 0;
         mailbox_post(flag, ticket);
     }
 }
-__global__ void k_set_counters(unsigned long long *cnt, int64_t nm, int64_t np) {
+__global__ void k_set_counters(unsigned long long *cnt, int64_t nm, int64_t np, int64_t nr) {
     if (threadIdx.x == 0) {
         cnt[0] = (unsigned long long)nm;
         cnt[1] = (unsigned long long)np;
         cnt[2] = 0;
+        cnt[3] = (unsigned long long)nr;
     }
 }
 
 // Each wave takes kTravPerWave frontier pairs in turn, one lane per child pair (at most
-// 8 x 8); the lane keeps its outcomes, the block reserves its output ranges once.  The
-// frontier pair and its split are wave-uniform; the data of the children are loaded once
-// (lanes 0-7: children of A, lanes 8-15: children of B) and passed on by cross-lane
-// shuffles.  An M2L pair also marks its target and enters its operator key into the key
-// table (the slot is stored beside the pair).
+// 8 x 8); the frontier pair and its split are wave-uniform; the data of the children are
+// loaded once (lanes 0-7: children of A, lanes 8-15: children of B) and passed on by
+// cross-lane shuffles.  Outputs are written in (wave, frontier pair, lane) order, so
+// that the lanes of one store write consecutive words and the M2L pairs of one target
+// child (lanes 8x .. 8x+7) are consecutive: such a group is a slot, and one record per
+// slot is written beside the pairs (target, first pair, the frontier pair's source cell,
+// how the frontier pair was split and the slot's pair count).  An M2L pair also marks its
+// target and enters its operator key into the key table (the slot is stored beside the pair).
 struct TravOut {
     int2 *m2l;
     int32_t *m2l_slot;
-    uint8_t *m2l_gen;     // per M2L pair: bit 0 the pair that produced it split its target side, bit 1 its source side
     int64_t cap_m;
+    int4 *rec;            // slot records {target, first pair, source-side cell, split bits | count << 2}
+    int64_t cap_r;
     int2 *p2p;
     int64_t cap_p;
     int2 *next;
@@ -377,9 +372,9 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t f0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + wave) * kTravPerWave;
     const int lane = threadIdx.x & 63, x = lane >> 3, y = lane & 7;
-    int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave], gen[kTravPerWave];
+    int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave], gsrc[kTravPerWave], gen[kTravPerWave];
     uint64_t key[kTravPerWave];
-    int m = 0, q = 0, nx = 0;
+    int cw[4] = {0, 0, 0, 0};   // this wave's M2L pairs, P2P pairs, next pairs, slot records
 #pragma unroll
     for (int k = 0; k < kTravPerWave; ++k) {
         const int64_t f = f0 + k;
@@ -387,12 +382,14 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
         act[k] = -1;
         key[k] = 0;
         gen[k] = 0;
+        gsrc[k] = 0;
         if (f < nf) {
             int a0, na, b0, nb;
             const int2 pr = front[f];
             const int ga = __builtin_amdgcn_readfirstlane(pr.x), gb = __builtin_amdgcn_readfirstlane(pr.y);
             split_ranges(C, ga, gb, a0, na, b0, nb);
             gen[k] = (a0 != ga ? 1 : 0) | (b0 != gb ? 2 : 0);
+            gsrc[k] = gb;
             const bool ld = lane < 8 ? lane < na : (lane < 16 && lane - 8 < nb);
             const int cell = lane < 8 ? a0 + lane : b0 + (lane - 8);
             int lv = 0, cx = 0, cy = 0, cz = 0, ch = 0;
@@ -430,38 +427,50 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
                 }
             }
         }
-        m += act[k] == 0;
-        q += act[k] == 1;
-        nx += act[k] == 2;
+        const uint64_t bm = __ballot(act[k] == 0);
+        cw[0] += __popcll(bm);
+        cw[1] += __popcll(__ballot(act[k] == 1));
+        cw[2] += __popcll(__ballot(act[k] == 2));
+        cw[3] += __popcll(__ballot(y == 0 && ((bm >> (8 * x)) & 0xffull) != 0));
     }
-    int e0, e1, e2, t0, t1, t2;
-    block_scan3(m, q, nx, e0, e1, e2, t0, t1, t2);
-    __shared__ unsigned long long base[3];
-    if (threadIdx.x == 0) {
-        base[0] = t0 ? atomicAdd(&cnt[0], (unsigned long long)t0) : 0;
-        base[1] = t1 ? atomicAdd(&cnt[1], (unsigned long long)t1) : 0;
-        base[2] = t2 ? atomicAdd(&cnt[2], (unsigned long long)t2) : 0;
-    }
+    int off[4], tot[4];
+    block_scan_waves4(cw, off, tot);
+    __shared__ unsigned long long base[4];
+    if (threadIdx.x < 4) base[threadIdx.x] = tot[threadIdx.x] ? atomicAdd(&cnt[threadIdx.x], (unsigned long long)tot[threadIdx.x]) : 0;
     __syncthreads();
-    int64_t wm = (int64_t)(base[0] + e0), wq = (int64_t)(base[1] + e1), wn = (int64_t)(base[2] + e2);
+    int64_t wm = (int64_t)base[0] + off[0], wq = (int64_t)base[1] + off[1], wn = (int64_t)base[2] + off[2],
+            wr = (int64_t)base[3] + off[3];
+    const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int k = 0; k < kTravPerWave; ++k) {
         const int2 v = make_int2(pa[k], pb[k]);
+        const uint64_t bm = __ballot(act[k] == 0), bq = __ballot(act[k] == 1), bn = __ballot(act[k] == 2);
+        const int mine = (int)((bm >> (8 * x)) & 0xffull);
+        const bool lead = y == 0 && mine != 0;
+        const uint64_t br = __ballot(lead);
         if (act[k] == 0) {
-            if (wm < o.cap_m) {
-                o.m2l[wm] = v;
-                o.m2l_slot[wm] = key_slot(key[k], o.table, o.mask, o.flags);
-                o.m2l_gen[wm] = (uint8_t)gen[k];
+            const int64_t i = wm + __popcll(bm & lt);
+            if (i < o.cap_m) {
+                o.m2l[i] = v;
+                o.m2l_slot[i] = key_slot(key[k], o.table, o.mask, o.flags);
             }
             o.is_target[pa[k]] = 1;
-            ++wm;
         } else if (act[k] == 1) {
-            if (wq < o.cap_p) o.p2p[wq] = v;
-            ++wq;
+            const int64_t i = wq + __popcll(bq & lt);
+            if (i < o.cap_p) o.p2p[i] = v;
         } else if (act[k] == 2) {
-            if (wn < o.cap_n) o.next[wn] = v;
-            ++wn;
+            const int64_t i = wn + __popcll(bn & lt);
+            if (i < o.cap_n) o.next[i] = v;
         }
+        if (lead) {
+            const int64_t i = wr + __popcll(br & lt);
+            const int64_t first = wm + __popcll(bm & lt);   // lane 8x: the M2L pairs of lanes < 8x come first
+            if (i < o.cap_r) o.rec[i] = make_int4(pa[k], (int)first, gsrc[k], gen[k] | (__popc(mine) << 2));
+        }
+        wm += __popcll(bm);
+        wq += __popcll(bq);
+        wn += __popcll(bn);
+        wr += __popcll(br);
     }
 }
 
@@ -566,7 +575,7 @@ __global__ void __launch_bounds__(256) k_dense_flags(const unsigned long long *l
 // the other cells are flagged for the slot pool (when `pool` is given).
 __global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pair_key_id, const int32_t *cell_tile,
                                const int32_t *cell_lane, const int32_t *present, const int32_t *entry_of,
-                               int64_t nkeys, int32_t *entry_src, int32_t *pool) {
+                               int64_t nkeys, int32_t *entry_src, uint8_t *pool) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         const int a = pairs[i].x;
         const int64_t tk = (int64_t)cell_tile[a] * nkeys + pair_key_id[i];
@@ -579,79 +588,70 @@ __global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pai
 // ---------------------------------------------------------------- M2L slot pool
 // Pairs of sparse (tile, key) cells are regrouped by the pair of cells the traversal split
 // to produce them: a slot is (target t, the source-side cell B of that pair), holding the
-// pairs (t, child of B) -- or the one pair (t, B) when B was not split.  Slots whose pairs
-// have the same key sequence (signature) share tiles of 64 columns, one column per slot,
-// so every column of every entry holds a source; each slot's column is a partial local
-// expansion of its target, and the targets' partials are summed in a fixed order.
+// pairs (t, child of B) -- or the one pair (t, B) when B was not split.  The traversal
+// writes the pairs of a slot consecutively, in source order, with one record per slot.
+// Slots whose pooled pairs have the same key sequence (signature) share tiles of 64
+// columns, one column per slot, so every column of every entry holds a source; each
+// slot's column is a partial local expansion of its target, and the targets' partials are
+// summed in a fixed order.
 
 __device__ inline int cell_octant(const CellView &C, int c) {
     return ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1);
 }
 
-// Sort keys of the pool pairs: (target, source, how the producing pair was split) in
-// `cbits`, `cbits` and 2 bits; values = pair index.
-__global__ void k_pool_keys(const int2 *pairs, const uint8_t *gen, int64_t np, const int32_t *pool,
-                            const int32_t *pool_at, int cbits, uint64_t *keys, int32_t *vals) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
-        if (pool[i]) {
-            const int64_t j = pool_at[i];
-            keys[j] = ((((uint64_t)pairs[i].x << cbits) | (uint64_t)pairs[i].y) << 2) | (uint64_t)(gen[i] & 3);
-            vals[j] = (int32_t)i;
-        }
-}
-
-struct PoolKey {   // a sorted pool key unpacked
-    int t, s, g;
-};
-__device__ inline PoolKey pool_key(uint64_t k, int cbits) {
-    const uint64_t m = (uint64_t(1) << cbits) - 1;
-    return PoolKey{(int)((k >> (cbits + 2)) & m), (int)((k >> 2) & m), (int)(k & 3)};
-}
-// Source-side cell of the pair that produced a pool pair: the source's parent when that
-// side was split, else the source itself.
-__device__ inline int gen_source(const PoolKey &p, const int32_t *parent) { return (p.g & 2) ? parent[p.s] : p.s; }
-
-// Slot boundaries along the sorted pool: a new slot where the target, the way the
-// producing pair was split, or its source-side cell changes.
-__global__ void k_slot_flags(const uint64_t *pk, int cbits, const int32_t *parent, int64_t npool, int32_t *flag) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npool; j += (int64_t)gridDim.x * blockDim.x) {
-        int f = 1;
-        if (j > 0) {
-            const PoolKey a = pool_key(pk[j], cbits), b = pool_key(pk[j - 1], cbits);
-            f = (a.t != b.t || a.g != b.g || gen_source(a, parent) != gen_source(b, parent)) ? 1 : 0;
-        }
-        flag[j] = f;
+// Pooled pairs of every slot record (bit j: the record's j-th pair went to the pool);
+// records with any are flagged.
+__global__ void k_rec_members(const int4 *rec, int64_t nrec, const uint8_t *pool, int32_t *mbits, int32_t *flag) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrec; r += (int64_t)gridDim.x * blockDim.x) {
+        const int4 R = rec[r];
+        const int c = R.w >> 2;
+        int m = 0;
+        for (int j = 0; j < c; ++j) m |= pool[(int64_t)R.y + j] ? 1 << j : 0;
+        mbits[r] = m;
+        flag[r] = m != 0;
     }
 }
 
-// Per slot: first pool position, pair count, target, and signature = (key id of its first
-// pair, target side split, source side split, target octant when split, octants of its
-// sources when split).  Given how the producing pair was split, the first key, the target
-// octant and the source octants fix that pair's geometry and so every key of the slot in
-// source order: slots with equal signatures have equal key sequences.
-__global__ void __launch_bounds__(256) k_slot_info(const uint64_t *pk, int cbits, const int32_t *key_id,
-                                                   const int32_t *order, const int32_t *flag, const int32_t *slot_at,
-                                                   int64_t npool, CellView C, int32_t *slot_first, int32_t *slot_cnt,
-                                                   int32_t *slot_tgt, uint64_t *slot_sig, int32_t *err,
-                                                   unsigned long long *partial_octants) {
+// Sort keys of the pooled slots: (target, source-side cell, how the producing pair was
+// split) in `cbits`, `cbits` and 2 bits -- unique per slot, so the order is the same on
+// every run whatever order the traversal wrote the records in; values = record index.
+__global__ void k_rec_keys(const int4 *rec, const int32_t *flag, const int32_t *at, int64_t nrec, int cbits,
+                           uint64_t *keys, int32_t *vals) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrec; r += (int64_t)gridDim.x * blockDim.x)
+        if (flag[r]) {
+            const int4 R = rec[r];
+            const int64_t j = at[r];
+            keys[j] = ((((uint64_t)R.x << cbits) | (uint64_t)R.z) << 2) | (uint64_t)(R.w & 3);
+            vals[j] = (int32_t)r;
+        }
+}
+
+// Per slot (in sorted order): first pair of its record, its pooled pairs (bits relative to
+// the first), target, and signature = (key id of its first pooled pair, target side split,
+// source side split, target octant when split, octants of its pooled sources when split).
+// Given how the producing pair was split, the first key, the target octant and the source
+// octants fix that pair's geometry and so every key of the slot in source order: slots
+// with equal signatures have equal key sequences.
+__global__ void __launch_bounds__(256) k_slot_info(const int4 *rec, const int32_t *mbits, const int32_t *order,
+                                                   int64_t ns, const int2 *pairs, const int32_t *key_id, CellView C,
+                                                   int32_t *slot_first, int32_t *slot_mb, int32_t *slot_tgt,
+                                                   uint64_t *slot_sig, unsigned long long *partial_octants) {
     unsigned long long part = 0;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npool; j += (int64_t)gridDim.x * blockDim.x) {
-        if (!flag[j]) continue;
-        const int64_t q = slot_at[j];
-        const int64_t i0 = order[j];
-        const PoolKey p0 = pool_key(pk[j], cbits);
-        const int t = p0.t, g = p0.g;
-        int c = 0, smask = 0;
-        for (int64_t jj = j; jj < npool && (jj == j || !flag[jj]); ++jj, ++c)
-            if (g & 2) smask |= 1 << cell_octant(C, pool_key(pk[jj], cbits).s);
-        if (c > 8) err[0] = 1;   // a slot holds the pairs of one split cell: never more than 8
-        if ((g & 2) && c < 8) ++part;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x) {
+        const int r = order[q];
+        const int4 R = rec[r];
+        const int m = mbits[r], g = R.w & 3, t = R.x;
+        int smask = 0;
+        if (g & 2)
+            for (int mm = m; mm; mm &= mm - 1)
+                smask |= 1 << cell_octant(C, pairs[(int64_t)R.y + __builtin_ctz(mm)].y);
+        if ((g & 2) && __popc(m) < 8) ++part;
         const uint64_t ot = (g & 1) ? (uint64_t)cell_octant(C, t) : 0;
-        slot_first[q] = (int32_t)j;
-        slot_cnt[q] = c;
+        slot_first[q] = R.y;
+        slot_mb[q] = m;
         slot_tgt[q] = t;
-        slot_sig[q] = (uint64_t)(uint32_t)key_id[i0] | ((uint64_t)(g & 1) << 32) | ((uint64_t)((g >> 1) & 1) << 33) |
-                      (ot << 34) | ((uint64_t)smask << 37);
+        slot_sig[q] = (uint64_t)(uint32_t)key_id[(int64_t)R.y + __builtin_ctz(m)] | ((uint64_t)(g & 1) << 32) |
+                      ((uint64_t)((g >> 1) & 1) << 33) | (ot << 34) | ((uint64_t)smask << 37);
     }
     block_add_u64(part, partial_octants);
 }
@@ -698,12 +698,14 @@ __global__ void k_group_rep(const int32_t *gflag, const int32_t *sorted, const i
 }
 
 // Key sequence of every signature, from its representative slot ([nsig][8], count in sig_n).
-__global__ void k_sig_keys(const int32_t *rep, int64_t nsig, const int32_t *slot_first, const int32_t *slot_cnt,
-                           const int32_t *order, const int32_t *key_id, int32_t *sig_keys, int32_t *sig_n) {
+__global__ void k_sig_keys(const int32_t *rep, int64_t nsig, const int32_t *slot_first, const int32_t *slot_mb,
+                           const int32_t *key_id, int32_t *sig_keys, int32_t *sig_n) {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nsig; g += (int64_t)gridDim.x * blockDim.x) {
-        const int q = rep[g], c = slot_cnt[q], j0 = slot_first[q];
-        sig_n[g] = c;
-        for (int e = 0; e < 8; ++e) sig_keys[g * 8 + e] = e < c ? key_id[order[j0 + e]] : 0;
+        const int q = rep[g], f = slot_first[q];
+        int e = 0;
+        for (int mm = slot_mb[q]; mm; mm &= mm - 1) sig_keys[g * 8 + e++] = key_id[(int64_t)f + __builtin_ctz(mm)];
+        sig_n[g] = e;
+        for (; e < 8; ++e) sig_keys[g * 8 + e] = 0;
     }
 }
 
@@ -752,15 +754,15 @@ __global__ void k_tile_sig(const int32_t *tflag, const int32_t *tid, const int32
 // slot tile T is partial tile `part0 + T`.
 __global__ void k_slot_entries(const int32_t *tflag, const int32_t *tid, const int32_t *flag, const int32_t *gid,
                                const int32_t *gstart, const int32_t *sorted, int64_t ns, const int32_t *slot_first,
-                               const int32_t *slot_cnt, const uint64_t *pk, int cbits, const int32_t *tile_eoff,
-                               int64_t e_base, int64_t part0, int32_t *entry_src, int64_t *slot_pos) {
+                               const int32_t *slot_mb, const int2 *pairs, const int32_t *tile_eoff, int64_t e_base,
+                               int64_t part0, int32_t *entry_src, int64_t *slot_pos) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x) {
         const int T = tid[j] + tflag[j] - 1;
         const int lane = (int)((j - gstart[gid[j] + flag[j] - 1]) % kTileN);
-        const int q = sorted[j];
-        const int64_t e0 = e_base + tile_eoff[T];
-        for (int e = 0; e < slot_cnt[q]; ++e)
-            entry_src[(e0 + e) * kTileN + lane] = pool_key(pk[slot_first[q] + e], cbits).s;
+        const int q = sorted[j], f = slot_first[q];
+        int64_t e = e_base + tile_eoff[T];
+        for (int mm = slot_mb[q]; mm; mm &= mm - 1, ++e)
+            entry_src[e * kTileN + lane] = pairs[(int64_t)f + __builtin_ctz(mm)].y;
         slot_pos[q] = (part0 + T) * kTileN + lane;
     }
 }
@@ -1150,19 +1152,15 @@ constexpr int kSlotsPerSig = 64;    // fewer slots per signature on average: the
 struct SlotTiles {
     bool abandoned = false;                         // the pool's slots were too diverse to tile well
     int64_t nslots = 0, ntiles = 0, ne = 0, nsig = 0;
-    int cbits = 0;
-    uint64_t *pk = nullptr;                         // sorted pool keys (target, source, split flags)
-    int32_t *order = nullptr;                       // pool position -> pair index (sorted by target, source)
-    int32_t *slot_first = nullptr, *slot_cnt = nullptr, *slot_tgt = nullptr;
+    int32_t *slot_first = nullptr, *slot_mb = nullptr, *slot_tgt = nullptr;   // slots in (target, source) order
     int32_t *sorted = nullptr;                      // tile order -> slot
     int32_t *gflag = nullptr, *gid = nullptr, *gstart = nullptr, *tflag = nullptr, *tid = nullptr;
     int32_t *tile_sig = nullptr, *tile_ne = nullptr, *tile_eoff = nullptr;
     int32_t *sig_keys = nullptr, *sig_n = nullptr;
     void release(Alloc &a) {
-        for (int32_t *p : {order, slot_first, slot_cnt, slot_tgt, sorted, gflag, gid, gstart, tflag, tid, tile_sig,
-                           tile_ne, tile_eoff, sig_keys, sig_n})
+        for (int32_t *p : {slot_first, slot_mb, slot_tgt, sorted, gflag, gid, gstart, tflag, tid, tile_sig, tile_ne,
+                           tile_eoff, sig_keys, sig_n})
             if (p) a.put(p);
-        if (pk) a.put(pk);
         *this = SlotTiles{};
     }
 };
@@ -1171,43 +1169,42 @@ struct SlotTiles {
 // every slot, relative to the first slot tile), P->run_first / P->run_tgt / P->nruns (the
 // slots of each target, for the fixed-order sum) and `st` (what the entry builders need).
 // Unless `keep`, gives the pool up (st.abandoned, no tiles) when its slots would tile poorly.
-static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64_t nm2l, const int32_t *key_id,
-                        const uint8_t *gen, const int32_t *pool, const int32_t *pool_at, int64_t npool, Alloc &a,
-                        hipStream_t s, SlotTiles &st, bool keep) {
+static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, const int32_t *key_id, const int4 *recs,
+                        int64_t nrec, const uint8_t *pool, int64_t npool, Alloc &a, hipStream_t s, SlotTiles &st,
+                        bool keep) {
     Mailbox &mb = *a.mb;
     StageLog lg;
     lg.s = s;
     const int64_t nc = P->ncells;
     const int cbits = bits_for(nc);
-    // pool pairs sorted by (target, source): a slot's pairs are consecutive, in source order
-    st.cbits = cbits;
-    st.pk = a.get_n<uint64_t>(npool);
-    st.order = a.get_n<int32_t>(npool);
-    uint64_t *&pk = st.pk;
-    hipLaunchKernelGGL(k_pool_keys, grid1(nm2l), 256, 0, s, m2l, gen, nm2l, pool, pool_at, cbits, pk, st.order);
-    radix_sort_u64(pk, st.order, npool, 2 * cbits + 2, a, s);
-    lg("  slots: pool sort");
-    int32_t *sflag = a.get_n<int32_t>(npool), *sat = a.get_n<int32_t>(npool);
-    hipLaunchKernelGGL(k_slot_flags, grid1(npool), 256, 0, s, (const uint64_t *)pk, cbits, (const int32_t *)P->c_parent,
-                       npool, sflag);
-    const int64_t ns = exclusive_scan_i32(sflag, sat, npool, a, s);
+    // records with pooled pairs, sorted by (target, source-side cell, split bits)
+    int32_t *mbits = a.get_n<int32_t>(nrec), *pflag = a.get_n<int32_t>(nrec), *pat = a.get_n<int32_t>(nrec);
+    hipLaunchKernelGGL(k_rec_members, grid1(nrec), 256, 0, s, recs, nrec, pool, mbits, pflag);
+    const int64_t ns = exclusive_scan_i32(pflag, pat, nrec, a, s);
+    uint64_t *pk = a.get_n<uint64_t>(ns);
+    int32_t *order = a.get_n<int32_t>(ns);
+    hipLaunchKernelGGL(k_rec_keys, grid1(nrec), 256, 0, s, recs, (const int32_t *)pflag, (const int32_t *)pat, nrec,
+                       cbits, pk, order);
+    a.put(pflag); a.put(pat);
+    radix_sort_u64(pk, order, ns, 2 * cbits + 2, a, s);
+    a.put(pk);
+    lg("  slots: sort");
     st.nslots = ns;
     st.slot_first = a.get_n<int32_t>(ns);
-    st.slot_cnt = a.get_n<int32_t>(ns);
+    st.slot_mb = a.get_n<int32_t>(ns);
     st.slot_tgt = a.get_n<int32_t>(ns);
     uint64_t *sig = a.get_n<uint64_t>(ns);
-    int32_t *err = a.get_n<int32_t>(4);   // [0] error flag, [2..3] slots whose split source has empty octants
-    fill_i32(err, 0, 4, s);
-    hipLaunchKernelGGL(k_slot_info, std::min(grid1(npool), 8192), 256, 0, s, (const uint64_t *)pk, cbits, key_id,
-                       (const int32_t *)st.order, (const int32_t *)sflag, (const int32_t *)sat, npool, C, st.slot_first,
-                       st.slot_cnt, st.slot_tgt, sig, err, reinterpret_cast<unsigned long long *>(err + 2));
-    a.put(sflag); a.put(sat);
+    unsigned long long *err = a.get_n<unsigned long long>(1);   // slots whose split source has empty octants
+    fill_i32(reinterpret_cast<int32_t *>(err), 0, 2, s);
+    hipLaunchKernelGGL(k_slot_info, std::min(grid1(ns), 8192), 256, 0, s, recs, (const int32_t *)mbits,
+                       (const int32_t *)order, ns, m2l, key_id, C, st.slot_first, st.slot_mb, st.slot_tgt, sig, err);
+    a.put(mbits); a.put(order);
     int64_t partial_oct = 0;
     {
-        int32_t h4[4];
-        std::memcpy(h4, mb.fetch(err, 16, s), 16);
-        if (h4[0]) fail(FMM_EDEVICE, "internal: an M2L slot with more than eight pairs");
-        std::memcpy(&partial_oct, h4 + 2, 8);
+        const uint64_t t = mb.next_ticket();
+        publish(err, 8, mb, t, s);
+        mb.wait(t, s);
+        partial_oct = (int64_t)mb.data_host<uint64_t>()[0];
     }
     lg("  slots: slot info");
     if (lg.on) fprintf(stderr, "[fmm plan]   %lld of %lld slots from sources with empty octants\n",
@@ -1304,8 +1301,7 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, int64
         st.sig_keys = a.get_n<int32_t>(8 * nsig);
         st.sig_n = a.get_n<int32_t>(nsig);
         hipLaunchKernelGGL(k_sig_keys, grid1(nsig), 256, 0, s, (const int32_t *)rep, nsig,
-                           (const int32_t *)st.slot_first, (const int32_t *)st.slot_cnt, (const int32_t *)st.order,
-                           key_id, st.sig_keys, st.sig_n);
+                           (const int32_t *)st.slot_first, (const int32_t *)st.slot_mb, key_id, st.sig_keys, st.sig_n);
         a.put(rep);
     }
     st.tflag = a.get_n<int32_t>(ns);
@@ -1376,15 +1372,18 @@ static void validate_m2l(fmm_plan_s *P, hipStream_t s) {
         if (ek[e] < 0 || ek[e] >= P->nkeys) bad("entry key", e, ek[e]);
     auto es = dl(P->entry_src, ne * kTileN, s);
     auto em = dl(P->entry_mask, ne, s);
+    int64_t nsrc = 0;
     for (int64_t e = 0; e < ne; ++e) {
         int m = 0;
         for (int l = 0; l < kTileN; ++l) {
             const int v = es[e * kTileN + l];
             if (v < -1 || v >= nc) bad("entry source", e * kTileN + l, v);
             if (v >= 0) m |= 1 << (l / 16);
+            nsrc += v >= 0;
         }
         if (m != em[e]) bad("entry mask", e, em[e]);
     }
+    if (nsrc != P->nm2l) bad("entry columns with a source (every M2L pair once)", 0, nsrc);
     auto tt = dl(P->tile_targets, nt * kTileN, s);
     for (int64_t i = 0; i < nt * kTileN; ++i)
         if (tt[i] < -1 || tt[i] >= nc) bad("tile target", i, tt[i]);
@@ -1560,12 +1559,12 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
     lg("m2m/l2l tiles");
     // ---- a4: dual traversal, one fused step per level of the pair tree
     const double theta2 = (double)P->theta * (double)P->theta;
-    unsigned long long *cnt = a.get_n<unsigned long long>(3);
-    fill_i32(reinterpret_cast<int32_t *>(cnt), 0, 6, s);
+    unsigned long long *cnt = a.get_n<unsigned long long>(4);
+    fill_i32(reinterpret_cast<int32_t *>(cnt), 0, 8, s);
     int2 *m2l = nullptr, *p2p = nullptr;
     int32_t *m2l_slot = nullptr;
-    uint8_t *m2l_gen = nullptr;
-    int64_t m2l_cap = 0, slot_cap = 0, gen_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0;
+    int4 *recs = nullptr;
+    int64_t m2l_cap = 0, slot_cap = 0, rec_cap = 0, p2p_cap = 0, nm2l = 0, np2p = 0, nrec = 0;
     // operator-key table filled by the traversal (its last word holds the two flags),
     // M2L targets marked by it
     const uint64_t H0 = uint64_t(1) << 16;
@@ -1577,10 +1576,11 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         np2p = 1;
     } else {
         // first guess of the list sizes (a uniform cloud at theta = 0.4 has ~450 M2L
-        // pairs per cell and ~75 P2P pairs per leaf); a step that overflows is repeated
+        // pairs per cell in ~90 slots and ~75 P2P pairs per leaf); a step that overflows
+        // is repeated
         grow(a, m2l, m2l_cap, 0, 512 * nc, s);
         grow(a, m2l_slot, slot_cap, 0, m2l_cap, s);
-        grow(a, m2l_gen, gen_cap, 0, m2l_cap, s);
+        grow(a, recs, rec_cap, 0, 128 * nc, s);
         grow(a, p2p, p2p_cap, 0, 96 * P->nleaves + 64, s);
         ktable = a.get_n<uint64_t>((int64_t)H0 + 1);
         HIP_CHECK(hipMemsetAsync(ktable, 0xff, 8 * H0, s));
@@ -1591,44 +1591,47 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         fill_i32(reinterpret_cast<int32_t *>(front), 0, 2, s);
         int64_t nf = 1;
         while (nf > 0) {
-            // steady state of a uniform tree: ~8 split pairs, ~56 M2L and ~8 P2P pairs per split pair
+            // steady state of a uniform tree: ~8 split pairs, ~56 M2L pairs in ~12 slots and
+            // ~8 P2P pairs per split pair
             int64_t cap_n = std::max<int64_t>(1024, std::min<int64_t>(64 * nf, 10 * nf));
             grow(a, m2l, m2l_cap, nm2l, nm2l + 64 * nf, s);
             grow(a, m2l_slot, slot_cap, nm2l, m2l_cap, s);
-            grow(a, m2l_gen, gen_cap, nm2l, m2l_cap, s);
+            grow(a, recs, rec_cap, nrec, nrec + 16 * nf, s);
             grow(a, p2p, p2p_cap, np2p, np2p + 12 * nf, s);
             int2 *next = a.get_n<int2>(cap_n);
-            uint64_t h3[3];
+            uint64_t h4[4];
             for (int attempt = 0;; ++attempt) {
                 const int64_t per_block = 4 * kTravPerWave;
                 const int64_t tb = (nf + per_block - 1) / per_block;
                 if (tb >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "traversal frontier too large");
                 const uint64_t t = mb.next_ticket();
-                const TravOut to{m2l, m2l_slot, m2l_gen, std::min(m2l_cap, gen_cap), p2p, p2p_cap, next, cap_n, ktable, H0 - 1,
-                                 reinterpret_cast<int32_t *>(ktable + H0), is_t};
+                const TravOut to{m2l, m2l_slot, std::min(m2l_cap, slot_cap), recs, rec_cap, p2p, p2p_cap, next, cap_n,
+                                 ktable, H0 - 1, reinterpret_cast<int32_t *>(ktable + H0), is_t};
                 hipLaunchKernelGGL(k_trav_step, (int)tb, 256, 0, s, C, (const int2 *)front, nf, theta2, cnt, to);
                 hipLaunchKernelGGL(k_trav_post, 1, 64, 0, s, cnt, mb.data_dev<unsigned long long>(), mb.flag_dev(), t);
                 mb.wait(t, s);
-                std::memcpy(h3, mb.data_host<uint64_t>(), sizeof(h3));
-                bool ok = (int64_t)h3[0] <= m2l_cap && (int64_t)h3[1] <= p2p_cap && (int64_t)h3[2] <= cap_n;
+                std::memcpy(h4, mb.data_host<uint64_t>(), sizeof(h4));
+                bool ok = (int64_t)h4[0] <= std::min(m2l_cap, slot_cap) && (int64_t)h4[1] <= p2p_cap &&
+                          (int64_t)h4[2] <= cap_n && (int64_t)h4[3] <= rec_cap;
                 if (ok) break;
                 if (attempt > 0) fail(FMM_EDEVICE, "traversal step overflowed twice");
-                hipLaunchKernelGGL(k_set_counters, 1, 64, 0, s, cnt, nm2l, np2p);
-                grow(a, m2l, m2l_cap, nm2l, (int64_t)h3[0], s);
+                hipLaunchKernelGGL(k_set_counters, 1, 64, 0, s, cnt, nm2l, np2p, nrec);
+                grow(a, m2l, m2l_cap, nm2l, (int64_t)h4[0], s);
                 grow(a, m2l_slot, slot_cap, nm2l, m2l_cap, s);
-                grow(a, m2l_gen, gen_cap, nm2l, m2l_cap, s);
-                grow(a, p2p, p2p_cap, np2p, (int64_t)h3[1], s);
-                if ((int64_t)h3[2] > cap_n) {
+                grow(a, recs, rec_cap, nrec, (int64_t)h4[3], s);
+                grow(a, p2p, p2p_cap, np2p, (int64_t)h4[1], s);
+                if ((int64_t)h4[2] > cap_n) {
                     a.put(next);
-                    cap_n = (int64_t)h3[2];
+                    cap_n = (int64_t)h4[2];
                     next = a.get_n<int2>(cap_n);
                 }
             }
-            nm2l = (int64_t)h3[0];
-            np2p = (int64_t)h3[1];
+            nm2l = (int64_t)h4[0];
+            np2p = (int64_t)h4[1];
+            nrec = (int64_t)h4[3];
             a.put(front);
             front = next;
-            nf = (int64_t)h3[2];
+            nf = (int64_t)h4[2];
         }
         a.put(front);
     }
@@ -1851,18 +1854,15 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         int64_t ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
         int32_t *dsrc = a.get_n<int32_t>(ne_d * kTileN);
         fill_i32(dsrc, -1, ne_d * kTileN, s);
-        int32_t *pool = try_pool ? a.get_n<int32_t>(nm2l) : nullptr;
+        uint8_t *pool = try_pool ? a.get_n<uint8_t>(nm2l) : nullptr;
         hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
                            (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)present,
                            (const int32_t *)entry_of, nkeys, dsrc, pool);
         SlotTiles st;
         if (try_pool) {
             // ---- slot pool (given up when its slots would tile poorly)
-            int32_t *pool_at = a.get_n<int32_t>(nm2l);
-            npool = exclusive_scan_i32(pool, pool_at, nm2l, a, s);
             lg("m2l dense cells");
-            build_slots(P, C, m2l, nm2l, pkid, m2l_gen, pool, pool_at, npool, a, s, st, force_pool);
-            a.put(pool_at);
+            build_slots(P, C, m2l, pkid, recs, nrec, pool, npool, a, s, st, force_pool);
         }
         if (pool) a.put(pool);
         if (st.ntiles == 0 && npool > 0) {
@@ -1875,14 +1875,15 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             fill_i32(dsrc, -1, ne_d * kTileN, s);
             hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
                                (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)present,
-                               (const int32_t *)entry_of, nkeys, dsrc, (int32_t *)nullptr);
+                               (const int32_t *)entry_of, nkeys, dsrc, (uint8_t *)nullptr);
         }
         if (st.ntiles == 0) npool = 0;
         P->npool = npool;
         P->nslots = st.nslots;
         P->nslot_tiles = st.ntiles;
         a.put(lanes);
-        a.put(m2l_gen);
+        a.put(recs);
+        recs = nullptr;
         lg("m2l slot pool");
 
         const int64_t ne = ne_d + st.ne;
@@ -1903,8 +1904,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             hipLaunchKernelGGL(k_slot_entries, grid1(st.nslots), 256, 0, s, (const int32_t *)st.tflag,
                                (const int32_t *)st.tid, (const int32_t *)st.gflag, (const int32_t *)st.gid,
                                (const int32_t *)st.gstart, (const int32_t *)st.sorted, st.nslots,
-                               (const int32_t *)st.slot_first, (const int32_t *)st.slot_cnt, (const uint64_t *)st.pk,
-                               st.cbits, (const int32_t *)st.tile_eoff, ne_d, (int64_t)0, P->entry_src, P->slot_pos);
+                               (const int32_t *)st.slot_first, (const int32_t *)st.slot_mb, (const int2 *)m2l,
+                               (const int32_t *)st.tile_eoff, ne_d, (int64_t)0, P->entry_src, P->slot_pos);
             hipLaunchKernelGGL(k_slot_entry_keys, grid1(st.ntiles), 256, 0, s, (const int32_t *)st.tile_sig,
                                (const int32_t *)st.tile_eoff, st.ntiles, (const int32_t *)st.sig_keys,
                                (const int32_t *)st.sig_n, ne_d, P->entry_key);
@@ -2076,6 +2077,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         }
     }
 
+    if (recs) a.put(recs);   // a plan without M2L pairs
     lg("m2l work items");
     // join the near-field lists built on the side stream
     HIP_CHECK(hipEventRecord(P->ev_join, P->side));
