@@ -573,15 +573,18 @@ __global__ void __launch_bounds__(256) k_dense_flags(const unsigned long long *l
 
 // Entries are the dense (tile, key) cells in tile-major, key-ascending order; the pairs of
 // the other cells are flagged for the slot pool (when `pool` is given).
+// `entry_of` is the exclusive scan of the dense flags with the total appended, so a cell
+// is dense iff its successor's value is larger.
 __global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pair_key_id, const int32_t *cell_tile,
-                               const int32_t *cell_lane, const int32_t *present, const int32_t *entry_of,
-                               int64_t nkeys, int32_t *entry_src, uint8_t *pool) {
+                               const int32_t *cell_lane, const int32_t *entry_of, int64_t nkeys, int32_t *entry_src,
+                               uint8_t *pool) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        const int a = pairs[i].x;
-        const int64_t tk = (int64_t)cell_tile[a] * nkeys + pair_key_id[i];
-        const int dense = present[tk];
+        const int2 pr = pairs[i];
+        const int64_t tk = (int64_t)cell_tile[pr.x] * nkeys + pair_key_id[i];
+        const int e = entry_of[tk];
+        const bool dense = entry_of[tk + 1] > e;
         if (pool) pool[i] = dense ? 0 : 1;
-        if (dense) entry_src[(int64_t)entry_of[tk] * kTileN + cell_lane[a]] = pairs[i].y;
+        if (dense) entry_src[(int64_t)e * kTileN + cell_lane[pr.x]] = pr.y;
     }
 }
 
@@ -712,21 +715,23 @@ __global__ void k_sig_keys(const int32_t *rep, int64_t nsig, const int32_t *slot
 // Tile order of the slots: (region of the target, signature, target).  The region is the
 // target's ancestor (or, for a coarser target, its descendant corner) at level `rl`, so the
 // workgroups in flight share operators (one signature) and source expansions (one region).
+// The slots are numbered in target order and the radix sort is stable, so the sort key
+// needs only (region, signature).
 __global__ void k_slot_sort_keys(const int32_t *slot_tgt, const int32_t *sig_id, int64_t ns, CellView C, int rl,
-                                 int sbits, int tbits, uint64_t *keys, int32_t *vals) {
+                                 int sbits, uint64_t *keys, int32_t *vals) {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x) {
         const int t = slot_tgt[q], l = C.level[t];
         const uint64_t pre = C.prefix[t];
         const uint64_t reg = l >= rl ? pre >> (3 * (l - rl)) : pre << (3 * (rl - l));
-        keys[q] = (((reg << sbits) | (uint64_t)sig_id[q]) << tbits) | (uint64_t)t;
+        keys[q] = (reg << sbits) | (uint64_t)sig_id[q];
         vals[q] = (int32_t)q;
     }
 }
 
 // Group starts along the sorted slots: (region, signature) changes.
-__global__ void k_group_flags(const uint64_t *keys, int64_t ns, int tbits, int32_t *flag) {
+__global__ void k_group_flags(const uint64_t *keys, int64_t ns, int32_t *flag) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x)
-        flag[j] = (j == 0 || (keys[j] >> tbits) != (keys[j - 1] >> tbits)) ? 1 : 0;
+        flag[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1 : 0;
 }
 __global__ void k_group_starts(const int32_t *flag, const int32_t *gid, int64_t ns, int32_t *gstart) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x)
@@ -1279,16 +1284,16 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, const
     // tile order: (region, signature, target); tiles of 64 slots inside each (region, signature)
     int rl = kSlotRegionLevel;
     if (const char *ev = getenv("FMM_M2L_REGION_LEVEL")) rl = std::max(0, std::min(6, atoi(ev)));
-    const int sbits = bits_for(nsig), tbits = cbits;
-    if (3 * rl + sbits + tbits > 64) rl = std::max(0, (64 - sbits - tbits) / 3);
+    const int sbits = bits_for(nsig);
+    if (3 * rl + sbits > 64) rl = std::max(0, (64 - sbits) / 3);
     uint64_t *tk = a.get_n<uint64_t>(ns);
     st.sorted = a.get_n<int32_t>(ns);
     hipLaunchKernelGGL(k_slot_sort_keys, grid1(ns), 256, 0, s, (const int32_t *)st.slot_tgt, (const int32_t *)sig_id, ns,
-                       C, rl, sbits, tbits, tk, st.sorted);
-    radix_sort_u64(tk, st.sorted, ns, 3 * rl + sbits + tbits, a, s);
+                       C, rl, sbits, tk, st.sorted);
+    radix_sort_u64(tk, st.sorted, ns, 3 * rl + sbits, a, s);
     st.gflag = a.get_n<int32_t>(ns);
     st.gid = a.get_n<int32_t>(ns);
-    hipLaunchKernelGGL(k_group_flags, grid1(ns), 256, 0, s, (const uint64_t *)tk, ns, tbits, st.gflag);
+    hipLaunchKernelGGL(k_group_flags, grid1(ns), 256, 0, s, (const uint64_t *)tk, ns, st.gflag);
     a.put(tk);
     const int64_t ngroups = exclusive_scan_i32(st.gflag, st.gid, ns, a, s);
     st.gstart = a.get_n<int32_t>(ngroups);
@@ -1824,7 +1829,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         hipLaunchKernelGGL(k_key_ids, std::min(grid1(nm2l), 4096), 256, 0, s, (const int2 *)m2l, nm2l,
                            (const int32_t *)slot_id, (const int32_t *)dsame, (const int32_t *)cell_tile,
                            (const int32_t *)cell_lane, nkeys, pkid, lanes, &counts[0]);
-        int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk);
+        int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk + 1);
         // in mixed precision the root tiles stay whole: their FP64 path reads their entries
         const int64_t root_tiles = P->prec == FMM_PREC_MIXED ? btile[(size_t)kRootLevels * 8] : 0;
         int fill_pct = kDenseFillPct;
@@ -1852,12 +1857,16 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         }
         // dense entries (their sources in a first array; the slot entries, if any, follow them)
         int64_t ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
+        {
+            const int32_t tot = (int32_t)ne_d;
+            mb.upload(entry_of + ntk, &tot, 4, s);
+        }
         int32_t *dsrc = a.get_n<int32_t>(ne_d * kTileN);
         fill_i32(dsrc, -1, ne_d * kTileN, s);
         uint8_t *pool = try_pool ? a.get_n<uint8_t>(nm2l) : nullptr;
         hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
-                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)present,
-                           (const int32_t *)entry_of, nkeys, dsrc, pool);
+                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of, nkeys,
+                           dsrc, pool);
         SlotTiles st;
         if (try_pool) {
             // ---- slot pool (given up when its slots would tile poorly)
@@ -1870,12 +1879,16 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
                                ntk, nkeys, 0, (int64_t)0, present, (unsigned long long *)nullptr);
             ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
+            {
+                const int32_t tot = (int32_t)ne_d;
+                mb.upload(entry_of + ntk, &tot, 4, s);
+            }
             a.put(dsrc);
             dsrc = a.get_n<int32_t>(ne_d * kTileN);
             fill_i32(dsrc, -1, ne_d * kTileN, s);
             hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
-                               (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)present,
-                               (const int32_t *)entry_of, nkeys, dsrc, (uint8_t *)nullptr);
+                               (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of,
+                               nkeys, dsrc, (uint8_t *)nullptr);
         }
         if (st.ntiles == 0) npool = 0;
         P->npool = npool;

@@ -386,14 +386,19 @@ void exclusive_scan_i64_to(const int64_t *in, int64_t *out, int64_t n, int64_t *
 }
 
 // ------------------------------------------------------------------ radix sort
-// LSD radix sort, 8-bit digits.  Per pass: (1) per-tile digit histogram, stored
-// digit-major so that (2) one exclusive scan gives every (digit, tile) its output
-// offset, (3) a stable scatter that ranks equal digits inside a tile with wave
-// ballots, keeping the input order among equal digits.
-constexpr int kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads * kSortItems;
+// LSD radix sort, 8-bit digits, tiles of 256 x ITEMS keys (ITEMS chosen by the size,
+// so that a pass has enough tiles to fill the chip).  Per pass: (1) per-tile digit
+// histogram, stored digit-major so that (2) one exclusive scan gives every (digit, tile)
+// its output offset, (3) a stable scatter: each wave ranks a contiguous quarter of the
+// tile on its own (equal digits in input order, through ballots and per-wave digit
+// counters), the quarters are merged by digit in LDS, and the tile is written out so
+// that consecutive threads write consecutive positions of one digit's run.
+constexpr int kSortThreads = 256, kSortWaves = kSortThreads / 64;
 
+template <int kSortItems>
 __global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint64_t *keys, int64_t n, int shift, int64_t ntiles,
                                                             int64_t *hist) {
+    constexpr int kSortTile = kSortThreads * kSortItems;
     __shared__ int cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -406,69 +411,120 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint64_t *keys
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
+template <int kSortItems>
 __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout,
                                                                int32_t *vout, int64_t n, int shift, int64_t ntiles,
                                                                const int64_t *off) {
+    constexpr int kSortTile = kSortThreads * kSortItems;
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ int32_t sval[kSortTile];
     __shared__ int64_t base_off[256];
-    __shared__ int run[256];
-    __shared__ int wcnt[kSortThreads / 64][256];
+    __shared__ int wrun[kSortWaves][256];   // per wave: its keys of each digit (then: where they start in the tile)
+    __shared__ int wsum[kSortWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     base_off[tid] = off[(int64_t)tid * ntiles + blockIdx.x];
-    run[tid] = 0;
+    for (int w = 0; w < kSortWaves; ++w) wrun[w][tid] = 0;
     __syncthreads();
-    int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile, part0 = tile0 + (int64_t)wave * 64 * kSortItems;
+    uint64_t key[kSortItems];
+    int32_t val[kSortItems];
+    int rank[kSortItems];
+    int *run = wrun[wave];
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        int64_t g = tile0 + (int64_t)r * kSortThreads + tid;
-        bool valid = g < n;
-        uint64_t key = valid ? kin[g] : 0;
-        int32_t val = valid ? vin[g] : 0;
-        unsigned d = (unsigned)(key >> shift) & 255u;
+        const int64_t g = part0 + (int64_t)r * 64 + lane;
+        const bool valid = g < n;
+        key[r] = valid ? kin[g] : 0;
+        val[r] = valid ? vin[g] : 0;
+        const unsigned d = (unsigned)(key[r] >> shift) & 255u;
         uint64_t mask = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot((d >> b) & 1u);
+            const uint64_t bal = __ballot((d >> b) & 1u);
             mask &= ((d >> b) & 1u) ? bal : ~bal;
         }
-        uint64_t lower = mask & ((1ull << lane) - 1ull);
-        int rank_in_wave = __popcll(lower);
-        if (valid && lower == 0) wcnt[wave][d] = __popcll(mask);   // lowest lane of the digit group
-        __syncthreads();
-        if (valid) {
-            int before = run[d];
-            for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-            int64_t dst = base_off[d] + before + rank_in_wave;
-            kout[dst] = key;
-            vout[dst] = val;
-        }
-        __syncthreads();
-        int add = 0;
-        for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][tid];
-        run[tid] += add;
-        __syncthreads();
+        const uint64_t lower = mask & ((1ull << lane) - 1ull);
+        rank[r] = valid ? run[d] + __popcll(lower) : -1;   // rank among this wave's keys of digit d
+        // LDS operations of one wave complete in order: every lane has read run[d] above
+        // before the lowest lane of the digit group writes it here
+        if (valid && lower == 0) run[d] += __popcll(mask);
     }
+    __syncthreads();
+    // where each wave's keys of each digit start in the digit-sorted tile: digits in
+    // order, and inside a digit the waves in order (the input order)
+    {
+        int c[kSortWaves], v = 0;
+        for (int w = 0; w < kSortWaves; ++w) {
+            c[w] = wrun[w][tid];
+            v += c[w];
+        }
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int start = incl - v;
+        for (int w = 0; w < wave; ++w) start += wsum[w];
+        for (int w = 0; w < kSortWaves; ++w) {
+            wrun[w][tid] = start;
+            start += c[w];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (rank[r] >= 0) {
+            const int j = run[(unsigned)(key[r] >> shift) & 255u] + rank[r];
+            skey[j] = key[r];
+            sval[j] = val[r];
+        }
+    __syncthreads();
+    // wrun[0][d] is now the tile-local start of digit d
+    const int cnt = (int)(n - tile0 < kSortTile ? n - tile0 : kSortTile);
+    for (int i = tid; i < cnt; i += kSortThreads) {
+        const uint64_t k = skey[i];
+        const unsigned d = (unsigned)(k >> shift) & 255u;
+        const int64_t dst = base_off[d] + (i - wrun[0][d]);
+        kout[dst] = k;
+        vout[dst] = sval[i];
+    }
+}
+
+template <int kSortItems>
+static void radix_passes(uint64_t *&ki, int32_t *&vi, uint64_t *&ko, int32_t *&vo, int64_t n, int passes, Alloc &a,
+                         hipStream_t s) {
+    constexpr int kSortTile = kSortThreads * kSortItems;
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    int64_t *hist = a.get_n<int64_t>(256 * ntiles);
+    int64_t *off = a.get_n<int64_t>(256 * ntiles);
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = 8 * ps;
+        hipLaunchKernelGGL(k_sort_hist<kSortItems>, (int)ntiles, kSortThreads, 0, s, ki, n, shift, ntiles, hist);
+        scan_rec<int64_t>(hist, off, 256 * ntiles, a, s);
+        hipLaunchKernelGGL(k_sort_scatter<kSortItems>, (int)ntiles, kSortThreads, 0, s, ki, vi, ko, vo, n, shift,
+                           ntiles, (const int64_t *)off);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+    }
+    a.put(hist);
+    a.put(off);
 }
 
 void radix_sort_u64(uint64_t *&keys, int32_t *&vals, int64_t n, int bits, Alloc &a, hipStream_t s) {
     if (n <= 1 || bits <= 0) return;
-    int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     uint64_t *k2 = a.get_n<uint64_t>(n);
     int32_t *v2 = a.get_n<int32_t>(n);
-    int64_t *hist = a.get_n<int64_t>(256 * ntiles);
-    int64_t *off = a.get_n<int64_t>(256 * ntiles);
     uint64_t *ki = keys, *ko = k2;
     int32_t *vi = vals, *vo = v2;
-    int passes = (bits + 7) / 8;
-    for (int ps = 0; ps < passes; ++ps) {
-        int shift = 8 * ps;
-        hipLaunchKernelGGL(k_sort_hist, (int)ntiles, kSortThreads, 0, s, ki, n, shift, ntiles, hist);
-        scan_rec<int64_t>(hist, off, 256 * ntiles, a, s);
-        hipLaunchKernelGGL(k_sort_scatter, (int)ntiles, kSortThreads, 0, s, ki, vi, ko, vo, n, shift, ntiles,
-                           (const int64_t *)off);
-        std::swap(ki, ko);
-        std::swap(vi, vo);
-    }
+    const int passes = (bits + 7) / 8;
+    // tiles of 4096 keys from 2^23 keys on, 2048 from 2^22, else 1024: at least ~2048 tiles
+    // per pass where the size allows, and long per-digit runs in the scatter
+    if (n >= (int64_t(1) << 23)) radix_passes<16>(ki, vi, ko, vo, n, passes, a, s);
+    else if (n >= (int64_t(1) << 22)) radix_passes<8>(ki, vi, ko, vo, n, passes, a, s);
+    else radix_passes<4>(ki, vi, ko, vo, n, passes, a, s);
     if (ki != keys) {   // odd number of passes: the result is in the second pair
         a.put(keys);
         a.put(vals);
@@ -478,8 +534,6 @@ void radix_sort_u64(uint64_t *&keys, int32_t *&vals, int64_t n, int bits, Alloc 
         a.put(k2);
         a.put(v2);
     }
-    a.put(hist);
-    a.put(off);
 }
 
 }  // namespace fmm
