@@ -348,14 +348,21 @@ __global__ void k_set_counters(unsigned long long *cnt, int64_t nm, int64_t np, 
 // cross-lane shuffles.  Outputs are written in (wave, frontier pair, lane) order, so
 // that the lanes of one store write consecutive words and the M2L pairs of one target
 // child (lanes 8x .. 8x+7) are consecutive: such a group is a slot, and one record per
-// slot is written beside the pairs (target, first pair, the frontier pair's source cell,
-// how the frontier pair was split and the slot's pair count).  An M2L pair also marks its
-// target and enters its operator key into the key table (the slot is stored beside the pair).
+// slot is written beside the pairs.  An M2L pair also marks its target and enters its
+// operator key into the key table (the slot is stored beside the pair).
+//
+// Slot record {target, first pair, b0, info}: the slot's pairs are (target, b0 + y) for the
+// set bits y of its source mask, stored from `first` on in increasing y; b0 is the first
+// child of the frontier pair's source cell B when B was split, else B.  info: bits 0-1 how
+// the frontier pair was split (bit 0 target side, bit 1 source side), bits 2-9 the source
+// mask, bits 10-12 the target's octant, bits 13-20 the octants of B's children (child y
+// has the y-th lowest of them: children are stored in Morton digit order, which is the
+// octant order).
 struct TravOut {
     int2 *m2l;
     int32_t *m2l_slot;
     int64_t cap_m;
-    int4 *rec;            // slot records {target, first pair, source-side cell, split bits | count << 2}
+    int4 *rec;            // slot records {target, first pair, b0, info}
     int64_t cap_r;
     int2 *p2p;
     int64_t cap_p;
@@ -372,7 +379,7 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t f0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + wave) * kTravPerWave;
     const int lane = threadIdx.x & 63, x = lane >> 3, y = lane & 7;
-    int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave], gsrc[kTravPerWave], gen[kTravPerWave];
+    int pa[kTravPerWave], pb[kTravPerWave], act[kTravPerWave], src0[kTravPerWave], info[kTravPerWave];
     uint64_t key[kTravPerWave];
     int cw[4] = {0, 0, 0, 0};   // this wave's M2L pairs, P2P pairs, next pairs, slot records
 #pragma unroll
@@ -381,15 +388,14 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
         pa[k] = pb[k] = 0;
         act[k] = -1;
         key[k] = 0;
-        gen[k] = 0;
-        gsrc[k] = 0;
+        info[k] = 0;
+        src0[k] = 0;
         if (f < nf) {
             int a0, na, b0, nb;
             const int2 pr = front[f];
             const int ga = __builtin_amdgcn_readfirstlane(pr.x), gb = __builtin_amdgcn_readfirstlane(pr.y);
             split_ranges(C, ga, gb, a0, na, b0, nb);
-            gen[k] = (a0 != ga ? 1 : 0) | (b0 != gb ? 2 : 0);
-            gsrc[k] = gb;
+            src0[k] = b0;
             const bool ld = lane < 8 ? lane < na : (lane < 16 && lane - 8 < nb);
             const int cell = lane < 8 ? a0 + lane : b0 + (lane - 8);
             int lv = 0, cx = 0, cy = 0, cz = 0, ch = 0;
@@ -404,6 +410,14 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
                       ca = __shfl(ch, x, 64);
             const int lb = __shfl(lv, 8 + y, 64), bx = __shfl(cx, 8 + y, 64), by = __shfl(cy, 8 + y, 64),
                       bz = __shfl(cz, 8 + y, 64), cb = __shfl(ch, 8 + y, 64);
+            // octants of B's children: OR of 1 << octant over lanes 0 .. nb-1 (y = lane there)
+            int bo = lane < nb ? 1 << (((bx & 1) << 2) | ((by & 1) << 1) | (bz & 1)) : 0;
+            bo |= __shfl_xor(bo, 1, 64);
+            bo |= __shfl_xor(bo, 2, 64);
+            bo |= __shfl_xor(bo, 4, 64);
+            bo = __shfl(bo, 0, 64);
+            info[k] = (a0 != ga ? 1 : 0) | (b0 != gb ? 2 : 0) | ((((ax & 1) << 2) | ((ay & 1) << 1) | (az & 1)) << 10) |
+                      (bo << 13);
             if (x < na && y < nb) {
                 pa[k] = a0 + x;
                 pb[k] = b0 + y;
@@ -465,7 +479,7 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
         if (lead) {
             const int64_t i = wr + __popcll(br & lt);
             const int64_t first = wm + __popcll(bm & lt);   // lane 8x: the M2L pairs of lanes < 8x come first
-            if (i < o.cap_r) o.rec[i] = make_int4(pa[k], (int)first, gsrc[k], gen[k] | (__popc(mine) << 2));
+            if (i < o.cap_r) o.rec[i] = make_int4(pa[k], (int)first, src0[k], info[k] | (mine << 2));
         }
         wm += __popcll(bm);
         wq += __popcll(bq);
@@ -598,8 +612,10 @@ __global__ void k_fill_entries(const int2 *pairs, int64_t np, const int32_t *pai
 // slot's column is a partial local expansion of its target, and the targets' partials are
 // summed in a fixed order.
 
-__device__ inline int cell_octant(const CellView &C, int c) {
-    return ((C.ix[c] & 1) << 2) | ((C.iy[c] & 1) << 1) | (C.iz[c] & 1);
+// Position of the n-th lowest set bit of v (n < popcount(v)).
+__device__ inline int nth_bit(unsigned v, int n) {
+    for (; n > 0; --n) v &= v - 1;
+    return __builtin_ctz(v);
 }
 
 // Pooled pairs of every slot record (bit j: the record's j-th pair went to the pool);
@@ -607,7 +623,7 @@ __device__ inline int cell_octant(const CellView &C, int c) {
 __global__ void k_rec_members(const int4 *rec, int64_t nrec, const uint8_t *pool, int32_t *mbits, int32_t *flag) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrec; r += (int64_t)gridDim.x * blockDim.x) {
         const int4 R = rec[r];
-        const int c = R.w >> 2;
+        const int c = __popc((R.w >> 2) & 0xff);
         int m = 0;
         for (int j = 0; j < c; ++j) m |= pool[(int64_t)R.y + j] ? 1 << j : 0;
         mbits[r] = m;
@@ -615,9 +631,9 @@ __global__ void k_rec_members(const int4 *rec, int64_t nrec, const uint8_t *pool
     }
 }
 
-// Sort keys of the pooled slots: (target, source-side cell, how the producing pair was
-// split) in `cbits`, `cbits` and 2 bits -- unique per slot, so the order is the same on
-// every run whatever order the traversal wrote the records in; values = record index.
+// Sort keys of the pooled slots: (target, b0, how the producing pair was split) in
+// `cbits`, `cbits` and 2 bits -- unique per slot, so the order is the same on every run
+// whatever order the traversal wrote the records in; values = record index.
 __global__ void k_rec_keys(const int4 *rec, const int32_t *flag, const int32_t *at, int64_t nrec, int cbits,
                            uint64_t *keys, int32_t *vals) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrec; r += (int64_t)gridDim.x * blockDim.x)
@@ -629,30 +645,36 @@ __global__ void k_rec_keys(const int4 *rec, const int32_t *flag, const int32_t *
         }
 }
 
-// Per slot (in sorted order): first pair of its record, its pooled pairs (bits relative to
-// the first), target, and signature = (key id of its first pooled pair, target side split,
-// source side split, target octant when split, octants of its pooled sources when split).
-// Given how the producing pair was split, the first key, the target octant and the source
-// octants fix that pair's geometry and so every key of the slot in source order: slots
-// with equal signatures have equal key sequences.
+// Per slot (in sorted order): first pair of its record and its pooled pairs (bits relative
+// to the first), b0 and the source mask of its pooled pairs, target, and signature = (key
+// id of its first pooled pair, target side split, source side split, target octant when
+// split, octants of its pooled sources when split).  Given how the producing pair was
+// split, the first key, the target octant and the source octants fix that pair's geometry
+// and so every key of the slot in source order: slots with equal signatures have equal
+// key sequences.
 __global__ void __launch_bounds__(256) k_slot_info(const int4 *rec, const int32_t *mbits, const int32_t *order,
-                                                   int64_t ns, const int2 *pairs, const int32_t *key_id, CellView C,
-                                                   int32_t *slot_first, int32_t *slot_mb, int32_t *slot_tgt,
-                                                   uint64_t *slot_sig, unsigned long long *partial_octants) {
+                                                   int64_t ns, const int32_t *key_id, int32_t *slot_first,
+                                                   int32_t *slot_mb, int32_t *slot_b0, int32_t *slot_ym,
+                                                   int32_t *slot_tgt, uint64_t *slot_sig,
+                                                   unsigned long long *partial_octants) {
     unsigned long long part = 0;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ns; q += (int64_t)gridDim.x * blockDim.x) {
         const int r = order[q];
         const int4 R = rec[r];
-        const int m = mbits[r], g = R.w & 3, t = R.x;
-        int smask = 0;
-        if (g & 2)
-            for (int mm = m; mm; mm &= mm - 1)
-                smask |= 1 << cell_octant(C, pairs[(int64_t)R.y + __builtin_ctz(mm)].y);
+        const int m = mbits[r], g = R.w & 3, ym = (R.w >> 2) & 0xff, bo = (R.w >> 13) & 0xff;
+        int pym = 0, smask = 0;
+        for (int mm = m; mm; mm &= mm - 1) {
+            const int y = nth_bit((unsigned)ym, __builtin_ctz(mm));
+            pym |= 1 << y;
+            if (g & 2) smask |= 1 << nth_bit((unsigned)bo, y);
+        }
         if ((g & 2) && __popc(m) < 8) ++part;
-        const uint64_t ot = (g & 1) ? (uint64_t)cell_octant(C, t) : 0;
+        const uint64_t ot = (g & 1) ? (uint64_t)((R.w >> 10) & 7) : 0;
         slot_first[q] = R.y;
         slot_mb[q] = m;
-        slot_tgt[q] = t;
+        slot_b0[q] = R.z;
+        slot_ym[q] = pym;
+        slot_tgt[q] = R.x;
         slot_sig[q] = (uint64_t)(uint32_t)key_id[(int64_t)R.y + __builtin_ctz(m)] | ((uint64_t)(g & 1) << 32) |
                       ((uint64_t)((g >> 1) & 1) << 33) | (ot << 34) | ((uint64_t)smask << 37);
     }
@@ -758,16 +780,15 @@ __global__ void k_tile_sig(const int32_t *tflag, const int32_t *tid, const int32
 // Entries of the slot tiles (keys, sources per column) and each slot's partial column:
 // slot tile T is partial tile `part0 + T`.
 __global__ void k_slot_entries(const int32_t *tflag, const int32_t *tid, const int32_t *flag, const int32_t *gid,
-                               const int32_t *gstart, const int32_t *sorted, int64_t ns, const int32_t *slot_first,
-                               const int32_t *slot_mb, const int2 *pairs, const int32_t *tile_eoff, int64_t e_base,
-                               int64_t part0, int32_t *entry_src, int64_t *slot_pos) {
+                               const int32_t *gstart, const int32_t *sorted, int64_t ns, const int32_t *slot_b0,
+                               const int32_t *slot_ym, const int32_t *tile_eoff, int64_t e_base, int64_t part0,
+                               int32_t *entry_src, int64_t *slot_pos) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x) {
         const int T = tid[j] + tflag[j] - 1;
         const int lane = (int)((j - gstart[gid[j] + flag[j] - 1]) % kTileN);
-        const int q = sorted[j], f = slot_first[q];
+        const int q = sorted[j], b0 = slot_b0[q];
         int64_t e = e_base + tile_eoff[T];
-        for (int mm = slot_mb[q]; mm; mm &= mm - 1, ++e)
-            entry_src[e * kTileN + lane] = pairs[(int64_t)f + __builtin_ctz(mm)].y;
+        for (int ym = slot_ym[q]; ym; ym &= ym - 1, ++e) entry_src[e * kTileN + lane] = b0 + __builtin_ctz(ym);
         slot_pos[q] = (part0 + T) * kTileN + lane;
     }
 }
@@ -1158,13 +1179,14 @@ struct SlotTiles {
     bool abandoned = false;                         // the pool's slots were too diverse to tile well
     int64_t nslots = 0, ntiles = 0, ne = 0, nsig = 0;
     int32_t *slot_first = nullptr, *slot_mb = nullptr, *slot_tgt = nullptr;   // slots in (target, source) order
+    int32_t *slot_b0 = nullptr, *slot_ym = nullptr;
     int32_t *sorted = nullptr;                      // tile order -> slot
     int32_t *gflag = nullptr, *gid = nullptr, *gstart = nullptr, *tflag = nullptr, *tid = nullptr;
     int32_t *tile_sig = nullptr, *tile_ne = nullptr, *tile_eoff = nullptr;
     int32_t *sig_keys = nullptr, *sig_n = nullptr;
     void release(Alloc &a) {
-        for (int32_t *p : {slot_first, slot_mb, slot_tgt, sorted, gflag, gid, gstart, tflag, tid, tile_sig, tile_ne,
-                           tile_eoff, sig_keys, sig_n})
+        for (int32_t *p : {slot_first, slot_mb, slot_tgt, slot_b0, slot_ym, sorted, gflag, gid, gstart, tflag, tid,
+                           tile_sig, tile_ne, tile_eoff, sig_keys, sig_n})
             if (p) a.put(p);
         *this = SlotTiles{};
     }
@@ -1174,7 +1196,7 @@ struct SlotTiles {
 // every slot, relative to the first slot tile), P->run_first / P->run_tgt / P->nruns (the
 // slots of each target, for the fixed-order sum) and `st` (what the entry builders need).
 // Unless `keep`, gives the pool up (st.abandoned, no tiles) when its slots would tile poorly.
-static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, const int32_t *key_id, const int4 *recs,
+static void build_slots(fmm_plan_s *P, const CellView &C, const int32_t *key_id, const int4 *recs,
                         int64_t nrec, const uint8_t *pool, int64_t npool, Alloc &a, hipStream_t s, SlotTiles &st,
                         bool keep) {
     Mailbox &mb = *a.mb;
@@ -1198,11 +1220,14 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int2 *m2l, const
     st.slot_first = a.get_n<int32_t>(ns);
     st.slot_mb = a.get_n<int32_t>(ns);
     st.slot_tgt = a.get_n<int32_t>(ns);
+    st.slot_b0 = a.get_n<int32_t>(ns);
+    st.slot_ym = a.get_n<int32_t>(ns);
     uint64_t *sig = a.get_n<uint64_t>(ns);
     unsigned long long *err = a.get_n<unsigned long long>(1);   // slots whose split source has empty octants
     fill_i32(reinterpret_cast<int32_t *>(err), 0, 2, s);
     hipLaunchKernelGGL(k_slot_info, std::min(grid1(ns), 8192), 256, 0, s, recs, (const int32_t *)mbits,
-                       (const int32_t *)order, ns, m2l, key_id, C, st.slot_first, st.slot_mb, st.slot_tgt, sig, err);
+                       (const int32_t *)order, ns, key_id, st.slot_first, st.slot_mb, st.slot_b0, st.slot_ym,
+                       st.slot_tgt, sig, err);
     a.put(mbits); a.put(order);
     int64_t partial_oct = 0;
     {
@@ -1871,7 +1896,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         if (try_pool) {
             // ---- slot pool (given up when its slots would tile poorly)
             lg("m2l dense cells");
-            build_slots(P, C, m2l, pkid, recs, nrec, pool, npool, a, s, st, force_pool);
+            build_slots(P, C, pkid, recs, nrec, pool, npool, a, s, st, force_pool);
         }
         if (pool) a.put(pool);
         if (st.ntiles == 0 && npool > 0) {
@@ -1917,8 +1942,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             hipLaunchKernelGGL(k_slot_entries, grid1(st.nslots), 256, 0, s, (const int32_t *)st.tflag,
                                (const int32_t *)st.tid, (const int32_t *)st.gflag, (const int32_t *)st.gid,
                                (const int32_t *)st.gstart, (const int32_t *)st.sorted, st.nslots,
-                               (const int32_t *)st.slot_first, (const int32_t *)st.slot_mb, (const int2 *)m2l,
-                               (const int32_t *)st.tile_eoff, ne_d, (int64_t)0, P->entry_src, P->slot_pos);
+                               (const int32_t *)st.slot_b0, (const int32_t *)st.slot_ym, (const int32_t *)st.tile_eoff,
+                               ne_d, (int64_t)0, P->entry_src, P->slot_pos);
             hipLaunchKernelGGL(k_slot_entry_keys, grid1(st.ntiles), 256, 0, s, (const int32_t *)st.tile_sig,
                                (const int32_t *)st.tile_eoff, st.ntiles, (const int32_t *)st.sig_keys,
                                (const int32_t *)st.sig_n, ne_d, P->entry_key);
