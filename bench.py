@@ -78,10 +78,20 @@ def m2l_kernel_sha():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def m2l_roofline(precision, m2l_tflops, traffic):
+def m2l_roofline(precision, m2l_tflops, traffic, form="dense"):
     """The M2L step (grouped GEMM + the fixed-order sum of split tiles) against the MFMA
     peak of the type it computes in.  The split-FP16 form runs three FP16 products (hi hi,
-    hi lo, lo hi) per algorithmic one."""
+    hi lo, lo hi) per algorithmic one.  The compressed forms count the flops they apply
+    (two rank-r products per pair for the SVD, the kept 16 x 16 blocks for block
+    dropping); the recorded traffic belongs to the dense kernel only."""
+    if form == "svd":
+        return {"kernel": "k_gemm_svd (two FP32 MFMA products of rank r per entry) + sums", "bound": "mfma",
+                "achieved": m2l_tflops, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s (factored flops)",
+                "frac": m2l_tflops / MFMA_FP32_PEAK_TFLOPS, "traffic": None}
+    if form == "blocks":
+        return {"kernel": "k_gemm with dropped 16x16 operator blocks + sums", "bound": "mfma",
+                "achieved": m2l_tflops, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s (applied blocks)",
+                "frac": m2l_tflops / MFMA_FP32_PEAK_TFLOPS, "traffic": None}
     if precision == "mixed":
         achieved = 3.0 * m2l_tflops
         return {"kernel": "k_m2l_f16 + k_m2l_reduce (split-FP16 MFMA grouped GEMM, 3 products)", "bound": "mfma",
@@ -389,7 +399,9 @@ def main():
     }
     result.update({k: v for k, v in run.items() if k not in ("particles_per_s", "ms_per_step")})
     result.update(stats_keys(st))
-    result["roofline"] = m2l_roofline(args.precision, run["m2l_tflops"], m2l_traffic(args.workload, p, theta, st))
+    form = "svd" if args.svd_tol > 0 else ("blocks" if args.m2l_tol > 0 else "dense")
+    result["roofline"] = m2l_roofline(args.precision, run["m2l_tflops"],
+                                      m2l_traffic(args.workload, p, theta, st) if form == "dense" else None, form)
     result["p2p_roofline"] = p2p_roofline(run["p2p_tflops"])
 
     refs = None

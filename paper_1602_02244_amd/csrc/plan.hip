@@ -348,8 +348,8 @@ __global__ void k_set_counters(unsigned long long *cnt, int64_t nm, int64_t np, 
 // cross-lane shuffles.  Outputs are written in (wave, frontier pair, lane) order, so
 // that the lanes of one store write consecutive words and the M2L pairs of one target
 // child (lanes 8x .. 8x+7) are consecutive: such a group is a slot, and one record per
-// slot is written beside the pairs.  An M2L pair also marks its target and enters its
-// operator key into the key table (the slot is stored beside the pair).
+// slot is written beside the pairs; it also marks its target.  An M2L pair enters its
+// operator key into the key table (the table slot is stored beside the pair).
 //
 // Slot record {target, first pair, b0, info}: the slot's pairs are (target, b0 + y) for the
 // set bits y of its source mask, stored from `first` on in increasing y; b0 is the first
@@ -468,7 +468,6 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
                 o.m2l[i] = v;
                 o.m2l_slot[i] = key_slot(key[k], o.table, o.mask, o.flags);
             }
-            o.is_target[pa[k]] = 1;
         } else if (act[k] == 1) {
             const int64_t i = wq + __popcll(bq & lt);
             if (i < o.cap_p) o.p2p[i] = v;
@@ -476,7 +475,8 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
             const int64_t i = wn + __popcll(bn & lt);
             if (i < o.cap_n) o.next[i] = v;
         }
-        if (lead) {
+        if (lead) {   // one lane per slot: the target is marked and the record written
+            o.is_target[pa[k]] = 1;
             const int64_t i = wr + __popcll(br & lt);
             const int64_t first = wm + __popcll(bm & lt);   // lane 8x: the M2L pairs of lanes < 8x come first
             if (i < o.cap_r) o.rec[i] = make_int4(pa[k], (int)first, src0[k], info[k] | (mine << 2));
