@@ -39,6 +39,7 @@ def _load():
     lib.oracle_multi_indices.argtypes = [C.c_int, _i32p]
     lib.oracle_taylor_T.argtypes = [C.c_int, _dp, _dp]
     lib.oracle_p2m.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _dp]
+    lib.oracle_p2m_dip.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _dp]
     lib.oracle_m2m.argtypes = [C.c_int, _dp, _dp, _dp]
     lib.oracle_m2l.argtypes = [C.c_int, _dp, _dp, _dp]
     lib.oracle_l2l.argtypes = [C.c_int, _dp, _dp, _dp]
@@ -54,6 +55,9 @@ def _load():
     lib.oracle_plan_order.argtypes = [C.c_void_p, _i64p, _u64p]
     lib.oracle_fmm_eval.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp, _dp, _dp]
     lib.oracle_direct_hessian.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _i64p, _dp]
+    lib.oracle_direct_dip.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_int64, _i64p, _dp, _dp]
+    lib.oracle_direct_dip.restype = None
+    lib.oracle_fmm_eval_dip.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp, _dp]
     _lib = lib
     return lib
 
@@ -104,6 +108,27 @@ def direct(points, q, targets=None):
     return phi, grad
 
 
+def direct_dip(points, q, dip, targets=None):
+    """Exact potential and gradient of charges q and dipoles dip ([n][3]) at the points
+    (or at the target indices): phi_i = sum_j q_j/|d| + g_j.d/|d|^3, d = x_i - x_j."""
+    lib = _load()
+    pts = _d(points).reshape(-1, 3)
+    n = pts.shape[0]
+    qq = _d(q).reshape(-1)
+    gg = _d(dip).reshape(-1, 3)
+    assert qq.shape[0] == n and gg.shape[0] == n
+    if targets is None:
+        nt, tp = n, None
+    else:
+        tp = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tp.shape[0]
+    phi = np.zeros(nt)
+    grad = np.zeros((nt, 3))
+    lib.oracle_direct_dip(n, _ptr(pts, _dp), _ptr(qq, _dp), _ptr(gg, _dp), nt if tp is not None else 0,
+                          _ptr(tp, _i64p), _ptr(phi, _dp), _ptr(grad, _dp))
+    return phi, grad
+
+
 def direct_targets(sources, q, targets):
     """Field of source charges at separate target positions (FP64):
     phi(y_t) = sum_j q_j / |y_t - x_j| over the sources with x_j != y_t, and its gradient in y_t.
@@ -141,6 +166,15 @@ def p2m(p, points, q, center):
     out = np.zeros(num_coeffs(p))
     _load().oracle_p2m(p, pts.shape[0], _ptr(pts, _dp), _ptr(qq, _dp), _ptr(c, _dp), _ptr(out, _dp))
     return out
+
+
+def p2m_dip(p, points, dip, center):
+    """Multipole of dipoles dip ([n][3]) at the points: M_a = sum_j sum_i g_ji a_i (x_j - c)^(a - e_i)."""
+    pts = _d(points).reshape(-1, 3)
+    gg = _d(dip).reshape(-1, 3)
+    M = np.zeros(num_coeffs(p))
+    _load().oracle_p2m_dip(p, pts.shape[0], _ptr(pts, _dp), _ptr(gg, _dp), _ptr(_d(center), _dp), _ptr(M, _dp))
+    return M
 
 
 def m2m(p, M, d):
@@ -239,6 +273,23 @@ class Plan:
         keys = np.zeros(self.n, np.uint64)
         _load().oracle_plan_order(self._h, _ptr(order, _i64p), _ptr(keys, _u64p))
         return order, keys
+
+    def eval_dip(self, q, dip, p: int, mode: int = BOTH, sample=None):
+        """FMM potential and gradient (FP64) of charges q and dipoles dip ([n][3]).
+        Returns (phi, grad)."""
+        qq = _d(q).reshape(-1)
+        gg = _d(dip).reshape(-1, 3)
+        assert qq.shape[0] == self.n and gg.shape[0] == self.n
+        if sample is None:
+            ns, sp, nt = 0, None, self.n
+        else:
+            sp = np.ascontiguousarray(sample, dtype=np.int64)
+            ns = nt = sp.shape[0]
+        phi = np.zeros(nt)
+        grad = np.zeros((nt, 3))
+        _load().oracle_fmm_eval_dip(self._h, int(p), _ptr(qq, _dp), _ptr(gg, _dp), int(mode), ns, _ptr(sp, _i64p),
+                                    _ptr(phi, _dp), _ptr(grad, _dp), None)
+        return phi, grad
 
     def eval(self, q, p: int, mode: int = BOTH, sample=None, hessian=False):
         """FMM potential and gradient (FP64).  Returns (phi, grad, timing[4]), and the

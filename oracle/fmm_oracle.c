@@ -137,6 +137,39 @@ void oracle_direct_hessian(int64_t n, const double *pts, const double *q, int64_
 
 /* ------------------------------------------------------------------------ */
 /* Cartesian multi-indices                                                   */
+/*
+ * Charges and dipoles (Sec. 1 with source positions as variables: a dipole g_j at x_j is
+ * the derivative of a unit charge's field along g_j when x_j moves):
+ *   phi_i  = sum_{j != i, x_j != x_i} [ q_j / |d| + g_j . d / |d|^3 ],      d = x_i - x_j
+ *   grad_i = sum_{j != i, x_j != x_i} [ -q_j d / |d|^3 + g_j / |d|^3 - 3 (g_j . d) d / |d|^5 ]
+ * dip is [n][3]; targets, phi and grad as in oracle_direct.
+ */
+void oracle_direct_dip(int64_t n, const double *pts, const double *q, const double *dip,
+                       int64_t nt, const int64_t *targ, double *phi, double *grad) {
+    if (!targ) nt = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = targ ? targ[t] : t;
+        double xi = pts[3 * i], yi = pts[3 * i + 1], zi = pts[3 * i + 2];
+        double s = 0, sc = 0, g[3] = {0, 0, 0}, gc[3] = {0, 0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3] = {xi - pts[3 * j], yi - pts[3 * j + 1], zi - pts[3 * j + 2]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2), r3 = r2 * r;
+            const double *gj = dip + 3 * j;
+            double gd = gj[0] * d[0] + gj[1] * d[1] + gj[2] * d[2];
+            neumaier_add(&s, &sc, q[j] / r + gd / r3);
+            for (int a = 0; a < 3; ++a)
+                neumaier_add(&g[a], &gc[a], -q[j] * d[a] / r3 + gj[a] / r3 - 3.0 * gd * d[a] / (r3 * r2));
+        }
+        phi[t] = s + sc;
+        if (grad)
+            for (int a = 0; a < 3; ++a) grad[3 * t + a] = g[a] + gc[a];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Multi-indices a = (a0,a1,a2) with |a| <= P, enumerated degree by degree.  */
 typedef struct {
@@ -273,6 +306,28 @@ static void p2m_acc(const expctx *e, int64_t n, const double *pts, const double 
     }
 }
 
+/* P2M of dipoles: the derivative of a charge's multipole along its dipole as the charge
+   moves, M_a += sum_j sum_i g_ji a_i (x_j - c)^(a - e_i) */
+static void p2m_dip_acc(const expctx *e, int64_t n, const double *pts, const double *dip, const double c[3],
+                        double *M) {
+    int p = e->p;
+    double px[32], py[32], pz[32];
+    for (int64_t j = 0; j < n; ++j) {
+        powers(pts[3 * j] - c[0], p, px);
+        powers(pts[3 * j + 1] - c[1], p, py);
+        powers(pts[3 * j + 2] - c[2], p, pz);
+        const double *g = dip + 3 * j;
+        for (int k = 0; k < e->mp.n; ++k) {
+            const int *a = e->mp.a + 3 * k;
+            double v = 0.0;
+            if (a[0] > 0) v += g[0] * a[0] * px[a[0] - 1] * py[a[1]] * pz[a[2]];
+            if (a[1] > 0) v += g[1] * a[1] * px[a[0]] * py[a[1] - 1] * pz[a[2]];
+            if (a[2] > 0) v += g[2] * a[2] * px[a[0]] * py[a[1]] * pz[a[2] - 1];
+            M[k] += v;
+        }
+    }
+}
+
 /* M2M: M_a(c) += sum_{b<=a} C(a,b) d^(a-b) M_b(c'),  d = c' - c */
 static void m2m_acc(const expctx *e, const double *Mc, const double d[3], double *Mp) {
     int p = e->p;
@@ -384,6 +439,14 @@ void oracle_p2m(int p, int64_t n, const double *pts, const double *q, const doub
     expctx e; exp_init(&e, p);
     memset(M, 0, sizeof(double) * e.mp.n);
     p2m_acc(&e, n, pts, q, c, M);
+    exp_free(&e);
+}
+
+void oracle_p2m_dip(int p, int64_t n, const double *pts, const double *dip, const double c[3], double *M) {
+    expctx e;
+    exp_init(&e, p);
+    for (int k = 0; k < e.mp.n; ++k) M[k] = 0.0;
+    p2m_dip_acc(&e, n, pts, dip, c, M);
     exp_free(&e);
 }
 
@@ -800,8 +863,8 @@ static void group_by_target(int64_t ncell, const int64_t *pairs, int64_t np, int
  * input order, phi [n], grad [n][3].  Charges q are in input order.
  * timing (nullable) receives seconds: [upward, m2l, downward+l2p, p2p].
  */
-void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample, const int64_t *sample,
-                     double *phi, double *grad, double *hess, double *timing) {
+static void fmm_eval_impl(void *h, int p, const double *q, const double *dip, int mode, int64_t nsample,
+                          const int64_t *sample, double *phi, double *grad, double *hess, double *timing) {
     oplan *P = (oplan *)h;
     int64_t nc = P->ncells, n = P->n;
     expctx e;
@@ -834,10 +897,12 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
     /* bodies in sorted order */
     double *sp = (double *)malloc(sizeof(double) * 3 * n);
     double *sq = (double *)malloc(sizeof(double) * n);
+    double *sd = dip ? (double *)malloc(sizeof(double) * 3 * n) : NULL;
     for (int64_t s = 0; s < n; ++s) {
         int64_t i = P->order[s];
         sp[3 * s] = P->pts[3 * i]; sp[3 * s + 1] = P->pts[3 * i + 1]; sp[3 * s + 2] = P->pts[3 * i + 2];
         sq[s] = q[i];
+        if (sd) { sd[3 * s] = dip[3 * i]; sd[3 * s + 1] = dip[3 * i + 1]; sd[3 * s + 2] = dip[3 * i + 2]; }
     }
     double *ctr = (double *)malloc(sizeof(double) * 3 * nc);
     for (int64_t c = 0; c < nc; ++c) cell_center(P, &P->cells[c], ctr + 3 * c);
@@ -860,6 +925,7 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
                 if (C->level != lev) continue;
                 if (is_leaf(C)) {
                     p2m_acc(&e, C->count, sp + 3 * C->start, sq + C->start, ctr + 3 * c, M + (size_t)c * nk);
+                    if (sd) p2m_dip_acc(&e, C->count, sp + 3 * C->start, sd + 3 * C->start, ctr + 3 * c, M + (size_t)c * nk);
                 } else {
                     for (int o = 0; o < 8; ++o) {
                         int64_t ch = C->child[o];
@@ -942,6 +1008,14 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
                     double r = sqrt(r2);
                     double v = sq[j] / r, w = v / r2;
                     f += v; gx -= w * dx; gy -= w * dy; gz -= w * dz;
+                    if (sd) {   /* dipole g_j: g.d / r^3, gradient g / r^3 - 3 (g.d) d / r^5 */
+                        const double *g = sd + 3 * j;
+                        double r3 = r2 * r, gd = g[0] * dx + g[1] * dy + g[2] * dz;
+                        f += gd / r3;
+                        gx += g[0] / r3 - 3.0 * gd * dx / (r3 * r2);
+                        gy += g[1] / r3 - 3.0 * gd * dy / (r3 * r2);
+                        gz += g[2] / r3 - 3.0 * gd * dz / (r3 * r2);
+                    }
                     if (ohess) {
                         double w5 = 3.0 * w / r2;      /* 3 q / r^5 */
                         hh[0] += w5 * dx * dx - w; hh[1] += w5 * dy * dy - w; hh[2] += w5 * dz * dz - w;
@@ -968,6 +1042,19 @@ void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample,
         timing[2] = t3 - t2;
         timing[3] = t4 - t3;
     }
-    free(ophi); free(ograd); free(ohess); free(ctr); free(sp); free(sq); free(need); free(tpos); free(leaf_of); free(pos_of);
+    free(ophi); free(ograd); free(ohess); free(ctr); free(sp); free(sq); free(sd); free(need); free(tpos); free(leaf_of);
+    free(pos_of);
     exp_free(&e);
+}
+
+void oracle_fmm_eval(void *h, int p, const double *q, int mode, int64_t nsample, const int64_t *sample,
+                     double *phi, double *grad, double *hess, double *timing) {
+    fmm_eval_impl(h, p, q, NULL, mode, nsample, sample, phi, grad, hess, timing);
+}
+
+/* The same with dipoles dip [n][3] (input order) beside the charges: P2M adds each
+   dipole's multipole (p2m_dip_acc), P2P its exact field; no Hessian. */
+void oracle_fmm_eval_dip(void *h, int p, const double *q, const double *dip, int mode, int64_t nsample,
+                         const int64_t *sample, double *phi, double *grad, double *timing) {
+    fmm_eval_impl(h, p, q, dip, mode, nsample, sample, phi, grad, NULL, timing);
 }

@@ -433,6 +433,34 @@ def test_adjoint_through_grad_phi_matches_finite_differences():
             assert abs(fd - dx[j, a]) <= 1e-5 * (1 + abs(dx[j, a]))
 
 
+def test_adjoint_through_grad_phi_with_dipoles_matches_finite_differences():
+    """The same adjoint in two evaluations: dL/dq = Psi and dL/dx = w grad phi + H g +
+    q grad Psi, Psi the field of charges w and dipoles g (a dipole g_i at x_i is the
+    derivative of a unit charge's field as it moves along g_i); checked on the exact loss."""
+    rng = np.random.default_rng(35)
+    n = 60
+    x = rng.random((n, 3)); q = rng.uniform(-1, 1, n); w = rng.standard_normal(n); g = rng.standard_normal((n, 3))
+    full = lambda h: np.stack([np.stack([h[:, 0], h[:, 3], h[:, 4]], 1), np.stack([h[:, 3], h[:, 1], h[:, 5]], 1),
+                               np.stack([h[:, 4], h[:, 5], h[:, 2]], 1)], 1)
+
+    def loss(xx, qq):
+        phi, E = oracle.direct(xx, qq)
+        return float(np.dot(w, phi) + np.sum(g * E))
+    psi, gpsi = oracle.direct_dip(x, w, g)
+    _, E = oracle.direct(x, q)
+    H = full(oracle.direct_hessian(x, q))
+    dq = psi
+    dx = w[:, None] * E + np.einsum("kab,kb->ka", H, g) + q[:, None] * gpsi
+    eps = 1e-6
+    for j in (0, 23, 59):
+        qp = q.copy(); qp[j] += eps; qm = q.copy(); qm[j] -= eps
+        assert abs((loss(x, qp) - loss(x, qm)) / (2 * eps) - dq[j]) <= 1e-6 * (1 + abs(dq[j]))
+        for a in range(3):
+            xp = x.copy(); xp[j, a] += eps; xm = x.copy(); xm[j, a] -= eps
+            fd = (loss(xp, q) - loss(xm, q)) / (2 * eps)
+            assert abs(fd - dx[j, a]) <= 1e-5 * (1 + abs(dx[j, a]))
+
+
 # ---- separate target set ------------------------------------------------------
 
 def test_direct_targets_closed_form_and_brute_force():
