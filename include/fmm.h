@@ -194,14 +194,26 @@ fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potent
                             void *stream);
 
 /*
+ * Field of charges and dipoles (Sec. 1, with the source positions as variables: a dipole
+ * g at x_j is the derivative of a unit charge's field as x_j moves along g):
+ *   phi_i  = sum_{j != i, x_j != x_i} q_j / |d| + g_j . d / |d|^3,   d = x_i - x_j,
+ *   grad_i = its gradient in x_i.
+ * charges [n], dipoles [n][3] (device, FP32, input order); potential [n] and gradient
+ * [n][3] as in fmm_eval (either may be NULL, not both).  Same plan, tree and lists: P2M
+ * adds each dipole's multipole (the derivative of its charge's), the near field the exact
+ * dipole kernel.  EINVAL for NULL pointers or a plan made by fmm_plan_targets.
+ */
+fmm_status fmm_eval_dipoles(fmm_plan_t plan, const float *charges, const float *dipoles, float *potential,
+                            float *gradient, void *stream);
+
+/*
  * Adjoint of a loss L(phi, grad phi) (fmm_adjoint extended to losses through the gradient
  * output): given w = dL/dphi [n] and g = dL/d(grad phi) [n][3],
- *   dL/dq_j = psi_j - sum_a d_a phi^(a)(x_j),
- *   dL/dx_k = w_k grad phi_k + q_k grad psi_k + H_k g_k - q_k sum_a H^(a)_k e_a,
- * where psi is the FMM of the charges w, grad phi and H the gradient and Hessian of the
- * FMM of the charges q, and phi^(a) the FMM of the charges g_a (the approximation is
- * symmetric, so its transpose is itself).  Five evaluations on the plan.  dL_dq [n] and
- * dL_dx [n][3] may each be NULL.
+ *   dL/dq = Psi,   dL/dx_k = w_k grad phi_k + H_k g_k + q_k grad Psi_k,
+ * where grad phi and H are the gradient and Hessian of the FMM of the charges q, and Psi the
+ * FMM of the charges w with the dipoles g (fmm_eval_dipoles).  Because the plan's pair
+ * kernel is symmetric, this is the exact gradient of the loss of the frozen-plan
+ * approximation.  Two evaluations on the plan.  dL_dq [n] and dL_dx [n][3] may each be NULL.
  */
 fmm_status fmm_adjoint_ex(fmm_plan_t plan, const float *charges, const float *dL_dphi, const float *dL_dgrad,
                           float *dL_dq, float *dL_dx, void *stream);

@@ -86,6 +86,7 @@ def load_library():
     lib.fmm_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.fmm_eval_hessian.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.fmm_adjoint_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.fmm_eval_dipoles.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.fmm_plan_targets.argtypes = [_vp, C.c_int64, _vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_int, _vp,
                                      C.POINTER(_vp)]
     lib.fmm_plan_svd.argtypes = [_vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_double, _vp, C.POINTER(_vp)]
@@ -98,7 +99,7 @@ def load_library():
     lib.fmm_plan_destroy.argtypes = [_vp]
     lib.fmm_plan_destroy.restype = None
     for f in ("fmm_set_allocator", "fmm_plan", "fmm_plan_ex", "fmm_plan_svd", "fmm_eval", "fmm_eval_ex", "fmm_adjoint",
-              "fmm_eval_hessian", "fmm_adjoint_ex", "fmm_plan_targets", "fmm_eval_targets",
+              "fmm_eval_hessian", "fmm_eval_dipoles", "fmm_adjoint_ex", "fmm_plan_targets", "fmm_eval_targets",
               "fmm_adjoint_targets", "fmm_plan_stats",
               "fmm_plan_export", "fmm_plan_set_timing", "fmm_plan_phase_times"):
         getattr(lib, f).restype = C.c_int
@@ -272,6 +273,16 @@ class FMM:
         _check(load_library().fmm_eval_hessian(self._handle(), q, _vp(phi.data_ptr()), _vp(grad.data_ptr()),
                                                _vp(hess.data_ptr()), _stream_handle()))
         return phi, grad, hess
+
+    def eval_dipoles(self, charges, dipoles):
+        """(phi [n], grad phi [n, 3]) of charges [n] and dipoles [n, 3] at the points."""
+        q = _dev_ptr(charges, "charges", (), self.n)
+        d = _dev_ptr(dipoles, "dipoles", (3,), self.n)
+        phi = torch.empty(self.n, device=self.device, dtype=torch.float32)
+        grad = torch.empty(self.n, 3, device=self.device, dtype=torch.float32)
+        _check(load_library().fmm_eval_dipoles(self._handle(), q, d, _vp(phi.data_ptr()), _vp(grad.data_ptr()),
+                                               _stream_handle()))
+        return phi, grad
 
     def adjoint(self, charges, dL_dphi, gradient_fwd=None, want_dq=True, want_dx=True, dL_dgrad=None):
         """(dL/dq [n], dL/dx [n, 3]) of L(phi, grad phi) with w = dL_dphi and, when given,

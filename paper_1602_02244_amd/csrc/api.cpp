@@ -13,7 +13,8 @@
 
 namespace fmm {
 void build_plan(fmm_plan_s *P, const float *points, hipStream_t s);
-void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *hess, int phases, hipStream_t s);
+void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *hess, int phases, hipStream_t s,
+              const float *dip = nullptr);
 void run_adjoint_grad(fmm_plan_s *Pl, const float *q, const float *w, const float *g, float *dq, float *dx,
                       hipStream_t s);
 void run_adjoint_combine(fmm_plan_s *Pl, const float *w, const float *gphi, const float *q, const float *gpsi, float *dx,
@@ -370,6 +371,18 @@ fmm_status fmm_eval_hessian(fmm_plan_t plan, const float *charges, float *potent
     return guarded([&] {
         note_stream(plan, s);
         run_eval(plan, charges, potential, gradient, hessian, FMM_ALL, s);
+    });
+}
+
+fmm_status fmm_eval_dipoles(fmm_plan_t plan, const float *charges, const float *dipoles, float *potential,
+                            float *gradient, void *stream) {
+    if (!plan || !charges || !dipoles) return set_err(FMM_EINVAL, "NULL argument");
+    if (!potential && !gradient) return set_err(FMM_EINVAL, "potential and gradient are both NULL");
+    if (plan->ntgt > 0) return set_err(FMM_EINVAL, "a plan with a separate target set takes fmm_eval_targets");
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        note_stream(plan, s);
+        run_eval(plan, charges, potential, gradient, nullptr, FMM_ALL, s, dipoles);
     });
 }
 

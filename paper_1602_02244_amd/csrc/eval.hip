@@ -1081,9 +1081,12 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
 // ------------------------------------------------------------------ P2P
 constexpr int kP2PBatch = 1024;
 
-template <bool CHECK>
-__device__ __forceinline__ void p2p_batch(const float4 *src, int ns, int g, int G, float xi, float yi, float zi, float &f,
-                                          float &gx, float &gy, float &gz) {
+// One target against sources src[g], src[g + G], ... (charges in .w); with DIP the
+// sources also carry dipoles (srcd[j].xyz): a dipole g at x_j adds g.d / r^3 to the
+// potential and g / r^3 - 3 (g.d) d / r^5 to its gradient (d = x_i - x_j).
+template <bool CHECK, bool DIP = false>
+__device__ __forceinline__ void p2p_batch(const float4 *src, const float4 *srcd, int ns, int g, int G, float xi,
+                                          float yi, float zi, float &f, float &gx, float &gy, float &gz) {
     int jj = g;
 #pragma unroll 4
     for (; jj < ns; jj += G) {
@@ -1098,6 +1101,16 @@ __device__ __forceinline__ void p2p_batch(const float4 *src, int ns, int g, int 
         gx -= dx * qi3;
         gy -= dy * qi3;
         gz -= dz * qi3;
+        if (DIP) {
+            const float4 dj = srcd[jj];
+            const float inv3 = inv * inv * inv;
+            const float t = (dj.x * dx + dj.y * dy + dj.z * dz) * inv3;
+            const float t5 = 3.f * t * inv * inv;
+            f += t;
+            gx += dj.x * inv3 - t5 * dx;
+            gy += dj.y * inv3 - t5 * dy;
+            gz += dj.z * inv3 - t5 * dz;
+        }
     }
 }
 
@@ -1114,13 +1127,13 @@ struct Comp4 {
     }
 };
 
-template <bool CHECK>
-__device__ __forceinline__ void p2p_batch_comp(const float4 *src, int ns, int g, int G, float xi, float yi, float zi,
-                                               Comp4 &c) {
+template <bool CHECK, bool DIP = false>
+__device__ __forceinline__ void p2p_batch_comp(const float4 *src, const float4 *srcd, int ns, int g, int G, float xi,
+                                               float yi, float zi, Comp4 &c) {
     for (int j0 = g; j0 < ns; j0 += 16 * G) {
         float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         const int j1 = min(ns, j0 + 16 * G);
-        p2p_batch<CHECK>(src + j0 - g, j1 - (j0 - g), g, G, xi, yi, zi, f, gx, gy, gz);
+        p2p_batch<CHECK, DIP>(src + j0 - g, DIP ? srcd + j0 - g : srcd, j1 - (j0 - g), g, G, xi, yi, zi, f, gx, gy, gz);
         c.add(0, f);
         c.add(1, gx);
         c.add(2, gy);
@@ -1135,7 +1148,8 @@ __device__ __forceinline__ void p2p_batch_comp(const float4 *src, int ns, int g,
 // in the leaf's concatenated source list lies in [lo, hi) are taken (run_pre: exclusive
 // prefix of all run lengths, base = its value at the leaf's first run).  flush(n)
 // consumes the n staged sources; it is called when the batch is full and at the end.
-// Every thread of the block calls this with the same arguments.
+// With `dips`, the sources' dipoles are staged in `srcd` beside them.  Every thread of the
+// block calls this with the same arguments.
 struct RunStage {
     int st[kP2PThreads];        // first body of each run of the chunk
     int off[kP2PThreads + 1];   // exclusive prefix of the run lengths
@@ -1144,7 +1158,8 @@ struct RunStage {
 template <class Flush>
 __device__ __forceinline__ void p2p_stream_runs(const int2 *segs, const int64_t *run_pre, int sg0, int sg1, int64_t base,
                                                 int64_t lo, int64_t hi, const float4 *bodies, float4 *src,
-                                                RunStage &rs, Flush flush) {
+                                                RunStage &rs, Flush flush, const float4 *dips = nullptr,
+                                                float4 *srcd = nullptr) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int pos = 0;
     for (int c0 = sg0; c0 < sg1; c0 += kP2PThreads) {
@@ -1182,6 +1197,7 @@ __device__ __forceinline__ void p2p_stream_runs(const int2 *segs, const int64_t 
                     else h = mid - 1;
                 }
                 src[pos + i] = bodies[rs.st[l] + (e - rs.off[l])];
+                if (dips) srcd[pos + i] = dips[rs.st[l] + (e - rs.off[l])];
             }
             pos += take;
             b0 += take;
@@ -1236,12 +1252,13 @@ __device__ inline P2PPiece p2p_piece(const int32_t *seg_off, const int64_t *run_
     return pc;
 }
 
-template <bool COMP>
+template <bool COMP, bool DIP = false>
 __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int4 *items, const int32_t *leaves, const int32_t *c_start,
                                                      const int32_t *c_count, const int32_t *seg_off, const int2 *segs,
                                                      const int64_t *run_pre, const float4 *bodies, float4 *out,
-                                                     float4 *part) {
+                                                     float4 *part, const float4 *dips = nullptr) {
     __shared__ float4 src[kP2PBatch];
+    __shared__ float4 srcd[DIP ? kP2PBatch : 1];
     __shared__ float4 red[kP2PThreads];
     __shared__ float4 redl[COMP ? kP2PThreads : 1];
     __shared__ RunStage rs;
@@ -1267,20 +1284,26 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int4 *items, const in
         for (int s0 = 0; piece == 0 && s0 < tn; s0 += kP2PBatch) {
             const int ns = min(kP2PBatch, tn - s0);
             __syncthreads();
-            for (int i = tid; i < ns; i += kP2PThreads) src[i] = bodies[ts + s0 + i];
+            for (int i = tid; i < ns; i += kP2PThreads) {
+                src[i] = bodies[ts + s0 + i];
+                if (DIP) srcd[i] = dips[ts + s0 + i];
+            }
             __syncthreads();
             if (active) {
-                if (COMP) p2p_batch_comp<true>(src, ns, g, G, xi, yi, zi, cmp);
-                else p2p_batch<true>(src, ns, g, G, xi, yi, zi, f, gx, gy, gz);
+                if (COMP) p2p_batch_comp<true, DIP>(src, srcd, ns, g, G, xi, yi, zi, cmp);
+                else p2p_batch<true, DIP>(src, srcd, ns, g, G, xi, yi, zi, f, gx, gy, gz);
             }
         }
         // neighbouring leaves, batched through LDS
-        p2p_stream_runs(segs, run_pre, pc.sg0, pc.sg1, pc.base, pc.lo, pc.hi, bodies, src, rs, [&](int ns) {
-            if (active) {
-                if (COMP) p2p_batch_comp<false>(src, ns, g, G, xi, yi, zi, cmp);
-                else p2p_batch<false>(src, ns, g, G, xi, yi, zi, f, gx, gy, gz);
-            }
-        });
+        p2p_stream_runs(
+            segs, run_pre, pc.sg0, pc.sg1, pc.base, pc.lo, pc.hi, bodies, src, rs,
+            [&](int ns) {
+                if (active) {
+                    if (COMP) p2p_batch_comp<false, DIP>(src, srcd, ns, g, G, xi, yi, zi, cmp);
+                    else p2p_batch<false, DIP>(src, srcd, ns, g, G, xi, yi, zi, f, gx, gy, gz);
+                }
+            },
+            DIP ? dips : nullptr, DIP ? srcd : nullptr);
         __syncthreads();
         if (COMP) {
             red[tid] = make_float4(cmp.h[0], cmp.h[1], cmp.h[2], cmp.h[3]);
@@ -1421,6 +1444,73 @@ __global__ void k_set_charges(const float *q, const int32_t *perm, int64_t n, fl
         bodies[i].w = q[perm[i]];
 }
 
+// Dipoles ([n][3], input order) into sorted order.
+__global__ void k_set_dipoles(const float *g, const int32_t *perm, int64_t n, float4 *dip) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = perm[i];
+        dip[i] = make_float4(g[3 * o], g[3 * o + 1], g[3 * o + 2], 0.f);
+    }
+}
+// The bodies with component a of their dipole as charge.
+__global__ void k_bodies_component(const float4 *bodies, const float4 *dip, int a, int64_t n, float4 *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 b = bodies[i], d = dip[i];
+        out[i] = make_float4(b.x, b.y, b.z, a == 0 ? d.x : (a == 1 ? d.y : d.z));
+    }
+}
+
+// Multipoles of dipole sources.  A dipole g at x is the derivative of a unit charge's
+// multipole conj(R_lm(u)) (u = (x - c) / side) as the charge moves along g, and the
+// derivatives of the regular harmonics are harmonics of one degree less:
+//   d_x R_lm = (R_{l-1,m+1} - R_{l-1,m-1}) / 2,  d_y R_lm = -i (R_{l-1,m-1} + R_{l-1,m+1}) / 2,
+//   d_z R_lm = R_{l-1,m},  with R_{l,-1} = -conj(R_{l,1}).
+// So with M^a the multipoles of the charges g_a (a = x, y, z, made by k_p2m), the dipoles
+// add to M_lm, per leaf, (1/side) [M^z_{l-1,m} + (M^x_{l-1,m+1} - M^x_{l-1,m-1}) / 2
+//   + i (M^y_{l-1,m-1} + M^y_{l-1,m+1}) / 2].
+template <int P>
+__global__ void k_dip_combine(const int32_t *leaves, int64_t nleaves, Geo g, const float *Mdip, int64_t ncells,
+                              float *M) {
+    using D = Dims<P>;
+    constexpr int KP = D::KP, NT = (P + 1) * (P + 2) / 2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nleaves * NT;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = leaves[i / NT];
+        const int t = (int)(i % NT);
+        int l = 0;
+        while ((l + 1) * (l + 2) / 2 <= t) ++l;
+        const int m = t - l * (l + 1) / 2;
+        if (l == 0) continue;
+        // coefficient (j, mm) of the multipole of component a, mm >= -1
+        auto get = [&](int a, int j, int mm, float &re, float &im) {
+            const float *Ma = Mdip + ((int64_t)a * ncells + c) * KP;
+            re = im = 0.f;
+            if (mm > j || -mm > j) return;
+            if (mm == 0) { re = Ma[j * j]; return; }
+            if (mm > 0) { re = Ma[j * j + 2 * mm - 1]; im = Ma[j * j + 2 * mm]; return; }
+            re = -Ma[j * j + 1];                // M_{j,-1} = -conj(M_{j,1})
+            im = Ma[j * j + 2];
+        };
+        float zr, zi, xpr, xpi, xmr, xmi, ypr, ypi, ymr, ymi;
+        get(2, l - 1, m, zr, zi);
+        get(0, l - 1, m + 1, xpr, xpi);
+        get(0, l - 1, m - 1, xmr, xmi);
+        get(1, l - 1, m + 1, ypr, ypi);
+        get(1, l - 1, m - 1, ymr, ymi);
+        const float dr = zr + 0.5f * (xpr - xmr) - 0.5f * (ymi + ypi);
+        const float di = zi + 0.5f * (xpi - xmi) + 0.5f * (ymr + ypr);
+        double cx, cy, cz, inv;
+        cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
+        const float fi = (float)inv;
+        float *Mc = M + (int64_t)c * KP;
+        if (m == 0) {
+            Mc[l * l] += fi * dr;
+        } else {
+            Mc[l * l + 2 * m - 1] += fi * dr;
+            Mc[l * l + 2 * m] += fi * di;
+        }
+    }
+}
+
 // Far + near field back to input order: one thread per output (coalesced writes), the
 // sorted-order inputs are gathered through the inverse permutation.
 __global__ void k_combine(const int32_t *iperm, int64_t n, const float4 *far, const float4 *near, float *phi,
@@ -1456,31 +1546,15 @@ __global__ void k_adjoint_combine(int64_t n, const float *w, const float *gphi, 
     }
 }
 
-// Adjoint through grad phi (see run_adjoint_grad): component a of a [n][3] array.
-__global__ void k_column(const float *v3, int a, int64_t n, float *out) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = v3[3 * i + a];
-}
-// dq -= d_a phi^(a);  col += column a of the Hessian of phi^(a)
-__global__ void k_adjoint_grad_acc(int64_t n, int a, const float *grad_a, const float *hess_a, float *dq, float *col) {
-    // symmetric 3x3 from (xx, yy, zz, xy, xz, yz): entry (r, a)
-    const int idx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        if (dq) dq[i] -= grad_a[3 * i + a];
-        if (col)
-            for (int r = 0; r < 3; ++r) col[3 * i + r] += hess_a[6 * i + idx[r][a]];
-    }
-}
-// dL/dx = w E + q grad psi + H g - q col
-__global__ void k_adjoint_grad_final(int64_t n, const float *w, const float *E, const float *q, const float *gpsi,
-                                     const float *H, const float *g, const float *col, float *dx) {
+// dL/dx = w E + H g + q grad Psi (input order; H as xx yy zz xy xz yz; see run_adjoint_grad)
+__global__ void k_adjoint_dip_final(int64_t n, const float *w, const float *E, const float *q, const float *gpsi,
+                                    const float *H, const float *g, float *dx) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float *h = H + 6 * i;
         const float gx = g[3 * i], gy = g[3 * i + 1], gz = g[3 * i + 2];
         const float hg[3] = {h[0] * gx + h[3] * gy + h[4] * gz, h[3] * gx + h[1] * gy + h[5] * gz,
                              h[4] * gx + h[5] * gy + h[2] * gz};
-        for (int r = 0; r < 3; ++r)
-            dx[3 * i + r] = w[i] * E[3 * i + r] + q[i] * gpsi[3 * i + r] + hg[r] - q[i] * col[3 * i + r];
+        for (int r = 0; r < 3; ++r) dx[3 * i + r] = w[i] * E[3 * i + r] + hg[r] + q[i] * gpsi[3 * i + r];
     }
 }
 
@@ -1512,16 +1586,14 @@ static void launch_near(fmm_plan_s *Pl, int phases, bool hess, hipStream_t s) {
                                (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
                                (const float4 *)Pl->p2p_part, Pl->near4, (const float *)Pl->p2p_part_h, Pl->nearh);
     } else if (phases & FMM_NEAR) {
-        if (Pl->prec == FMM_PREC_MIXED)
-            hipLaunchKernelGGL(k_p2p<true>, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
-                               (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
-                               (const int32_t *)Pl->seg_off, (const int2 *)Pl->segs, (const int64_t *)Pl->run_pre,
-                               (const float4 *)Pl->bodies, Pl->near4, Pl->p2p_part);
-        else
-            hipLaunchKernelGGL(k_p2p<false>, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
-                               (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
-                               (const int32_t *)Pl->seg_off, (const int2 *)Pl->segs, (const int64_t *)Pl->run_pre,
-                               (const float4 *)Pl->bodies, Pl->near4, Pl->p2p_part);
+        const bool comp = Pl->prec == FMM_PREC_MIXED;
+        auto kern = Pl->dip_on ? (comp ? k_p2p<true, true> : k_p2p<false, true>)
+                               : (comp ? k_p2p<true, false> : k_p2p<false, false>);
+        hipLaunchKernelGGL(kern, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
+                           (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
+                           (const int32_t *)Pl->seg_off, (const int2 *)Pl->segs, (const int64_t *)Pl->run_pre,
+                           (const float4 *)Pl->bodies, Pl->near4, Pl->p2p_part,
+                           (const float4 *)(Pl->dip_on ? Pl->dip : nullptr));
         if (Pl->np2p_part > 0)
             hipLaunchKernelGGL(k_p2p_join, (int)Pl->np2p_items, kP2PThreads, 0, Pl->side, (const int4 *)Pl->p2p_items,
                                (const int32_t *)Pl->leaves, (const int32_t *)Pl->c_start, (const int32_t *)Pl->c_count,
@@ -1547,6 +1619,18 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
     ev_rec(Pl, 2 * PH_P2M, s);
     hipLaunchKernelGGL(k_p2m<P>, (int)((Pl->nleaves + 1) / 2), 64, 0, s, (const int32_t *)Pl->leaves, Pl->nleaves,
                        g, (const float4 *)Pl->bodies, Pl->M);
+    if (Pl->dip_on) {
+        // dipole sources: leaf multipoles of each dipole component as charges, then the
+        // degree-raising combination into M
+        for (int a = 0; a < 3; ++a) {
+            hipLaunchKernelGGL(k_bodies_component, grid1(Pl->n), 256, 0, s, (const float4 *)Pl->bodies,
+                               (const float4 *)Pl->dip, a, Pl->n, Pl->dipb);
+            hipLaunchKernelGGL(k_p2m<P>, (int)((Pl->nleaves + 1) / 2), 64, 0, s, (const int32_t *)Pl->leaves,
+                               Pl->nleaves, g, (const float4 *)Pl->dipb, Pl->Mdip + (int64_t)a * Pl->ncells * D::KP);
+        }
+        hipLaunchKernelGGL(k_dip_combine<P>, grid1(Pl->nleaves * (int64_t)((P + 1) * (P + 2) / 2)), 256, 0, s,
+                           (const int32_t *)Pl->leaves, Pl->nleaves, g, (const float *)Pl->Mdip, Pl->ncells, Pl->M);
+    }
     ev_rec(Pl, 2 * PH_P2M + 1, s);
     ev_rec(Pl, 2 * PH_M2M, s);
     for (int l = Pl->max_level - 1; l >= RL; --l) {
@@ -1666,9 +1750,20 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
 
 #define FMM_CASE(PP) case PP: far_field<PP>(Pl, g, s, near); break;
 
-void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *hess, int phases, hipStream_t s) {
+void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *hess, int phases, hipStream_t s,
+              const float *dip = nullptr) {
     const int64_t n = Pl->n;
+    if (hess && dip) fail(FMM_EINVAL, "internal: a Hessian of dipole sources is not supported");
     Pl->hess_on = hess != nullptr;
+    Pl->dip_on = dip != nullptr;
+    if (dip && !Pl->dip) {
+        hipStream_t keep = Pl->mem.stream;
+        Pl->mem.stream = s;
+        Pl->dip = Pl->mem.get_n<float4>(n);
+        Pl->dipb = Pl->mem.get_n<float4>(n);
+        Pl->Mdip = Pl->mem.get_n<float>(3 * Pl->ncells * (int64_t)Pl->KP);
+        Pl->mem.stream = keep;
+    }
     if (hess && !Pl->farh) {
         hipStream_t keep = Pl->mem.stream;
         Pl->mem.stream = s;
@@ -1682,6 +1777,7 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *he
     ev_rec(Pl, 2 * PH_TOTAL, s);
     ev_rec(Pl, 2 * PH_PERM, s);
     hipLaunchKernelGGL(k_set_charges, grid1(n), 256, 0, s, q, (const int32_t *)Pl->perm, n, Pl->bodies);
+    if (dip) hipLaunchKernelGGL(k_set_dipoles, grid1(n), 256, 0, s, dip, (const int32_t *)Pl->perm, n, Pl->dip);
     ev_rec(Pl, 2 * PH_PERM + 1, s);
     auto near = [&]() { launch_near(Pl, phases, hess != nullptr, s); };
     if ((phases & FMM_FAR) && Pl->nm2l > 0) {
@@ -1710,39 +1806,28 @@ void run_eval(fmm_plan_s *Pl, const float *q, float *phi, float *grad, float *he
     Pl->ev_valid = Pl->timing;
 }
 
-// Adjoint of L(phi, grad phi) with w = dL/dphi and g = dL/d(grad phi) ([n][3]):
-//   dL/dq_j = psi_j - sum_a d_a phi^(a)(x_j)
-//   dL/dx_k = w_k E_k + q_k grad psi_k + H_k g_k - q_k sum_a H^(a)_k e_a
-// with psi the FMM of charges w, E and H the gradient and Hessian of the FMM of the charges
-// q, and phi^(a) the FMM of the charges g_a (grad phi is the transpose of that map; the
-// operator's symmetry turns it into these three evaluations).
+// Adjoint of L(phi, grad phi) with w = dL/dphi and g = dL/d(grad phi) ([n][3]), in two
+// evaluations on the frozen plan:
+//   dL/dq = Psi,   dL/dx = w E + H g + q grad Psi,
+// with E and H the gradient and Hessian of the field of the charges q, and Psi the field of
+// the charges w together with dipoles g at the same points.  With K the plan's symmetric
+// pair kernel, d(g_i . grad phi_i)/dq_j = g_i . d_1 K(x_i, x_j) = g_i . d_2 K(x_j, x_i): the
+// field at x_j of a dipole g_i at x_i (the derivative of its charge's field as x_i moves);
+// the same symmetry turns the mixed second derivatives into the gradient of that field.
 void run_adjoint_grad(fmm_plan_s *Pl, const float *q, const float *w, const float *g, float *dq, float *dx,
                       hipStream_t s) {
     const int64_t n = Pl->n;
-    if (!Pl->tmp_h) {
+    if (dx && !Pl->tmp_h) {
         hipStream_t keep = Pl->mem.stream;
         Pl->mem.stream = s;
         Pl->tmp_h = Pl->mem.get_n<float>(6 * n);
-        Pl->tmp_h2 = Pl->mem.get_n<float>(6 * n);
-        Pl->tmp_col = Pl->mem.get_n<float>(3 * n);
-        Pl->tmp_ga = Pl->mem.get_n<float>(n);
-        Pl->tmp_gg = Pl->mem.get_n<float>(3 * n);
         Pl->mem.stream = keep;
     }
-    run_eval(Pl, w, dq ? dq : Pl->tmp_phi, dx ? Pl->tmp_grad : nullptr, nullptr, FMM_ALL, s);
-    if (dx) {
-        run_eval(Pl, q, nullptr, Pl->tmp_gfwd, Pl->tmp_h, FMM_ALL, s);
-        fill_f32(Pl->tmp_col, 0.f, 3 * n, s);
-    }
-    for (int a = 0; a < 3; ++a) {
-        hipLaunchKernelGGL(k_column, grid1(n), 256, 0, s, g, a, n, Pl->tmp_ga);
-        run_eval(Pl, Pl->tmp_ga, nullptr, Pl->tmp_gg, dx ? Pl->tmp_h2 : nullptr, FMM_ALL, s);
-        hipLaunchKernelGGL(k_adjoint_grad_acc, grid1(n), 256, 0, s, n, a, (const float *)Pl->tmp_gg,
-                           (const float *)Pl->tmp_h2, dq, dx ? Pl->tmp_col : nullptr);
-    }
+    if (dx) run_eval(Pl, q, nullptr, Pl->tmp_gfwd, Pl->tmp_h, FMM_ALL, s);
+    run_eval(Pl, w, dq ? dq : Pl->tmp_phi, dx ? Pl->tmp_grad : nullptr, nullptr, FMM_ALL, s, g);
     if (dx)
-        hipLaunchKernelGGL(k_adjoint_grad_final, grid1(n), 256, 0, s, n, w, (const float *)Pl->tmp_gfwd, q,
-                           (const float *)Pl->tmp_grad, (const float *)Pl->tmp_h, g, (const float *)Pl->tmp_col, dx);
+        hipLaunchKernelGGL(k_adjoint_dip_final, grid1(n), 256, 0, s, n, w, (const float *)Pl->tmp_gfwd, q,
+                           (const float *)Pl->tmp_grad, (const float *)Pl->tmp_h, g, dx);
     HIP_CHECK(hipGetLastError());
 }
 

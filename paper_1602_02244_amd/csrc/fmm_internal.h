@@ -274,7 +274,12 @@ struct fmm_plan_s {
     float *farh = nullptr, *nearh = nullptr;    // sorted order: Hessian (xx yy zz xy xz yz), allocated on first use
     bool hess_on = false;                       // the running evaluation also produces the Hessian
     float *tmp_phi = nullptr, *tmp_grad = nullptr, *tmp_gfwd = nullptr;   // adjoint scratch (input order)
-    float *tmp_h = nullptr, *tmp_h2 = nullptr, *tmp_col = nullptr, *tmp_ga = nullptr, *tmp_gg = nullptr;   // adjoint through grad phi
+    float *tmp_h = nullptr;                     // adjoint through grad phi: Hessian of the forward field
+    // dipole sources (sorted order, .xyz), the bodies with one dipole component as charge,
+    // and the three leaf multipoles of those charges; allocated on first use
+    float4 *dip = nullptr, *dipb = nullptr;
+    float *Mdip = nullptr;
+    bool dip_on = false;                        // the running evaluation has dipole sources
     std::vector<hipStream_t> streams_used;       // every stream the plan's memory was used on
     int fp64_levels = 0;                        // levels 0..fp64_levels-1 kept in FP64 (mixed)
 

@@ -104,6 +104,16 @@ def test_null_pointers_rejected(lib):
     lib.fmm_plan_destroy(None)          # no-op
 
 
+def test_dipole_eval_rejects_null_arguments_before_any_device_call(lib):
+    f = lib.fmm_eval_dipoles
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p] * 6
+    fake = C.c_void_p(0x1000)
+    for args in ((None, fake, fake, fake, fake, None), (fake, None, fake, fake, fake, None),
+                 (fake, fake, None, fake, fake, None), (fake, fake, fake, None, None, None)):
+        assert f(*args) == FMM_EINVAL
+
+
 def test_target_calls_reject_bad_arguments_before_any_device_call(lib):
     f = lib.fmm_plan_targets
     f.restype = C.c_int
