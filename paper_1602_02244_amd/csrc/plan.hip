@@ -225,7 +225,30 @@ struct CellView {
     const int32_t *level, *ix, *iy, *iz, *child0, *nchild;
     const uint64_t *prefix;   // Morton prefix (key >> 3 (21 - level))
     int lists;                // 0: rule 3 splits both cells; 1: only the smaller prefix (level skip)
+    // separate target set only (else null): bit 0 the cell holds a source, bit 1 a target
+    const uint8_t *kind = nullptr;
 };
+
+// With a separate target set a pair of cells (A, B) carries something only when A holds a
+// target and B a source (the field at the targets) or A a source and B a target (the
+// adjoint, whose weights sit on the targets); a child holds a subset of its cell's bodies,
+// so a pair that carries nothing has no descendant pair that does.
+__device__ inline bool pair_carries(int ka, int kb) { return ((ka & 2) && (kb & 1)) || ((ka & 1) && (kb & 2)); }
+
+// Kind of every cell of a target-set plan: counts of sources among its bodies from the
+// exclusive prefix `srcpre` of the sorted bodies' source flags (srcpre[n] = total).
+__global__ void k_src_flags(const int32_t *perm, int64_t n, int64_t nsrc, int32_t *flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = perm[i] < nsrc ? 1 : 0;
+}
+__global__ void k_cell_kind(const int32_t *start, const int32_t *count, int64_t nc, const int32_t *srcpre,
+                            uint8_t *kind) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        const int s0 = start[c], k = count[c];
+        const int ns = srcpre[s0 + k] - srcpre[s0];
+        kind[c] = (uint8_t)((ns > 0 ? 1 : 0) | (k - ns > 0 ? 2 : 0));
+    }
+}
 
 // Exclusive scan of four wave-uniform counters over the four waves of a 256-thread
 // block: `off` = the counts of the waves before this one, `tot` = the block's totals.
@@ -398,13 +421,14 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
             src0[k] = b0;
             const bool ld = lane < 8 ? lane < na : (lane < 16 && lane - 8 < nb);
             const int cell = lane < 8 ? a0 + lane : b0 + (lane - 8);
-            int lv = 0, cx = 0, cy = 0, cz = 0, ch = 0;
+            int lv = 0, cx = 0, cy = 0, cz = 0, ch = 0, kd = 3;
             if (ld) {
                 lv = C.level[cell];
                 cx = C.ix[cell];
                 cy = C.iy[cell];
                 cz = C.iz[cell];
                 ch = C.nchild[cell];
+                if (C.kind) kd = C.kind[cell];
             }
             const int la = __shfl(lv, x, 64), ax = __shfl(cx, x, 64), ay = __shfl(cy, x, 64), az = __shfl(cz, x, 64),
                       ca = __shfl(ch, x, 64);
@@ -418,9 +442,16 @@ __global__ void __launch_bounds__(256) k_trav_step(CellView C, const int2 *front
             bo = __shfl(bo, 0, 64);
             info[k] = (a0 != ga ? 1 : 0) | (b0 != gb ? 2 : 0) | ((((ax & 1) << 2) | ((ay & 1) << 1) | (az & 1)) << 10) |
                       (bo << 13);
+            // a cell's pair with itself is always kept: it carries every leaf's self pair,
+            // which the near-field lists rely on (at least one pair per leaf).  The lane's
+            // cells are set whether or not the pair is kept: the slot's lead lane (y = 0)
+            // names the target of the slot's kept pairs.
+            const int ka = __shfl(kd, x, 64), kb = __shfl(kd, 8 + y, 64);
             if (x < na && y < nb) {
                 pa[k] = a0 + x;
                 pb[k] = b0 + y;
+            }
+            if (x < na && y < nb && (a0 + x == b0 + y || pair_carries(ka, kb))) {
                 // rule 1, the MAC: accept A <- B iff A != B and theta |c_A - c_B| >= R_A + R_B
                 // (R = half side), exactly: centres and radii in units of the finer half side
                 const int lf = la > lb ? la : lb;
@@ -1552,6 +1583,24 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
 
     lg("leaves");
     CellView C{P->c_level, P->c_ix, P->c_iy, P->c_iz, P->c_child0, P->c_nchild, P->c_prefix_dev, P->lists};
+    uint8_t *ckind = nullptr;
+    if (P->ntgt > 0) {
+        // separate target set: which cells hold sources and which targets, so that the
+        // traversal keeps only the pairs that carry a field to a target or an adjoint
+        // weight to a source
+        int32_t *flag = a.get_n<int32_t>(n), *pre = a.get_n<int32_t>(n + 1);
+        hipLaunchKernelGGL(k_src_flags, grid1(n), 256, 0, s, (const int32_t *)P->perm, n, P->nsrc, flag);
+        exclusive_scan_i32(flag, pre, n, a, s);
+        {
+            const int32_t tot = (int32_t)P->nsrc;
+            mb.upload(pre + n, &tot, 4, s);
+        }
+        ckind = a.get_n<uint8_t>(nc);
+        hipLaunchKernelGGL(k_cell_kind, grid1(nc), 256, 0, s, (const int32_t *)P->c_start, (const int32_t *)P->c_count,
+                           nc, (const int32_t *)pre, ckind);
+        a.put(flag); a.put(pre);
+        C.kind = ckind;
+    }
 
     // ---- M2M and L2L as grouped GEMMs: per-level tiles of parents (M2M) and of
     // same-octant children (L2L)
@@ -1666,6 +1715,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         a.put(front);
     }
     a.put(cnt);
+    if (ckind) a.put(ckind);
     P->nm2l = nm2l;
     P->np2p = np2p;
     P->m2l_pairs = m2l;

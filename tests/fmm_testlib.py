@@ -15,10 +15,13 @@ def cell_ids(level, prefix):
     return (np.uint64(1) << (np.uint64(3) * level)) | np.asarray(prefix, np.uint64)
 
 
-def compare_plans(gpu, ora_plan):
-    """Assert the GPU plan (export dict) and the oracle plan hold identical cells, order and lists."""
+def compare_plans(gpu, ora_plan, keep=None):
+    """Assert the GPU plan (export dict) and the oracle plan hold identical cells, order and
+    lists (with `keep`, only the oracle pairs for which keep(pairs) is True)."""
     oc = ora_plan.cells()
     om2l, op2p = ora_plan.pairs()
+    if keep is not None:
+        om2l, op2p = om2l[keep(om2l)], op2p[keep(op2p)]
     oorder, _ = ora_plan.order()
     assert np.array_equal(gpu["order"], oorder), "sorted order differs"
     gid = cell_ids(gpu["level"], gpu["prefix"])

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_1602_02244_amd import inputs
-from fmm_testlib import rel_l2
+from fmm_testlib import compare_plans, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def _ids(c):
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 @pytest.mark.parametrize("p,ncrit", [(8, 32), (10, 64)])
-def test_targets_bitwise_union_and_oracle_parity(case, p, ncrit):
+def test_targets_union_and_oracle_parity(case, p, ncrit):
     from paper_1602_02244_amd import FMM, FMMTargets
     x, q, y = _sets(case)
     ns, nt = len(x), len(y)
@@ -65,7 +65,9 @@ def test_targets_bitwise_union_and_oracle_parity(case, p, ncrit):
     qu = np.concatenate([q, np.zeros(nt, np.float32)])
     one = FMM(_dev(union), ncrit, p, 0.4)
     uphi, ugrad = one.eval(_dev(qu))
-    assert np.array_equal(_np(phi), _np(uphi)[ns:]) and np.array_equal(_np(grad), _np(ugrad)[ns:])
+    # the target plan keeps only the pairs that carry something, so it matches the one-set
+    # plan on the union to rounding (the dropped pairs add exact zeros there)
+    assert rel_l2(_np(phi), _np(uphi)[ns:]) <= 1e-6 and rel_l2(_np(grad), _np(ugrad)[ns:]) <= 1e-6
     assert np.array_equal(_np(phi_only), _np(phi))
     ora = oracle.Plan(union.astype(np.float64), ncrit, 0.4)
     ophi, ograd, _ = ora.eval(qu.astype(np.float64), p, sample=np.arange(ns, ns + nt))
@@ -79,6 +81,35 @@ def test_targets_bitwise_union_and_oracle_parity(case, p, ncrit):
         assert ed <= (1e-3 if p == 8 else 2e-4)
     plan.close()
     one.close()
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=_ids)
+def test_target_plan_keeps_the_pairs_that_carry_something(case):
+    """The target plan's tree is the union's; its lists are the union's lists (the oracle's)
+    without the pairs (A, B), A != B, in which neither A holds a target and B a source nor
+    A a source and B a target."""
+    from paper_1602_02244_amd import FMMTargets
+    x, q, y = _sets(case)
+    ns = len(x)
+    plan = FMMTargets(_dev(x), _dev(y), 32, 8, 0.4)
+    ora = oracle.Plan(np.concatenate([x, y]).astype(np.float64), 32, 0.4)
+    oc = ora.cells()
+    order, _ = ora.order()
+    is_src = (order < ns).astype(np.int64)
+    pre = np.concatenate([[0], np.cumsum(is_src)])
+    start, count = np.asarray(oc["start"]), np.asarray(oc["count"])
+    nsrc = pre[start + count] - pre[start]
+    kind = (nsrc > 0).astype(np.int64) | ((count - nsrc > 0).astype(np.int64) << 1)
+
+    def keep(pairs):
+        ka, kb = kind[pairs[:, 0]], kind[pairs[:, 1]]
+        return (pairs[:, 0] == pairs[:, 1]) | (((ka & 2) > 0) & ((kb & 1) > 0)) | (((ka & 1) > 0) & ((kb & 2) > 0))
+    compare_plans(plan.export(), ora, keep)
+    om2l, op2p = ora.pairs()
+    st = plan.stats()
+    print(f"{_ids(case)}: M2L pairs {st['m2l_pairs']} of {len(om2l)}, P2P pairs {st['p2p_pairs']} of {len(op2p)}")
+    ora.close()
+    plan.close()
 
 
 def test_targets_on_sources_skip_the_coincident_source():
@@ -112,8 +143,8 @@ def test_mixed_precision_targets():
 
 def test_target_adjoint_matches_union_and_oracle():
     """dL/dq = psi at the sources, dL/dx_tgt = w grad phi, dL/dx_src = q grad psi, with
-    psi = sum_t w_t / |x - y_t|: bitwise the one-set adjoint on the union, sliced, and the
-    FP64 oracle's FMM of the same formulas to 1e-5."""
+    psi = sum_t w_t / |x - y_t|: the one-set adjoint on the union, sliced, to rounding, and
+    the FP64 oracle's FMM of the same formulas to 1e-5."""
     from paper_1602_02244_amd import FMM, FMMTargets
     x, q, y = _sets(("plummer", 15000, "cube", 6000, 41))
     ns, nt = len(x), len(y)
@@ -130,8 +161,8 @@ def test_target_adjoint_matches_union_and_oracle():
     wu = np.concatenate([np.zeros(ns, np.float32), w])
     one = FMM(_dev(union), 32, 10, 0.4)
     udq, udx = one.adjoint(_dev(qu), _dev(wu))
-    assert np.array_equal(_np(dq), _np(udq)[:ns])
-    assert np.array_equal(_np(dxs), _np(udx)[:ns]) and np.array_equal(_np(dxt), _np(udx)[ns:])
+    assert rel_l2(_np(dq), _np(udq)[:ns]) <= 1e-6
+    assert rel_l2(_np(dxs), _np(udx)[:ns]) <= 1e-6 and rel_l2(_np(dxt), _np(udx)[ns:]) <= 1e-6
     ora = oracle.Plan(union.astype(np.float64), 32, 0.4)
     _, gphi, _ = ora.eval(qu.astype(np.float64), 10)
     psi, gpsi, _ = ora.eval(wu.astype(np.float64), 10)
@@ -157,8 +188,8 @@ def test_target_adjoint_through_grad_matches_union():
     udq, udx = one.adjoint(_dev(np.concatenate([q, np.zeros(nt, np.float32)])),
                            _dev(np.concatenate([np.zeros(ns, np.float32), w])),
                            dL_dgrad=_dev(np.concatenate([np.zeros((ns, 3), np.float32), g])))
-    assert np.array_equal(_np(dq), _np(udq)[:ns])
-    assert np.array_equal(_np(dxs), _np(udx)[:ns]) and np.array_equal(_np(dxt), _np(udx)[ns:])
+    assert rel_l2(_np(dq), _np(udq)[:ns]) <= 1e-6
+    assert rel_l2(_np(dxs), _np(udx)[:ns]) <= 1e-6 and rel_l2(_np(dxt), _np(udx)[ns:]) <= 1e-6
     plan.close()
     one.close()
 
