@@ -90,6 +90,40 @@ __device__ __forceinline__ void stream_regular(float x, float y, float z, F &&f)
     }
 }
 
+// The same stream with the loops kept rolled: for callers that index their coefficients
+// at run time (from LDS), where full unrolling only lengthens live ranges.
+template <int P, class F>
+__device__ __forceinline__ void stream_regular_rolled(float x, float y, float z, F &&f) {
+    const float r2 = x * x + y * y + z * z;
+    float mr = 1.f, mi = 0.f;                   // R_mm
+#pragma unroll 1
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            const float c = -1.f / (2.f * m);
+            const float nr = c * (x * mr - y * mi), ni = c * (x * mi + y * mr);
+            mr = nr;
+            mi = ni;
+        }
+        f(m, m, mr, mi);
+        if (m < P) {
+            float pr = mr, pi = mi;             // R_{l-1,m}
+            float cr = z * mr, ci = z * mi;     // R_{m+1,m}
+            f(m + 1, m, cr, ci);
+#pragma unroll 1
+            for (int l = m + 1; l < P; ++l) {
+                const float den = 1.f / (float)((l + m + 1) * (l - m + 1));
+                const float c1 = (2 * l + 1) * den;
+                const float nr = c1 * z * cr - den * r2 * pr, ni = c1 * z * ci - den * r2 * pi;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+                f(l + 1, m, cr, ci);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -955,7 +989,10 @@ __global__ void k_root_to32(int64_t nroot, int KP, const double *in, float *out)
 }
 
 // ------------------------------------------------------------------ L2P
-// One wave per leaf; the local coefficients are broadcast from LDS.  With HESS the second
+// One wave per leaf; the local coefficients are broadcast from LDS.  With HESS the harmonic
+// stream stays rolled and the coefficients are indexed at run time (unrolled, the six
+// Hessian expansions keep too many values live: one wave per SIMD and a register spill at
+// p >= 9; without HESS the unrolled stream is the faster one).  With HESS the second
 // derivatives are also evaluated: the gradient of a local expansion is again a local
 // expansion (coefficients of degree l from those of degree l+1: x: (L_{l+1,m-1} -
 // L_{l+1,m+1})/2, y: i (L_{l+1,m+1} + L_{l+1,m-1})/2, z: L_{l+1,m}), so the six Hessian
@@ -1044,7 +1081,7 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
         const float uz = (float)(((double)b.z - cz) * inv);
         float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         float h[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        stream_regular<P>(ux, uy, uz, [&](int l, int m, float rr, float ri) {
+        auto term = [&](int l, int m, float rr, float ri) {
             const float wgt = m == 0 ? 1.f : 2.f;
             f += wgt * (lre(l, m) * rr + lim(l, m) * ri);
             if (l < P) {
@@ -1067,7 +1104,9 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
                 h[4] += wgt * (hre[4][t] * rr + him[4][t] * ri);
                 h[5] += wgt * (hre[5][t] * rr + him[5][t] * ri);
             }
-        });
+        };
+        if (HESS) stream_regular_rolled<P>(ux, uy, uz, term);
+        else stream_regular<P>(ux, uy, uz, term);
         const float g2 = finv * finv;
         out[s + j] = make_float4(f * finv, gx * g2, gy * g2, gz * g2);   // potential, gradient
         if (HESS) {
