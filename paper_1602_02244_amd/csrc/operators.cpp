@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <complex>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -425,7 +426,9 @@ struct BlockPool {
     size_t block_bytes = 0;
     std::vector<char *> chunks;
     int used = kChunk;
-    void *take() {
+    // `fresh` (if given) tells whether the block opens a new chunk
+    void *take(bool *fresh = nullptr) {
+        if (fresh) *fresh = used == kChunk;
         if (used == kChunk) {
             char *c = nullptr;
             HIP_CHECK(hipMalloc(&c, block_bytes * kChunk));
@@ -473,7 +476,7 @@ struct Store {
     std::unordered_map<uint64_t, std::vector<float>> bsum;   // key -> weighted block sums (see block_sums)
     BlockPool pool32, pool16, pool64;
     OpTables tables;
-    float *alloc_matrix() { return static_cast<float *>(pool32.take()); }
+    float *alloc_matrix(bool *fresh = nullptr) { return static_cast<float *>(pool32.take(fresh)); }
 };
 
 std::mutex g_mu;
@@ -561,37 +564,89 @@ const OpTables &op_tables(int p) {
     return store_for(p).tables;
 }
 
+// Device copies of host blocks of `bytes` each: consecutive blocks of one pool chunk (adjacent
+// on the device, and no block opens a new chunk: two chunks may be adjacent too, but a copy
+// must stay inside one allocation) go in one copy.
+static void upload_blocks(const std::vector<void *> &dst, const std::vector<char> &fresh, const char *src,
+                          size_t bytes) {
+    size_t j = 0;
+    while (j < dst.size()) {
+        size_t k = j + 1;
+        while (k < dst.size() && !fresh[k] && static_cast<char *>(dst[k]) == static_cast<char *>(dst[k - 1]) + bytes) ++k;
+        HIP_CHECK(hipMemcpy(dst[j], src + j * bytes, (k - j) * bytes, hipMemcpyHostToDevice));
+        j = k;
+    }
+}
+
 void m2l_operator_ptrs(int p, const std::vector<uint64_t> &keys, std::vector<uint64_t> &f32_ptrs,
                        std::vector<uint64_t> &f16_ptrs, bool need_f16) {
     std::lock_guard<std::mutex> lk(g_mu);
     Store &s = store_for(p);
+    const int KP = ncoef_pad(p);
     f32_ptrs.resize(keys.size());
     f16_ptrs.assign(keys.size(), 0);
-    std::vector<double> A;
-    std::vector<float> host(s.mat_floats);
+    // operators missing from the cache: built on all host cores, then uploaded in runs
+    std::vector<size_t> miss32, miss16;
     for (size_t i = 0; i < keys.size(); ++i) {
-        auto it = s.f32.find(keys[i]);
-        if (it == s.f32.end()) {
-            build_m2l(p, keys[i], A);
-            to_gemm_layout(A, ncoef_pad(p), host.data());
-            float *d = s.alloc_matrix();
-            HIP_CHECK(hipMemcpy(d, host.data(), sizeof(float) * s.mat_floats, hipMemcpyHostToDevice));
-            it = s.f32.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
-            s.bsum[keys[i]] = block_sums(A, p, ncoef_pad(p));
+        if (!s.f32.count(keys[i])) miss32.push_back(i);
+        if (need_f16 && !s.f16.count(keys[i])) miss16.push_back(i);
+    }
+    if (!miss32.empty() || !miss16.empty()) {
+        std::vector<size_t> todo = miss32;   // keys to build: the union of the two lists
+        todo.insert(todo.end(), miss16.begin(), miss16.end());
+        std::sort(todo.begin(), todo.end());
+        todo.erase(std::unique(todo.begin(), todo.end()), todo.end());
+        std::vector<int> pos32(keys.size(), -1), pos16(keys.size(), -1);
+        for (size_t j = 0; j < miss32.size(); ++j) pos32[miss32[j]] = (int)j;
+        for (size_t j = 0; j < miss16.size(); ++j) pos16[miss16[j]] = (int)j;
+        std::vector<float> h32(miss32.size() * s.mat_floats);
+        std::vector<std::vector<float>> bs(miss32.size());
+        std::vector<std::vector<char>> blobs(miss16.size());
+        const unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 64));
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t] {
+                std::vector<double> A;
+                for (size_t j = t; j < todo.size(); j += nt) {
+                    const size_t i = todo[j];
+                    build_m2l(p, keys[i], A);
+                    if (pos32[i] >= 0) {
+                        to_gemm_layout(A, KP, h32.data() + (size_t)pos32[i] * s.mat_floats);
+                        bs[pos32[i]] = block_sums(A, p, KP);
+                    }
+                    if (pos16[i] >= 0) split16(A, p, KP, blobs[pos16[i]]);
+                }
+            });
+        for (auto &x : th) x.join();
+        std::vector<void *> d32(miss32.size());
+        std::vector<char> f32(miss32.size());
+        for (size_t j = 0; j < miss32.size(); ++j) {
+            bool fr = false;
+            d32[j] = s.alloc_matrix(&fr);
+            f32[j] = fr;
+            s.f32.emplace(keys[miss32[j]], (uint64_t)(uintptr_t)d32[j]);
+            s.bsum[keys[miss32[j]]] = std::move(bs[j]);
         }
-        f32_ptrs[i] = it->second;
-        if (need_f16) {
-            auto jt = s.f16.find(keys[i]);
-            if (jt == s.f16.end()) {
-                build_m2l(p, keys[i], A);
-                std::vector<char> blob;
-                split16(A, p, ncoef_pad(p), blob);
-                void *d = s.pool16.take();
-                HIP_CHECK(hipMemcpy(d, blob.data(), blob.size(), hipMemcpyHostToDevice));
-                jt = s.f16.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
+        upload_blocks(d32, f32, reinterpret_cast<const char *>(h32.data()), sizeof(float) * s.mat_floats);
+        if (!miss16.empty()) {
+            const size_t bb = blobs[0].size();
+            std::vector<char> h16(miss16.size() * bb);
+            std::vector<void *> d16(miss16.size());
+            std::vector<char> f16(miss16.size());
+            for (size_t j = 0; j < miss16.size(); ++j) {
+                if (blobs[j].size() != bb) fail(FMM_EDEVICE, "internal: FP16 operator blobs differ in size");
+                std::memcpy(h16.data() + j * bb, blobs[j].data(), bb);
+                bool fr = false;
+                d16[j] = s.pool16.take(&fr);
+                f16[j] = fr;
+                s.f16.emplace(keys[miss16[j]], (uint64_t)(uintptr_t)d16[j]);
             }
-            f16_ptrs[i] = jt->second;
+            upload_blocks(d16, f16, h16.data(), bb);
         }
+    }
+    for (size_t i = 0; i < keys.size(); ++i) {
+        f32_ptrs[i] = s.f32.at(keys[i]);
+        if (need_f16) f16_ptrs[i] = s.f16.at(keys[i]);
     }
 }
 
@@ -674,19 +729,35 @@ void m2l_operator_ptrs64(int p, const std::vector<uint64_t> &keys, std::vector<u
     std::lock_guard<std::mutex> lk(g_mu);
     Store &s = store_for(p);
     f64_ptrs.resize(keys.size());
-    std::vector<double> A, At(s.mat_floats);
-    int KP = ncoef_pad(p);
-    for (size_t i = 0; i < keys.size(); ++i) {
-        auto it = s.f64.find(keys[i]);
-        if (it == s.f64.end()) {
-            build_m2l(p, keys[i], A);
-            transpose_into(A, KP, At.data());
-            void *d = s.pool64.take();
-            HIP_CHECK(hipMemcpy(d, At.data(), sizeof(double) * s.mat_floats, hipMemcpyHostToDevice));
-            it = s.f64.emplace(keys[i], (uint64_t)(uintptr_t)d).first;
+    const int KP = ncoef_pad(p);
+    // missing operators built on all host cores, then uploaded in runs
+    std::vector<size_t> miss;
+    for (size_t i = 0; i < keys.size(); ++i)
+        if (!s.f64.count(keys[i])) miss.push_back(i);
+    if (!miss.empty()) {
+        std::vector<double> h(miss.size() * s.mat_floats);
+        const unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 64));
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t] {
+                std::vector<double> A;
+                for (size_t j = t; j < miss.size(); j += nt) {
+                    build_m2l(p, keys[miss[j]], A);
+                    transpose_into(A, KP, h.data() + j * s.mat_floats);
+                }
+            });
+        for (auto &x : th) x.join();
+        std::vector<void *> d(miss.size());
+        std::vector<char> fresh(miss.size());
+        for (size_t j = 0; j < miss.size(); ++j) {
+            bool fr = false;
+            d[j] = s.pool64.take(&fr);
+            fresh[j] = fr;
+            s.f64.emplace(keys[miss[j]], (uint64_t)(uintptr_t)d[j]);
         }
-        f64_ptrs[i] = it->second;
+        upload_blocks(d, fresh, reinterpret_cast<const char *>(h.data()), sizeof(double) * s.mat_floats);
     }
+    for (size_t i = 0; i < keys.size(); ++i) f64_ptrs[i] = s.f64.at(keys[i]);
 }
 
 }  // namespace fmm
