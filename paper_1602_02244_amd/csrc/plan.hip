@@ -7,6 +7,7 @@
 // traversal with a multipole acceptance criterion (Sec. 2.2), translation operators
 // shared by boxes with the same relative position (Sec. 2.2).
 #include <algorithm>
+#include <unordered_map>
 #include <cmath>
 #include <chrono>
 #include <cstdio>
@@ -578,17 +579,23 @@ __global__ void k_slot_ids(const uint64_t *table, uint64_t H, const uint64_t *ke
 // Key id of every pair (from its slot), the (tile, key) table of target lanes (bit l: the
 // target in lane l of the tile has a source under that key), and the number of pairs whose
 // key joins cells of the same level.
+// The lane masks are stored per tile in a row of `row` words, the key of id k at position
+// lpos[oct * nkeys + k] for the tile's target octant oct: the keys of the pairs that one
+// target has with the children of one split source cell sit together (eight positions,
+// one 64-byte line), so that the lanes of one slot OR into a single line.
 __global__ void __launch_bounds__(256) k_key_ids(const int2 *pairs, int64_t np, const int32_t *slot_id,
                                                  const int32_t *key_same, const int32_t *cell_tile,
-                                                 const int32_t *cell_lane, int64_t nkeys, int32_t *pair_key_id,
-                                                 unsigned long long *lanes, unsigned long long *nsame) {
+                                                 const int32_t *cell_lane, const uint8_t *tile_oct,
+                                                 const int32_t *lpos, int64_t nkeys, int64_t row,
+                                                 int32_t *pair_key_id, unsigned long long *lanes,
+                                                 unsigned long long *nsame) {
     static_assert(kTileN == 64, "one 64-bit lane mask per (tile, key)");
     unsigned long long loc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         const int id = slot_id[pair_key_id[i]];
         pair_key_id[i] = id;
-        const int a = pairs[i].x;
-        atomicOr(&lanes[(int64_t)cell_tile[a] * nkeys + id], 1ull << cell_lane[a]);
+        const int a = pairs[i].x, t = cell_tile[a];
+        atomicOr(&lanes[(int64_t)t * row + lpos[(int64_t)tile_oct[t] * nkeys + id]], 1ull << cell_lane[a]);
         loc += key_same[id] ? 1ull : 0ull;
     }
     block_add_u64(loc, nsame);
@@ -597,12 +604,14 @@ __global__ void __launch_bounds__(256) k_key_ids(const int2 *pairs, int64_t np, 
 // A (tile, key) cell becomes an entry of the target tile (dense) when its sources fill at
 // least fill_pct percent of the 16-column blocks it touches, or when the tile is one of the
 // first `all_dense` tiles; its pairs go to the slot pool otherwise.
-__global__ void __launch_bounds__(256) k_dense_flags(const unsigned long long *lanes, int64_t ntk, int64_t nkeys,
+__global__ void __launch_bounds__(256) k_dense_flags(const unsigned long long *lanes, const uint8_t *tile_oct,
+                                                     const int32_t *lpos, int64_t row, int64_t ntk, int64_t nkeys,
                                                      int fill_pct, int64_t all_dense, int32_t *present,
                                                      unsigned long long *sparse_pairs) {
     unsigned long long loc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntk; i += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long m = lanes[i];
+        const int64_t t = i / nkeys;
+        const unsigned long long m = lanes[t * row + lpos[(int64_t)tile_oct[t] * nkeys + i % nkeys]];
         int f = 0;
         if (m) {
             int blocks = 0;
@@ -927,6 +936,7 @@ __global__ void k_bucket_starts(const uint64_t *tkeys, int64_t nt, int cls_bits,
 }
 
 constexpr int kBuckets = (kMaxLevel + 1) * 8;
+constexpr int64_t kGroupedKeysMax = 8192;   // the grouped lane-mask layout up to this many keys
 struct BucketBase {   // first tile of every (level, octant) bucket, passed by value
     int32_t v[kBuckets];
 };
@@ -1899,11 +1909,76 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         // (tile-major, key-ascending); the pairs of the others go to the slot pool.
         const int64_t ntk = ntiles * nkeys;
         if (ntk >= (int64_t(1) << 31)) fail(FMM_EUNSUPPORTED, "M2L tile x key table exceeds 2^31 entries");
-        unsigned long long *lanes = a.get_n<unsigned long long>(ntk);
-        fill_i32(reinterpret_cast<int32_t *>(lanes), 0, 2 * ntk, s);
+        // lane-mask rows: per target octant, the keys a target has with the eight children of
+        // one split source cell get one group of eight positions -- same level: x offset
+        // n = 2 (child - target) in half sides, u = n / 2 + (target octant bit), group u >> 1,
+        // position u & 1 (the child's bit); finer sources (level difference d > 0): u = (n - 1
+        // + (d == 1 ? 2 : 0)) / 2 -- and the keys with coarser sources follow one by one
+        // (large key sets, as in deep adaptive trees, keep the plain layout: the host work of
+        // the grouping would cost more than it saves)
+        int64_t row = nkeys;
+        std::vector<int32_t> hpos(8 * (size_t)nkeys);
+        bool grouped = false;
+        if (nkeys <= kGroupedKeysMax) {
+            int64_t rmax = 0;
+            std::vector<int32_t> tmp(nkeys);
+            std::unordered_map<uint64_t, int32_t> gid;
+            gid.reserve(2 * (size_t)nkeys);
+            std::vector<int64_t> neg;
+            for (int o = 0; o < 8; ++o) {
+                gid.clear();
+                neg.clear();
+                int32_t ng = 0;
+                for (int64_t k2 = 0; k2 < nkeys; ++k2) {
+                    const uint64_t key = hkeys[k2];
+                    const int dl = int(key >> 57) - 32;
+                    if (dl < 0) {
+                        neg.push_back(k2);
+                        continue;
+                    }
+                    int64_t g3[3];
+                    int sub = 0;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int64_t n = int64_t((key >> (38 - 19 * ax)) & 0x7ffff) - kKeyOffBias;
+                        const int ob = (o >> (2 - ax)) & 1;
+                        const int64_t u = dl == 0 ? n / 2 + ob : (n - 1 + (dl == 1 ? 2 : 0)) / 2;
+                        g3[ax] = u >> 1;   // arithmetic shift: floor for negative offsets
+                        sub |= int(u & 1) << (2 - ax);
+                    }
+                    const uint64_t g = pack_key(dl, g3[0], g3[1], g3[2]);
+                    auto it = gid.find(g);
+                    if (it == gid.end()) it = gid.emplace(g, ng++).first;
+                    tmp[k2] = 8 * it->second + sub;
+                }
+                for (size_t j = 0; j < neg.size(); ++j) tmp[neg[j]] = 8 * ng + (int32_t)j;
+                rmax = std::max<int64_t>(rmax, 8 * (int64_t)ng + (int64_t)neg.size());
+                std::copy(tmp.begin(), tmp.end(), hpos.begin() + (size_t)o * nkeys);
+            }
+            // rows much longer than the key count (sparse groups): the plain layout instead
+            if (rmax <= 3 * nkeys && ntiles * rmax < (int64_t(1) << 31)) {
+                row = rmax;
+                grouped = true;
+            }
+        }
+        if (!grouped)
+            for (int o = 0; o < 8; ++o)
+                for (int64_t k2 = 0; k2 < nkeys; ++k2) hpos[(size_t)o * nkeys + k2] = (int32_t)k2;
+        int32_t *lpos = a.get_n<int32_t>(8 * nkeys);
+        mb.upload(lpos, hpos.data(), 4 * hpos.size(), s);
+        uint8_t *tile_oct = a.get_n<uint8_t>(ntiles);
+        {
+            std::vector<uint8_t> ho(ntiles);
+            for (int b2 = 0; b2 < kBuckets; ++b2)
+                for (int64_t t = btile[b2]; t < btile[b2 + 1]; ++t) ho[t] = (uint8_t)(b2 % 8);
+            mb.upload(tile_oct, ho.data(), ntiles, s);
+        }
+        const int64_t nlanes = ntiles * row;
+        unsigned long long *lanes = a.get_n<unsigned long long>(nlanes);
+        fill_i32(reinterpret_cast<int32_t *>(lanes), 0, 2 * nlanes, s);
         hipLaunchKernelGGL(k_key_ids, std::min(grid1(nm2l), 4096), 256, 0, s, (const int2 *)m2l, nm2l,
                            (const int32_t *)slot_id, (const int32_t *)dsame, (const int32_t *)cell_tile,
-                           (const int32_t *)cell_lane, nkeys, pkid, lanes, &counts[0]);
+                           (const int32_t *)cell_lane, (const uint8_t *)tile_oct, (const int32_t *)lpos, nkeys, row,
+                           pkid, lanes, &counts[0]);
         int32_t *present = a.get_n<int32_t>(ntk), *entry_of = a.get_n<int32_t>(ntk + 1);
         // in mixed precision the root tiles stay whole: their FP64 path reads their entries
         const int64_t root_tiles = P->prec == FMM_PREC_MIXED ? btile[(size_t)kRootLevels * 8] : 0;
@@ -1911,8 +1986,9 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         if (const char *ev = getenv("FMM_M2L_DENSE_PCT")) fill_pct = std::max(0, std::min(101, atoi(ev)));
         unsigned long long *nsparse = a.get_n<unsigned long long>(1);
         fill_i32(reinterpret_cast<int32_t *>(nsparse), 0, 2, s);
-        hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes, ntk,
-                           nkeys, fill_pct, root_tiles, present, nsparse);
+        hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
+                           (const uint8_t *)tile_oct, (const int32_t *)lpos, row, ntk, nkeys, fill_pct, root_tiles,
+                           present, nsparse);
         int64_t npool = 0;
         {
             const uint64_t t = mb.next_ticket();
@@ -1927,7 +2003,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         if (npool > 0 && !try_pool) {
             // a small pool is not built: every (tile, key) cell with a pair is an entry
             hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
-                               ntk, nkeys, 0, (int64_t)0, present, (unsigned long long *)nullptr);
+                               (const uint8_t *)tile_oct, (const int32_t *)lpos, row, ntk, nkeys, 0, (int64_t)0,
+                               present, (unsigned long long *)nullptr);
             npool = 0;
         }
         // dense entries (their sources in a first array; the slot entries, if any, follow them)
@@ -1952,7 +2029,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         if (st.ntiles == 0 && npool > 0) {
             // no pool: every (tile, key) cell with a pair is an entry of its target tile
             hipLaunchKernelGGL(k_dense_flags, std::min(grid1(ntk), 4096), 256, 0, s, (const unsigned long long *)lanes,
-                               ntk, nkeys, 0, (int64_t)0, present, (unsigned long long *)nullptr);
+                               (const uint8_t *)tile_oct, (const int32_t *)lpos, row, ntk, nkeys, 0, (int64_t)0,
+                               present, (unsigned long long *)nullptr);
             ne_d = exclusive_scan_i32(present, entry_of, ntk, a, s);
             {
                 const int32_t tot = (int32_t)ne_d;
@@ -1970,6 +2048,8 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         P->nslots = st.nslots;
         P->nslot_tiles = st.ntiles;
         a.put(lanes);
+        a.put(lpos);
+        a.put(tile_oct);
         a.put(recs);
         recs = nullptr;
         lg("m2l slot pool");
