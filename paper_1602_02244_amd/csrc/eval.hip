@@ -989,24 +989,82 @@ __global__ void k_root_to32(int64_t nroot, int KP, const double *in, float *out)
 }
 
 // ------------------------------------------------------------------ L2P
-// One wave per leaf; the local coefficients are broadcast from LDS.  With HESS the harmonic
-// stream stays rolled and the coefficients are indexed at run time (unrolled, the six
-// Hessian expansions keep too many values live: one wave per SIMD and a register spill at
-// p >= 9; without HESS the unrolled stream is the faster one).  With HESS the second
-// derivatives are also evaluated: the gradient of a local expansion is again a local
-// expansion (coefficients of degree l from those of degree l+1: x: (L_{l+1,m-1} -
-// L_{l+1,m+1})/2, y: i (L_{l+1,m+1} + L_{l+1,m-1})/2, z: L_{l+1,m}), so the six Hessian
-// expansions (degree <= p-2) are built once per leaf in LDS by applying that map twice.
-template <int P, bool HESS>
-__global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const float4 *bodies, const float *L,
-                                            float4 *out, float *out_h) {
+// Local coefficient (j, m) of a packed real vector, m >= -1: L_{j,-1} = -conj(L_{j,1}).
+__device__ __forceinline__ float loc_re(const float *v, int j, int m) {
+    if (m > j) return 0.f;
+    if (m == 0) return v[j * j];
+    if (m > 0) return v[j * j + 2 * m - 1];
+    return -v[j * j + 1];
+}
+__device__ __forceinline__ float loc_im(const float *v, int j, int m) {
+    if (m > j || m == 0) return 0.f;
+    if (m > 0) return v[j * j + 2 * m];
+    return v[j * j + 2];
+}
+
+// The term (l, m) of a local expansion at one point (R_lm = rr + i ri): the potential, and
+// the gradient through the local expansion of the gradient, whose coefficients of degree l
+// come from those of degree l+1: x: (L_{l+1,m-1} - L_{l+1,m+1})/2, y: i (L_{l+1,m+1} +
+// L_{l+1,m-1})/2, z: L_{l+1,m}.
+template <int P>
+__device__ __forceinline__ void l2p_term(const float *v, int l, int m, float rr, float ri, float &f, float &gx,
+                                         float &gy, float &gz) {
+    const float wgt = m == 0 ? 1.f : 2.f;
+    f += wgt * (loc_re(v, l, m) * rr + loc_im(v, l, m) * ri);
+    if (l < P) {
+        const float zr = loc_re(v, l + 1, m), zi = loc_im(v, l + 1, m);
+        const float pr = loc_re(v, l + 1, m + 1), pi = loc_im(v, l + 1, m + 1);
+        const float mr = loc_re(v, l + 1, m - 1), mi = loc_im(v, l + 1, m - 1);
+        const float xr = 0.5f * (mr - pr), xi = 0.5f * (mi - pi);
+        const float yr = -0.5f * (pi + mi), yi = 0.5f * (pr + mr);
+        gx += wgt * (xr * rr + xi * ri);
+        gy += wgt * (yr * rr + yi * ri);
+        gz += wgt * (zr * rr + zi * ri);
+    }
+}
+
+// Potential and gradient: one thread per body (sorted order), so that every lane has work
+// whatever the leaf sizes (a leaf holds at most ncrit bodies, often far fewer than a
+// wave).  Each thread reads its leaf's coefficients at compile-time offsets from its own
+// base; the lanes of one leaf read the same addresses.
+template <int P>
+__global__ void __launch_bounds__(256) k_l2p(const int32_t *body_leaf, int64_t n, Geo g, const float4 *bodies,
+                                             const float *L, float4 *out) {
+    using D = Dims<P>;
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const int c = body_leaf[b];
+    double cx, cy, cz, inv;
+    cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
+    const float finv = (float)inv;
+    const float *v = L + (int64_t)c * D::KP;
+    const float4 bd = bodies[b];
+    const float ux = (float)(((double)bd.x - cx) * inv);
+    const float uy = (float)(((double)bd.y - cy) * inv);
+    const float uz = (float)(((double)bd.z - cz) * inv);
+    float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    stream_regular<P>(ux, uy, uz,
+                      [&](int l, int m, float rr, float ri) { l2p_term<P>(v, l, m, rr, ri, f, gx, gy, gz); });
+    const float g2 = finv * finv;
+    out[b] = make_float4(f * finv, gx * g2, gy * g2, gz * g2);   // potential, gradient
+}
+
+// Potential, gradient and Hessian: one wave per leaf, the local coefficients broadcast
+// from LDS.  The harmonic stream stays rolled and the coefficients are indexed at run time
+// (unrolled, the six Hessian expansions keep too many values live: one wave per SIMD and a
+// register spill at p >= 9).  The gradient of a local expansion is again a local
+// expansion (the map in l2p_term), so the six Hessian expansions (degree <= p-2) are built
+// once per leaf in LDS by applying that map twice.
+template <int P>
+__global__ void __launch_bounds__(64) k_l2p_hess(const int32_t *leaves, Geo g, const float4 *bodies, const float *L,
+                                                 float4 *out, float *out_h) {
     using D = Dims<P>;
     constexpr int KP = D::KP;
     constexpr int NT1 = P >= 1 ? P * (P + 1) / 2 : 1;          // (l, m >= 0) pairs with l <= P-1
     constexpr int NT2 = P >= 2 ? (P - 1) * P / 2 : 1;          // l <= P-2
     __shared__ float sL[KP];
-    __shared__ float cre[HESS ? 3 : 1][NT1], cim[HESS ? 3 : 1][NT1];
-    __shared__ float hre[HESS ? 6 : 1][NT2], him[HESS ? 6 : 1][NT2];
+    __shared__ float cre[3][NT1], cim[3][NT1];
+    __shared__ float hre[6][NT2], him[6][NT2];
     const int c = leaves[blockIdx.x];
     const int lane = threadIdx.x;
     for (int d = lane; d < KP; d += 64) sL[d] = L[(int64_t)c * KP + d];
@@ -1015,20 +1073,10 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
     double cx, cy, cz, inv;
     cell_center(g.level[c], g.ix[c], g.iy[c], g.iz[c], g.x0x, g.x0y, g.x0z, g.k, cx, cy, cz, inv);
     const float finv = (float)inv;
-    // coefficient (j, m) of the local expansion, m >= -1
     const float *vL = sL;
-    auto lre = [&](int j, int m) -> float {
-        if (m > j) return 0.f;
-        if (m == 0) return vL[j * j];
-        if (m > 0) return vL[j * j + 2 * m - 1];
-        return -vL[j * j + 1];                  // L_{j,-1} = -conj(L_{j,1})
-    };
-    auto lim = [&](int j, int m) -> float {
-        if (m > j || m == 0) return 0.f;
-        if (m > 0) return vL[j * j + 2 * m];
-        return vL[j * j + 2];
-    };
-    if (HESS && P >= 2) {
+    auto lre = [&](int j, int m) { return loc_re(vL, j, m); };
+    auto lim = [&](int j, int m) { return loc_im(vL, j, m); };
+    if (P >= 2) {
         // gradient expansions C^a, degree <= P-1
         for (int e = lane; e < NT1; e += 64) {
             int l = 0;
@@ -1082,20 +1130,9 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
         float f = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         float h[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         auto term = [&](int l, int m, float rr, float ri) {
+            l2p_term<P>(vL, l, m, rr, ri, f, gx, gy, gz);
             const float wgt = m == 0 ? 1.f : 2.f;
-            f += wgt * (lre(l, m) * rr + lim(l, m) * ri);
-            if (l < P) {
-                // gradient coefficients of degree l from the local coefficients of degree l+1
-                const float zr = lre(l + 1, m), zi = lim(l + 1, m);
-                const float pr = lre(l + 1, m + 1), pi = lim(l + 1, m + 1);
-                const float mr = lre(l + 1, m - 1), mi = lim(l + 1, m - 1);
-                const float xr = 0.5f * (mr - pr), xi = 0.5f * (mi - pi);
-                const float yr = -0.5f * (pi + mi), yi = 0.5f * (pr + mr);
-                gx += wgt * (xr * rr + xi * ri);
-                gy += wgt * (yr * rr + yi * ri);
-                gz += wgt * (zr * rr + zi * ri);
-            }
-            if (HESS && l + 2 <= P) {
+            if (l + 2 <= P) {
                 const int t = l * (l + 1) / 2 + m;
                 h[0] += wgt * (hre[0][t] * rr + him[0][t] * ri);
                 h[1] += wgt * (hre[1][t] * rr + him[1][t] * ri);
@@ -1105,15 +1142,12 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *leaves, Geo g, const 
                 h[5] += wgt * (hre[5][t] * rr + him[5][t] * ri);
             }
         };
-        if (HESS) stream_regular_rolled<P>(ux, uy, uz, term);
-        else stream_regular<P>(ux, uy, uz, term);
+        stream_regular_rolled<P>(ux, uy, uz, term);
         const float g2 = finv * finv;
         out[s + j] = make_float4(f * finv, gx * g2, gy * g2, gz * g2);   // potential, gradient
-        if (HESS) {
-            const float g3 = g2 * finv;
+        const float g3 = g2 * finv;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) out_h[(int64_t)(s + j) * 6 + q] = h[q] * g3;
-        }
+        for (int q = 0; q < 6; ++q) out_h[(int64_t)(s + j) * 6 + q] = h[q] * g3;
     }
 }
 
@@ -1779,11 +1813,11 @@ template <int P, class Near> static void far_field(fmm_plan_s *Pl, const Geo &g,
     ev_rec(Pl, 2 * PH_L2L + 1, s);
     ev_rec(Pl, 2 * PH_L2P, s);
     if (Pl->hess_on)
-        hipLaunchKernelGGL((k_l2p<P, true>), (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g,
+        hipLaunchKernelGGL(k_l2p_hess<P>, (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g,
                            (const float4 *)Pl->bodies, (const float *)Pl->L, Pl->far4, Pl->farh);
     else
-        hipLaunchKernelGGL((k_l2p<P, false>), (int)Pl->nleaves, 64, 0, s, (const int32_t *)Pl->leaves, g,
-                           (const float4 *)Pl->bodies, (const float *)Pl->L, Pl->far4, (float *)nullptr);
+        hipLaunchKernelGGL(k_l2p<P>, (int)((Pl->n + 255) / 256), 256, 0, s, (const int32_t *)Pl->body_leaf, Pl->n, g,
+                           (const float4 *)Pl->bodies, (const float *)Pl->L, Pl->far4);
     ev_rec(Pl, 2 * PH_L2P + 1, s);
 }
 

@@ -224,6 +224,7 @@ struct fmm_plan_s {
     uint64_t *c_prefix_dev = nullptr;
     int32_t *leaves = nullptr;       // leaf cell ids, in cell order
     int32_t *leaf_id = nullptr;      // cell -> leaf index or -1
+    int32_t *body_leaf = nullptr;    // [n] sorted position -> leaf cell
 
     // M2L
     int64_t nm2l = 0, nkeys = 0, ntargets = 0, ntiles = 0, nentries = 0, nwork = 0;

@@ -1009,6 +1009,15 @@ __global__ void k_leaf_compact(const int32_t *flag, const int32_t *ex, int64_t n
     }
 }
 
+// Leaf cell of every body (sorted order): the leaves' body ranges partition the bodies.
+__global__ void k_body_leaf(const int32_t *leaves, int64_t nleaves, const int32_t *c_start, const int32_t *c_count,
+                            int32_t *body_leaf) {
+    for (int64_t li = blockIdx.x; li < nleaves; li += gridDim.x) {
+        const int c = leaves[li], s0 = c_start[c], cnt = c_count[c];
+        for (int j = threadIdx.x; j < cnt; j += blockDim.x) body_leaf[s0 + j] = c;
+    }
+}
+
 // (target leaf id, source leaf id) packed into `lbits`-bit halves; the value is the source cell.
 __global__ void k_p2p_composite(const int2 *pairs, int64_t np, const int32_t *leaf_id, int lbits, uint64_t *comp,
                                 int32_t *vals) {
@@ -1589,6 +1598,10 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         hipLaunchKernelGGL(k_leaf_compact, grid1(nc), 256, 0, s, (const int32_t *)flag, (const int32_t *)ex, nc,
                            P->leaves, P->leaf_id);
         a.put(flag); a.put(ex);
+        P->body_leaf = a.get_n<int32_t>(n);
+        hipLaunchKernelGGL(k_body_leaf, (int)std::min<int64_t>(P->nleaves, 65536), 64, 0, s,
+                           (const int32_t *)P->leaves, P->nleaves, (const int32_t *)P->c_start,
+                           (const int32_t *)P->c_count, P->body_leaf);
     }
 
     lg("leaves");
