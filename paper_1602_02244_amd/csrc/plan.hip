@@ -1677,10 +1677,12 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         fill_i32(reinterpret_cast<int32_t *>(p2p), 0, 2, s);
         np2p = 1;
     } else {
-        // first guess of the list sizes (a uniform cloud at theta = 0.4 has ~450 M2L
-        // pairs per cell in ~90 slots and ~75 P2P pairs per leaf); a step that overflows
-        // is repeated
-        grow(a, m2l, m2l_cap, 0, 512 * nc, s);
+        // first guess of the list sizes (a uniform cloud at theta = 0.4 has ~350-450 M2L
+        // pairs per cell in ~50-90 slots and ~75 P2P pairs per leaf); the M2L list starts
+        // large enough for the worst-case reserve of the largest step of such a cloud (64
+        // per split pair, ~14.5M split pairs at 2^24 points), so that it is not grown (and
+        // copied) during the traversal; a step that overflows is repeated
+        grow(a, m2l, m2l_cap, 0, 1024 * nc, s);
         grow(a, m2l_slot, slot_cap, 0, m2l_cap, s);
         grow(a, recs, rec_cap, 0, 128 * nc, s);
         grow(a, p2p, p2p_cap, 0, 96 * P->nleaves + 64, s);
@@ -1698,7 +1700,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             int64_t cap_n = std::max<int64_t>(1024, std::min<int64_t>(64 * nf, 10 * nf));
             grow(a, m2l, m2l_cap, nm2l, nm2l + 64 * nf, s);
             grow(a, m2l_slot, slot_cap, nm2l, m2l_cap, s);
-            grow(a, recs, rec_cap, nrec, nrec + 16 * nf, s);
+            grow(a, recs, rec_cap, nrec, nrec + 8 * nf, s);   // a record per target child at most
             grow(a, p2p, p2p_cap, np2p, np2p + 12 * nf, s);
             int2 *next = a.get_n<int2>(cap_n);
             uint64_t h4[4];
@@ -2029,9 +2031,12 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
         int32_t *dsrc = a.get_n<int32_t>(ne_d * kTileN);
         fill_i32(dsrc, -1, ne_d * kTileN, s);
         uint8_t *pool = try_pool ? a.get_n<uint8_t>(nm2l) : nullptr;
-        hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
-                           (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of, nkeys,
-                           dsrc, pool);
+        auto fill_entries = [&](int32_t *dst, uint8_t *pl) {
+            hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
+                               (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of,
+                               nkeys, dst, pl);
+        };
+        fill_entries(dsrc, pool);
         SlotTiles st;
         if (try_pool) {
             // ---- slot pool (given up when its slots would tile poorly)
@@ -2052,9 +2057,7 @@ void build_plan(fmm_plan_s *P, const float *points, hipStream_t s) {
             a.put(dsrc);
             dsrc = a.get_n<int32_t>(ne_d * kTileN);
             fill_i32(dsrc, -1, ne_d * kTileN, s);
-            hipLaunchKernelGGL(k_fill_entries, grid1(nm2l), 256, 0, s, (const int2 *)m2l, nm2l, (const int32_t *)pkid,
-                               (const int32_t *)cell_tile, (const int32_t *)cell_lane, (const int32_t *)entry_of,
-                               nkeys, dsrc, (uint8_t *)nullptr);
+            fill_entries(dsrc, (uint8_t *)nullptr);
         }
         if (st.ntiles == 0) npool = 0;
         P->npool = npool;
