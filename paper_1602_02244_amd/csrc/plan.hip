@@ -671,16 +671,17 @@ __global__ void k_rec_members(const int4 *rec, int64_t nrec, const uint8_t *pool
     }
 }
 
-// Sort keys of the pooled slots: (target, b0, how the producing pair was split) in
-// `cbits`, `cbits` and 2 bits -- unique per slot, so the order is the same on every run
-// whatever order the traversal wrote the records in; values = record index.
-__global__ void k_rec_keys(const int4 *rec, const int32_t *flag, const int32_t *at, int64_t nrec, int cbits,
-                           uint64_t *keys, int32_t *vals) {
+// Sort keys of the pooled slots: (target, key id of the slot's first pooled pair) in
+// `kbits` + the target's bits.  Unique per slot -- a pair (target, source) is in exactly one
+// slot, and a target and an operator key fix the source cell -- so the order is the same on
+// every run whatever order the traversal wrote the records in; values = record index.
+__global__ void k_rec_keys(const int4 *rec, const int32_t *flag, const int32_t *at, const int32_t *mbits,
+                           const int32_t *key_id, int64_t nrec, int kbits, uint64_t *keys, int32_t *vals) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrec; r += (int64_t)gridDim.x * blockDim.x)
         if (flag[r]) {
             const int4 R = rec[r];
             const int64_t j = at[r];
-            keys[j] = ((((uint64_t)R.x << cbits) | (uint64_t)R.z) << 2) | (uint64_t)(R.w & 3);
+            keys[j] = ((uint64_t)R.x << kbits) | (uint64_t)(uint32_t)key_id[(int64_t)R.y + __builtin_ctz(mbits[r])];
             vals[j] = (int32_t)r;
         }
 }
@@ -1228,7 +1229,7 @@ constexpr int kSlotsPerSig = 64;    // fewer slots per signature on average: the
 struct SlotTiles {
     bool abandoned = false;                         // the pool's slots were too diverse to tile well
     int64_t nslots = 0, ntiles = 0, ne = 0, nsig = 0;
-    int32_t *slot_first = nullptr, *slot_mb = nullptr, *slot_tgt = nullptr;   // slots in (target, source) order
+    int32_t *slot_first = nullptr, *slot_mb = nullptr, *slot_tgt = nullptr;   // slots in (target, first key) order
     int32_t *slot_b0 = nullptr, *slot_ym = nullptr;
     int32_t *sorted = nullptr;                      // tile order -> slot
     int32_t *gflag = nullptr, *gid = nullptr, *gstart = nullptr, *tflag = nullptr, *tid = nullptr;
@@ -1254,16 +1255,17 @@ static void build_slots(fmm_plan_s *P, const CellView &C, const int32_t *key_id,
     lg.s = s;
     const int64_t nc = P->ncells;
     const int cbits = bits_for(nc);
-    // records with pooled pairs, sorted by (target, source-side cell, split bits)
+    // records with pooled pairs, sorted by (target, key of the first pooled pair)
     int32_t *mbits = a.get_n<int32_t>(nrec), *pflag = a.get_n<int32_t>(nrec), *pat = a.get_n<int32_t>(nrec);
     hipLaunchKernelGGL(k_rec_members, grid1(nrec), 256, 0, s, recs, nrec, pool, mbits, pflag);
     const int64_t ns = exclusive_scan_i32(pflag, pat, nrec, a, s);
     uint64_t *pk = a.get_n<uint64_t>(ns);
     int32_t *order = a.get_n<int32_t>(ns);
-    hipLaunchKernelGGL(k_rec_keys, grid1(nrec), 256, 0, s, recs, (const int32_t *)pflag, (const int32_t *)pat, nrec,
-                       cbits, pk, order);
+    const int kbits = bits_for(P->nkeys);
+    hipLaunchKernelGGL(k_rec_keys, grid1(nrec), 256, 0, s, recs, (const int32_t *)pflag, (const int32_t *)pat,
+                       (const int32_t *)mbits, key_id, nrec, kbits, pk, order);
     a.put(pflag); a.put(pat);
-    radix_sort_u64(pk, order, ns, 2 * cbits + 2, a, s);
+    radix_sort_u64(pk, order, ns, cbits + kbits, a, s);
     a.put(pk);
     lg("  slots: sort");
     st.nslots = ns;
