@@ -865,13 +865,23 @@ __global__ void __launch_bounds__(256) k_slot_reduce(int64_t nruns, const int32_
     for (int64_t r = blockIdx.x; r < nruns; r += gridDim.x) {
         const int q0 = run_first[r], q1 = run_first[r + 1];
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        // group g sums the columns q0 + g, q0 + g + G, ... in that order; eight of them are
+        // loaded before they are added, so that their latencies overlap
+        constexpr int U = 8;
         if (g < G)
-            for (int q = q0 + g; q < q1; q += G) {
-                const float4 v = reinterpret_cast<const float4 *>(partial + slot_pos[q] * KP)[c];
-                acc.x += v.x;
-                acc.y += v.y;
-                acc.z += v.z;
-                acc.w += v.w;
+            for (int q = q0 + g; q < q1; q += U * G) {
+                float4 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (q + u * G < q1) v[u] = reinterpret_cast<const float4 *>(partial + slot_pos[q + u * G] * KP)[c];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (q + u * G < q1) {
+                        acc.x += v[u].x;
+                        acc.y += v[u].y;
+                        acc.z += v[u].z;
+                        acc.w += v[u].w;
+                    }
             }
         if (g < G) part[g * NQ + c] = acc;
         __syncthreads();
