@@ -125,6 +125,29 @@ def test_deterministic_bitwise(torch_mod):
     assert torch.equal(p1, p2) and torch.equal(g1, g2) and torch.equal(p1, p3) and torch.equal(g1, g3)
 
 
+def test_slot_pool_order_deterministic_bitwise(torch_mod, monkeypatch):
+    """Every pair through the slot pool: the traversal writes its slot records in an order
+    that depends on which workgroup finishes first, and the pool sorts them by (target,
+    key of the first pooled pair); two plans of one cloud must still give bit-identical
+    results, and both match the oracle."""
+    import torch
+    from paper_1602_02244_amd import FMM
+    monkeypatch.setenv("FMM_M2L_DENSE_PCT", "101")
+    x, q = inputs.make("cube", 40000, 31)
+    xt, qt = torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda()
+    a = FMM(xt, 32, 6, 0.4)
+    b = FMM(xt, 32, 6, 0.4)
+    assert a.stats()["m2l_slots"] > 0 and a.stats()["m2l_slots"] == b.stats()["m2l_slots"]
+    p1, g1 = a.eval(qt)
+    p2, g2 = b.eval(qt)
+    assert torch.equal(p1, p2) and torch.equal(g1, g2)
+    ora = oracle.Plan(x.astype(np.float64), 32, 0.4)
+    ophi, ograd, _ = ora.eval(q.astype(np.float64), 6)
+    assert rel_l2(p1.cpu().numpy(), ophi) <= TOL and rel_l2(g1.cpu().numpy(), ograd) <= TOL
+    a.close()
+    b.close()
+
+
 def test_nonfinite_coordinates_rejected(torch_mod):
     import torch
     from paper_1602_02244_amd import FMM, FMMError
