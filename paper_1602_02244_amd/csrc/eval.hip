@@ -21,43 +21,14 @@
 
 namespace fmm {
 
-#define TRI(l, m) ((l) * ((l) + 1) / 2 + (m))
-
 template <int P> struct Dims {
     static constexpr int NT = (P + 1) * (P + 2) / 2;    // (l, m >= 0) pairs
     static constexpr int NC = (P + 1) * (P + 1);        // real coefficients
     static constexpr int KP = (NC + 15) / 16 * 16;      // padded
 };
 
-// Regular solid harmonics R_lm(x, y, z), m >= 0, as (re, im) in TRI order.
-template <int P>
-__device__ __forceinline__ void regular_harmonics(float x, float y, float z, float *Rr, float *Ri) {
-    const float r2 = x * x + y * y + z * z;
-    Rr[0] = 1.f;
-    Ri[0] = 0.f;
-#pragma unroll
-    for (int m = 1; m <= P; ++m) {
-        const float c = -1.f / (2.f * m);
-        const float ar = Rr[TRI(m - 1, m - 1)], ai = Ri[TRI(m - 1, m - 1)];
-        Rr[TRI(m, m)] = c * (x * ar - y * ai);
-        Ri[TRI(m, m)] = c * (x * ai + y * ar);
-    }
-#pragma unroll
-    for (int m = 0; m < P; ++m) {
-        Rr[TRI(m + 1, m)] = z * Rr[TRI(m, m)];
-        Ri[TRI(m + 1, m)] = z * Ri[TRI(m, m)];
-#pragma unroll
-        for (int l = m + 1; l < P; ++l) {
-            const float den = 1.f / (float)((l + m + 1) * (l - m + 1));
-            const float c1 = (2 * l + 1) * den;
-            Rr[TRI(l + 1, m)] = c1 * z * Rr[TRI(l, m)] - den * r2 * Rr[TRI(l - 1, m)];
-            Ri[TRI(l + 1, m)] = c1 * z * Ri[TRI(l, m)] - den * r2 * Ri[TRI(l - 1, m)];
-        }
-    }
-}
-
-// The same harmonics streamed to f(l, m, re, im) one column (fixed m, increasing l) at a
-// time, so that only the last two values of a column are live.
+// Regular solid harmonics R_lm(x, y, z), m >= 0, streamed to f(l, m, re, im) one column
+// (fixed m, increasing l) at a time, so that only the last two values of a column are live.
 template <int P, class F>
 __device__ __forceinline__ void stream_regular(float x, float y, float z, F &&f) {
     const float r2 = x * x + y * y + z * z;
@@ -122,12 +93,6 @@ __device__ __forceinline__ void stream_regular_rolled(float x, float y, float z,
             }
         }
     }
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
 }
 
 __device__ __forceinline__ void cell_center(int lvl, int ix, int iy, int iz, double x0x, double x0y, double x0z, int k,

@@ -893,11 +893,6 @@ __global__ void k_tile_first(const int32_t *entry_of, int64_t ntiles, int64_t nk
         tile_first[t] = entry_of[t * nkeys];
 }
 
-__global__ void k_flag_diff(const uint64_t *keys, int64_t n, int shift, int32_t *flag) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        flag[i] = (i == 0 || (keys[i] >> shift) != (keys[i - 1] >> shift)) ? 1 : 0;
-}
-
 
 // Boundary class of a cell: per axis, its distance (in cells of its octant, capped at 2)
 // to the low and to the high face of the root cube, 9 values per axis.  Cells of one
