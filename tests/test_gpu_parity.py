@@ -71,6 +71,23 @@ def test_parity_near_far_full(torch_mod, case):
         assert e_phi <= TOL and e_grad <= TOL, (mode, e_phi, e_grad)
 
 
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_parity_every_pair_through_the_slot_pool(torch_mod, monkeypatch, case):
+    """The same clouds with every M2L pair regrouped into slots (the test mode that pools
+    every (tile, key) cell and keeps the pool whatever its shape): full FMM parity."""
+    dist, n, p, ncrit, theta = case
+    monkeypatch.setenv("FMM_M2L_DENSE_PCT", "101")
+    x, q = inputs.make(dist, n, 100 + n)
+    plan, phi, grad = _run(torch_mod, x, q, p, ncrit, theta)
+    st = plan.stats()
+    assert st["m2l_pairs"] == 0 or st["m2l_slots"] > 0
+    ora = oracle.Plan(x.astype(np.float64), ncrit, theta)
+    ophi, ograd, _ = ora.eval(q.astype(np.float64), p)
+    e_phi, e_grad = rel_l2(phi, ophi), rel_l2(grad, ograd)
+    print(f"{case} pooled: slots {st['m2l_slots']} phi {e_phi:.2e} grad {e_grad:.2e}")
+    assert e_phi <= TOL and e_grad <= TOL
+
+
 def test_full_accuracy_against_direct_sum(torch_mod):
     x, q = inputs.workload("uniform-4k")
     _, phi, grad = _run(torch_mod, x, q, 6, 64, 0.4)
