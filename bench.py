@@ -43,6 +43,10 @@ ACC_TOL = 1e-4
 M2L_TRAFFIC = {"kernel_sha256": "6a28cdac88939087", "workload": "uniform-16M", "p": 12, "theta": 0.4,
                "entries": 7271803, "work_items": 1040804, "bytes": 796.8e9,
                "source": "profiles/m2l_uniform-16M_hbm_bytes.md"}
+# The same for the split-FP16 M2L step (k_m2l_f16 + sums), keyed to that kernel's source.
+M2L_TRAFFIC_MIXED = {"kernel_sha256": "89e4136b21d141bc", "workload": "uniform-16M", "p": 12, "theta": 0.4,
+                     "entries": 7275201, "work_items": 1040638, "bytes": 679.9e9,
+                     "source": "profiles/m2l_mixed_uniform-16M_hbm_bytes.md"}
 
 
 def parse(argv=None):
@@ -70,11 +74,16 @@ def parse(argv=None):
     return ap.parse_args(argv)
 
 
-def m2l_kernel_sha():
-    """sha256 prefix of the M2L kernel's source text (the k_gemm template in eval.hip)."""
+def m2l_kernel_sha(mixed=False):
+    """sha256 prefix of the M2L kernel's source text in eval.hip: the k_gemm template, or
+    with `mixed` the k_m2l_f16 template."""
     src = open(os.path.join(ROOT, "paper_1602_02244_amd", "csrc", "eval.hip")).read()
-    a = src.index("template <int P, bool ADD, bool MASKED")
-    b = src.index("// ---", a)
+    if mixed:
+        a = src.index("template <int P, int NW = f16_waves<P>()>")
+        b = src.index("constexpr int kReduceChunks", a)
+    else:
+        a = src.index("template <int P, bool ADD, bool MASKED")
+        b = src.index("// ---", a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -83,7 +92,8 @@ def m2l_roofline(precision, m2l_tflops, traffic, form="dense"):
     peak of the type it computes in.  The split-FP16 form runs three FP16 products (hi hi,
     hi lo, lo hi) per algorithmic one.  The compressed forms count the flops they apply
     (two rank-r products per pair for the SVD, the kept 16 x 16 blocks for block
-    dropping); the recorded traffic belongs to the dense kernel only."""
+    dropping) and report no traffic: the recorded counters belong to the dense FP32 and
+    split-FP16 kernels."""
     if form == "svd":
         return {"kernel": "k_gemm_svd (two FP32 MFMA products of rank r per entry) + sums", "bound": "mfma",
                 "achieved": m2l_tflops, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s (factored flops)",
@@ -96,7 +106,9 @@ def m2l_roofline(precision, m2l_tflops, traffic, form="dense"):
         achieved = 3.0 * m2l_tflops
         return {"kernel": "k_m2l_f16 + k_m2l_reduce (split-FP16 MFMA grouped GEMM, 3 products)", "bound": "mfma",
                 "achieved": achieved, "peak": MFMA_FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_FP16_PEAK_TFLOPS, "fp32_equivalent": m2l_tflops, "traffic": None}
+                "frac": achieved / MFMA_FP16_PEAK_TFLOPS, "fp32_equivalent": m2l_tflops, "traffic": traffic,
+                "traffic_kind": "L2-to-fabric bytes per launch (FETCH_SIZE/WRITE_SIZE, copy-scaled)",
+                "traffic_source": M2L_TRAFFIC_MIXED["source"] if traffic is not None else None}
     return {"kernel": "k_gemm (FP32 MFMA grouped GEMM) + k_m2l_reduce", "bound": "mfma", "achieved": m2l_tflops,
             "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": m2l_tflops / MFMA_FP32_PEAK_TFLOPS,
             "traffic": traffic, "traffic_kind": "L2-to-fabric bytes per launch (FETCH_SIZE/WRITE_SIZE, copy-scaled)",
@@ -109,11 +121,11 @@ def p2p_roofline(p2p_tflops):
             "frac_of_packed_peak": p2p_tflops / VALU_FP32_PACKED_PEAK_TFLOPS}
 
 
-def m2l_traffic(workload, p, theta, st):
-    t = M2L_TRAFFIC
+def m2l_traffic(workload, p, theta, st, mixed=False):
+    t = M2L_TRAFFIC_MIXED if mixed else M2L_TRAFFIC
     if t["bytes"] is None:
         return None
-    if (m2l_kernel_sha() == t["kernel_sha256"] and (workload, p, theta) == (t["workload"], t["p"], t["theta"])
+    if (m2l_kernel_sha(mixed) == t["kernel_sha256"] and (workload, p, theta) == (t["workload"], t["p"], t["theta"])
             and (st["m2l_entries"], st["m2l_work_items"]) == (t["entries"], t["work_items"])):
         return t["bytes"]
     return None
@@ -401,7 +413,8 @@ def main():
     result.update(stats_keys(st))
     form = "svd" if args.svd_tol > 0 else ("blocks" if args.m2l_tol > 0 else "dense")
     result["roofline"] = m2l_roofline(args.precision, run["m2l_tflops"],
-                                      m2l_traffic(args.workload, p, theta, st) if form == "dense" else None, form)
+                                      m2l_traffic(args.workload, p, theta, st, args.precision == "mixed")
+                                      if form == "dense" else None, form)
     result["p2p_roofline"] = p2p_roofline(run["p2p_tflops"])
 
     refs = None
@@ -421,7 +434,8 @@ def main():
         print("[bench] mixed precision", file=sys.stderr, flush=True)
         mr, (mphi, mgrad, mdq, mdx) = run_steps(xt, qt, wt, ncrit, p, theta, "mixed", ks, kw)
         mst = mr.pop("stats")
-        mixed = dict(mr, steps=ks, warmup=kw, roofline=m2l_roofline("mixed", mr["m2l_tflops"], None),
+        mixed = dict(mr, steps=ks, warmup=kw,
+                     roofline=m2l_roofline("mixed", mr["m2l_tflops"], m2l_traffic(args.workload, p, theta, mst, True)),
                      p2p_roofline=p2p_roofline(mr["p2p_tflops"]))
         if refs is not None:
             mixed["rel_err_vs_direct_1000"] = refs.errors(mphi, mgrad, mdq, mdx)
