@@ -416,8 +416,10 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint64_t *k
                                                                int32_t *vout, int64_t n, int shift, int64_t ntiles,
                                                                const int64_t *off) {
     constexpr int kSortTile = kSortThreads * kSortItems;
-    __shared__ uint64_t skey[kSortTile];
-    __shared__ int32_t sval[kSortTile];
+    // the tile in digit order: keys first, then (reusing the storage) the values, so that
+    // the workgroup holds 42 KB of LDS at 4096 keys and three fit on a compute unit
+    __shared__ uint64_t sbuf[kSortTile];
+    __shared__ uint8_t sdig[kSortTile];   // digit of each position of the ordered tile
     __shared__ int64_t base_off[256];
     __shared__ int wrun[kSortWaves][256];   // per wave: its keys of each digit (then: where they start in the tile)
     __shared__ int wsum[kSortWaves];
@@ -477,19 +479,27 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint64_t *k
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r)
         if (rank[r] >= 0) {
-            const int j = run[(unsigned)(key[r] >> shift) & 255u] + rank[r];
-            skey[j] = key[r];
-            sval[j] = val[r];
+            rank[r] += run[(unsigned)(key[r] >> shift) & 255u];   // position in the ordered tile
+            sbuf[rank[r]] = key[r];
         }
     __syncthreads();
     // wrun[0][d] is now the tile-local start of digit d
     const int cnt = (int)(n - tile0 < kSortTile ? n - tile0 : kSortTile);
     for (int i = tid; i < cnt; i += kSortThreads) {
-        const uint64_t k = skey[i];
+        const uint64_t k = sbuf[i];
         const unsigned d = (unsigned)(k >> shift) & 255u;
-        const int64_t dst = base_off[d] + (i - wrun[0][d]);
-        kout[dst] = k;
-        vout[dst] = sval[i];
+        sdig[i] = (uint8_t)d;
+        kout[base_off[d] + (i - wrun[0][d])] = k;
+    }
+    __syncthreads();
+    int32_t *sv = reinterpret_cast<int32_t *>(sbuf);
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (rank[r] >= 0) sv[rank[r]] = val[r];
+    __syncthreads();
+    for (int i = tid; i < cnt; i += kSortThreads) {
+        const unsigned d = sdig[i];
+        vout[base_off[d] + (i - wrun[0][d])] = sv[i];
     }
 }
 
