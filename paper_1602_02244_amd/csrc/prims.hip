@@ -391,8 +391,9 @@ void exclusive_scan_i64_to(const int64_t *in, int64_t *out, int64_t n, int64_t *
 // histogram, stored digit-major so that (2) one exclusive scan gives every (digit, tile)
 // its output offset, (3) a stable scatter: each wave ranks a contiguous quarter of the
 // tile on its own (equal digits in input order, through ballots and per-wave digit
-// counters), the quarters are merged by digit in LDS, and the tile is written out so
-// that consecutive threads write consecutive positions of one digit's run.
+// counters), the quarters are merged by digit in LDS, and the tile is written out (the
+// keys, then the values through the same LDS) so that consecutive threads write
+// consecutive positions of one digit's run.
 constexpr int kSortThreads = 256, kSortWaves = kSortThreads / 64;
 
 template <int kSortItems>
